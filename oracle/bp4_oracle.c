@@ -222,7 +222,7 @@ static int hard_decision(const double q[3])
 static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
                        const uint8_t *s, uint8_t *est, uint8_t *conv_out, int32_t *iters_out,
                        double *mvc, double *mcv, double *q, double *qprev, double *pit,
-                       double *acc, double *msum, int *ehat,
+                       double *acc, double *dev, double *msum, int *ehat,
                        double *q_trace, double *m_trace)
 {
     const int n = g->n, m = g->m, nnz = g->nnz;
@@ -233,7 +233,7 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
      * Q^{(0)} = Pi^{(0)}, momentum / gradient accumulators g^{(0)} = G^{(0)} = 0. */
     for (int e = 0; e < nnz; ++e)
         mvc[e] = clampd(lambda_h(g->elab[e], &pi0[3 * g->evar[e]]), C);
-    for (int i = 0; i < 3 * n; ++i) { q[i] = pi0[i]; pit[i] = pi0[i]; acc[i] = 0.0; }
+    for (int i = 0; i < 3 * n; ++i) { q[i] = pi0[i]; pit[i] = pi0[i]; acc[i] = 0.0; dev[i] = 0.0; }
 
     int t_done = p->max_iter, converged = 0;
     for (int t = 1; t <= p->max_iter; ++t) {
@@ -291,14 +291,20 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
                 break;
             }
             case OR_ADAGRAD: { /* eq. boost; active from the second iteration (READING) */
-                double grad = qprev[i] - pi0[i] - msum[i];
+                /* Carried as the deviation D = Q - Pi^{(0)} (READING: the gradient
+                 * g' = Q^{(t-1)} - Pi - sum m of eq. boost is then D^{(t-1)} - sum m,
+                 * which is exactly 0 when the incoming sums repeat; the step
+                 * g'/(sqrt(G)+eps) would otherwise turn rounding residue into a full
+                 * step of size alpha). */
+                double grad = dev[i] - msum[i];
                 if (t == 1) {
                     if (p->adagrad_g_from_t1) acc[i] += grad * grad;
-                    q[i] = pi0[i] + msum[i];
+                    dev[i] = msum[i];
                 } else {
                     acc[i] += grad * grad;
-                    q[i] = qprev[i] - p->alpha * grad / (sqrt(acc[i]) + p->eps);
+                    dev[i] = dev[i] - p->alpha * grad / (sqrt(acc[i]) + p->eps);
                 }
+                q[i] = pi0[i] + dev[i];
                 break;
             }
             }
@@ -392,9 +398,10 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
         double *qprev = malloc(sizeof(double) * 3 * n);
         double *pit = malloc(sizeof(double) * 3 * n);
         double *acc = malloc(sizeof(double) * 3 * n);
+        double *dev = malloc(sizeof(double) * 3 * n);
         double *msum = malloc(sizeof(double) * 3 * n);
         int *ehat = malloc(sizeof(int) * n);
-        if (!mvc || !mcv || !q || !qprev || !pit || !acc || !msum || !ehat) {
+        if (!mvc || !mcv || !q || !qprev || !pit || !acc || !dev || !msum || !ehat) {
 #pragma omp atomic write
             rc = -1;
         } else {
@@ -403,13 +410,13 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
                 double *qt = o->q_trace ? o->q_trace + (size_t)i * p->max_iter * 3 * n : NULL;
                 double *mt = o->m_trace ? o->m_trace + (size_t)i * p->max_iter * 3 * n : NULL;
                 decode_one(&g, p, pi0, synd + (size_t)i * m, est + (size_t)i * n, conv + i,
-                           iters + i, mvc, mcv, q, qprev, pit, acc, msum, ehat, qt, mt);
+                           iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, ehat, qt, mt);
                 if (o->q_out) memcpy(o->q_out + (size_t)i * 3 * n, q, sizeof(double) * 3 * n);
                 if (o->mvc_out) memcpy(o->mvc_out + (size_t)i * nnz, mvc, sizeof(double) * nnz);
                 if (o->mcv_out) memcpy(o->mcv_out + (size_t)i * nnz, mcv, sizeof(double) * nnz);
             }
         }
-        free(mvc); free(mcv); free(q); free(qprev); free(pit); free(acc); free(msum); free(ehat);
+        free(mvc); free(mcv); free(q); free(qprev); free(pit); free(acc); free(dev); free(msum); free(ehat);
     }
     graph_free(&g);
     return rc;
