@@ -1,0 +1,184 @@
+/*
+ * bp4.h -- C ABI of the MI355X (gfx950) flooding-schedule GF(4) belief
+ * propagation library: traditional LLR-BP4 and the Momentum-BP, AdaGrad-BP
+ * and EWAInit-BP variants of Chen, Yi, Liang, Wang, "Improved Belief
+ * Propagation Decoding Algorithms for Surface Codes" (arXiv 2407.11523), on
+ * very large batches of syndromes.
+ *
+ * Conventions (all entry points)
+ *   - Pauli code per qubit, one byte: bit0 = x, bit1 = z (I=0, X=1, Z=2, Y=3).
+ *   - Per-qubit LLR triples are (X, Y, Z), the order of section II-B1.
+ *   - Syndrome bits are bytes in {0, 1}; the check sign is (-1)^{s_c}
+ *     (eq. h_update).
+ *   - "dev" pointers are device memory of the current HIP device, "host"
+ *     pointers host memory.  The library allocates no device memory: the
+ *     caller passes every device buffer (graph image, workspace, outputs).
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Device work is enqueued on it asynchronously; host arguments are read
+ *     before the call returns.
+ *   - Every function returns BP4_OK (0) or a negative error code; the
+ *     message of the calling thread's last error is bp4_last_error().
+ *     Arguments are validated on the host before anything is launched; on
+ *     error nothing is enqueued.
+ */
+#ifndef BP4_H
+#define BP4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BP4_OK = 0,
+    BP4_EINVAL = -1,       /* bad shape, pointer, entry or parameter */
+    BP4_ENONCOMM = -2,     /* two stabilizer rows anticommute */
+    BP4_EDEGREE = -3,      /* a check or qubit degree exceeds the compiled maximum */
+    BP4_EWORKSPACE = -4,   /* workspace or graph buffer too small */
+    BP4_EHIP = -5,         /* a HIP runtime call failed */
+    BP4_EUNSUPPORTED = -6  /* size beyond what the kernels index */
+};
+
+/* Decoder variants (section III). */
+typedef enum {
+    BP4_BP = 0,        /* traditional LLR-BP4, section II-B1 */
+    BP4_MOMENTUM = 1,  /* Momentum-BP, parallel form, eqs. mombp1-mombp3 */
+    BP4_ADAGRAD = 2,   /* AdaGrad-BP, eq. boost */
+    BP4_EWAINIT = 3    /* EWAInit-BP, eq. EWAInit, Algorithm 2 */
+} bp4_variant;
+
+/* Hyperparameters of one decode.
+ *   alpha: Momentum step (learning rate), AdaGrad boost learning rate,
+ *          EWAInit discount factor.  Momentum / EWAInit need 0 <= alpha <= 1,
+ *          AdaGrad alpha > 0.  Ignored by BP.
+ *   gamma: Momentum decay, 0 <= gamma < 1.
+ *   eps:   AdaGrad epsilon, > 0.
+ *   llr_clamp: every message is clamped to [-llr_clamp, llr_clamp], > 0.
+ *   max_iter: iter_max >= 1.
+ *   stop_on_syndrome: 1 halts a shot at the first iteration whose hard
+ *          decision reproduces its syndrome (Algorithm 2); 0 runs max_iter.
+ *   adagrad_g_from_t1: 1 also accumulates the squared gradient at t = 1. */
+typedef struct {
+    int32_t variant;
+    int32_t max_iter;
+    int32_t stop_on_syndrome;
+    int32_t adagrad_g_from_t1;
+    float alpha;
+    float gamma;
+    float eps;
+    float llr_clamp;
+} bp4_params;
+
+/* Opaque host object describing one code's Tanner graph (section II-B1). */
+typedef struct bp4_graph bp4_graph;
+
+#define BP4_ALLOW_ANTICOMMUTING 1u   /* graph_create flag: skip the commutation check */
+
+/* Build the Tanner graph of the symplectic check matrix (hx | hz), host
+ * uint8 arrays [m][n] row-major; row i is the stabilizer S_i, entry j its
+ * Pauli on qubit j (section II-B1).  Edge (i, j) exists where the entry is
+ * not I; its label is the GF(4) entry H_ij.  The inputs are copied.
+ * Errors: EINVAL (m, n <= 0, entries not 0/1, empty row or column, NULL),
+ * ENONCOMM (rows anticommute, unless BP4_ALLOW_ANTICOMMUTING), EDEGREE
+ * (check or qubit degree above 4), EUNSUPPORTED (n > 16383 or more than
+ * 65535 edges). */
+int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
+                     uint32_t flags, bp4_graph **out);
+
+/* Attach a logical-operator basis (host uint8 [nlog][n] each, the x and z
+ * parts) used by bp4_bookkeep to tell undetected logical errors from
+ * success (section IV).  Errors: EINVAL. */
+int bp4_graph_set_logicals(bp4_graph *g, const uint8_t *lx, const uint8_t *lz, int32_t nlog);
+
+/* Sizes of the graph: qubits, checks, edges, maximum check and qubit degree. */
+int bp4_graph_info(const bp4_graph *g, int32_t *n, int32_t *m, int32_t *nnz,
+                   int32_t *max_cdeg, int32_t *max_vdeg);
+
+/* Bytes of device memory that bp4_graph_upload fills. */
+int bp4_graph_device_bytes(const bp4_graph *g, size_t *bytes);
+
+/* Copy the graph image (edge lists, labels, logicals) into dev_buf
+ * (caller-owned, >= bp4_graph_device_bytes, 256-byte aligned).  Blocks until
+ * the copy is done.  Call again after bp4_graph_set_logicals.
+ * Errors: EINVAL, EWORKSPACE (buffer too small), EHIP. */
+int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stream);
+
+void bp4_graph_destroy(bp4_graph *g);
+
+/* Canonical edge order: the nonzeros of H in row-major order.  Writes, for
+ * each canonical edge k, its check and qubit (host int32 [nnz] each). */
+int bp4_graph_edges(const bp4_graph *g, int32_t *check, int32_t *qubit);
+
+/* Device workspace bytes bp4_decode needs for `shots` shots (a few counters
+ * for the small-code kernel; message arrays for the large-code kernel). */
+int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes);
+
+/* Sample i.i.d. Pauli errors and their syndromes (section IV: each qubit is
+ * X, Y, Z with probabilities pX, pY, pZ).  Shot i (global index shot0 + i)
+ * uses Philox4x64-10 (Salmon et al., SC'11) with key (seed, stream_id) and
+ * counter (shot0 + i, q / 8, 0, 0); qubit q takes 32-bit half (q % 2) of
+ * output word (q % 8) / 2 and compares it with the integer thresholds
+ * thr = (tX, tY, tZ) of 2^32: u < tX -> X, < tX+tY -> Y, < tX+tY+tZ -> Z.
+ * Writes err dev [shots][n] and synd dev [shots][m], s_c = sum_v <H_cv, E_v>
+ * mod 2.  Errors: EINVAL (thresholds sum >= 2^32, NULL), EHIP. */
+int bp4_sample(const bp4_graph *g, const void *dev_graph, int64_t shots, int64_t shot0,
+               const uint32_t thr[3], uint64_t seed, uint64_t stream_id,
+               uint8_t *err, uint8_t *synd, void *stream);
+
+/* Decode `shots` syndromes (synd dev [shots][m]) with prior LLRs
+ * prior_llr dev [n][3], Pi_{v,W} = ln(p_v^I / p_v^W) (section II-B1,
+ * Algorithm 2 input), by flooding-schedule BP of the chosen variant.  Per
+ * shot: est dev [shots][n] (hard decision, section II-B1), conv dev [shots]
+ * (1 iff the hard decision reproduces the syndrome at the last iteration
+ * run), iters dev [shots] (iterations run, 1..max_iter).  ws is a device
+ * workspace of >= bp4_workspace_bytes.
+ * Errors: EINVAL (parameters out of range, NULL), EWORKSPACE, EHIP. */
+int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, int64_t shots,
+               const float *prior_llr, const uint8_t *synd,
+               uint8_t *est, uint8_t *conv, int32_t *iters,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* Launch choices of the decode kernels.  group_lanes: lanes that decode one
+ * shot together in the LDS kernel (4, 8, 16, 32, 64, 128 or 256; 0 picks by
+ * lane use).  Other fields are reserved and must be 0. */
+typedef struct {
+    int32_t group_lanes;
+    int32_t reserved[7];
+} bp4_tuning;
+
+/* As bp4_decode, with launch choices `tune` (NULL: automatic) and, for
+ * verification, the state after the last iteration run: q_out dev
+ * [shots][n][3] posterior LLRs Q; mvc_out and mcv_out dev [shots][nnz]
+ * variable-to-check and check-to-variable messages in canonical edge order.
+ * Each of q_out and the (mvc_out, mcv_out) pair may be NULL; writing them
+ * slows the decode.  Errors: as bp4_decode; EINVAL for a group size the code
+ * does not fit (more than 64 checks per lane, or LDS exhausted). */
+int bp4_decode_ex(const bp4_graph *g, const void *dev_graph, const bp4_params *p,
+                  const bp4_tuning *tune, int64_t shots, const float *prior_llr,
+                  const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters,
+                  float *q_out, float *mvc_out, float *mcv_out,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Classify each shot (section IV): with R = E^ E, fail dev [shots] = 1
+ * ("detected": R anticommutes with a stabilizer), 2 ("undetected": R
+ * commutes with every stabilizer but not with a logical operator of the
+ * basis set by bp4_graph_set_logicals) or 0 (success).  counts dev int64[3]
+ * is incremented by the number of shots of each class (the caller zeroes it
+ * first).  err, est: dev [shots][n].  Errors: EINVAL (no logicals), EHIP. */
+int bp4_bookkeep(const bp4_graph *g, const void *dev_graph, int64_t shots,
+                 const uint8_t *err, const uint8_t *est, uint8_t *fail, int64_t *counts,
+                 void *stream);
+
+/* Message of the calling thread's last non-OK return. */
+const char *bp4_last_error(void);
+
+/* Library version string. */
+const char *bp4_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BP4_H */

@@ -1,0 +1,10 @@
+"""MI355X (gfx950) flooding-schedule GF(4) belief propagation decoders for surface codes.
+
+Traditional LLR-BP4, Momentum-BP, AdaGrad-BP and EWAInit-BP (Chen, Yi, Liang, Wang,
+"Improved Belief Propagation Decoding Algorithms for Surface Codes") over very large
+batches of syndromes, as hand-written HIP kernels behind the C ABI of include/bp4.h.
+"""
+from ._lib import BP4Error, load
+from .api import Graph, Params, bookkeep, decode, prior_llr, sample
+
+__all__ = ["BP4Error", "Graph", "Params", "bookkeep", "decode", "load", "prior_llr", "sample"]

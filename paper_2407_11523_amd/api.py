@@ -1,0 +1,196 @@
+"""Python binding of the bp4 C ABI: argument marshalling over torch device tensors.
+
+Every computation runs in the HIP kernels of libbp4.so; this module only
+allocates torch tensors, passes their pointers and the current stream, and
+turns error codes into exceptions.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from ._lib import BP4Error, Params as _CParams, Tuning as _CTuning, check, load
+
+VARIANTS = {"bp": 0, "momentum": 1, "adagrad": 2, "ewainit": 3}
+ALLOW_ANTICOMMUTING = 1
+
+
+def _stream(device=None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _u8(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+@dataclass
+class Params:
+    """Decoder hyperparameters (section III of the paper)."""
+    variant: str = "bp"
+    max_iter: int = 100
+    stop_on_syndrome: bool = True
+    adagrad_g_from_t1: bool = False
+    alpha: float = 1.0
+    gamma: float = 0.0
+    eps: float = 1e-8
+    llr_clamp: float = 30.0
+
+    def c(self) -> _CParams:
+        return _CParams(VARIANTS[self.variant], int(self.max_iter), int(bool(self.stop_on_syndrome)),
+                        int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
+                        float(self.eps), float(self.llr_clamp))
+
+
+class Graph:
+    """A code's Tanner graph: host object plus its uploaded device image."""
+
+    def __init__(self, hx, hz, lx=None, lz=None, *, allow_anticommuting: bool = False,
+                 device: Optional[torch.device] = None, upload: bool = True):
+        lib = load()
+        hx, hz = _u8(hx), _u8(hz)
+        if hx.ndim != 2 or hx.shape != hz.shape:
+            raise BP4Error(-1, "hx and hz must be 2-D arrays of one shape")
+        m, n = hx.shape
+        h = ctypes.c_void_p()
+        check(lib.bp4_graph_create(hx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   hz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), m, n,
+                                   ALLOW_ANTICOMMUTING if allow_anticommuting else 0, ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        vals = [ctypes.c_int32() for _ in range(5)]
+        check(lib.bp4_graph_info(h, *[ctypes.byref(v) for v in vals]))
+        self.n, self.m, self.nnz, self.max_cdeg, self.max_vdeg = (int(v.value) for v in vals)
+        self.nlog = 0
+        if lx is not None:
+            self.set_logicals(lx, lz)
+        self.dev = None
+        if upload:
+            self.upload(device)
+
+    def set_logicals(self, lx, lz) -> None:
+        lx, lz = _u8(lx), _u8(lz)
+        check(self._lib.bp4_graph_set_logicals(self._h, lx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                               lz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                               int(lx.shape[0])))
+        self.nlog = int(lx.shape[0])
+        if getattr(self, "dev", None) is not None:
+            self.upload(self.dev.device)
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        check(self._lib.bp4_graph_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def upload(self, device=None) -> None:
+        device = torch.device(device if device is not None else "cuda")
+        buf = torch.empty(self.device_bytes(), dtype=torch.uint8, device=device)
+        check(self._lib.bp4_graph_upload(self._h, _ptr(buf), buf.numel(), _stream(device)))
+        self.dev = buf
+
+    def edges(self):
+        """(check, qubit) of every edge in canonical (row-major) order."""
+        c = np.zeros(self.nnz, np.int32)
+        q = np.zeros(self.nnz, np.int32)
+        check(self._lib.bp4_graph_edges(self._h, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return c, q
+
+    def workspace_bytes(self, params: Params, shots: int) -> int:
+        b = ctypes.c_size_t()
+        cp = params.c()
+        check(self._lib.bp4_workspace_bytes(self._h, ctypes.byref(cp), int(shots), ctypes.byref(b)))
+        return int(b.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.bp4_graph_destroy(h)
+            self._h = None
+
+
+def prior_llr(probs, device=None) -> torch.Tensor:
+    """Pi_{v,W} = ln(p^I / p^W) (section II-B1) as a float32 [n][3] device tensor."""
+    probs = np.asarray(probs, dtype=np.float64)
+    pi = np.log(1.0 - probs.sum(axis=1, keepdims=True)) - np.log(probs)
+    return torch.as_tensor(pi.astype(np.float32), device=device if device is not None else "cuda")
+
+
+def sample(g: Graph, shots: int, thr, seed: int, stream_id: int = 0, shot0: int = 0,
+           err: Optional[torch.Tensor] = None, synd: Optional[torch.Tensor] = None):
+    """Errors [shots][n] and syndromes [shots][m] (uint8 device tensors)."""
+    dev = g.dev.device
+    if err is None:
+        err = torch.empty((shots, g.n), dtype=torch.uint8, device=dev)
+    if synd is None:
+        synd = torch.empty((shots, g.m), dtype=torch.uint8, device=dev)
+    t = (ctypes.c_uint32 * 3)(*[int(x) for x in thr])
+    check(g._lib.bp4_sample(g.handle, _ptr(g.dev), int(shots), int(shot0), t,
+                            ctypes.c_uint64(seed & (2 ** 64 - 1)), ctypes.c_uint64(stream_id & (2 ** 64 - 1)),
+                            _ptr(err), _ptr(synd), _stream(dev)))
+    return err, synd
+
+
+def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *, trace: bool = False,
+           group_lanes: int = 0, out: Optional[dict] = None, ws: Optional[torch.Tensor] = None):
+    """Decode syndromes [shots][m]; returns dict(est, conv, iters[, q, mvc, mcv]).
+
+    group_lanes forces the lanes per shot of the LDS kernel (0: automatic)."""
+    dev = g.dev.device
+    if synd.dtype != torch.uint8 or synd.dim() != 2 or synd.shape[1] != g.m or not synd.is_contiguous():
+        raise BP4Error(-1, "synd must be a contiguous uint8 [shots][m] tensor")
+    if prior.dtype != torch.float32 or tuple(prior.shape) != (g.n, 3) or not prior.is_contiguous():
+        raise BP4Error(-1, "prior must be a contiguous float32 [n][3] tensor")
+    shots = synd.shape[0]
+    o = out if out is not None else {}
+    est = o.get("est")
+    if est is None:
+        est = torch.empty((shots, g.n), dtype=torch.uint8, device=dev)
+    conv = o.get("conv")
+    if conv is None:
+        conv = torch.empty(shots, dtype=torch.uint8, device=dev)
+    iters = o.get("iters")
+    if iters is None:
+        iters = torch.empty(shots, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = torch.empty(g.workspace_bytes(params, shots), dtype=torch.uint8, device=dev)
+    cp = params.c()
+    res = {"est": est, "conv": conv, "iters": iters}
+    if trace or group_lanes:
+        q = mvc = mcv = None
+        if trace:
+            q = torch.empty((shots, g.n, 3), dtype=torch.float32, device=dev)
+            mvc = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
+            mcv = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
+            res.update(q=q, mvc=mvc, mcv=mcv)
+        tune = _CTuning(int(group_lanes))
+        check(g._lib.bp4_decode_ex(g.handle, _ptr(g.dev), ctypes.byref(cp), ctypes.byref(tune), shots,
+                                   _ptr(prior), _ptr(synd), _ptr(est), _ptr(conv), _ptr(iters), _ptr(q),
+                                   _ptr(mvc), _ptr(mcv), _ptr(ws), ws.numel(), _stream(dev)))
+    else:
+        check(g._lib.bp4_decode(g.handle, _ptr(g.dev), ctypes.byref(cp), shots, _ptr(prior), _ptr(synd),
+                                _ptr(est), _ptr(conv), _ptr(iters), _ptr(ws), ws.numel(), _stream(dev)))
+    return res
+
+
+def bookkeep(g: Graph, err: torch.Tensor, est: torch.Tensor, counts: Optional[torch.Tensor] = None):
+    """Per-shot class (0 ok, 1 detected, 2 undetected) and int64[3] class counts."""
+    dev = g.dev.device
+    shots = err.shape[0]
+    fail = torch.empty(shots, dtype=torch.uint8, device=dev)
+    if counts is None:
+        counts = torch.zeros(3, dtype=torch.int64, device=dev)
+    check(g._lib.bp4_bookkeep(g.handle, _ptr(g.dev), shots, _ptr(err), _ptr(est), _ptr(fail), _ptr(counts),
+                              _stream(dev)))
+    return fail, counts

@@ -1,0 +1,435 @@
+// Host side of the C ABI declared in include/bp4.h: Tanner-graph construction
+// and validation, the packed device image, argument checks, and kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bp4.h"
+#include "bp4_internal.h"
+
+using namespace bp4;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(BP4_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// Host graph object.  Edges are numbered canonically (row-major nonzeros of H);
+// message slots are numbered variable-major (each qubit's edges in increasing
+// check order) so that a qubit's slots are contiguous.
+struct bp4_graph {
+    int32_t m = 0, n = 0, nnz = 0, max_cdeg = 0, max_vdeg = 0, nlog = 0;
+    std::vector<int32_t> canon_chk, canon_var;   // canonical edge -> check, qubit
+    std::vector<uint32_t> cedge;                 // [m][kMaxCheckDeg]
+    std::vector<uint32_t> vinfo;                 // [n]
+    std::vector<uint32_t> vcanon;                // [nnz]
+    std::vector<uint32_t> lptr, lent;            // logicals
+    // byte offsets of the sections in the device image
+    size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_lptr = 0, off_lent = 0, bytes = 0;
+
+    void layout()
+    {
+        size_t o = 0;
+        off_cedge = o; o = align256(o + cedge.size() * 4);
+        off_vinfo = o; o = align256(o + vinfo.size() * 4);
+        off_vcanon = o; o = align256(o + vcanon.size() * 4);
+        off_lptr = o; o = align256(o + lptr.size() * 4);
+        off_lent = o; o = align256(o + (lent.empty() ? 1 : lent.size()) * 4);
+        bytes = o;
+    }
+
+    GraphView view(const void *dev) const
+    {
+        const char *b = static_cast<const char *>(dev);
+        GraphView v;
+        v.cedge = reinterpret_cast<const uint32_t *>(b + off_cedge);
+        v.vinfo = reinterpret_cast<const uint32_t *>(b + off_vinfo);
+        v.vcanon = reinterpret_cast<const uint32_t *>(b + off_vcanon);
+        v.lptr = reinterpret_cast<const uint32_t *>(b + off_lptr);
+        v.lent = reinterpret_cast<const uint32_t *>(b + off_lent);
+        v.m = m;
+        v.n = n;
+        v.nnz = nnz;
+        v.nlog = nlog;
+        return v;
+    }
+};
+
+extern "C" {
+
+const char *bp4_last_error(void) { return g_err.c_str(); }
+
+const char *bp4_version(void) { return "bp4 0.1 gfx950"; }
+
+int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n, uint32_t flags,
+                     bp4_graph **out)
+{
+    if (!out) return fail(BP4_EINVAL, "graph_create: out is NULL");
+    *out = nullptr;
+    if (!hx || !hz) return fail(BP4_EINVAL, "graph_create: NULL matrix");
+    if (m <= 0 || n <= 0) return fail(BP4_EINVAL, "graph_create: m=%d n=%d must be positive", m, n);
+    if (n > kMaxVars) return fail(BP4_EUNSUPPORTED, "graph_create: n=%d above %d", n, kMaxVars);
+    std::vector<int32_t> cdeg(m, 0), vdeg(n, 0);
+    long nnz = 0;
+    for (long i = 0; i < (long)m * n; ++i) {
+        if (hx[i] > 1 || hz[i] > 1)
+            return fail(BP4_EINVAL, "graph_create: entry (%ld,%ld) not 0/1", i / n, i % n);
+        if (hx[i] | hz[i]) {
+            ++cdeg[i / n];
+            ++vdeg[i % n];
+            ++nnz;
+        }
+    }
+    if (nnz > kMaxEdges) return fail(BP4_EUNSUPPORTED, "graph_create: %ld edges above %d", nnz, kMaxEdges);
+    int maxc = 0, maxv = 0;
+    for (int c = 0; c < m; ++c) {
+        if (cdeg[c] == 0) return fail(BP4_EINVAL, "graph_create: check %d is empty", c);
+        maxc = cdeg[c] > maxc ? cdeg[c] : maxc;
+    }
+    for (int v = 0; v < n; ++v) {
+        if (vdeg[v] == 0) return fail(BP4_EINVAL, "graph_create: qubit %d is in no check", v);
+        maxv = vdeg[v] > maxv ? vdeg[v] : maxv;
+    }
+    if (maxc > kMaxCheckDeg || maxv > kMaxVarDeg)
+        return fail(BP4_EDEGREE, "graph_create: degrees (check %d, qubit %d) above (%d, %d)", maxc, maxv,
+                    kMaxCheckDeg, kMaxVarDeg);
+
+    auto *g = new bp4_graph;
+    g->m = m;
+    g->n = n;
+    g->nnz = (int32_t)nnz;
+    g->max_cdeg = maxc;
+    g->max_vdeg = maxv;
+    std::vector<uint32_t> lab(nnz);
+    for (int c = 0; c < m; ++c)
+        for (int v = 0; v < n; ++v) {
+            const long i = (long)c * n + v;
+            if (hx[i] | hz[i]) {
+                g->canon_chk.push_back(c);
+                g->canon_var.push_back(v);
+                lab[g->canon_chk.size() - 1] = (uint32_t)(hx[i] | (hz[i] << 1));
+            }
+        }
+    // variable-major slots
+    std::vector<int32_t> vptr(n + 1, 0);
+    for (int v = 0; v < n; ++v) vptr[v + 1] = vptr[v] + vdeg[v];
+    std::vector<int32_t> fill(n, 0), slot_of(nnz);
+    g->vcanon.assign(nnz, 0);
+    for (long k = 0; k < nnz; ++k) {   // canonical order visits checks increasingly
+        const int v = g->canon_var[k];
+        const int s = vptr[v] + fill[v]++;
+        slot_of[k] = s;
+        g->vcanon[s] = (uint32_t)k;
+    }
+    // commutation of the rows: only pairs sharing a qubit can anticommute
+    if (!(flags & BP4_ALLOW_ANTICOMMUTING)) {
+        std::vector<std::vector<std::pair<int, uint32_t>>> vchk(n);
+        for (long k = 0; k < nnz; ++k) vchk[g->canon_var[k]].push_back({g->canon_chk[k], lab[k]});
+        std::vector<int32_t> cptr(m + 1, 0);
+        for (int c = 0; c < m; ++c) cptr[c + 1] = cptr[c] + cdeg[c];
+        std::vector<uint8_t> par(m, 0), seen(m, 0);
+        std::vector<int> touched;
+        for (int c = 0; c < m; ++c) {
+            touched.clear();
+            for (int k = cptr[c]; k < cptr[c + 1]; ++k) {
+                const uint32_t a = lab[k];
+                for (auto &pr : vchk[g->canon_var[k]]) {
+                    const int c2 = pr.first;
+                    if (c2 <= c) continue;
+                    const uint32_t b = pr.second;
+                    if (!seen[c2]) { seen[c2] = 1; touched.push_back(c2); }
+                    par[c2] ^= (uint8_t)(((a & (b >> 1)) ^ ((a >> 1) & b)) & 1u);
+                }
+            }
+            for (int c2 : touched) {
+                if (par[c2]) {
+                    delete g;
+                    return fail(BP4_ENONCOMM, "graph_create: rows %d and %d anticommute", c, c2);
+                }
+            }
+            for (int c2 : touched) { par[c2] = 0; seen[c2] = 0; }
+        }
+    }
+    // packed check edges (ELL, padded)
+    g->cedge.assign((size_t)m * kMaxCheckDeg, kEdgePad);
+    {
+        std::vector<int> cfill(m, 0);
+        for (long k = 0; k < nnz; ++k) {
+            const int c = g->canon_chk[k];
+            const uint32_t w = (uint32_t)slot_of[k] | ((uint32_t)g->canon_var[k] << 16) | (lab[k] << 30);
+            g->cedge[(size_t)c * kMaxCheckDeg + cfill[c]++] = w;
+        }
+    }
+    // packed qubit words
+    g->vinfo.assign(n, 0);
+    for (int v = 0; v < n; ++v) {
+        uint32_t w = (uint32_t)vptr[v] | ((uint32_t)vdeg[v] << 16);
+        for (int j = 0; j < vdeg[v]; ++j) w |= lab[g->vcanon[vptr[v] + j]] << (20 + 2 * j);
+        g->vinfo[v] = w;
+    }
+    g->lptr.assign(1, 0);
+    g->layout();
+    *out = g;
+    return BP4_OK;
+}
+
+int bp4_graph_set_logicals(bp4_graph *g, const uint8_t *lx, const uint8_t *lz, int32_t nlog)
+{
+    if (!g) return fail(BP4_EINVAL, "set_logicals: NULL graph");
+    if (nlog < 0 || (nlog > 0 && (!lx || !lz))) return fail(BP4_EINVAL, "set_logicals: bad arguments");
+    std::vector<uint32_t> ptr(1, 0), ent;
+    for (int k = 0; k < nlog; ++k) {
+        for (int v = 0; v < g->n; ++v) {
+            const uint8_t x = lx[(size_t)k * g->n + v], z = lz[(size_t)k * g->n + v];
+            if (x > 1 || z > 1) return fail(BP4_EINVAL, "set_logicals: entry not 0/1");
+            if (x | z) ent.push_back((uint32_t)v | ((uint32_t)(x | (z << 1)) << 16));
+        }
+        ptr.push_back((uint32_t)ent.size());
+    }
+    g->lptr = ptr;
+    g->lent = ent;
+    g->nlog = nlog;
+    g->layout();
+    return BP4_OK;
+}
+
+int bp4_graph_info(const bp4_graph *g, int32_t *n, int32_t *m, int32_t *nnz, int32_t *max_cdeg,
+                   int32_t *max_vdeg)
+{
+    if (!g) return fail(BP4_EINVAL, "graph_info: NULL graph");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (nnz) *nnz = g->nnz;
+    if (max_cdeg) *max_cdeg = g->max_cdeg;
+    if (max_vdeg) *max_vdeg = g->max_vdeg;
+    return BP4_OK;
+}
+
+int bp4_graph_device_bytes(const bp4_graph *g, size_t *bytes)
+{
+    if (!g || !bytes) return fail(BP4_EINVAL, "graph_device_bytes: NULL argument");
+    *bytes = g->bytes;
+    return BP4_OK;
+}
+
+int bp4_graph_edges(const bp4_graph *g, int32_t *check, int32_t *qubit)
+{
+    if (!g || !check || !qubit) return fail(BP4_EINVAL, "graph_edges: NULL argument");
+    std::memcpy(check, g->canon_chk.data(), sizeof(int32_t) * g->nnz);
+    std::memcpy(qubit, g->canon_var.data(), sizeof(int32_t) * g->nnz);
+    return BP4_OK;
+}
+
+int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stream)
+{
+    if (!g || !dev_buf) return fail(BP4_EINVAL, "graph_upload: NULL argument");
+    if (bytes < g->bytes) return fail(BP4_EWORKSPACE, "graph_upload: %zu bytes < %zu", bytes, g->bytes);
+    if (reinterpret_cast<uintptr_t>(dev_buf) & 255) return fail(BP4_EINVAL, "graph_upload: buffer not 256-byte aligned");
+    std::vector<uint8_t> img(g->bytes, 0);
+    std::memcpy(img.data() + g->off_cedge, g->cedge.data(), g->cedge.size() * 4);
+    std::memcpy(img.data() + g->off_vinfo, g->vinfo.data(), g->vinfo.size() * 4);
+    std::memcpy(img.data() + g->off_vcanon, g->vcanon.data(), g->vcanon.size() * 4);
+    std::memcpy(img.data() + g->off_lptr, g->lptr.data(), g->lptr.size() * 4);
+    if (!g->lent.empty()) std::memcpy(img.data() + g->off_lent, g->lent.data(), g->lent.size() * 4);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(dev_buf, img.data(), g->bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "graph_upload: hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "graph_upload: hipStreamSynchronize");
+    return BP4_OK;
+}
+
+void bp4_graph_destroy(bp4_graph *g) { delete g; }
+
+}  // extern "C"
+
+namespace {
+
+int check_params(const bp4_params *p)
+{
+    if (!p) return fail(BP4_EINVAL, "params: NULL");
+    if (p->variant < BP4_BP || p->variant > BP4_EWAINIT) return fail(BP4_EINVAL, "params: variant %d", p->variant);
+    if (p->max_iter < 1) return fail(BP4_EINVAL, "params: max_iter %d < 1", p->max_iter);
+    if (!(p->llr_clamp > 0.0f) || !std::isfinite(p->llr_clamp)) return fail(BP4_EINVAL, "params: llr_clamp must be finite and > 0");
+    if (p->variant == BP4_MOMENTUM || p->variant == BP4_EWAINIT) {
+        if (!(p->alpha >= 0.0f && p->alpha <= 1.0f)) return fail(BP4_EINVAL, "params: alpha must lie in [0, 1]");
+    }
+    if (p->variant == BP4_MOMENTUM && !(p->gamma >= 0.0f && p->gamma < 1.0f))
+        return fail(BP4_EINVAL, "params: gamma must lie in [0, 1)");
+    if (p->variant == BP4_ADAGRAD) {
+        if (!(p->alpha > 0.0f) || !std::isfinite(p->alpha)) return fail(BP4_EINVAL, "params: AdaGrad alpha must be > 0");
+        if (!(p->eps > 0.0f) || !std::isfinite(p->eps)) return fail(BP4_EINVAL, "params: eps must be > 0");
+    }
+    return BP4_OK;
+}
+
+constexpr size_t kSmallWorkspace = 256;   // one queue counter, padded
+
+// Largest dynamic LDS allocation of one workgroup on the current device.
+int device_max_lds(size_t *bytes)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int v = 0;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    *bytes = (size_t)v;
+    return BP4_OK;
+}
+
+int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p,
+                  const bp4_tuning *tune, int64_t shots,
+                  const float *prior_llr, const uint8_t *synd, uint8_t *est, uint8_t *conv,
+                  int32_t *iters, float *q_out, float *mvc_out, float *mcv_out, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    if (!g || !dev_graph) return fail(BP4_EINVAL, "decode: NULL graph");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (shots < 0 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "decode: shots %lld outside [0, 2^31)", (long long)shots);
+    if (!prior_llr) return fail(BP4_EINVAL, "decode: NULL prior");
+    if (shots == 0) return BP4_OK;
+    if (!synd || !est || !conv || !iters) return fail(BP4_EINVAL, "decode: NULL buffer");
+    if ((mvc_out == nullptr) != (mcv_out == nullptr)) return fail(BP4_EINVAL, "decode: mvc_out and mcv_out go together");
+    if (!ws) return fail(BP4_EINVAL, "decode: NULL workspace");
+    if (ws_bytes < kSmallWorkspace) return fail(BP4_EWORKSPACE, "decode: workspace %zu < %zu bytes", ws_bytes, kSmallWorkspace);
+    int G = -1;
+    if (tune) {
+        for (int i = 0; i < 7; ++i)
+            if (tune->reserved[i]) return fail(BP4_EINVAL, "decode: reserved tuning fields must be 0");
+        G = tune->group_lanes;
+        if (G != 0 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64 && G != 128 && G != 256)
+            return fail(BP4_EINVAL, "decode: group_lanes %d not in {4, 8, ..., 256}", G);
+        if (G && (g->m + G - 1) / G > 64) return fail(BP4_EINVAL, "decode: group_lanes %d leaves > 64 checks per lane", G);
+    }
+    size_t max_lds = 0;
+    rc = device_max_lds(&max_lds);
+    if (rc) return rc;
+    if (G > 0) {
+        if (decode_lds_layout(g->m, g->n, g->nnz, p->variant, G).bytes > max_lds)
+            return fail(BP4_EINVAL, "decode: group_lanes %d exceeds the LDS of a workgroup", G);
+    } else {
+        G = decode_lds_pick_group(g->m, g->n, g->nnz, p->variant, max_lds);
+    }
+    if (G < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the LDS kernel");
+    const LdsLayout L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G);
+    DecodeArgs a;
+    a.g = g->view(dev_graph);
+    a.prior = prior_llr;
+    a.synd = synd;
+    a.est = est;
+    a.conv = conv;
+    a.iters = iters;
+    a.q_out = q_out;
+    a.mvc_out = mvc_out;
+    a.mcv_out = mcv_out;
+    a.counter = static_cast<unsigned int *>(ws);
+    a.shots = (int32_t)shots;
+    a.variant = p->variant;
+    a.max_iter = p->max_iter;
+    a.stop = p->stop_on_syndrome ? 1 : 0;
+    a.g_from_t1 = p->adagrad_g_from_t1 ? 1 : 0;
+    a.alpha = p->alpha;
+    a.gamma = p->gamma;
+    a.eps = p->eps;
+    a.clamp = p->llr_clamp;
+    a.static_words = L.static_words;
+    a.region_words = L.region_words;
+    a.q_off = L.q_off;
+    a.acc_off = L.acc_off;
+    a.ehat_off = L.ehat_off;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_zero_u32(a.counter, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "decode: zero counter");
+    e = launch_decode_lds(a, L, s);
+    if (e != hipSuccess) return hip_fail(e, "decode: launch");
+    return BP4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes)
+{
+    if (!g || !bytes) return fail(BP4_EINVAL, "workspace_bytes: NULL argument");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (shots < 0) return fail(BP4_EINVAL, "workspace_bytes: negative shots");
+    *bytes = kSmallWorkspace;
+    return BP4_OK;
+}
+
+int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, int64_t shots,
+               const float *prior_llr, const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters,
+               void *ws, size_t ws_bytes, void *stream)
+{
+    return decode_common(g, dev_graph, p, nullptr, shots, prior_llr, synd, est, conv, iters, nullptr,
+                         nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int bp4_decode_ex(const bp4_graph *g, const void *dev_graph, const bp4_params *p, const bp4_tuning *tune,
+                  int64_t shots, const float *prior_llr, const uint8_t *synd, uint8_t *est, uint8_t *conv,
+                  int32_t *iters, float *q_out, float *mvc_out, float *mcv_out, void *ws, size_t ws_bytes,
+                  void *stream)
+{
+    return decode_common(g, dev_graph, p, tune, shots, prior_llr, synd, est, conv, iters, q_out, mvc_out,
+                         mcv_out, ws, ws_bytes, stream);
+}
+
+int bp4_sample(const bp4_graph *g, const void *dev_graph, int64_t shots, int64_t shot0,
+               const uint32_t thr[3], uint64_t seed, uint64_t stream_id, uint8_t *err, uint8_t *synd,
+               void *stream)
+{
+    if (!g || !dev_graph || !thr) return fail(BP4_EINVAL, "sample: NULL argument");
+    if (shots < 0 || shots > 0x7FFFFFFF || shot0 < 0) return fail(BP4_EINVAL, "sample: shots out of range");
+    if ((uint64_t)thr[0] + thr[1] + thr[2] > 0xFFFFFFFFull)
+        return fail(BP4_EINVAL, "sample: thresholds sum to 2^32 or more");
+    if (shots == 0) return BP4_OK;
+    if (!err || !synd) return fail(BP4_EINVAL, "sample: NULL output");
+    hipError_t e = launch_sample(g->view(dev_graph), (int32_t)shots, shot0, thr, seed, stream_id, err, synd,
+                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "sample: launch");
+    return BP4_OK;
+}
+
+int bp4_bookkeep(const bp4_graph *g, const void *dev_graph, int64_t shots, const uint8_t *err,
+                 const uint8_t *est, uint8_t *fail_out, int64_t *counts, void *stream)
+{
+    if (!g || !dev_graph) return fail(BP4_EINVAL, "bookkeep: NULL argument");
+    if (g->nlog <= 0) return fail(BP4_EINVAL, "bookkeep: no logical operators set");
+    if (shots < 0 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "bookkeep: shots out of range");
+    if (shots == 0) return BP4_OK;
+    if (!err || !est || !fail_out || !counts) return fail(BP4_EINVAL, "bookkeep: NULL buffer");
+    hipError_t e = launch_bookkeep(g->view(dev_graph), (int32_t)shots, err, est, fail_out, counts,
+                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "bookkeep: launch");
+    return BP4_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Internal declarations shared by the host ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bp4.h"
+
+namespace bp4 {
+
+// Compiled degree limits of the padded (ELL) edge lists.
+constexpr int kMaxCheckDeg = 4;
+constexpr int kMaxVarDeg = 4;
+constexpr int kMaxVars = 16383;      // 14-bit qubit index in a packed check edge
+constexpr int kMaxEdges = 65535;     // 16-bit message slot; 0xFFFF marks padding
+
+// Packed check-side edge word: bits 0-15 message slot (variable-major position of
+// the edge), bits 16-29 qubit index, bits 30-31 Pauli label (1 X, 2 Z, 3 Y).
+constexpr uint32_t kEdgePad = 0xFFFFFFFFu;
+__host__ __device__ inline uint32_t edge_slot(uint32_t w) { return w & 0xFFFFu; }
+__host__ __device__ inline uint32_t edge_var(uint32_t w) { return (w >> 16) & 0x3FFFu; }
+__host__ __device__ inline uint32_t edge_lab(uint32_t w) { return w >> 30; }
+
+// Packed qubit word: bits 0-15 first message slot, bits 16-18 degree, bits 20+2j
+// the label of the qubit's j-th edge (edges in increasing check order).
+__host__ __device__ inline uint32_t var_base(uint32_t w) { return w & 0xFFFFu; }
+__host__ __device__ inline uint32_t var_deg(uint32_t w) { return (w >> 16) & 7u; }
+__host__ __device__ inline uint32_t var_lab(uint32_t w, int j) { return (w >> (20 + 2 * j)) & 3u; }
+
+// Device view of an uploaded graph image.
+struct GraphView {
+    const uint32_t *cedge;   // [m][kMaxCheckDeg] packed check edges, padded with kEdgePad
+    const uint32_t *vinfo;   // [n] packed qubit words
+    const uint32_t *vcanon;  // [nnz] canonical (row-major) edge id of each message slot
+    const uint32_t *lptr;    // [nlog + 1] offsets into lent
+    const uint32_t *lent;    // logical supports: qubit | (Pauli << 16)
+    int32_t m, n, nnz, nlog;
+};
+
+struct DecodeArgs {
+    GraphView g;
+    const float *prior;      // [n][3]
+    const uint8_t *synd;     // [shots][m]
+    uint8_t *est;            // [shots][n]
+    uint8_t *conv;           // [shots]
+    int32_t *iters;          // [shots]
+    float *q_out;            // optional [shots][n][3]
+    float *mvc_out;          // optional [shots][nnz] canonical order
+    float *mcv_out;          // optional [shots][nnz]
+    unsigned int *counter;   // shot queue head (zeroed before launch)
+    int32_t shots;
+    int32_t variant, max_iter, stop, g_from_t1;
+    float alpha, gamma, eps, clamp;
+    // LDS layout (words): workgroup-static part, then one region per shot group
+    int32_t static_words, region_words, q_off, acc_off, ehat_off;
+};
+
+// LDS layout of the small-code kernel for one code, variant and group size.
+struct LdsLayout {
+    int32_t static_words = 0, region_words = 0, q_off = 0, acc_off = 0, ehat_off = 0;
+    int32_t group_lanes = 0, block = 0;
+    size_t bytes = 0;        // dynamic LDS bytes per workgroup
+};
+
+LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes);
+int decode_lds_pick_group(int m, int n, int nnz, int variant, size_t max_lds);
+hipError_t launch_decode_lds(const DecodeArgs &a, const LdsLayout &L, hipStream_t s);
+
+hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const uint32_t thr[3],
+                         uint64_t seed, uint64_t stream_id, uint8_t *err, uint8_t *synd,
+                         hipStream_t s);
+hipError_t launch_bookkeep(const GraphView &g, int32_t shots, const uint8_t *err,
+                           const uint8_t *est, uint8_t *fail, int64_t *counts, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s);
+
+}  // namespace bp4

@@ -1,0 +1,127 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, builds graphs, and rejects bad arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qecgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bp4.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2407_11523_amd import _lib
+    return _lib.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bp4_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2407_11523_amd import _lib
+    names = declared_functions()
+    assert "bp4_decode" in names and "bp4_sample" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def _graph(code, flags=0):
+    from paper_2407_11523_amd import Graph
+    return Graph(code.hx, code.hz, code.lx, code.lz, upload=False,
+                 allow_anticommuting=bool(flags))
+
+
+@pytest.mark.parametrize("make", [lambda: qecgen.planar(3), lambda: qecgen.toric(8), lambda: qecgen.xzzx(5),
+                                  lambda: qecgen.planar(31)])
+def test_graph_info_and_canonical_edges(lib, make):
+    code = make()
+    g = _graph(code)
+    assert (g.n, g.m, g.nnz) == (code.n, code.m, code.nnz)
+    lab = code.labels()
+    assert g.max_cdeg == (lab > 0).sum(1).max() and g.max_vdeg == (lab > 0).sum(0).max()
+    c, q = g.edges()
+    rows, cols = np.nonzero(lab)
+    assert np.array_equal(c, rows) and np.array_equal(q, cols)
+    assert g.device_bytes() > 0 and g.device_bytes() % 256 == 0
+
+
+def _err(fn):
+    from paper_2407_11523_amd import BP4Error
+    with pytest.raises(BP4Error) as ei:
+        fn()
+    return ei.value.name
+
+
+def test_graph_create_errors(lib):
+    from paper_2407_11523_amd import Graph
+    code = qecgen.planar(3)
+    assert _err(lambda: Graph(code.hx * 2, code.hz, upload=False)) == "EINVAL"
+    z = np.zeros((0, 4), np.uint8)
+    assert _err(lambda: Graph(z, z, upload=False)) == "EINVAL"
+    hx = code.hx.copy()
+    hz = code.hz.copy()
+    hx[0] = 0
+    hz[0] = 0
+    assert _err(lambda: Graph(hx, hz, upload=False)) == "EINVAL"          # empty check
+    hx = np.hstack([code.hx, np.zeros((code.m, 1), np.uint8)])
+    hz = np.hstack([code.hz, np.zeros((code.m, 1), np.uint8)])
+    assert _err(lambda: Graph(hx, hz, upload=False)) == "EINVAL"          # qubit in no check
+    a = np.array([[1, 0], [0, 1]], np.uint8)
+    b = np.array([[0, 0], [1, 0]], np.uint8)
+    assert _err(lambda: Graph(a, b, upload=False)) == "ENONCOMM"
+    Graph(a, b, upload=False, allow_anticommuting=True)                    # allowed with the flag
+    wide = np.ones((1, 5), np.uint8)
+    assert _err(lambda: Graph(wide, np.zeros_like(wide), upload=False)) == "EDEGREE"
+    big = np.ones((1, 16384), np.uint8)
+    assert _err(lambda: Graph(big, np.zeros_like(big), upload=False)) == "EUNSUPPORTED"
+
+
+def test_param_validation_before_launch(lib):
+    from paper_2407_11523_amd import Params
+    g = _graph(qecgen.toric(4))
+    ok = Params(variant="ewainit", alpha=0.5)
+    assert g.workspace_bytes(ok, 100) >= 4
+    for bad in (Params(variant="ewainit", alpha=1.5), Params(variant="momentum", alpha=-0.1),
+                Params(variant="momentum", gamma=1.0), Params(variant="adagrad", alpha=0.0),
+                Params(variant="adagrad", alpha=5.0, eps=0.0), Params(max_iter=0),
+                Params(llr_clamp=0.0), Params(llr_clamp=float("inf"))):
+        assert _err(lambda: g.workspace_bytes(bad, 10)) == "EINVAL"
+
+
+def test_decode_rejects_bad_pointers_without_gpu(lib):
+    from paper_2407_11523_amd import Params, _lib
+    g = _graph(qecgen.toric(4))
+    cp = Params().c()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+    rc = lib.bp4_decode(g.handle, null, ctypes.byref(cp), 10, fake, fake, fake, fake, fake, fake, 256, null)
+    assert rc == -1
+    rc = lib.bp4_decode(g.handle, fake, ctypes.byref(cp), 10, null, fake, fake, fake, fake, fake, 256, null)
+    assert rc == -1
+    rc = lib.bp4_decode(g.handle, fake, ctypes.byref(cp), 10, fake, fake, fake, fake, fake, fake, 8, null)
+    assert rc == -4
+    rc = lib.bp4_decode(g.handle, fake, ctypes.byref(cp), -1, fake, fake, fake, fake, fake, fake, 256, null)
+    assert rc == -1
+    tune = _lib.Tuning(48)
+    rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                           fake, null, null, null, fake, 256, null)
+    assert rc == -1
+    t = (ctypes.c_uint32 * 3)(2 ** 31, 2 ** 31, 1)
+    rc = lib.bp4_sample(g.handle, fake, 10, 0, t, 1, 0, fake, fake, null)
+    assert rc == -1
+    g2 = _graph(qecgen.toric(4))
+    from paper_2407_11523_amd import Graph
+    g3 = Graph(qecgen.toric(4).hx, qecgen.toric(4).hz, upload=False)   # no logicals
+    rc = lib.bp4_bookkeep(g3.handle, fake, 10, fake, fake, fake, fake, null)
+    assert rc == -1
+    assert b"logical" in lib.bp4_last_error()
+    del g2

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: bit-exact for sampling, syndromes and bookkeeping; messages within
+|m32 - m64| <= 1e-5 max(|m64|, 1) at iterations 1..5 with stopping off; at
+least 99.9% identical hard decisions; logical error rates inside each
+other's Wilson 95% interval.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import qecgen
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2407_11523_amd as P  # noqa: E402
+
+REL_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_graph(code):
+    return P.Graph(code.hx, code.hz, code.lx, code.lz)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def clifford_relabel(code, seed):
+    rng = np.random.default_rng(seed)
+    lab = code.labels()
+    new = np.zeros_like(lab)
+    for v in range(code.n):
+        p = rng.permutation([1, 2, 3])
+        mp = np.array([0, p[0], p[1], p[2]], np.uint8)
+        new[:, v] = mp[lab[:, v]]
+    return (new & 1).astype(np.uint8), (new >> 1).astype(np.uint8)
+
+
+# ---------------------------------------------------------------------------
+# Integer work: bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make,shots,shot0", [(lambda: qecgen.planar(3), 1000, 0),
+                                             (lambda: qecgen.toric(8), 4096, 12345),
+                                             (lambda: qecgen.xzzx(5), 777, 3),
+                                             (lambda: qecgen.planar(31), 64, 99)])
+def test_sample_bit_exact(make, shots, shot0):
+    code = make()
+    say("sample", code.name, shots, shot0)
+    g = gpu_graph(code)
+    thr = qecgen.thresholds(0.03, 0.02, 0.05)
+    err, syn = P.sample(g, shots, thr, seed=2024, stream_id=7, shot0=shot0)
+    torch.cuda.synchronize()
+    e0, s0 = O.sample(code.hx, code.hz, shots, thr, seed=2024, stream=7, shot0=shot0)
+    assert np.array_equal(np_(err), e0)
+    assert np.array_equal(np_(syn), s0)
+
+
+def test_sample_zero_shots():
+    code = qecgen.toric(4)
+    g = gpu_graph(code)
+    err, syn = P.sample(g, 0, qecgen.thresholds(0.01, 0.01, 0.01), seed=1)
+    torch.cuda.synchronize()
+    assert err.shape == (0, code.n) and syn.shape == (0, code.m)
+
+
+@pytest.mark.parametrize("make", [lambda: qecgen.planar(5), lambda: qecgen.toric(6), lambda: qecgen.xzzx(9),
+                                  lambda: qecgen.planar(31)])
+def test_bookkeep_bit_exact(make):
+    code = make()
+    say("bookkeep", code.name)
+    g = gpu_graph(code)
+    rng = np.random.default_rng(4)
+    shots = 3000 if code.n < 1000 else 200
+    err = rng.integers(0, 4, size=(shots, code.n)).astype(np.uint8) * (rng.random((shots, code.n)) < 0.05)
+    est = err.copy()
+    # a third unchanged, a third multiplied by a stabilizer or logical, a third random
+    lab = code.labels()
+    logical = (code.lx | (code.lz << 1)).astype(np.uint8)
+    for i in range(shots):
+        k = i % 3
+        if k == 1:
+            est[i] ^= lab[rng.integers(code.m)]
+            if rng.random() < 0.5:
+                est[i] ^= logical[rng.integers(len(logical))]
+        elif k == 2:
+            est[i] = rng.integers(0, 4, size=code.n) * (rng.random(code.n) < 0.03)
+    fail_o, cnt_o = O.bookkeep(code.hx, code.hz, code.lx, code.lz, err, est)
+    fail_g, cnt_g = P.bookkeep(g, torch.as_tensor(err, device="cuda"), torch.as_tensor(est, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(fail_g), fail_o)
+    assert np_(cnt_g).tolist() == cnt_o.tolist()
+    assert cnt_o[2] > 0 and cnt_o[1] > 0 and cnt_o[0] > 0
+
+
+# ---------------------------------------------------------------------------
+# Messages at iterations 1..5 (stopping off) against FP64
+# ---------------------------------------------------------------------------
+
+VARIANTS = [("bp", 1.0), ("ewainit", 0.5), ("momentum", 0.6), ("adagrad", 5.0)]
+
+
+def _msg_parity(code_hx, code_hz, lx, lz, probs, shots, seed, variant, alpha, T, group_lanes=0,
+                gamma=0.0):
+    code_like = qecgen.StabilizerCode("x", code_hx, code_hz, lx, lz)
+    g = P.Graph(code_hx, code_hz, lx, lz)
+    thr = qecgen.thresholds(*probs[0])
+    _, syn = O.sample(code_hx, code_hz, shots, thr, seed=seed)
+    pi64 = O.prior_llr(probs)
+    pi32 = P.prior_llr(probs)
+    prm_o = O.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=T, stop_on_syndrome=False)
+    prm_g = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=T, stop_on_syndrome=False)
+    ro = O.decode(code_hx, code_hz, prm_o, pi64, syn, want_q=True, want_msgs=True)
+    rg = P.decode(g, prm_g, pi32, torch.as_tensor(syn, device="cuda"), trace=True, group_lanes=group_lanes)
+    torch.cuda.synchronize()
+    out = {}
+    for k64, k32 in (("mvc", "mvc"), ("mcv", "mcv"), ("q", "q")):
+        a = ro[k64]
+        b = np_(rg[k32]).astype(np.float64)
+        err = np.abs(b - a) / np.maximum(np.abs(a), 1.0)
+        out[k64] = float(err.max())
+    out["iters_equal"] = bool(np.array_equal(np_(rg["iters"]), ro["iters"]))
+    out["est_agree"] = float((np_(rg["est"]) == ro["est"]).mean())
+    del code_like
+    return out
+
+
+@pytest.mark.parametrize("variant,alpha", VARIANTS)
+@pytest.mark.parametrize("T", [1, 2, 3, 5])
+def test_messages_planar_d3(variant, alpha, T):
+    code = qecgen.planar(3)
+    probs = qecgen.depolarizing_probs(code.n, 0.05)
+    r = _msg_parity(code.hx, code.hz, code.lx, code.lz, probs, 2000, 11, variant, alpha, T)
+    say("msg planar3", variant, T, r)
+    assert r["mvc"] <= REL_TOL and r["mcv"] <= REL_TOL and r["q"] <= REL_TOL
+    assert r["iters_equal"]
+
+
+@pytest.mark.parametrize("variant,alpha", VARIANTS)
+def test_messages_toric_l8_and_relabelled(variant, alpha):
+    code = qecgen.toric(8)
+    probs = qecgen.depolarizing_probs(code.n, 0.08)
+    r = _msg_parity(code.hx, code.hz, code.lx, code.lz, probs, 1024, 12, variant, alpha, 5)
+    say("msg toric8", variant, r)
+    assert r["mvc"] <= REL_TOL and r["mcv"] <= REL_TOL and r["q"] <= REL_TOL
+    # Y labels and non-uniform priors: random local Cliffords on the XZZX code
+    x = qecgen.xzzx(5)
+    hx, hz = clifford_relabel(x, 3)
+    rng = np.random.default_rng(5)
+    probs = rng.uniform(0.01, 0.04, size=(x.n, 3))
+    r = _msg_parity(hx, hz, x.lx, x.lz, probs, 1024, 13, variant, alpha, 5)
+    say("msg xzzx5-clifford", variant, r)
+    assert r["mvc"] <= REL_TOL and r["mcv"] <= REL_TOL and r["q"] <= REL_TOL
+
+
+@pytest.mark.parametrize("G", [4, 8, 16, 32, 64, 128, 256])
+def test_every_group_size(G):
+    # one code per lane-group size, including ragged tails (m, n not multiples of G)
+    code = qecgen.planar(7) if G >= 16 else qecgen.planar(3)
+    probs = qecgen.depolarizing_probs(code.n, 0.06)
+    r = _msg_parity(code.hx, code.hz, code.lx, code.lz, probs, 777, 14, "ewainit", 0.7, 4, group_lanes=G)
+    say("group", G, code.name, r)
+    assert r["mvc"] <= REL_TOL and r["mcv"] <= REL_TOL and r["q"] <= REL_TOL
+
+
+# ---------------------------------------------------------------------------
+# Decisions and logical error rates with early stopping
+# ---------------------------------------------------------------------------
+
+def _ler_parity(code, p, shots, variant, alpha, max_iter, seed, group_lanes=0, oracle_shots=None):
+    g = gpu_graph(code)
+    thr = qecgen.thresholds(p / 3, p / 3, p / 3)
+    err, syn = P.sample(g, shots, thr, seed=seed)
+    prm = P.Params(variant=variant, alpha=alpha, max_iter=max_iter)
+    rg = P.decode(g, prm, P.prior_llr(qecgen.depolarizing_probs(code.n, p)), syn, group_lanes=group_lanes)
+    fail_g, cnt_g = P.bookkeep(g, err, rg["est"])
+    torch.cuda.synchronize()
+    k = oracle_shots or shots
+    e_o, s_o = O.sample(code.hx, code.hz, k, thr, seed=seed)
+    assert np.array_equal(np_(syn[:k]), s_o)
+    ro = O.decode(code.hx, code.hz, O.Params(variant=variant, alpha=alpha, max_iter=max_iter),
+                  O.prior_llr(qecgen.depolarizing_probs(code.n, p)), s_o)
+    f_o, cnt_o = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
+    agree = float((np_(rg["est"][:k]) == ro["est"]).mean())
+    shot_agree = float(np.all(np_(rg["est"][:k]) == ro["est"], axis=1).mean())
+    ler_g = int(cnt_g[1] + cnt_g[2]) / shots
+    ler_o = int(cnt_o[1] + cnt_o[2]) / k
+    ci_g = O.wilson_ci(int(cnt_g[1] + cnt_g[2]), shots)
+    ci_o = O.wilson_ci(int(cnt_o[1] + cnt_o[2]), k)
+    return dict(agree=agree, shot_agree=shot_agree, ler_g=ler_g, ler_o=ler_o, ci_g=ci_g, ci_o=ci_o,
+                iters_g=float(np_(rg["iters"]).mean()), iters_o=float(ro["iters"].mean()),
+                conv_g=float(np_(rg["conv"]).mean()), conv_o=float(ro["conv"].mean()))
+
+
+@pytest.mark.parametrize("variant,alpha", [("bp", 1.0), ("ewainit", 0.5)])
+def test_config1_planar_d3(variant, alpha):
+    # planar d=3, depolarizing p=0.05, 10^4 shots, iter_max 50
+    r = _ler_parity(qecgen.planar(3), 0.05, 10000, variant, alpha, 50, qecgen.config_seed(1, 0, 0))
+    say("config1", variant, r)
+    assert r["agree"] >= 0.999
+    assert r["ci_o"][0] <= r["ler_g"] <= r["ci_o"][1]
+    assert r["ci_g"][0] <= r["ler_o"] <= r["ci_g"][1]
+
+
+@pytest.mark.parametrize("variant,alpha", [("momentum", 0.6), ("adagrad", 5.0), ("ewainit", 0.5)])
+def test_config2_toric_l8_sample(variant, alpha):
+    # toric L=8 at p=0.08, iter_max 100: GPU on 2^16 shots, oracle on the first 2^13
+    r = _ler_parity(qecgen.toric(8), 0.08, 1 << 16, variant, alpha, 100, qecgen.config_seed(2, 0, 3),
+                    oracle_shots=1 << 13)
+    say("config2", variant, r)
+    assert r["agree"] >= 0.999
+    assert r["ci_o"][0] <= r["ler_g"] <= r["ci_o"][1]
+
+
+def test_edge_cases():
+    code = qecgen.toric(6)
+    g = gpu_graph(code)
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, 0.05))
+    # zero syndrome converges at t = 1 to the identity
+    syn = torch.zeros((300, code.m), dtype=torch.uint8, device="cuda")
+    r = P.decode(g, P.Params(variant="ewainit", alpha=0.5, max_iter=10), pr, syn)
+    torch.cuda.synchronize()
+    assert np_(r["conv"]).all() and (np_(r["iters"]) == 1).all() and not np_(r["est"]).any()
+    # zero shots
+    r = P.decode(g, P.Params(), pr, torch.zeros((0, code.m), dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert r["est"].shape == (0, code.n)
+    # max_iter = 1 and a single shot
+    thr = qecgen.thresholds(0.03, 0.03, 0.03)
+    e, s = P.sample(g, 1, thr, seed=3)
+    r = P.decode(g, P.Params(max_iter=1), pr, s)
+    torch.cuda.synchronize()
+    _, so = O.sample(code.hx, code.hz, 1, thr, seed=3)
+    ro = O.decode(code.hx, code.hz, O.Params(max_iter=1), O.prior_llr(qecgen.depolarizing_probs(code.n, 0.05)), so)
+    assert np_(r["iters"]).tolist() == [1] and np.array_equal(np_(r["est"]), ro["est"])
+    # determinism: two runs are bit-identical
+    e, s = P.sample(g, 5000, thr, seed=4)
+    a = P.decode(g, P.Params(variant="ewainit", alpha=0.5), pr, s)
+    b = P.decode(g, P.Params(variant="ewainit", alpha=0.5), pr, s)
+    torch.cuda.synchronize()
+    for k in ("est", "conv", "iters"):
+        assert torch.equal(a[k], b[k])
