@@ -186,6 +186,9 @@ static double clampd(double x, double c)
 
 enum { OR_BP = 0, OR_MOMENTUM = 1, OR_ADAGRAD = 2, OR_EWAINIT = 3 };
 
+/* AdaGrad gradients at or below this fraction of |D| + sum |m| count as 0. */
+#define ADAGRAD_DEADBAND 1.52587890625e-05   /* 2^-16 */
+
 typedef struct {
     int32_t variant;            /* OR_BP, OR_MOMENTUM, OR_ADAGRAD, OR_EWAINIT */
     int32_t max_iter;           /* iter_max >= 1 */
@@ -222,7 +225,7 @@ static int hard_decision(const double q[3])
 static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
                        const uint8_t *s, uint8_t *est, uint8_t *conv_out, int32_t *iters_out,
                        double *mvc, double *mcv, double *q, double *qprev, double *pit,
-                       double *acc, double *dev, double *msum, int *ehat,
+                       double *acc, double *dev, double *msum, double *mabs, int *ehat,
                        double *q_trace, double *m_trace)
 {
     const int n = g->n, m = g->m, nnz = g->nnz;
@@ -266,12 +269,16 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
          * with <W, H_cv> = 1 of m_{c->v} (the sum in eqs. p_update / mombp3). */
         for (int v = 0; v < n; ++v) {
             for (int w = 0; w < 3; ++w) {
-                double sum = 0.0;
+                double sum = 0.0, asum = 0.0;
                 for (int k = g->vptr[v]; k < g->vptr[v + 1]; ++k) {
                     int e = g->vedge[k];
-                    if (anticommute(PAULI_OF_INDEX[w], g->elab[e])) sum += mcv[e];
+                    if (anticommute(PAULI_OF_INDEX[w], g->elab[e])) {
+                        sum += mcv[e];
+                        asum += fabs(mcv[e]);
+                    }
                 }
                 msum[3 * v + w] = sum;
+                mabs[3 * v + w] = asum;
             }
         }
 
@@ -295,8 +302,14 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
                  * g' = Q^{(t-1)} - Pi - sum m of eq. boost is then D^{(t-1)} - sum m,
                  * which is exactly 0 when the incoming sums repeat; the step
                  * g'/(sqrt(G)+eps) would otherwise turn rounding residue into a full
-                 * step of size alpha). */
+                 * step of size alpha).  READING: a gradient below the rounding
+                 * resolution of its operands, |g'| <= 2^-16 (|D| + sum |m|), is 0:
+                 * while G is still 0 the first adaptive step is alpha * sign(g'),
+                 * so a difference of message sums that cancel exactly (opposite
+                 * syndromes on a symmetric neighbourhood) must not pick a sign from
+                 * rounding. */
                 double grad = dev[i] - msum[i];
+                if (fabs(grad) <= ADAGRAD_DEADBAND * (fabs(dev[i]) + mabs[i])) grad = 0.0;
                 if (t == 1) {
                     if (p->adagrad_g_from_t1) acc[i] += grad * grad;
                     dev[i] = msum[i];
@@ -400,8 +413,9 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
         double *acc = malloc(sizeof(double) * 3 * n);
         double *dev = malloc(sizeof(double) * 3 * n);
         double *msum = malloc(sizeof(double) * 3 * n);
+        double *mabs = malloc(sizeof(double) * 3 * n);
         int *ehat = malloc(sizeof(int) * n);
-        if (!mvc || !mcv || !q || !qprev || !pit || !acc || !dev || !msum || !ehat) {
+        if (!mvc || !mcv || !q || !qprev || !pit || !acc || !dev || !msum || !mabs || !ehat) {
 #pragma omp atomic write
             rc = -1;
         } else {
@@ -410,13 +424,13 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
                 double *qt = o->q_trace ? o->q_trace + (size_t)i * p->max_iter * 3 * n : NULL;
                 double *mt = o->m_trace ? o->m_trace + (size_t)i * p->max_iter * 3 * n : NULL;
                 decode_one(&g, p, pi0, synd + (size_t)i * m, est + (size_t)i * n, conv + i,
-                           iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, ehat, qt, mt);
+                           iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, mabs, ehat, qt, mt);
                 if (o->q_out) memcpy(o->q_out + (size_t)i * 3 * n, q, sizeof(double) * 3 * n);
                 if (o->mvc_out) memcpy(o->mvc_out + (size_t)i * nnz, mvc, sizeof(double) * nnz);
                 if (o->mcv_out) memcpy(o->mcv_out + (size_t)i * nnz, mcv, sizeof(double) * nnz);
             }
         }
-        free(mvc); free(mcv); free(q); free(qprev); free(pit); free(acc); free(dev); free(msum); free(ehat);
+        free(mvc); free(mcv); free(q); free(qprev); free(pit); free(acc); free(dev); free(msum); free(mabs); free(ehat);
     }
     graph_free(&g);
     return rc;

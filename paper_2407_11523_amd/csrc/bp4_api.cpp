@@ -188,7 +188,11 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
     g->vinfo.assign(n, 0);
     for (int v = 0; v < n; ++v) {
         uint32_t w = (uint32_t)vptr[v] | ((uint32_t)vdeg[v] << 16);
-        for (int j = 0; j < vdeg[v]; ++j) w |= lab[g->vcanon[vptr[v] + j]] << (20 + 2 * j);
+        for (int j = 0; j < vdeg[v]; ++j) {
+            const uint32_t l = lab[g->vcanon[vptr[v] + j]];
+            w |= l << (20 + 2 * j);
+            w |= 1u << (27 + l);
+        }
         g->vinfo[v] = w;
     }
     g->lptr.assign(1, 0);

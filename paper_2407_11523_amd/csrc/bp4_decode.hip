@@ -20,6 +20,8 @@
 // The qubit phase uses lambda_H(Q - [<W,H>=1] m_{c->v}) = lambda_H(Q) - m_{c->v}
 // (both anticommuting LLRs drop by m, which factors out of the denominator),
 // so lambda is evaluated once per (qubit, label) instead of once per edge.
+#include <cmath>
+
 #include "bp4_internal.h"
 
 namespace bp4 {
@@ -36,25 +38,73 @@ __device__ __forceinline__ void wave_sync()
 
 __device__ __forceinline__ float clampf(float x, float c) { return fminf(fmaxf(x, -c), c); }
 
-// phi(x) = ln((e^x + 1) / (e^x - 1)) = -ln tanh(x / 2), x >= 0, phi(0) = inf,
-// phi(inf) = 0.  2 atanh(prod tanh(m_k / 2)) = (prod sgn m_k) phi(sum phi(|m_k|)).
-__device__ __forceinline__ float phi(float x) { return log1pf(2.0f / expm1f(x)); }
+constexpr float kLog2e = 1.44269504088896341f;
+constexpr float kLn2 = 0.693147180559945309f;
+constexpr float kLn4 = 1.38629436111989061f;
 
-// lambda_H(Q) = ln(1 + e^{-Q_H}) - ln(e^{-Q_a} + e^{-Q_b}), {a, b} = {X,Y,Z} \ {H}.
-// The two maxima are inputs, so their difference rounds once.
-__device__ __forceinline__ float lambda3(float qh, float qa, float qb)
+// Hardware base-2 exponential and logarithm (v_exp_f32, v_log_f32).
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+// phi(x) = -ln tanh(x/2) = 2 atanh(e^{-x}) for x >= 0, phi(0) = inf, phi(inf) = 0;
+// 2 atanh(prod tanh(m_k/2)) = (prod sgn m_k) phi(sum phi(|m_k|)).
+//   x >= ln 4: z = e^{-x} <= 1/4 and phi = 2 z P(z^2), P(w) = atanh(sqrt w)/sqrt w;
+//   x <  ln 4: phi = ln(2/x) + u G(u), u = x^2/4, u G(u) = -ln(tanh(sqrt u)/sqrt u).
+// P and G are least-squares fits on those ranges (relative error < 1e-7 in FP32);
+// both forms keep full relative accuracy (no 1 - z or log(1 + tiny) cancellation).
+__device__ __forceinline__ float phi(float x)
 {
-    const float m1 = fmaxf(-qh, 0.0f);
-    const float m2 = fmaxf(-qa, -qb);
-    return (m1 - m2) + log1pf(expf(-fabsf(qh))) - log1pf(expf(-fabsf(qa - qb)));
+    if (x >= kLn4) {
+        const float z = hw_exp2(-x * kLog2e);
+        const float w = z * z;
+        float p = fmaf(w, 0.12663664294804267f, 0.1419839934660223f);
+        p = fmaf(w, p, 0.2000197421889f);
+        p = fmaf(w, p, 0.3333331781245287f);
+        p = fmaf(w, p, 1.00000000019442f);
+        return (2.0f * z) * p;
+    }
+    const float u = 0.25f * x * x;
+    float g = fmaf(u, 0.0014921690150859843f, -0.006451527278442298f);
+    g = fmaf(u, g, 0.02182510967622784f);
+    g = fmaf(u, g, -0.07777514939719771f);
+    g = fmaf(u, g, 0.33333330803159383f);
+    return fmaf(-hw_log2(0.5f * x), kLn2, u * g);
 }
 
-// lambda for label code lab (1 X, 2 Z, 3 Y) from the (X, Y, Z) posterior q.
+// ln(1 + e^{-|y|}): the correction term of a two-term log-sum-exp.
+__device__ __forceinline__ float softplus_neg_abs(float y)
+{
+    return hw_log2(1.0f + hw_exp2(-fabsf(y) * kLog2e)) * kLn2;
+}
+
+// lambda_H(Q) = ln(1 + e^{-Q_H}) - ln(e^{-Q_a} + e^{-Q_b}), {a, b} = {X,Y,Z} \ {H}
+//             = [max(-Q_H, 0) - max(-Q_a, -Q_b)] + sp(Q_H) - sp(Q_a - Q_b),
+// with sp(y) = ln(1 + e^{-|y|}) given precomputed (spH, spAB).
+__device__ __forceinline__ float lambda_sp(float qh, float qa, float qb, float spH, float spAB)
+{
+    return (fmaxf(-qh, 0.0f) - fmaxf(-qa, -qb)) + (spH - spAB);
+}
+
+// lambda for the (X, Y, Z) posterior q with a generic label (setup code only).
 __device__ __forceinline__ float lambda_lab(uint32_t lab, const float q[3])
 {
-    return lab == 1u ? lambda3(q[0], q[1], q[2]) : (lab == 3u ? lambda3(q[1], q[0], q[2])
-                                                             : lambda3(q[2], q[0], q[1]));
+    const int h = lab == 1u ? 0 : (lab == 3u ? 1 : 2);
+    const float qa = q[h == 0 ? 1 : 0], qb = q[h == 2 ? 1 : 2];
+    return lambda_sp(q[h], qa, qb, softplus_neg_abs(q[h]), softplus_neg_abs(qa - qb));
 }
+
+// Sum of three non-negative values in an order fixed by their values:
+// (min + median) + max, so the result depends only on the multiset.
+__device__ __forceinline__ float sum3_canonical(float a, float b, float c)
+{
+    const float lo = fminf(fminf(a, b), c);
+    const float hi = fmaxf(fmaxf(a, b), c);
+    const float mid = __builtin_amdgcn_fmed3f(a, b, c);
+    return (lo + mid) + hi;
+}
+
+// AdaGrad gradients at or below this fraction of |D| + sum |m| count as 0.
+constexpr float kAdaGradDeadband = 1.52587890625e-05f;   // 2^-16
 
 // 1 iff single-qubit Paulis a, b (codes) anticommute.
 __device__ __forceinline__ uint32_t anticomm(uint32_t a, uint32_t b)
@@ -164,9 +214,10 @@ decode_lds_kernel(DecodeArgs a)
                     neg ^= sgn[j];
                     f[j] = phi(fabsf(mv));
                 }
-                // leave-one-out sums of phi, formed directly (no subtraction)
-                const float s01 = f[0] + f[1], s23 = f[2] + f[3];
-                const float loo[4] = {f[1] + s23, f[0] + s23, s01 + f[3], s01 + f[2]};
+                // leave-one-out sums of phi, formed directly (no subtraction) and in
+                // value order, so equal multisets of inputs give bitwise equal outputs
+                const float loo[4] = {sum3_canonical(f[1], f[2], f[3]), sum3_canonical(f[0], f[2], f[3]),
+                                      sum3_canonical(f[0], f[1], f[3]), sum3_canonical(f[0], f[1], f[2])};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (w[j] == kEdgePad) continue;
@@ -182,19 +233,21 @@ decode_lds_kernel(DecodeArgs a)
                 const uint32_t info = s_vi[v];
                 const uint32_t base = var_base(info), deg = var_deg(info);
                 float mc[4];
-                float M[3] = {0.0f, 0.0f, 0.0f};
+                // per-label sums of m_{c->v} (index = label code; 1 X, 2 Z, 3 Y)
+                float S[4] = {0.0f, 0.0f, 0.0f, 0.0f}, A[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     mc[j] = 0.0f;
                     if ((uint32_t)j < deg) {
                         const uint32_t lab = var_lab(info, j);
                         mc[j] = msg[base + j];
-                        // M_{v,W}: sum of m_{c->v} over edges whose label anticommutes with W
-                        if (lab != 1u) M[0] += mc[j];
-                        if (lab != 3u) M[1] += mc[j];
-                        if (lab != 2u) M[2] += mc[j];
+                        S[lab] += mc[j];
+                        A[lab] += fabsf(mc[j]);
                     }
                 }
+                // M_{v,W}: sum of m_{c->v} over edges whose label anticommutes with W,
+                // i.e. the two other labels (eqs. p_update, mombp3, boost)
+                const float M[3] = {S[3] + S[2], S[1] + S[2], S[1] + S[3]};
                 const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
                 float qn[3];
                 if (variant == BP4_BP) {                 // eq. p_update
@@ -216,10 +269,13 @@ decode_lds_kernel(DecodeArgs a)
                     }
                 } else {                                 // eq. boost, adaptive from t = 2
                     // qs holds D = Q - Pi^{(0)}; the gradient Q^{(t-1)} - Pi - M is D - M.
+                    const float Mabs[3] = {A[3] + A[2], A[1] + A[2], A[1] + A[3]};
 #pragma unroll
                     for (int x = 0; x < 3; ++x) {
                         const float dp = qs[3 * v + x];
-                        const float grad = dp - M[x];
+                        float grad = dp - M[x];
+                        // a gradient below the rounding resolution of its operands is 0
+                        if (fabsf(grad) <= kAdaGradDeadband * (fabsf(dp) + Mabs[x])) grad = 0.0f;
                         float d;
                         if (t == 1) {
                             if (a.g_from_t1) acc[3 * v + x] = grad * grad;
@@ -249,13 +305,13 @@ decode_lds_kernel(DecodeArgs a)
                     for (int x = 0; x < 3; ++x) qs[3 * v + x] = qn[x];
                 // Vertical update (eqs. v_update / mombp5): m_{v->c} = lambda_H(Q) - m_{c->v}.
                 float lam[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // by label code
-                const uint32_t labs = info >> 20;
-                const bool hasX = (labs & 0x3u) == 1u || ((labs >> 2) & 3u) == 1u || ((labs >> 4) & 3u) == 1u || ((labs >> 6) & 3u) == 1u;
-                const bool hasZ = (labs & 0x3u) == 2u || ((labs >> 2) & 3u) == 2u || ((labs >> 4) & 3u) == 2u || ((labs >> 6) & 3u) == 2u;
-                const bool hasY = (labs & 0x3u) == 3u || ((labs >> 2) & 3u) == 3u || ((labs >> 4) & 3u) == 3u || ((labs >> 6) & 3u) == 3u;
-                if (hasX) lam[1] = lambda3(qn[0], qn[1], qn[2]);
-                if (hasZ) lam[2] = lambda3(qn[2], qn[0], qn[1]);
-                if (hasY) lam[3] = lambda3(qn[1], qn[0], qn[2]);
+                const uint32_t present = var_labels_present(info);
+                if (present & 2u)   // X: pair (Y, Z)
+                    lam[1] = lambda_sp(qn[0], qn[1], qn[2], softplus_neg_abs(qn[0]), softplus_neg_abs(qn[1] - qn[2]));
+                if (present & 4u)   // Z: pair (X, Y)
+                    lam[2] = lambda_sp(qn[2], qn[0], qn[1], softplus_neg_abs(qn[2]), softplus_neg_abs(qn[0] - qn[1]));
+                if (present & 8u)   // Y: pair (X, Z)
+                    lam[3] = lambda_sp(qn[1], qn[0], qn[2], softplus_neg_abs(qn[1]), softplus_neg_abs(qn[0] - qn[2]));
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if ((uint32_t)j >= deg) continue;
@@ -360,21 +416,30 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G)
     return L;
 }
 
-// Lanes per shot for a code: best lane use (padding of m and n up to multiples of G)
-// with at most 64 checks per lane and at most `max_lds` bytes of LDS per workgroup.
+// Lanes per shot for a code when no tuned choice is given.  Score = lane use
+// (padding of m and n up to multiples of G) times an occupancy factor: the
+// wavefronts per CU that the LDS allows (up to 16, beyond which latency is
+// hidden) over 16.  At most 64 checks per lane; at most `max_lds` bytes of LDS
+// per workgroup.
 int decode_lds_pick_group(int m, int n, int nnz, int variant, size_t max_lds)
 {
     const int cand[7] = {256, 128, 64, 32, 16, 8, 4};
+    const double cu_lds = 160.0 * 1024.0;
     int best = -1;
-    double best_util = -1.0;
+    double best_score = -1.0;
     for (int i = 0; i < 7; ++i) {
         const int G = cand[i];
         if ((m + G - 1) / G > 64) continue;
-        if (decode_lds_layout(m, n, nnz, variant, G).bytes > max_lds) continue;
+        const LdsLayout L = decode_lds_layout(m, n, nnz, variant, G);
+        if (L.bytes > max_lds) continue;
         const int kc = (m + G - 1) / G, kv = (n + G - 1) / G;
         const double util = 0.5 * ((double)m / (G * kc) + (double)n / (G * kv));
-        if (util > best_util + 0.02) {
-            best_util = util;
+        const double blocks = std::floor(cu_lds / (double)L.bytes);
+        double waves = blocks * (L.block / 64);
+        if (waves > 16.0) waves = 16.0;
+        const double score = util * waves / 16.0;
+        if (score > best_score * 1.02) {
+            best_score = score;
             best = G;
         }
     }

@@ -22,10 +22,13 @@ __host__ __device__ inline uint32_t edge_var(uint32_t w) { return (w >> 16) & 0x
 __host__ __device__ inline uint32_t edge_lab(uint32_t w) { return w >> 30; }
 
 // Packed qubit word: bits 0-15 first message slot, bits 16-18 degree, bits 20+2j
-// the label of the qubit's j-th edge (edges in increasing check order).
+// the label of the qubit's j-th edge (edges in increasing check order), bits 28-30
+// the labels present (bit 28 + label - 1).
 __host__ __device__ inline uint32_t var_base(uint32_t w) { return w & 0xFFFFu; }
 __host__ __device__ inline uint32_t var_deg(uint32_t w) { return (w >> 16) & 7u; }
 __host__ __device__ inline uint32_t var_lab(uint32_t w, int j) { return (w >> (20 + 2 * j)) & 3u; }
+// bit (label) set for each label present: 2 X, 4 Z, 8 Y
+__host__ __device__ inline uint32_t var_labels_present(uint32_t w) { return (w >> 27) & 0xEu; }
 
 // Device view of an uploaded graph image.
 struct GraphView {

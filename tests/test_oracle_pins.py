@@ -372,9 +372,12 @@ def test_adagrad_step_invariants():
     steps = np.abs(np.diff(Q, axis=1))
     assert np.all(steps <= a * (1 + 1e-12))
     gp = M[:, 0] - M[:, 1]          # Q^{(1)} - Pi - M^{(2)} with Q^{(1)} = Pi + M^{(1)}
-    assert np.allclose(np.abs(Q[:, 1] - Q[:, 0]), a * np.abs(gp) / (np.abs(gp) + 1e-8), rtol=1e-9, atol=1e-9)
-    # a gradient that vanishes exactly gives no step
-    assert np.all(np.abs(Q[:, 1] - Q[:, 0])[gp == 0] == 0)
+    big = np.abs(gp) > 1e-3         # far above the sub-resolution deadband
+    assert big.mean() > 0.3
+    step = np.abs(Q[:, 1] - Q[:, 0])
+    assert np.allclose(step[big], (a * np.abs(gp) / (np.abs(gp) + 1e-8))[big], rtol=1e-9, atol=1e-9)
+    # a gradient that vanishes (exactly, or below the rounding resolution) gives no step
+    assert np.all(step[np.abs(gp) < 1e-12] == 0)
     # accumulating G from t = 1 gives a smaller first adaptive step
     r2 = O.decode(code.hx, code.hz, O.Params(variant="adagrad", alpha=a, max_iter=T, stop_on_syndrome=False,
                                              adagrad_g_from_t1=True), pi, syn, want_trace=True)
