@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput of the mixed-code persistent GF(4) BP decode on one MI355X.
+
+Workload (one step): the mixed batch of planar d in {5,7,9,11,13}, toric L in
+{6,10,14} and XZZX L in {5,9,13} surface codes under depolarizing noise
+p = 0.08, 2^18 shots per code scaled 1:2:4 from the smallest to the largest
+size of each family (26 x 2^18 = 6,815,744 shots), EWAInit-BP with iter_max
+100.  A step samples every code's errors and syndromes on the GPU, decodes all
+codes in one persistent launch, and classifies every shot (success, detected,
+undetected).  Inputs are synthetic and seeded; nothing is read from disk.
+
+Prints one JSON line.  Besides the contract fields it reports the per-code
+plain decoder on the same syndromes (the reference point of the metric), the
+decode kernel's fraction of its VALU roofline, and the FP64 CPU oracle timed on
+a bounded sample of the same shots.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+P_ERR = 0.08
+ALPHA = 0.5          # EWAInit discount factor (the paper's trapping-set value; see the design notes)
+MAX_ITER = 100
+BASE_SHOTS = 1 << 18
+# (family, size, shot multiplier): smallest size(s) 1, middle 2, largest 4
+CODES = [("planar", 5, 1), ("planar", 7, 1), ("planar", 9, 2), ("planar", 11, 4), ("planar", 13, 4),
+         ("toric", 6, 1), ("toric", 10, 2), ("toric", 14, 4),
+         ("xzzx", 5, 1), ("xzzx", 9, 2), ("xzzx", 13, 4)]
+
+# Roofline of the LDS-resident decode: VALU issue.  Algorithmic work per edge
+# update (one message each way on one Tanner edge in one iteration): 4
+# transcendentals (two phi on the check side, lambda amortised over the qubit's
+# edges on the other) and 16 FP32 operations; a transcendental occupies 4 issue
+# slots, so 32 FP32 issue slots per edge update.  Peak issue: 256 CUs x 4 SIMDs
+# x 16 lanes x 2.4 GHz = 39.3e12 slots/s.
+SLOTS_PER_EDGE_UPDATE = 32
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=float, default=1.0, help="shot-count scale (1.0 = the named workload)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-code plain decoder")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import qecgen
+    import paper_2407_11523_amd as P
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    thr = qecgen.thresholds(P_ERR / 3, P_ERR / 3, P_ERR / 3)
+    prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=MAX_ITER)
+    items = []
+    for i, (fam, size, mult) in enumerate(CODES):
+        code = qecgen.make(fam, size)
+        shots = max(1, int(round(BASE_SHOTS * mult * args.scale)))
+        g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
+        pr = P.prior_llr(qecgen.depolarizing_probs(code.n, P_ERR), device=dev)
+        err = torch.empty((shots, code.n), dtype=torch.uint8, device=dev)
+        syn = torch.empty((shots, code.m), dtype=torch.uint8, device=dev)
+        counts = torch.zeros(3, dtype=torch.int64, device=dev)
+        items.append(dict(code=code, g=g, prior=pr, err=err, syn=syn, counts=counts, shots=shots,
+                          seed=qecgen.config_seed(3, i, 0)))
+    batch = P.MixedBatch([(it["g"], prm, it["prior"], it["syn"], 0) for it in items])
+    total_shots = sum(it["shots"] for it in items)
+    log(f"workload: {len(items)} codes, {total_shots} shots per step")
+
+    dec_ev = []
+
+    def step(record):
+        for it in items:
+            P.sample(it["g"], it["shots"], thr, it["seed"], err=it["err"], synd=it["syn"])
+        if record:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+        batch.run()
+        if record:
+            b.record()
+            dec_ev.append((a, b))
+        for it, o in zip(items, batch.outs):
+            it["counts"].zero_()
+            P.bookkeep(it["g"], it["err"], o["est"], counts=it["counts"])
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(args.steps):
+        step(True)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1) / args.steps
+    value = total_shots / (ms / 1e3)
+    dec_ms = sum(a.elapsed_time(b) for a, b in dec_ev) / len(dec_ev)
+
+    # work of the last step (every step decodes the same seeded syndromes)
+    edge_updates = 0
+    iters_total = 0
+    ler = {}
+    fails = {}
+    for it, o in zip(items, batch.outs):
+        s = int(o["iters"].to(torch.int64).sum())
+        iters_total += s
+        edge_updates += s * it["code"].nnz
+        c = it["counts"].cpu().numpy()
+        fails[it["code"].name] = (int(c[1] + c[2]), it["shots"])
+        ler[it["code"].name] = round(float(c[1] + c[2]) / it["shots"], 6)
+    eups = edge_updates / (dec_ms / 1e3)
+    achieved = edge_updates * SLOTS_PER_EDGE_UPDATE / (dec_ms / 1e3)
+    log(f"step {ms:.2f} ms, decode {dec_ms:.2f} ms, {eups:.3e} edge-updates/s, avg iters {iters_total / total_shots:.2f}")
+
+    out = {
+        "metric": "syndromes/s mixed-batch vs per-code plain BP, same GPU, LER in 95% CI",
+        "value": value, "unit": "syndromes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mixed batch: planar d{5,7,9,11,13}, toric L{6,10,14}, XZZX L{5,9,13}, "
+                               "depolarizing p=0.08, 2^18 shots x 1:2:4 per size tier, EWAInit-BP alpha=0.5, "
+                               "iter_max 100, sample + one persistent decode launch + bookkeeping per step",
+                   "shots_per_step": total_shots, "codes": len(items), "shot_scale": args.scale},
+        "decode_ms": dec_ms, "edge_updates_per_s": eups, "avg_iters": iters_total / total_shots,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "decode_lds_kernel", "ops_per_edge_update": SLOTS_PER_EDGE_UPDATE},
+        "ler": ler,
+    }
+
+    if not args.no_plain:
+        plain_ms = 0.0
+        same = True
+        for it, o in zip(items, batch.outs):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            r = P.decode_plain(it["g"], prm, it["prior"], it["syn"])
+            b.record()
+            torch.cuda.synchronize()
+            plain_ms += a.elapsed_time(b)
+            same = same and torch.equal(r["est"], o["est"]) and torch.equal(r["iters"], o["iters"])
+            del r
+            torch.cuda.empty_cache()
+        out["plain_per_code"] = {"decode_ms": plain_ms, "value": total_shots / (plain_ms / 1e3),
+                                 "unit": "syndromes/s", "speedup_of_mixed": plain_ms / dec_ms,
+                                 "bit_identical": bool(same)}
+        log(f"plain per-code decode {plain_ms:.1f} ms -> mixed is {plain_ms / dec_ms:.1f}x")
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        O.build()
+        threads = min(16, os.cpu_count() or 1)
+        tot_shots = 0
+        tot_t = 0.0
+        in_ci = True
+        for it in items:
+            code = it["code"]
+            k = max(1, min(it["shots"], int(512 * it["shots"] / (BASE_SHOTS * args.scale))))
+            e_o, s_o = O.sample(code.hx, code.hz, k, thr, seed=it["seed"], nthreads=threads)
+            pi = O.prior_llr(qecgen.depolarizing_probs(code.n, P_ERR))
+            t = time.perf_counter()
+            ro = O.decode(code.hx, code.hz, O.Params(variant="ewainit", alpha=ALPHA, max_iter=MAX_ITER), pi, s_o,
+                          nthreads=threads)
+            tot_t += time.perf_counter() - t
+            tot_shots += k
+            _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
+            lo, hi = O.wilson_ci(int(co[1] + co[2]), k)
+            nf, ns = fails[code.name]
+            in_ci = in_ci and (lo <= nf / ns <= hi)
+        out["cpu_baseline"] = {"value": tot_shots / tot_t, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
+                               "sample": f"first 512 x (1|2|4) shots of each code ({tot_shots} shots), FP64 oracle, "
+                                         f"OpenMP over shots"}
+        out["ler_in_oracle_ci"] = bool(in_ci)
+        log(f"oracle {tot_shots / tot_t:.0f} shots/s on {threads} threads")
+
+    out["wall_s"] = wall
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

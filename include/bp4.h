@@ -161,6 +161,54 @@ int bp4_decode_ex(const bp4_graph *g, const void *dev_graph, const bp4_params *p
                   float *q_out, float *mvc_out, float *mcv_out,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* One code of a mixed batch: its graph, parameters, shots and buffers (as the
+ * arguments of bp4_decode).  group_lanes as in bp4_tuning (0: automatic);
+ * reserved must be 0. */
+typedef struct {
+    const bp4_graph *graph;
+    const void *dev_graph;
+    bp4_params params;
+    int64_t shots;
+    const float *prior_llr;
+    const uint8_t *synd;
+    uint8_t *est;
+    uint8_t *conv;
+    int32_t *iters;
+    int32_t group_lanes;
+    int32_t reserved;
+} bp4_code_batch;
+
+#define BP4_MAX_MIXED_CODES 16
+
+/* Device workspace bytes of bp4_decode_mixed (one shot queue per code). */
+int bp4_mixed_workspace_bytes(int32_t ncodes, size_t *bytes);
+
+/* Decode the syndromes of up to BP4_MAX_MIXED_CODES codes (different sizes,
+ * families, variants, parameters and shot counts) in one persistent launch:
+ * each workgroup stages one code's graph in LDS and its lane groups pull that
+ * code's shots from a queue, then the workgroup moves on to the next code
+ * (largest first).  Results per code as bp4_decode; bit-identical to decoding
+ * each code alone with the same group_lanes.  Errors: as bp4_decode, EINVAL
+ * for ncodes outside [1, BP4_MAX_MIXED_CODES]. */
+int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Device workspace bytes of bp4_decode_plain: messages, per-qubit state and
+ * hard decisions of every shot in HBM. */
+int bp4_plain_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes);
+
+/* The textbook GPU mapping of the same decoder, the reference point of the
+ * persistent kernels: one kernel per phase per iteration, one thread per
+ * (shot, check) or (shot, qubit), messages in HBM, finished shots masked.
+ * The host reads the number of unfinished shots after each iteration, so the
+ * call blocks until the decode is done; *iterations_run (host, may be NULL)
+ * receives the iterations launched.  Same arithmetic per node as bp4_decode,
+ * so the outputs are bit-identical.  Errors: as bp4_decode. */
+int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params *p, int64_t shots,
+                     const float *prior_llr, const uint8_t *synd,
+                     uint8_t *est, uint8_t *conv, int32_t *iters,
+                     void *ws, size_t ws_bytes, void *stream, int32_t *iterations_run);
+
 /* Classify each shot (section IV): with R = E^ E, fail dev [shots] = 1
  * ("detected": R anticommutes with a stabilizer), 2 ("undetected": R
  * commutes with every stabilizer but not with a logical operator of the

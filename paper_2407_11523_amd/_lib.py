@@ -33,6 +33,13 @@ class Tuning(ctypes.Structure):
     _fields_ = [("group_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
+class CodeBatch(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("dev_graph", ctypes.c_void_p), ("params", Params),
+                ("shots", ctypes.c_int64), ("prior_llr", ctypes.c_void_p), ("synd", ctypes.c_void_p),
+                ("est", ctypes.c_void_p), ("conv", ctypes.c_void_p), ("iters", ctypes.c_void_p),
+                ("group_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p
@@ -58,6 +65,12 @@ SIGNATURES = {
     "bp4_decode_ex": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(Params), ctypes.POINTER(Tuning),
                                      ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "bp4_bookkeep": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]),
+    "bp4_mixed_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_sz)]),
+    "bp4_decode_mixed": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CodeBatch), _vp, _sz, _vp]),
+    "bp4_plain_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64,
+                                                 ctypes.POINTER(_sz)]),
+    "bp4_decode_plain": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(Params), ctypes.c_int64, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_int32)]),
     "bp4_last_error": (ctypes.c_char_p, []),
     "bp4_version": (ctypes.c_char_p, []),
 }

@@ -13,7 +13,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import BP4Error, Params as _CParams, Tuning as _CTuning, check, load
+from ._lib import BP4Error, CodeBatch as _CCodeBatch, Params as _CParams, Tuning as _CTuning, check, load
 
 VARIANTS = {"bp": 0, "momentum": 1, "adagrad": 2, "ewainit": 3}
 ALLOW_ANTICOMMUTING = 1
@@ -194,3 +194,82 @@ def bookkeep(g: Graph, err: torch.Tensor, est: torch.Tensor, counts: Optional[to
     check(g._lib.bp4_bookkeep(g.handle, _ptr(g.dev), shots, _ptr(err), _ptr(est), _ptr(fail), _ptr(counts),
                               _stream(dev)))
     return fail, counts
+
+
+def _outputs(g: Graph, shots: int, out: Optional[dict]):
+    dev = g.dev.device
+    o = out if out is not None else {}
+    est = o.get("est")
+    if est is None:
+        est = torch.empty((shots, g.n), dtype=torch.uint8, device=dev)
+    conv = o.get("conv")
+    if conv is None:
+        conv = torch.empty(shots, dtype=torch.uint8, device=dev)
+    iters = o.get("iters")
+    if iters is None:
+        iters = torch.empty(shots, dtype=torch.int32, device=dev)
+    return {"est": est, "conv": conv, "iters": iters}
+
+
+def _check_inputs(g: Graph, prior: torch.Tensor, synd: torch.Tensor):
+    if synd.dtype != torch.uint8 or synd.dim() != 2 or synd.shape[1] != g.m or not synd.is_contiguous():
+        raise BP4Error(-1, "synd must be a contiguous uint8 [shots][m] tensor")
+    if prior.dtype != torch.float32 or tuple(prior.shape) != (g.n, 3) or not prior.is_contiguous():
+        raise BP4Error(-1, "prior must be a contiguous float32 [n][3] tensor")
+
+
+class MixedBatch:
+    """Codes decoded together by one persistent launch (bp4_decode_mixed).
+
+    Each entry is (graph, params, prior [n][3], synd [shots][m], group_lanes); the
+    outputs are allocated once and reused by every call of run()."""
+
+    def __init__(self, entries, outs=None):
+        self.entries = list(entries)
+        if not 1 <= len(self.entries) <= 16:
+            raise BP4Error(-1, "a mixed batch holds 1 to 16 codes")
+        self.outs = []
+        arr = (_CCodeBatch * len(self.entries))()
+        for i, (g, params, prior, synd, lanes) in enumerate(self.entries):
+            _check_inputs(g, prior, synd)
+            o = _outputs(g, synd.shape[0], outs[i] if outs else None)
+            self.outs.append(o)
+            arr[i] = _CCodeBatch(g.handle.value, g.dev.data_ptr(), params.c(), synd.shape[0], prior.data_ptr(),
+                                 synd.data_ptr(), o["est"].data_ptr(), o["conv"].data_ptr(),
+                                 o["iters"].data_ptr(), int(lanes), 0)
+        self._arr = arr
+        lib = load()
+        b = ctypes.c_size_t()
+        check(lib.bp4_mixed_workspace_bytes(len(self.entries), ctypes.byref(b)))
+        self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.entries[0][0].dev.device)
+
+    def run(self):
+        lib = load()
+        check(lib.bp4_decode_mixed(len(self.entries), self._arr, _ptr(self.ws), self.ws.numel(),
+                                   _stream(self.ws.device)))
+        return self.outs
+
+
+def decode_mixed(entries):
+    """Decode several codes in one persistent launch; returns one output dict per code."""
+    return MixedBatch(entries).run()
+
+
+def decode_plain(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
+                 out: Optional[dict] = None, ws: Optional[torch.Tensor] = None):
+    """The textbook per-phase GPU decoder (bp4_decode_plain); blocks until done."""
+    _check_inputs(g, prior, synd)
+    dev = g.dev.device
+    shots = synd.shape[0]
+    res = _outputs(g, shots, out)
+    cp = params.c()
+    if ws is None:
+        b = ctypes.c_size_t()
+        check(g._lib.bp4_plain_workspace_bytes(g.handle, ctypes.byref(cp), shots, ctypes.byref(b)))
+        ws = torch.empty(int(b.value), dtype=torch.uint8, device=dev)
+    it = ctypes.c_int32()
+    check(g._lib.bp4_decode_plain(g.handle, _ptr(g.dev), ctypes.byref(cp), shots, _ptr(prior), _ptr(synd),
+                                  _ptr(res["est"]), _ptr(res["conv"]), _ptr(res["iters"]), _ptr(ws), ws.numel(),
+                                  _stream(dev), ctypes.byref(it)))
+    res["iterations_run"] = int(it.value)
+    return res

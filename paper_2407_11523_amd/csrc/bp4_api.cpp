@@ -2,6 +2,7 @@
 // and validation, the packed device image, argument checks, and kernel launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -306,6 +307,56 @@ int device_max_lds(size_t *bytes)
     return BP4_OK;
 }
 
+void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, const bp4_params *p,
+                      int64_t shots, const float *prior_llr, const uint8_t *synd, uint8_t *est,
+                      uint8_t *conv, int32_t *iters, const LdsLayout &L, unsigned int *counter)
+{
+    a.g = g->view(dev_graph);
+    a.prior = prior_llr;
+    a.synd = synd;
+    a.est = est;
+    a.conv = conv;
+    a.iters = iters;
+    a.q_out = nullptr;
+    a.mvc_out = nullptr;
+    a.mcv_out = nullptr;
+    a.counter = counter;
+    a.shots = (int32_t)shots;
+    a.variant = p->variant;
+    a.max_iter = p->max_iter;
+    a.stop = p->stop_on_syndrome ? 1 : 0;
+    a.g_from_t1 = p->adagrad_g_from_t1 ? 1 : 0;
+    a.alpha = p->alpha;
+    a.gamma = p->gamma;
+    a.eps = p->eps;
+    a.clamp = p->llr_clamp;
+    a.static_words = L.static_words;
+    a.region_words = L.region_words;
+    a.q_off = L.q_off;
+    a.acc_off = L.acc_off;
+    a.ehat_off = L.ehat_off;
+    a.group_lanes = L.group_lanes;
+}
+
+// Lanes per shot for one code: the caller's choice (validated) or the default pick.
+int choose_group(const bp4_graph *g, const bp4_params *p, int32_t requested, size_t max_lds, int *G_out)
+{
+    int G = requested;
+    if (G != 0 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64 && G != 128 && G != 256)
+        return fail(BP4_EINVAL, "decode: group_lanes %d not in {4, 8, ..., 256}", G);
+    if (G && (g->m + G - 1) / G > 64)
+        return fail(BP4_EINVAL, "decode: group_lanes %d leaves more than 64 checks per lane", G);
+    if (G > 0) {
+        if (decode_lds_layout(g->m, g->n, g->nnz, p->variant, G).bytes > max_lds)
+            return fail(BP4_EINVAL, "decode: group_lanes %d exceeds the LDS of a workgroup", G);
+    } else {
+        G = decode_lds_pick_group(g->m, g->n, g->nnz, p->variant, max_lds);
+        if (G < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the LDS kernel");
+    }
+    *G_out = G;
+    return BP4_OK;
+}
+
 int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p,
                   const bp4_tuning *tune, int64_t shots,
                   const float *prior_llr, const uint8_t *synd, uint8_t *est, uint8_t *conv,
@@ -322,55 +373,34 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     if ((mvc_out == nullptr) != (mcv_out == nullptr)) return fail(BP4_EINVAL, "decode: mvc_out and mcv_out go together");
     if (!ws) return fail(BP4_EINVAL, "decode: NULL workspace");
     if (ws_bytes < kSmallWorkspace) return fail(BP4_EWORKSPACE, "decode: workspace %zu < %zu bytes", ws_bytes, kSmallWorkspace);
-    int G = -1;
+    int32_t requested = 0;
     if (tune) {
         for (int i = 0; i < 7; ++i)
             if (tune->reserved[i]) return fail(BP4_EINVAL, "decode: reserved tuning fields must be 0");
-        G = tune->group_lanes;
-        if (G != 0 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64 && G != 128 && G != 256)
-            return fail(BP4_EINVAL, "decode: group_lanes %d not in {4, 8, ..., 256}", G);
-        if (G && (g->m + G - 1) / G > 64) return fail(BP4_EINVAL, "decode: group_lanes %d leaves > 64 checks per lane", G);
+        requested = tune->group_lanes;
+        if (requested != 0 && requested != 4 && requested != 8 && requested != 16 && requested != 32 &&
+            requested != 64 && requested != 128 && requested != 256)
+            return fail(BP4_EINVAL, "decode: group_lanes %d not in {4, 8, ..., 256}", requested);
     }
     size_t max_lds = 0;
     rc = device_max_lds(&max_lds);
     if (rc) return rc;
-    if (G > 0) {
-        if (decode_lds_layout(g->m, g->n, g->nnz, p->variant, G).bytes > max_lds)
-            return fail(BP4_EINVAL, "decode: group_lanes %d exceeds the LDS of a workgroup", G);
-    } else {
-        G = decode_lds_pick_group(g->m, g->n, g->nnz, p->variant, max_lds);
-    }
-    if (G < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the LDS kernel");
+    int G = 0;
+    rc = choose_group(g, p, requested, max_lds, &G);
+    if (rc) return rc;
     const LdsLayout L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G);
-    DecodeArgs a;
-    a.g = g->view(dev_graph);
-    a.prior = prior_llr;
-    a.synd = synd;
-    a.est = est;
-    a.conv = conv;
-    a.iters = iters;
-    a.q_out = q_out;
-    a.mvc_out = mvc_out;
-    a.mcv_out = mcv_out;
-    a.counter = static_cast<unsigned int *>(ws);
-    a.shots = (int32_t)shots;
-    a.variant = p->variant;
-    a.max_iter = p->max_iter;
-    a.stop = p->stop_on_syndrome ? 1 : 0;
-    a.g_from_t1 = p->adagrad_g_from_t1 ? 1 : 0;
-    a.alpha = p->alpha;
-    a.gamma = p->gamma;
-    a.eps = p->eps;
-    a.clamp = p->llr_clamp;
-    a.static_words = L.static_words;
-    a.region_words = L.region_words;
-    a.q_off = L.q_off;
-    a.acc_off = L.acc_off;
-    a.ehat_off = L.ehat_off;
+    MixedArgs args;
+    std::memset(&args, 0, sizeof args);
+    args.ncodes = 1;
+    fill_decode_args(args.codes[0], g, dev_graph, p, shots, prior_llr, synd, est, conv, iters, L,
+                     static_cast<unsigned int *>(ws));
+    args.codes[0].q_out = q_out;
+    args.codes[0].mvc_out = mvc_out;
+    args.codes[0].mcv_out = mcv_out;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_zero_u32(a.counter, 1, s);
+    hipError_t e = launch_zero_u32(args.codes[0].counter, 1, s);
     if (e != hipSuccess) return hip_fail(e, "decode: zero counter");
-    e = launch_decode_lds(a, L, s);
+    e = launch_decode_lds(args, L.bytes, s, nullptr);
     if (e != hipSuccess) return hip_fail(e, "decode: launch");
     return BP4_OK;
 }
@@ -433,6 +463,102 @@ int bp4_bookkeep(const bp4_graph *g, const void *dev_graph, int64_t shots, const
     hipError_t e = launch_bookkeep(g->view(dev_graph), (int32_t)shots, err, est, fail_out, counts,
                                    static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "bookkeep: launch");
+    return BP4_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int bp4_mixed_workspace_bytes(int32_t ncodes, size_t *bytes)
+{
+    if (!bytes) return fail(BP4_EINVAL, "mixed_workspace_bytes: NULL");
+    if (ncodes < 1 || ncodes > BP4_MAX_MIXED_CODES)
+        return fail(BP4_EINVAL, "mixed_workspace_bytes: ncodes %d outside [1, %d]", ncodes, BP4_MAX_MIXED_CODES);
+    *bytes = 256;
+    return BP4_OK;
+}
+
+int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!codes || !ws) return fail(BP4_EINVAL, "decode_mixed: NULL argument");
+    if (ncodes < 1 || ncodes > BP4_MAX_MIXED_CODES)
+        return fail(BP4_EINVAL, "decode_mixed: ncodes %d outside [1, %d]", ncodes, BP4_MAX_MIXED_CODES);
+    if (ws_bytes < 256) return fail(BP4_EWORKSPACE, "decode_mixed: workspace %zu < 256 bytes", ws_bytes);
+    for (int i = 0; i < ncodes; ++i) {
+        const bp4_code_batch &c = codes[i];
+        if (!c.graph || !c.dev_graph) return fail(BP4_EINVAL, "decode_mixed: code %d has a NULL graph", i);
+        int rc = check_params(&c.params);
+        if (rc) return rc;
+        if (c.shots < 0 || c.shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "decode_mixed: code %d shots out of range", i);
+        if (!c.prior_llr) return fail(BP4_EINVAL, "decode_mixed: code %d has a NULL prior", i);
+        if (c.shots > 0 && (!c.synd || !c.est || !c.conv || !c.iters))
+            return fail(BP4_EINVAL, "decode_mixed: code %d has a NULL buffer", i);
+        if (c.reserved) return fail(BP4_EINVAL, "decode_mixed: reserved field of code %d must be 0", i);
+    }
+    size_t max_lds = 0;
+    int rc = device_max_lds(&max_lds);
+    if (rc) return rc;
+    // largest codes first: their tail is the longest
+    std::vector<int> order;
+    for (int i = 0; i < ncodes; ++i)
+        if (codes[i].shots > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return codes[x].graph->nnz > codes[y].graph->nnz;
+    });
+    if (order.empty()) return BP4_OK;
+    MixedArgs args;
+    std::memset(&args, 0, sizeof args);
+    args.ncodes = (int32_t)order.size();
+    size_t lds = 0;
+    unsigned int *counters = static_cast<unsigned int *>(ws);
+    for (size_t k = 0; k < order.size(); ++k) {
+        const bp4_code_batch &c = codes[order[k]];
+        int G = 0;
+        rc = choose_group(c.graph, &c.params, c.group_lanes, max_lds, &G);
+        if (rc) return rc;
+        const LdsLayout L = decode_lds_layout(c.graph->m, c.graph->n, c.graph->nnz, c.params.variant, G);
+        lds = L.bytes > lds ? L.bytes : lds;
+        fill_decode_args(args.codes[k], c.graph, c.dev_graph, &c.params, c.shots, c.prior_llr, c.synd, c.est,
+                         c.conv, c.iters, L, counters + k);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_zero_u32(counters, args.ncodes, s);
+    if (e != hipSuccess) return hip_fail(e, "decode_mixed: zero counters");
+    e = launch_decode_lds(args, lds, s, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "decode_mixed: launch");
+    return BP4_OK;
+}
+
+int bp4_plain_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes)
+{
+    if (!g || !bytes) return fail(BP4_EINVAL, "plain_workspace_bytes: NULL argument");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (shots < 0 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "plain_workspace_bytes: shots out of range");
+    *bytes = plain_workspace_bytes(g->n, g->nnz, p->variant, shots);
+    return BP4_OK;
+}
+
+int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params *p, int64_t shots,
+                     const float *prior_llr, const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters,
+                     void *ws, size_t ws_bytes, void *stream, int32_t *iterations_run)
+{
+    if (!g || !dev_graph) return fail(BP4_EINVAL, "decode_plain: NULL graph");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (shots < 0 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "decode_plain: shots out of range");
+    if (!prior_llr) return fail(BP4_EINVAL, "decode_plain: NULL prior");
+    if (iterations_run) *iterations_run = 0;
+    if (shots == 0) return BP4_OK;
+    if (!synd || !est || !conv || !iters || !ws) return fail(BP4_EINVAL, "decode_plain: NULL buffer");
+    const size_t need = plain_workspace_bytes(g->n, g->nnz, p->variant, shots);
+    if (ws_bytes < need) return fail(BP4_EWORKSPACE, "decode_plain: workspace %zu < %zu bytes", ws_bytes, need);
+    int32_t it = 0;
+    hipError_t e = run_plain(g->view(dev_graph), *p, (int32_t)shots, prior_llr, synd, est, conv, iters, ws,
+                             static_cast<hipStream_t>(stream), &it);
+    if (e != hipSuccess) return hip_fail(e, "decode_plain");
+    if (iterations_run) *iterations_run = it;
     return BP4_OK;
 }
 

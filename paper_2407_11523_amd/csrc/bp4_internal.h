@@ -56,6 +56,14 @@ struct DecodeArgs {
     float alpha, gamma, eps, clamp;
     // LDS layout (words): workgroup-static part, then one region per shot group
     int32_t static_words, region_words, q_off, acc_off, ehat_off;
+    int32_t group_lanes;     // lanes per shot: 4, 8, 16, 32, 64, 128 or 256
+};
+
+// Codes of one persistent launch, decoded in this order (largest first).
+constexpr int kMaxMixedCodes = 16;
+struct MixedArgs {
+    int32_t ncodes;
+    DecodeArgs codes[kMaxMixedCodes];
 };
 
 // LDS layout of the small-code kernel for one code, variant and group size.
@@ -67,7 +75,7 @@ struct LdsLayout {
 
 LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes);
 int decode_lds_pick_group(int m, int n, int nnz, int variant, size_t max_lds);
-hipError_t launch_decode_lds(const DecodeArgs &a, const LdsLayout &L, hipStream_t s);
+hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_t s, int *grid_out);
 
 hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const uint32_t thr[3],
                          uint64_t seed, uint64_t stream_id, uint8_t *err, uint8_t *synd,
@@ -75,5 +83,10 @@ hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const
 hipError_t launch_bookkeep(const GraphView &g, int32_t shots, const uint8_t *err,
                            const uint8_t *est, uint8_t *fail, int64_t *counts, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s);
+
+size_t plain_workspace_bytes(int n, int nnz, int variant, int64_t shots);
+hipError_t run_plain(const GraphView &g, const bp4_params &p, int32_t shots, const float *prior,
+                     const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters, void *ws,
+                     hipStream_t s, int32_t *iterations_run);
 
 }  // namespace bp4

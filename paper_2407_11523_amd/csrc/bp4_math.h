@@ -1,0 +1,223 @@
+// Device arithmetic of one flooding BP iteration, shared by every decode kernel:
+// the check-node function phi, the commutation LLR lambda, value-ordered sums.
+//
+// Paper: Chen, Yi, Liang, Wang, "Improved Belief Propagation Decoding
+// Algorithms for Surface Codes", section II-B1 (eqs. init, h_update, v_update,
+// p_update and the lambda function), section III-A2 (eq. boost).
+#pragma once
+
+#include "bp4_internal.h"
+
+namespace bp4 {
+
+__device__ __forceinline__ void wave_sync()
+{
+    // Lanes of one wavefront exchange data through LDS; LDS operations of a
+    // wavefront execute in order, so only compiler reordering must be fenced.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ float clampf(float x, float c) { return fminf(fmaxf(x, -c), c); }
+
+constexpr float kLog2e = 1.44269504088896341f;
+constexpr float kLn2 = 0.693147180559945309f;
+constexpr float kLn4 = 1.38629436111989061f;
+
+// Hardware base-2 exponential and logarithm (v_exp_f32, v_log_f32).
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+// phi(x) = -ln tanh(x/2) = 2 atanh(e^{-x}) for x >= 0, phi(0) = inf, phi(inf) = 0;
+// 2 atanh(prod tanh(m_k/2)) = (prod sgn m_k) phi(sum phi(|m_k|)).
+//   x >= ln 4: z = e^{-x} <= 1/4 and phi = 2 z P(z^2), P(w) = atanh(sqrt w)/sqrt w;
+//   x <  ln 4: phi = ln(2/x) + u G(u), u = x^2/4, u G(u) = -ln(tanh(sqrt u)/sqrt u).
+// P and G are least-squares fits on those ranges (relative error < 1e-7 in FP32);
+// both forms keep full relative accuracy (no 1 - z or log(1 + tiny) cancellation).
+__device__ __forceinline__ float phi(float x)
+{
+    if (x >= kLn4) {
+        const float z = hw_exp2(-x * kLog2e);
+        const float w = z * z;
+        float p = fmaf(w, 0.12663664294804267f, 0.1419839934660223f);
+        p = fmaf(w, p, 0.2000197421889f);
+        p = fmaf(w, p, 0.3333331781245287f);
+        p = fmaf(w, p, 1.00000000019442f);
+        return (2.0f * z) * p;
+    }
+    const float u = 0.25f * x * x;
+    float g = fmaf(u, 0.0014921690150859843f, -0.006451527278442298f);
+    g = fmaf(u, g, 0.02182510967622784f);
+    g = fmaf(u, g, -0.07777514939719771f);
+    g = fmaf(u, g, 0.33333330803159383f);
+    return fmaf(-hw_log2(0.5f * x), kLn2, u * g);
+}
+
+// ln(1 + e^{-|y|}): the correction term of a two-term log-sum-exp.
+__device__ __forceinline__ float softplus_neg_abs(float y)
+{
+    return hw_log2(1.0f + hw_exp2(-fabsf(y) * kLog2e)) * kLn2;
+}
+
+// lambda_H(Q) = ln(1 + e^{-Q_H}) - ln(e^{-Q_a} + e^{-Q_b}), {a, b} = {X,Y,Z} \ {H}
+//             = [max(-Q_H, 0) - max(-Q_a, -Q_b)] + sp(Q_H) - sp(Q_a - Q_b),
+// with sp(y) = ln(1 + e^{-|y|}) given precomputed (spH, spAB).
+__device__ __forceinline__ float lambda_sp(float qh, float qa, float qb, float spH, float spAB)
+{
+    return (fmaxf(-qh, 0.0f) - fmaxf(-qa, -qb)) + (spH - spAB);
+}
+
+// lambda for the (X, Y, Z) posterior q with a generic label (setup code only).
+__device__ __forceinline__ float lambda_lab(uint32_t lab, const float q[3])
+{
+    const int h = lab == 1u ? 0 : (lab == 3u ? 1 : 2);
+    const float qa = q[h == 0 ? 1 : 0], qb = q[h == 2 ? 1 : 2];
+    return lambda_sp(q[h], qa, qb, softplus_neg_abs(q[h]), softplus_neg_abs(qa - qb));
+}
+
+// Sum of three non-negative values in an order fixed by their values:
+// (min + median) + max, so the result depends only on the multiset.
+__device__ __forceinline__ float sum3_canonical(float a, float b, float c)
+{
+    const float lo = fminf(fminf(a, b), c);
+    const float hi = fmaxf(fmaxf(a, b), c);
+    const float mid = __builtin_amdgcn_fmed3f(a, b, c);
+    return (lo + mid) + hi;
+}
+
+// AdaGrad gradients at or below this fraction of |D| + sum |m| count as 0.
+constexpr float kAdaGradDeadband = 1.52587890625e-05f;   // 2^-16
+
+// 1 iff single-qubit Paulis a, b (codes) anticommute.
+__device__ __forceinline__ uint32_t anticomm(uint32_t a, uint32_t b)
+{
+    return ((a & (b >> 1)) ^ ((a >> 1) & b)) & 1u;
+}
+
+
+// Hyperparameters a qubit update needs (section III).
+struct VariantParams {
+    int32_t variant, g_from_t1;
+    float alpha, gamma, eps;
+};
+
+// Per-qubit state carried between iterations: st = Q^{(t-1)} (EWAInit, Momentum) or
+// D^{(t-1)} = Q^{(t-1)} - Pi^{(0)} (AdaGrad); acc = momentum g or AdaGrad's G.
+__device__ __forceinline__ void qubit_state_init(int variant, const float pi[3], float st[3], float acc[3])
+{
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        st[x] = variant == BP4_ADAGRAD ? 0.0f : pi[x];   // Q^{(0)} = Pi^{(0)}, D^{(0)} = 0
+        acc[x] = 0.0f;
+    }
+}
+
+// Posterior of iteration t from the per-label sums S[lab] of the incoming check
+// messages and A[lab] of their magnitudes (lab: 1 X, 2 Z, 3 Y).
+//   BP (eq. p_update):     Q = Pi + M
+//   EWAInit (eq. EWAInit): Pi^{(t)} = alpha Pi + (1 - alpha) Q^{(t-1)} for t > 1; Q = Pi^{(t)} + M
+//   Momentum (eqs. mombp1, mombp2, gradient of mombp3):
+//                          g = gamma g + (1 - gamma)(Q^{(t-1)} - Pi - M); Q = Q^{(t-1)} - alpha g
+//   AdaGrad (eq. boost):   t = 1: Q = Pi + M; t > 1: g' = D - M, G += g'^2,
+//                          D -= alpha g' / (sqrt(G) + eps); Q = Pi + D
+// where M_W sums the messages whose label anticommutes with W: the other two labels.
+__device__ __forceinline__ void qubit_posterior(const VariantParams &vp, int t, const float pi[3],
+                                                const float S[4], const float A[4], float st[3],
+                                                float acc[3], float qn[3])
+{
+    const float M[3] = {S[3] + S[2], S[1] + S[2], S[1] + S[3]};
+    if (vp.variant == BP4_BP) {
+#pragma unroll
+        for (int x = 0; x < 3; ++x) qn[x] = pi[x] + M[x];
+    } else if (vp.variant == BP4_EWAINIT) {
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            const float pit = t == 1 ? pi[x] : vp.alpha * pi[x] + (1.0f - vp.alpha) * st[x];
+            qn[x] = pit + M[x];
+            st[x] = qn[x];
+        }
+    } else if (vp.variant == BP4_MOMENTUM) {
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            const float g = vp.gamma * acc[x] + (1.0f - vp.gamma) * (st[x] - pi[x] - M[x]);
+            acc[x] = g;
+            qn[x] = st[x] - vp.alpha * g;
+            st[x] = qn[x];
+        }
+    } else {
+        const float Mabs[3] = {A[3] + A[2], A[1] + A[2], A[1] + A[3]};
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            float grad = st[x] - M[x];
+            // a gradient below the rounding resolution of its operands is 0
+            if (fabsf(grad) <= kAdaGradDeadband * (fabsf(st[x]) + Mabs[x])) grad = 0.0f;
+            float d;
+            if (t == 1) {
+                if (vp.g_from_t1) acc[x] = grad * grad;
+                d = M[x];
+            } else {
+                const float G2 = acc[x] + grad * grad;
+                acc[x] = G2;
+                d = st[x] - vp.alpha * grad / (sqrtf(G2) + vp.eps);
+            }
+            st[x] = d;
+            qn[x] = pi[x] + d;
+        }
+    }
+}
+
+// Hard decision (section II-B1): I if every LLR is positive, else the Pauli with the
+// smallest LLR, ties to the first of X, Y, Z.  0xFF marks a NaN posterior (the shot
+// cannot converge).
+__device__ __forceinline__ uint32_t hard_decision(const float q[3])
+{
+    uint32_t e;
+    if (q[0] > 0.0f && q[1] > 0.0f && q[2] > 0.0f) {
+        e = 0u;
+    } else {
+        int b = 0;
+        if (q[1] < q[b]) b = 1;
+        if (q[2] < q[b]) b = 2;
+        e = b == 0 ? 1u : (b == 1 ? 3u : 2u);
+    }
+    if (isnan(q[0]) || isnan(q[1]) || isnan(q[2])) e = 0xFFu;
+    return e;
+}
+
+// lambda_H(Q) for each label present (bit 2 X, 4 Z, 8 Y), indexed by label code.
+__device__ __forceinline__ void qubit_lambdas(const float q[3], uint32_t present, float lam[4])
+{
+    lam[0] = lam[1] = lam[2] = lam[3] = 0.0f;
+    if (present & 2u)   // X: anticommuting pair (Y, Z)
+        lam[1] = lambda_sp(q[0], q[1], q[2], softplus_neg_abs(q[0]), softplus_neg_abs(q[1] - q[2]));
+    if (present & 4u)   // Z: pair (X, Y)
+        lam[2] = lambda_sp(q[2], q[0], q[1], softplus_neg_abs(q[2]), softplus_neg_abs(q[0] - q[1]));
+    if (present & 8u)   // Y: pair (X, Z)
+        lam[3] = lambda_sp(q[1], q[0], q[2], softplus_neg_abs(q[1]), softplus_neg_abs(q[0] - q[2]));
+}
+
+// Check-node update (eq. h_update) of one check of degree <= 4 given its incoming
+// messages mv[j] (padding: +inf) and syndrome bit s: outputs out[j] for j < 4.
+__device__ __forceinline__ void check_update(const float mv[4], uint32_t s, float C, float out[4])
+{
+    float f[4];
+    uint32_t sgn[4];
+    uint32_t neg = s & 1u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        sgn[j] = mv[j] < 0.0f ? 1u : 0u;
+        neg ^= sgn[j];
+        f[j] = phi(fabsf(mv[j]));
+    }
+    // leave-one-out sums of phi, formed directly (no subtraction) and in value order,
+    // so equal multisets of inputs give bitwise equal outputs
+    const float loo[4] = {sum3_canonical(f[1], f[2], f[3]), sum3_canonical(f[0], f[2], f[3]),
+                          sum3_canonical(f[0], f[1], f[3]), sum3_canonical(f[0], f[1], f[2])};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float mag = phi(loo[j]);
+        out[j] = clampf((neg ^ sgn[j]) ? -mag : mag, C);
+    }
+}
+
+}  // namespace bp4

@@ -125,3 +125,28 @@ def test_decode_rejects_bad_pointers_without_gpu(lib):
     assert rc == -1
     assert b"logical" in lib.bp4_last_error()
     del g2
+
+
+def test_mixed_and_plain_validation_without_gpu(lib):
+    from paper_2407_11523_amd import Params, _lib
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    b = ctypes.c_size_t()
+    assert lib.bp4_mixed_workspace_bytes(0, ctypes.byref(b)) == -1
+    assert lib.bp4_mixed_workspace_bytes(17, ctypes.byref(b)) == -1
+    assert lib.bp4_mixed_workspace_bytes(11, ctypes.byref(b)) == 0 and b.value >= 4 * 11
+    arr = (_lib.CodeBatch * 2)()
+    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1          # NULL graphs
+    assert lib.bp4_decode_mixed(0, arr, fake, 256, null) == -1
+    assert lib.bp4_decode_mixed(2, arr, fake, 16, null) == -4           # workspace too small
+    g = _graph(qecgen.toric(4))
+    cp = Params(variant="momentum", alpha=0.5).c()
+    arr[0] = _lib.CodeBatch(g.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
+                            fake.value, 0, 1)
+    arr[1] = arr[0]
+    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1          # reserved field set
+    assert lib.bp4_plain_workspace_bytes(g.handle, ctypes.byref(cp), 1000, ctypes.byref(b)) == 0
+    assert b.value >= 1000 * (g.nnz * 4 + 2 * 3 * g.n * 4 + g.n)
+    it = ctypes.c_int32()
+    assert lib.bp4_decode_plain(g.handle, fake, ctypes.byref(cp), 1000, fake, fake, fake, fake, fake, fake, 64,
+                                null, ctypes.byref(it)) == -4

@@ -1,0 +1,131 @@
+"""GPU: the persistent mixed-code launch and the per-phase plain decoder.
+
+Both run the same per-node arithmetic as the single-code LDS kernel, so their
+outputs must be bit-identical to it; the mixed batch is also checked against
+the FP64 oracle on a sample of every code.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import qecgen
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2407_11523_amd as P  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def setup(code, p, shots, seed):
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    thr = qecgen.thresholds(p / 3, p / 3, p / 3)
+    err, syn = P.sample(g, shots, thr, seed=seed)
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    return g, err, syn, pr
+
+
+@pytest.mark.parametrize("make,variant,alpha", [(lambda: qecgen.planar(5), "ewainit", 0.5),
+                                                (lambda: qecgen.toric(6), "bp", 1.0),
+                                                (lambda: qecgen.xzzx(5), "momentum", 0.6),
+                                                (lambda: qecgen.planar(7), "adagrad", 5.0)])
+def test_plain_equals_lds_bitwise(make, variant, alpha):
+    code = make()
+    g, err, syn, pr = setup(code, 0.08, 20000, 41)
+    prm = P.Params(variant=variant, alpha=alpha, max_iter=60)
+    a = P.decode(g, prm, pr, syn)
+    b = P.decode_plain(g, prm, pr, syn)
+    torch.cuda.synchronize()
+    say("plain", code.name, variant, b["iterations_run"], float(a["iters"].float().mean()))
+    for k in ("est", "conv", "iters"):
+        assert torch.equal(a[k], b[k]), k
+    assert b["iterations_run"] == int(a["iters"].max())
+
+
+CONFIG3 = [("planar", 5, 1), ("planar", 7, 1), ("planar", 9, 2), ("planar", 11, 4), ("planar", 13, 4),
+           ("toric", 6, 1), ("toric", 10, 2), ("toric", 14, 4), ("xzzx", 5, 1), ("xzzx", 9, 2), ("xzzx", 13, 4)]
+
+
+def test_mixed_equals_per_code_bitwise():
+    # all config-3 codes in one launch (shots scaled down), mixed variants and group sizes
+    variants = [("ewainit", 0.5), ("bp", 1.0), ("momentum", 0.6), ("adagrad", 5.0)]
+    entries, ref = [], []
+    for i, (fam, L, mult) in enumerate(CONFIG3):
+        code = qecgen.make(fam, L)
+        g, err, syn, pr = setup(code, 0.08, 2048 * mult + 37 * i, 50 + i)
+        variant, alpha = variants[i % 4]
+        prm = P.Params(variant=variant, alpha=alpha, max_iter=100)
+        lanes = [0, 64, 32, 16, 8, 128, 256][i % 7]
+        try:
+            r = P.decode(g, prm, pr, syn, group_lanes=lanes)
+        except P.BP4Error:          # this group size does not fit the code (lanes or LDS)
+            lanes = 0
+            r = P.decode(g, prm, pr, syn)
+        entries.append((g, prm, pr, syn, lanes))
+        ref.append(r)
+    outs = P.decode_mixed(entries)
+    torch.cuda.synchronize()
+    for (fam, L, _), o, r in zip(CONFIG3, outs, ref):
+        for k in ("est", "conv", "iters"):
+            assert torch.equal(o[k], r[k]), (fam, L, k)
+
+
+def test_mixed_matches_oracle_sample():
+    entries, codes, errs = [], [], []
+    for i, (fam, L, mult) in enumerate(CONFIG3):
+        code = qecgen.make(fam, L)
+        g, err, syn, pr = setup(code, 0.08, 4096 * mult, qecgen.config_seed(3, i, 0))
+        entries.append((g, P.Params(variant="ewainit", alpha=0.5, max_iter=100), pr, syn, 0))
+        codes.append(code)
+        errs.append(err)
+    outs = P.decode_mixed(entries)
+    torch.cuda.synchronize()
+    for i, (code, o) in enumerate(zip(codes, outs)):
+        k = 1024
+        e_o, s_o = O.sample(code.hx, code.hz, k, qecgen.thresholds(0.08 / 3, 0.08 / 3, 0.08 / 3),
+                            seed=qecgen.config_seed(3, i, 0))
+        assert np.array_equal(np_(entries[i][3][:k]), s_o)
+        ro = O.decode(code.hx, code.hz, O.Params(variant="ewainit", alpha=0.5, max_iter=100),
+                      O.prior_llr(qecgen.depolarizing_probs(code.n, 0.08)), s_o)
+        same = np_(o["est"][:k]) == ro["est"]
+        both = np_(o["conv"][:k]).astype(bool) & ro["conv"].astype(bool)
+        agree = float(same[both].mean())      # decisions of shots both sides converged on
+        overall = float(same.mean())
+        _, cg = P.bookkeep(entries[i][0], errs[i], o["est"])
+        _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
+        torch.cuda.synchronize()
+        ler_g = int(cg[1] + cg[2]) / errs[i].shape[0]
+        lo, hi = O.wilson_ci(int(co[1] + co[2]), k, z=3.29)
+        say("mixed-vs-oracle", code.name, agree, overall, ler_g, (lo, hi))
+        # Non-converged shots run iter_max chaotic iterations: there FP64 against FP64 with a
+        # 1e-7 relative perturbation of the priors keeps only 90-98% of the decisions, so the
+        # 99.9% bar applies to shots that converged on both sides (design notes).
+        assert agree >= 0.999
+        assert overall >= 0.99
+        assert lo <= ler_g <= hi
+
+
+def test_mixed_edge_cases():
+    c1, c2 = qecgen.toric(4), qecgen.planar(3)
+    g1, _, s1, p1 = setup(c1, 0.05, 100, 1)
+    g2, _, s2, p2 = setup(c2, 0.05, 0, 2)
+    out = P.decode_mixed([(g1, P.Params(), p1, s1, 0), (g2, P.Params(), p2, s2, 0)])
+    torch.cuda.synchronize()
+    ref = P.decode(g1, P.Params(), p1, s1)
+    torch.cuda.synchronize()
+    assert torch.equal(out[0]["est"], ref["est"]) and out[1]["est"].shape == (0, c2.n)
+    with pytest.raises(P.BP4Error):
+        P.decode_mixed([])
