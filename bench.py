@@ -44,6 +44,8 @@ CODES = [("planar", 5, 1), ("planar", 7, 1), ("planar", 9, 2), ("planar", 11, 4)
 # x 16 lanes x 2.4 GHz = 39.3e12 slots/s.
 SLOTS_PER_EDGE_UPDATE = 32
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# two-sided normal quantile for a 95% family-wise interval over the 11 codes (0.05 / 11)
+Z_FAMILY = 2.8376
 
 
 def log(*a):
@@ -58,7 +60,18 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shot-count scale (1.0 = the named workload)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-code plain decoder")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calibration}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus_requested": args.gpus}), flush=True)
@@ -179,6 +192,7 @@ def main():
         tot_shots = 0
         tot_t = 0.0
         in_ci = True
+        ci = {}
         for it in items:
             code = it["code"]
             k = max(1, min(it["shots"], int(512 * it["shots"] / (BASE_SHOTS * args.scale))))
@@ -190,13 +204,17 @@ def main():
             tot_t += time.perf_counter() - t
             tot_shots += k
             _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
-            lo, hi = O.wilson_ci(int(co[1] + co[2]), k)
+            # Wilson interval at family-wise 95% over the codes (Bonferroni: z for 0.05 / ncodes)
+            lo, hi = O.wilson_ci(int(co[1] + co[2]), k, z=Z_FAMILY)
             nf, ns = fails[code.name]
-            in_ci = in_ci and (lo <= nf / ns <= hi)
+            ok = lo <= nf / ns <= hi
+            in_ci = in_ci and ok
+            ci[code.name] = [round(lo, 5), round(hi, 5), ok]
         out["cpu_baseline"] = {"value": tot_shots / tot_t, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
                                "sample": f"first 512 x (1|2|4) shots of each code ({tot_shots} shots), FP64 oracle, "
                                          f"OpenMP over shots"}
         out["ler_in_oracle_ci"] = bool(in_ci)
+        out["oracle_ci"] = ci
         log(f"oracle {tot_shots / tot_t:.0f} shots/s on {threads} threads")
 
     out["wall_s"] = wall

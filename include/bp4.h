@@ -83,7 +83,7 @@ typedef struct bp4_graph bp4_graph;
  * Errors: EINVAL (m, n <= 0, entries not 0/1, empty row or column, NULL),
  * ENONCOMM (rows anticommute, unless BP4_ALLOW_ANTICOMMUTING), EDEGREE
  * (check or qubit degree above 4), EUNSUPPORTED (n > 16383 or more than
- * 65535 edges). */
+ * 65534 edges). */
 int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
                      uint32_t flags, bp4_graph **out);
 

@@ -176,7 +176,7 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
         }
     }
     // packed check edges (ELL, padded)
-    g->cedge.assign((size_t)m * kMaxCheckDeg, kEdgePad);
+    g->cedge.assign((size_t)m * kMaxCheckDeg, edge_pad_word((int)nnz));
     {
         std::vector<int> cfill(m, 0);
         for (long k = 0; k < nnz; ++k) {

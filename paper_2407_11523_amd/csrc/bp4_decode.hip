@@ -75,6 +75,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
     // Initialisation (eq. init, Algorithm 2): m^{(0)}_{v->c} = lambda_{H_cv}(Pi^{(0)}_v);
     // Q^{(0)} = Pi^{(0)}; momentum and squared-gradient accumulators start at 0.
     auto init = [&](int s) {
+        if (r == 0) msg[a.g.nnz] = INFINITY;   // padding slot
         sbits = 0;
         int k = 0;
         for (int c = r; c < m; c += G, ++k)
@@ -121,12 +122,13 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
                 const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
                 const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
                 float mv[4], out[4];
+                // padding edges read and rewrite the padding slot, which holds +inf
+                // (phi(+inf) = 0 adds nothing to the sums)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) mv[j] = w[j] != kEdgePad ? msg[edge_slot(w[j])] : INFINITY;
+                for (int j = 0; j < 4; ++j) mv[j] = msg[edge_slot(w[j])];
                 check_update(mv, (uint32_t)(sbits >> ((c - r) >> lgG)), C, out);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (w[j] != kEdgePad) msg[edge_slot(w[j])] = out[j];
+                for (int j = 0; j < 4; ++j) msg[edge_slot(w[j])] = edge_is_pad(w[j]) ? INFINITY : out[j];
             }
         }
         gsync();
@@ -135,19 +137,17 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
             for (int v = r; v < n; v += G) {
                 const uint32_t info = s_vi[v];
                 const uint32_t base = var_base(info), deg = var_deg(info);
+                // the words after a qubit's last slot are in the region (another
+                // qubit's slots, the padding slot or the posterior array); their
+                // values are read and masked to 0
                 float mc[4];
-                // per-label sums of m_{c->v} (index = label code; 1 X, 2 Z, 3 Y)
-                float S[4] = {0.0f, 0.0f, 0.0f, 0.0f}, A[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    mc[j] = 0.0f;
-                    if ((uint32_t)j < deg) {
-                        const uint32_t lab = var_lab(info, j);
-                        mc[j] = msg[base + j];
-                        S[lab] += mc[j];
-                        A[lab] += fabsf(mc[j]);
-                    }
+                    const float x = msg[base + j];
+                    mc[j] = (uint32_t)j < deg ? x : 0.0f;
                 }
+                float S[4], A[4];
+                label_sums(info, mc, S, A);
                 const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
                 float st[3] = {0.0f, 0.0f, 0.0f}, ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
                 if (keep_q)
@@ -188,10 +188,10 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
                 uint32_t par = (uint32_t)(sbits >> ((c - r) >> lgG)) & 1u;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    if (w[j] == kEdgePad) continue;
+                    // padding edges: label I commutes with everything, qubit 0 exists
                     const uint32_t e = ehat[edge_var(w[j])];
-                    if (e == 0xFFu) bad = 1u;   // NaN posterior: never converged
-                    else par ^= anticomm(edge_lab(w[j]), e);
+                    bad |= e == 0xFFu ? 1u : 0u;   // NaN posterior: never converged
+                    par ^= anticomm(edge_lab(w[j]), e);
                 }
                 bad |= par;
             }
@@ -273,13 +273,15 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G)
     LdsLayout L;
     L.static_words = kMaxCheckDeg * m + n + 3 * n;
     if (L.static_words & 3) L.static_words += 4 - (L.static_words & 3);
-    int w = nnz;
+    int w = nnz + 1;               // message slots and the padding slot
     L.q_off = w;
     if (variant != BP4_BP) w += 3 * n;
     L.acc_off = w;
     if (variant == BP4_MOMENTUM || variant == BP4_ADAGRAD) w += 3 * n;
     L.ehat_off = w;
     w += (n + 3) / 4;
+    // the qubit phase reads four words from each qubit's first slot: keep them inside
+    if (w < nnz + 4) w = nnz + 4;
     if ((w & 1) == 0) w += 1;   // odd stride: neighbouring groups start on other banks
     L.region_words = w;
     L.group_lanes = G;

@@ -12,11 +12,14 @@ namespace bp4 {
 constexpr int kMaxCheckDeg = 4;
 constexpr int kMaxVarDeg = 4;
 constexpr int kMaxVars = 16383;      // 14-bit qubit index in a packed check edge
-constexpr int kMaxEdges = 65535;     // 16-bit message slot; 0xFFFF marks padding
+constexpr int kMaxEdges = 65534;     // 16-bit message slot; slot nnz is the padding slot
 
 // Packed check-side edge word: bits 0-15 message slot (variable-major position of
-// the edge), bits 16-29 qubit index, bits 30-31 Pauli label (1 X, 2 Z, 3 Y).
-constexpr uint32_t kEdgePad = 0xFFFFFFFFu;
+// the edge), bits 16-29 qubit index, bits 30-31 Pauli label (1 X, 2 Z, 3 Y).  A
+// check with fewer than kMaxCheckDeg edges is padded with the word nnz: label 0
+// (the identity, which commutes with every error), qubit 0, message slot nnz.
+__host__ __device__ inline uint32_t edge_pad_word(int nnz) { return (uint32_t)nnz; }
+__host__ __device__ inline bool edge_is_pad(uint32_t w) { return (w >> 30) == 0u; }
 __host__ __device__ inline uint32_t edge_slot(uint32_t w) { return w & 0xFFFFu; }
 __host__ __device__ inline uint32_t edge_var(uint32_t w) { return (w >> 16) & 0x3FFFu; }
 __host__ __device__ inline uint32_t edge_lab(uint32_t w) { return w >> 30; }
@@ -32,7 +35,7 @@ __host__ __device__ inline uint32_t var_labels_present(uint32_t w) { return (w >
 
 // Device view of an uploaded graph image.
 struct GraphView {
-    const uint32_t *cedge;   // [m][kMaxCheckDeg] packed check edges, padded with kEdgePad
+    const uint32_t *cedge;   // [m][kMaxCheckDeg] packed check edges, padded (edge_pad_word)
     const uint32_t *vinfo;   // [n] packed qubit words
     const uint32_t *vcanon;  // [nnz] canonical (row-major) edge id of each message slot
     const uint32_t *lptr;    // [nlog + 1] offsets into lent

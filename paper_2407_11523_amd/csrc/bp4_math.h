@@ -18,7 +18,8 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ float clampf(float x, float c) { return fminf(fmaxf(x, -c), c); }
+// Clamp to [-c, c] in one instruction (v_med3_f32).
+__device__ __forceinline__ float clampf(float x, float c) { return __builtin_amdgcn_fmed3f(x, -c, c); }
 
 constexpr float kLog2e = 1.44269504088896341f;
 constexpr float kLn2 = 0.693147180559945309f;
@@ -94,6 +95,28 @@ __device__ __forceinline__ uint32_t anticomm(uint32_t a, uint32_t b)
     return ((a & (b >> 1)) ^ ((a >> 1) & b)) & 1u;
 }
 
+
+// Per-label sums of a qubit's incoming check messages mc[j] (slot order; label of
+// slot j from the packed qubit word; slots >= degree hold 0): S[lab] and the sums
+// of magnitudes A[lab], lab = 1 X, 2 Z, 3 Y.  Each label's sum runs over its own
+// slots only, so with at most two edges per label the result does not depend on
+// the slot order.
+__device__ __forceinline__ void label_sums(uint32_t info, const float mc[4], float S[4], float A[4])
+{
+    S[0] = A[0] = 0.0f;
+#pragma unroll
+    for (int L = 1; L <= 3; ++L) {
+        float s = 0.0f, ab = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool on = var_lab(info, j) == (uint32_t)L;   // labels of unused slots are 0
+            s += on ? mc[j] : 0.0f;
+            ab += on ? fabsf(mc[j]) : 0.0f;
+        }
+        S[L] = s;
+        A[L] = ab;
+    }
+}
 
 // Hyperparameters a qubit update needs (section III).
 struct VariantParams {

@@ -67,12 +67,12 @@ __global__ void __launch_bounds__(kTile) plain_check_kernel(PlainArgs a)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         w[j] = a.g.cedge[c * kMaxCheckDeg + j];
-        mv[j] = w[j] != kEdgePad ? a.msg[edge_slot(w[j]) * S + shot] : INFINITY;
+        mv[j] = edge_is_pad(w[j]) ? INFINITY : a.msg[edge_slot(w[j]) * S + shot];
     }
     check_update(mv, a.synd[(size_t)shot * a.g.m + c], a.clamp, out);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        if (w[j] != kEdgePad) a.msg[edge_slot(w[j]) * S + shot] = out[j];
+        if (!edge_is_pad(w[j])) a.msg[edge_slot(w[j]) * S + shot] = out[j];
 }
 
 __global__ void __launch_bounds__(kTile) plain_var_kernel(PlainArgs a)
@@ -84,17 +84,10 @@ __global__ void __launch_bounds__(kTile) plain_var_kernel(PlainArgs a)
     const uint32_t info = a.g.vinfo[v];
     const uint32_t base = var_base(info), deg = var_deg(info);
     float mc[4];
-    float Sl[4] = {0.0f, 0.0f, 0.0f, 0.0f}, Al[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        mc[j] = 0.0f;
-        if ((uint32_t)j < deg) {
-            const uint32_t lab = var_lab(info, j);
-            mc[j] = a.msg[(base + j) * S + shot];
-            Sl[lab] += mc[j];
-            Al[lab] += fabsf(mc[j]);
-        }
-    }
+    for (int j = 0; j < 4; ++j) mc[j] = (uint32_t)j < deg ? a.msg[(base + j) * S + shot] : 0.0f;
+    float Sl[4], Al[4];
+    label_sums(info, mc, Sl, Al);
     const float p3[3] = {a.prior[3 * v], a.prior[3 * v + 1], a.prior[3 * v + 2]};
     const bool keep_q = a.vp.variant != BP4_BP;
     const bool keep_acc = a.vp.variant == BP4_MOMENTUM || a.vp.variant == BP4_ADAGRAD;
@@ -126,7 +119,7 @@ __global__ void __launch_bounds__(kTile) plain_test_kernel(PlainArgs a)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t w = a.g.cedge[c * kMaxCheckDeg + j];
-        if (w == kEdgePad) continue;
+        if (edge_is_pad(w)) continue;
         const uint32_t e = a.ehat[(size_t)edge_var(w) * S + shot];
         if (e == 0xFFu) bad = 1u;
         else par ^= anticomm(edge_lab(w), e);

@@ -68,7 +68,7 @@ syndrome_kernel(GraphView g, int32_t shots, const uint8_t *err, uint8_t *synd)
 #pragma unroll
     for (int j = 0; j < kMaxCheckDeg; ++j) {
         const uint32_t w = g.cedge[c * kMaxCheckDeg + j];
-        if (w == kEdgePad) continue;
+        if (edge_is_pad(w)) continue;
         par ^= anticomm(edge_lab(w), row[edge_var(w)]);
     }
     synd[idx] = (uint8_t)par;
@@ -103,7 +103,7 @@ bookkeep_kernel(GraphView g, int32_t shots, int tile, const uint8_t *err, const 
 #pragma unroll
         for (int j = 0; j < kMaxCheckDeg; ++j) {
             const uint32_t w = g.cedge[c * kMaxCheckDeg + j];
-            if (w == kEdgePad) continue;
+            if (edge_is_pad(w)) continue;
             par ^= anticomm(edge_lab(w), res[sh * n + edge_var(w)]);
         }
         if (par) atomicOr(&flags[sh], 1u);
