@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shot-count scale (1.0 = the named workload)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-code plain decoder")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tuning-cache", default=None, help="autotuner cache file (default: the package's)")
+    ap.add_argument("--no-tune", action="store_true", help="use the default lanes-per-shot pick")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -96,7 +98,20 @@ def main():
         counts = torch.zeros(3, dtype=torch.int64, device=dev)
         items.append(dict(code=code, g=g, prior=pr, err=err, syn=syn, counts=counts, shots=shots,
                           seed=qecgen.config_seed(3, i, 0)))
-    batch = P.MixedBatch([(it["g"], prm, it["prior"], it["syn"], 0) for it in items])
+    # launch shape per code from the autotuner (timed on the first 2^15 syndromes of each code)
+    lanes = [0] * len(items)
+    tuned = None
+    if not args.no_tune:
+        from paper_2407_11523_amd import tune
+        for it in items:
+            P.sample(it["g"], it["shots"], thr, it["seed"], err=it["err"], synd=it["syn"])
+        kw = {"cache_path": args.tuning_cache} if args.tuning_cache else {}
+        tuned = tune.tune_mixed([(it["g"], prm, it["prior"], it["syn"]) for it in items],
+                                [tune.digest(it["code"].hx, it["code"].hz) for it in items],
+                                [it["shots"] for it in items], **kw)
+        lanes = tuned["lanes"]
+        log(f"tuned lanes per shot {lanes}, LDS budget {tuned['budget']}")
+    batch = P.MixedBatch([(it["g"], prm, it["prior"], it["syn"], G) for it, G in zip(items, lanes)])
     total_shots = sum(it["shots"] for it in items)
     log(f"workload: {len(items)} codes, {total_shots} shots per step")
 
@@ -157,7 +172,8 @@ def main():
         "config": {"workload": "mixed batch: planar d{5,7,9,11,13}, toric L{6,10,14}, XZZX L{5,9,13}, "
                                "depolarizing p=0.08, 2^18 shots x 1:2:4 per size tier, EWAInit-BP alpha=0.5, "
                                "iter_max 100, sample + one persistent decode launch + bookkeeping per step",
-                   "shots_per_step": total_shots, "codes": len(items), "shot_scale": args.scale},
+                   "shots_per_step": total_shots, "codes": len(items), "shot_scale": args.scale,
+                   "lanes_per_shot": [int(x) for x in lanes]},
         "decode_ms": dec_ms, "edge_updates_per_s": eups, "avg_iters": iters_total / total_shots,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_SLOTS, "traffic": None,

@@ -142,10 +142,14 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
 
 /* Launch choices of the decode kernels.  group_lanes: lanes that decode one
  * shot together in the LDS kernel (4, 8, 16, 32, 64, 128 or 256; 0 picks by
- * lane use).  Other fields are reserved and must be 0. */
+ * lane use and occupancy).  lds_bytes: if larger than the code's own layout,
+ * each workgroup reserves this much LDS (so a single-code launch runs at the
+ * occupancy of a mixed launch that needs it; 0: the layout's size).  Other
+ * fields are reserved and must be 0. */
 typedef struct {
     int32_t group_lanes;
-    int32_t reserved[7];
+    int32_t lds_bytes;
+    int32_t reserved[6];
 } bp4_tuning;
 
 /* As bp4_decode, with launch choices `tune` (NULL: automatic) and, for
@@ -160,6 +164,11 @@ int bp4_decode_ex(const bp4_graph *g, const void *dev_graph, const bp4_params *p
                   const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters,
                   float *q_out, float *mvc_out, float *mcv_out,
                   void *ws, size_t ws_bytes, void *stream);
+
+/* LDS bytes per workgroup the LDS decode kernel needs for this code, variant
+ * and group size.  Errors: EINVAL if group_lanes is not a valid size or leaves
+ * more than 64 checks per lane. */
+int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int32_t group_lanes, size_t *bytes);
 
 /* One code of a mixed batch: its graph, parameters, shots and buffers (as the
  * arguments of bp4_decode).  group_lanes as in bp4_tuning (0: automatic);

@@ -143,10 +143,12 @@ def sample(g: Graph, shots: int, thr, seed: int, stream_id: int = 0, shot0: int 
 
 
 def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *, trace: bool = False,
-           group_lanes: int = 0, out: Optional[dict] = None, ws: Optional[torch.Tensor] = None):
+           group_lanes: int = 0, lds_bytes: int = 0, out: Optional[dict] = None,
+           ws: Optional[torch.Tensor] = None):
     """Decode syndromes [shots][m]; returns dict(est, conv, iters[, q, mvc, mcv]).
 
-    group_lanes forces the lanes per shot of the LDS kernel (0: automatic)."""
+    group_lanes forces the lanes per shot of the LDS kernel (0: automatic);
+    lds_bytes reserves at least that much LDS per workgroup."""
     dev = g.dev.device
     if synd.dtype != torch.uint8 or synd.dim() != 2 or synd.shape[1] != g.m or not synd.is_contiguous():
         raise BP4Error(-1, "synd must be a contiguous uint8 [shots][m] tensor")
@@ -167,14 +169,14 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
         ws = torch.empty(g.workspace_bytes(params, shots), dtype=torch.uint8, device=dev)
     cp = params.c()
     res = {"est": est, "conv": conv, "iters": iters}
-    if trace or group_lanes:
+    if trace or group_lanes or lds_bytes:
         q = mvc = mcv = None
         if trace:
             q = torch.empty((shots, g.n, 3), dtype=torch.float32, device=dev)
             mvc = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
             mcv = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
             res.update(q=q, mvc=mvc, mcv=mcv)
-        tune = _CTuning(int(group_lanes))
+        tune = _CTuning(int(group_lanes), int(lds_bytes))
         check(g._lib.bp4_decode_ex(g.handle, _ptr(g.dev), ctypes.byref(cp), ctypes.byref(tune), shots,
                                    _ptr(prior), _ptr(synd), _ptr(est), _ptr(conv), _ptr(iters), _ptr(q),
                                    _ptr(mvc), _ptr(mcv), _ptr(ws), ws.numel(), _stream(dev)))

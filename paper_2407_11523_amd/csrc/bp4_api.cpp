@@ -43,7 +43,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // message slots are numbered variable-major (each qubit's edges in increasing
 // check order) so that a qubit's slots are contiguous.
 struct bp4_graph {
-    int32_t m = 0, n = 0, nnz = 0, max_cdeg = 0, max_vdeg = 0, nlog = 0;
+    int32_t m = 0, n = 0, nnz = 0, max_cdeg = 0, max_vdeg = 0, nlog = 0, with_y = 0;
     std::vector<int32_t> canon_chk, canon_var;   // canonical edge -> check, qubit
     std::vector<uint32_t> cedge;                 // [m][kMaxCheckDeg]
     std::vector<uint32_t> vinfo;                 // [n]
@@ -126,6 +126,8 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
     g->max_cdeg = maxc;
     g->max_vdeg = maxv;
     std::vector<uint32_t> lab(nnz);
+    for (long i = 0; i < (long)m * n; ++i)
+        if (hx[i] && hz[i]) g->with_y = 1;
     for (int c = 0; c < m; ++c)
         for (int v = 0; v < n; ++v) {
             const long i = (long)c * n + v;
@@ -336,6 +338,7 @@ void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, 
     a.acc_off = L.acc_off;
     a.ehat_off = L.ehat_off;
     a.group_lanes = L.group_lanes;
+    a.with_y = g->with_y;
 }
 
 // Lanes per shot for one code: the caller's choice (validated) or the default pick.
@@ -373,10 +376,12 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     if ((mvc_out == nullptr) != (mcv_out == nullptr)) return fail(BP4_EINVAL, "decode: mvc_out and mcv_out go together");
     if (!ws) return fail(BP4_EINVAL, "decode: NULL workspace");
     if (ws_bytes < kSmallWorkspace) return fail(BP4_EWORKSPACE, "decode: workspace %zu < %zu bytes", ws_bytes, kSmallWorkspace);
-    int32_t requested = 0;
+    int32_t requested = 0, lds_floor = 0;
     if (tune) {
-        for (int i = 0; i < 7; ++i)
+        for (int i = 0; i < 6; ++i)
             if (tune->reserved[i]) return fail(BP4_EINVAL, "decode: reserved tuning fields must be 0");
+        lds_floor = tune->lds_bytes;
+        if (lds_floor < 0) return fail(BP4_EINVAL, "decode: negative lds_bytes");
         requested = tune->group_lanes;
         if (requested != 0 && requested != 4 && requested != 8 && requested != 16 && requested != 32 &&
             requested != 64 && requested != 128 && requested != 256)
@@ -400,7 +405,9 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_zero_u32(args.codes[0].counter, 1, s);
     if (e != hipSuccess) return hip_fail(e, "decode: zero counter");
-    e = launch_decode_lds(args, L.bytes, s, nullptr);
+    if ((size_t)lds_floor > max_lds) return fail(BP4_EINVAL, "decode: lds_bytes %d above the device limit", lds_floor);
+    const size_t lds = L.bytes > (size_t)lds_floor ? L.bytes : (size_t)lds_floor;
+    e = launch_decode_lds(args, lds, s, nullptr);
     if (e != hipSuccess) return hip_fail(e, "decode: launch");
     return BP4_OK;
 }
@@ -563,3 +570,16 @@ int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params
 }
 
 }  // extern "C"
+
+extern "C" int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int32_t group_lanes, size_t *bytes)
+{
+    if (!g || !bytes) return fail(BP4_EINVAL, "lds_layout_bytes: NULL argument");
+    int rc = check_params(p);
+    if (rc) return rc;
+    const int G = group_lanes;
+    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64 && G != 128 && G != 256)
+        return fail(BP4_EINVAL, "lds_layout_bytes: group_lanes %d not in {4, 8, ..., 256}", G);
+    if ((g->m + G - 1) / G > 64) return fail(BP4_EINVAL, "lds_layout_bytes: more than 64 checks per lane");
+    *bytes = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G).bytes;
+    return BP4_OK;
+}

@@ -57,6 +57,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
     const int variant = a.variant;
     const bool keep_q = variant != BP4_BP;
     const bool keep_acc = variant == BP4_MOMENTUM || variant == BP4_ADAGRAD;
+    const bool with_y = a.with_y != 0;
     VariantParams vp;
     vp.variant = variant;
     vp.g_from_t1 = a.g_from_t1;
@@ -147,7 +148,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
                     mc[j] = (uint32_t)j < deg ? x : 0.0f;
                 }
                 float S[4], A[4];
-                label_sums(info, mc, S, A);
+                label_sums(info, mc, with_y, keep_acc && variant == BP4_ADAGRAD, S, A);
                 const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
                 float st[3] = {0.0f, 0.0f, 0.0f}, ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
                 if (keep_q)
@@ -159,7 +160,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
                     for (int x = 0; x < 3; ++x) qs[3 * v + x] = st[x];
                 if (keep_acc)
                     for (int x = 0; x < 3; ++x) acc[3 * v + x] = ac[x];
-                ehat[v] = (uint8_t)hard_decision(qn);
+                ehat[v] = (uint8_t)decision_byte(hard_decision(qn));
                 // Vertical update (eqs. v_update / mombp5): m_{v->c} = lambda_H(Q) - m_{c->v}.
                 float lam[4];
                 qubit_lambdas(qn, var_labels_present(info), lam);
@@ -185,15 +186,17 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
             for (int c = r; c < m; c += G) {
                 const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
                 const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
-                uint32_t par = (uint32_t)(sbits >> ((c - r) >> lgG)) & 1u;
+                uint32_t par = (uint32_t)(sbits >> ((c - r) >> lgG)) & 1u, any = 0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    // padding edges: label I commutes with everything, qubit 0 exists
-                    const uint32_t e = ehat[edge_var(w[j])];
-                    bad |= e == 0xFFu ? 1u : 0u;   // NaN posterior: never converged
-                    par ^= anticomm(edge_lab(w[j]), e);
+                    // <H_cv, E^_v> is bit H_cv of the decision byte (padding edges read
+                    // bit 0 of qubit 0's byte, which is set only if that shot already
+                    // holds a NaN posterior and cannot converge)
+                    const uint32_t b = ehat[edge_var(w[j])];
+                    par ^= (b >> edge_lab(w[j])) & 1u;
+                    any |= b;
                 }
-                bad |= par;
+                bad |= par | (any & 1u);   // bit 0: a NaN posterior never converges
             }
         }
         bool sat;
@@ -211,8 +214,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
         const bool fin = live && ((a.stop && sat) || t >= a.max_iter);
         if (fin) {
             for (int v = r; v < n; v += G) {
-                const uint8_t e = ehat[v];
-                a.est[(size_t)shot * n + v] = e == 0xFFu ? 0 : e;
+                a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(ehat[v]);
             }
             if (r == 0) {
                 a.conv[shot] = sat ? 1 : 0;

@@ -60,6 +60,7 @@ struct DecodeArgs {
     // LDS layout (words): workgroup-static part, then one region per shot group
     int32_t static_words, region_words, q_off, acc_off, ehat_off;
     int32_t group_lanes;     // lanes per shot: 4, 8, 16, 32, 64, 128 or 256
+    int32_t with_y;          // the code has Y entries
 };
 
 // Codes of one persistent launch, decoded in this order (largest first).

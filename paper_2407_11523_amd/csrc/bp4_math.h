@@ -101,21 +101,35 @@ __device__ __forceinline__ uint32_t anticomm(uint32_t a, uint32_t b)
 // of magnitudes A[lab], lab = 1 X, 2 Z, 3 Y.  Each label's sum runs over its own
 // slots only, so with at most two edges per label the result does not depend on
 // the slot order.
-__device__ __forceinline__ void label_sums(uint32_t info, const float mc[4], float S[4], float A[4])
+// with_y: the code has Y entries (else S[3] = 0); with_abs: also form A.
+__device__ __forceinline__ void label_sums(uint32_t info, const float mc[4], bool with_y, bool with_abs,
+                                           float S[4], float A[4])
 {
     S[0] = A[0] = 0.0f;
+    float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
-    for (int L = 1; L <= 3; ++L) {
-        float s = 0.0f, ab = 0.0f;
+    for (int j = 0; j < 4; ++j) {   // labels of unused slots are 0
+        const uint32_t l = var_lab(info, j);
+        s1 += l == 1u ? mc[j] : 0.0f;
+        s2 += l == 2u ? mc[j] : 0.0f;
+        if (with_y) s3 += l == 3u ? mc[j] : 0.0f;
+    }
+    S[1] = s1;
+    S[2] = s2;
+    S[3] = s3;
+    float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    if (with_abs) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const bool on = var_lab(info, j) == (uint32_t)L;   // labels of unused slots are 0
-            s += on ? mc[j] : 0.0f;
-            ab += on ? fabsf(mc[j]) : 0.0f;
+            const uint32_t l = var_lab(info, j);
+            a1 += l == 1u ? fabsf(mc[j]) : 0.0f;
+            a2 += l == 2u ? fabsf(mc[j]) : 0.0f;
+            a3 += l == 3u ? fabsf(mc[j]) : 0.0f;
         }
-        S[L] = s;
-        A[L] = ab;
     }
+    A[1] = a1;
+    A[2] = a2;
+    A[3] = a3;
 }
 
 // Hyperparameters a qubit update needs (section III).
@@ -206,6 +220,17 @@ __device__ __forceinline__ uint32_t hard_decision(const float q[3])
     if (isnan(q[0]) || isnan(q[1]) || isnan(q[2])) e = 0xFFu;
     return e;
 }
+
+// Decision byte of a qubit: bits 0-3 say which stabilizer labels the decision
+// anticommutes with (bit L for label L = 1 X, 2 Z, 3 Y; bit 0 marks a NaN
+// posterior), bits 4-5 hold the Pauli code itself.  A check then adds
+// <H_cv, E^_v> to its parity as bit H_cv of the byte.
+__device__ __forceinline__ uint32_t decision_byte(uint32_t e)
+{
+    if (e == 0xFFu) return 1u;                        // NaN: never satisfies a check
+    return ((0x6AC0u >> (4u * e)) & 0xFu) | (e << 4);  // I: 0, X: {Z,Y}, Z: {X,Y}, Y: {X,Z}
+}
+__device__ __forceinline__ uint32_t decision_pauli(uint32_t byte) { return byte >> 4; }
 
 // lambda_H(Q) for each label present (bit 2 X, 4 Z, 8 Y), indexed by label code.
 __device__ __forceinline__ void qubit_lambdas(const float q[3], uint32_t present, float lam[4])

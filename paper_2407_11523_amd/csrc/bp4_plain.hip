@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kTile) plain_var_kernel(PlainArgs a)
 #pragma unroll
     for (int j = 0; j < 4; ++j) mc[j] = (uint32_t)j < deg ? a.msg[(base + j) * S + shot] : 0.0f;
     float Sl[4], Al[4];
-    label_sums(info, mc, Sl, Al);
+    label_sums(info, mc, true, a.vp.variant == BP4_ADAGRAD, Sl, Al);
     const float p3[3] = {a.prior[3 * v], a.prior[3 * v + 1], a.prior[3 * v + 2]};
     const bool keep_q = a.vp.variant != BP4_BP;
     const bool keep_acc = a.vp.variant == BP4_MOMENTUM || a.vp.variant == BP4_ADAGRAD;

@@ -129,3 +129,38 @@ def test_mixed_edge_cases():
     assert torch.equal(out[0]["est"], ref["est"]) and out[1]["est"].shape == (0, c2.n)
     with pytest.raises(P.BP4Error):
         P.decode_mixed([])
+
+
+def test_group_size_does_not_change_results():
+    # every lane-group size runs the same per-node arithmetic: outputs are bit-identical
+    code = qecgen.planar(9)
+    g, err, syn, pr = setup(code, 0.08, 5000, 61)
+    for variant, alpha in (("ewainit", 0.5), ("adagrad", 5.0)):
+        prm = P.Params(variant=variant, alpha=alpha, max_iter=100)
+        ref = P.decode(g, prm, pr, syn, group_lanes=64)
+        for G in (8, 16, 32, 128, 256):
+            try:
+                r = P.decode(g, prm, pr, syn, group_lanes=G, lds_bytes=40960)
+            except P.BP4Error:
+                continue
+            torch.cuda.synchronize()
+            for k in ("est", "conv", "iters"):
+                assert torch.equal(r[k], ref[k]), (variant, G, k)
+
+
+def test_autotuner_picks_feasible_sizes(tmp_path):
+    from paper_2407_11523_amd import tune
+    entries, digests, shots = [], [], []
+    for fam, L in (("planar", 5), ("toric", 10)):
+        code = qecgen.make(fam, L)
+        g, err, syn, pr = setup(code, 0.08, 4096, 71)
+        entries.append((g, P.Params(variant="ewainit", alpha=0.5), pr, syn))
+        digests.append(tune.digest(code.hx, code.hz))
+        shots.append(1 << 18)
+    res = tune.tune_mixed(entries, digests, shots, sample=2048, cache_path=str(tmp_path / "c.json"))
+    say("tuned", res["lanes"], res["budget"])
+    for (g, p, _, _), G in zip(entries, res["lanes"]):
+        assert G in tune.GROUP_SIZES
+        assert tune.layout_bytes(g, p, G) <= res["budget"]
+    again = tune.tune_mixed(entries, digests, shots, sample=2048, cache_path=str(tmp_path / "c.json"))
+    assert again["lanes"] == res["lanes"]
