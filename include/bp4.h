@@ -111,8 +111,9 @@ void bp4_graph_destroy(bp4_graph *g);
  * each canonical edge k, its check and qubit (host int32 [nnz] each). */
 int bp4_graph_edges(const bp4_graph *g, int32_t *check, int32_t *qubit);
 
-/* Device workspace bytes bp4_decode needs for `shots` shots (a few counters
- * for the small-code kernel; message arrays for the large-code kernel). */
+/* Device workspace bytes bp4_decode needs for `shots` shots with the automatic
+ * kernel choice (a queue counter for the LDS kernel; lane-resident message and
+ * state arrays for the SOA kernel). */
 int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes);
 
 /* Sample i.i.d. Pauli errors and their syndromes (section IV: each qubit is
@@ -140,19 +141,46 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
                uint8_t *est, uint8_t *conv, int32_t *iters,
                void *ws, size_t ws_bytes, void *stream);
 
-/* Launch choices of the decode kernels.  group_lanes: lanes that decode one
- * shot together in the LDS kernel (4, 8, 16, 32, 64, 128 or 256; 0 picks by
- * lane use and occupancy).  lds_bytes: if larger than the code's own layout,
- * each workgroup reserves this much LDS (so a single-code launch runs at the
- * occupancy of a mixed launch that needs it; 0: the layout's size).  Other
- * fields are reserved and must be 0. */
+/* Launch choices of the decode kernels.  kernel: BP4_KERNEL_AUTO, _LDS or
+ * _SOA (below).  group_lanes: lanes that decode one shot together in the LDS
+ * kernel (4, 8, 16, 32, 64, 128 or 256; 0 picks by lane use and occupancy).
+ * lds_bytes: if larger than the code's own layout, each workgroup of the LDS
+ * kernel reserves this much LDS (so a single-code launch runs at the
+ * occupancy of a mixed launch that needs it; 0: the layout's size).
+ * soa_lanes: shots the SOA kernel keeps in flight (0: 262,144; rounded up to
+ * a multiple of 256 and capped by the shot count); the SOA workspace grows
+ * with it.  soa_iter_block: iterations per SOA launch, after which the shots
+ * still running are packed onto fully populated wavefronts (0: 16); results
+ * do not depend on it.  group_lanes and lds_bytes select the LDS kernel under
+ * AUTO and are rejected with SOA; soa_lanes and soa_iter_block select SOA
+ * under AUTO and are rejected with LDS.  reserved: 0. */
 typedef struct {
     int32_t group_lanes;
     int32_t lds_bytes;
-    int32_t reserved[6];
+    int32_t kernel;
+    int32_t soa_lanes;
+    int32_t soa_iter_block;
+    int32_t reserved[3];
 } bp4_tuning;
 
-/* As bp4_decode, with launch choices `tune` (NULL: automatic) and, for
+/* Decode kernels.  LDS: a lane group per shot, state in LDS (small and medium
+ * codes).  SOA: one lane per shot, messages and state in HBM as
+ * structure-of-arrays [slot][lane] (large codes).  AUTO picks SOA when even
+ * 256-lane groups would need more than 80 KB of LDS per workgroup. */
+enum { BP4_KERNEL_AUTO = 0, BP4_KERNEL_LDS = 1, BP4_KERNEL_SOA = 2 };
+
+/* Device workspace bytes of the SOA kernel for `shots` shots with soa_lanes
+ * lanes in flight (0: the default): per lane, two records (the running one
+ * and the packed one of the next launch) of every message, the posterior
+ * (all variants but BP), the momentum or AdaGrad accumulator and the
+ * syndrome bits, plus the decisions.  Errors: EINVAL (negative shots or
+ * lanes). */
+int bp4_soa_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, int32_t soa_lanes,
+                            size_t *bytes);
+
+/* As bp4_decode, with launch choices `tune` (NULL: automatic; with
+ * tune->kernel = BP4_KERNEL_SOA the workspace must hold
+ * bp4_soa_workspace_bytes) and, for
  * verification, the state after the last iteration run: q_out dev
  * [shots][n][3] posterior LLRs Q; mvc_out and mcv_out dev [shots][nnz]
  * variable-to-check and check-to-variable messages in canonical edge order.

@@ -30,7 +30,8 @@ class Params(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("group_lanes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("group_lanes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("soa_lanes", ctypes.c_int32), ("soa_iter_block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class CodeBatch(ctypes.Structure):
@@ -66,6 +67,8 @@ SIGNATURES = {
                                      ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "bp4_bookkeep": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]),
     "bp4_mixed_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_sz)]),
+    "bp4_soa_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int32,
+                                               ctypes.POINTER(_sz)]),
     "bp4_lds_layout_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(_sz)]),
     "bp4_decode_mixed": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CodeBatch), _vp, _sz, _vp]),
     "bp4_plain_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64,

@@ -142,13 +142,20 @@ def sample(g: Graph, shots: int, thr, seed: int, stream_id: int = 0, shot0: int 
     return err, synd
 
 
+KERNELS = {"auto": 0, "lds": 1, "soa": 2}
+
+
 def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *, trace: bool = False,
-           group_lanes: int = 0, lds_bytes: int = 0, out: Optional[dict] = None,
+           group_lanes: int = 0, lds_bytes: int = 0, kernel: str = "auto", soa_lanes: int = 0,
+           soa_iter_block: int = 0, out: Optional[dict] = None,
            ws: Optional[torch.Tensor] = None):
     """Decode syndromes [shots][m]; returns dict(est, conv, iters[, q, mvc, mcv]).
 
     group_lanes forces the lanes per shot of the LDS kernel (0: automatic);
-    lds_bytes reserves at least that much LDS per workgroup."""
+    lds_bytes reserves at least that much LDS per workgroup; kernel picks the
+    LDS ("lds") or structure-of-arrays ("soa") kernel ("auto": by code size);
+    soa_lanes sets the shots the SOA kernel keeps in flight and soa_iter_block
+    its iterations per launch (0: defaults)."""
     dev = g.dev.device
     if synd.dtype != torch.uint8 or synd.dim() != 2 or synd.shape[1] != g.m or not synd.is_contiguous():
         raise BP4Error(-1, "synd must be a contiguous uint8 [shots][m] tensor")
@@ -165,18 +172,25 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
     iters = o.get("iters")
     if iters is None:
         iters = torch.empty(shots, dtype=torch.int32, device=dev)
-    if ws is None:
-        ws = torch.empty(g.workspace_bytes(params, shots), dtype=torch.uint8, device=dev)
     cp = params.c()
+    if ws is None:
+        if kernel == "soa" or soa_lanes or soa_iter_block:
+            b = ctypes.c_size_t()
+            check(g._lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(cp), shots, int(soa_lanes),
+                                                 ctypes.byref(b)))
+            nbytes = int(b.value)
+        else:
+            nbytes = g.workspace_bytes(params, shots)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     res = {"est": est, "conv": conv, "iters": iters}
-    if trace or group_lanes or lds_bytes:
+    if trace or group_lanes or lds_bytes or soa_lanes or soa_iter_block or kernel != "auto":
         q = mvc = mcv = None
         if trace:
             q = torch.empty((shots, g.n, 3), dtype=torch.float32, device=dev)
             mvc = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
             mcv = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
             res.update(q=q, mvc=mvc, mcv=mcv)
-        tune = _CTuning(int(group_lanes), int(lds_bytes))
+        tune = _CTuning(int(group_lanes), int(lds_bytes), KERNELS[kernel], int(soa_lanes), int(soa_iter_block))
         check(g._lib.bp4_decode_ex(g.handle, _ptr(g.dev), ctypes.byref(cp), ctypes.byref(tune), shots,
                                    _ptr(prior), _ptr(synd), _ptr(est), _ptr(conv), _ptr(iters), _ptr(q),
                                    _ptr(mvc), _ptr(mcv), _ptr(ws), ws.numel(), _stream(dev)))

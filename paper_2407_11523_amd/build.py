@@ -16,8 +16,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbp4.so")
 ARCH = "gfx950"
 
-SOURCES = ["bp4_api.cpp", "bp4_decode.hip", "bp4_sample.hip", "bp4_plain.hip", "bp4_large.hip",
-           "bp4_mixed.hip", "bp4_unrolled.hip"]
+SOURCES = ["bp4_api.cpp", "bp4_decode.hip", "bp4_sample.hip", "bp4_plain.hip", "bp4_soa.hip",
+           "bp4_unrolled.hip"]
 
 # Packed FP32 VALU forms are kept out of generated code.
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -341,6 +341,15 @@ void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, 
     a.with_y = g->with_y;
 }
 
+// The automatic kernel: SOA when even 256-lane groups need more than kLdsAutoLimit
+// bytes of LDS per workgroup, or the code has more than 64 checks per lane at 256.
+int auto_kernel(const bp4_graph *g, int variant)
+{
+    if ((g->m + 255) / 256 > 64) return BP4_KERNEL_SOA;
+    return decode_lds_layout(g->m, g->n, g->nnz, variant, 256).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA
+                                                                                   : BP4_KERNEL_LDS;
+}
+
 // Lanes per shot for one code: the caller's choice (validated) or the default pick.
 int choose_group(const bp4_graph *g, const bp4_params *p, int32_t requested, size_t max_lds, int *G_out)
 {
@@ -376,16 +385,38 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     if ((mvc_out == nullptr) != (mcv_out == nullptr)) return fail(BP4_EINVAL, "decode: mvc_out and mcv_out go together");
     if (!ws) return fail(BP4_EINVAL, "decode: NULL workspace");
     if (ws_bytes < kSmallWorkspace) return fail(BP4_EWORKSPACE, "decode: workspace %zu < %zu bytes", ws_bytes, kSmallWorkspace);
-    int32_t requested = 0, lds_floor = 0;
+    int32_t requested = 0, lds_floor = 0, kernel = BP4_KERNEL_AUTO, soa_lanes = 0, soa_block = 0;
     if (tune) {
-        for (int i = 0; i < 6; ++i)
+        for (int i = 0; i < 3; ++i)
             if (tune->reserved[i]) return fail(BP4_EINVAL, "decode: reserved tuning fields must be 0");
         lds_floor = tune->lds_bytes;
         if (lds_floor < 0) return fail(BP4_EINVAL, "decode: negative lds_bytes");
+        kernel = tune->kernel;
+        if (kernel != BP4_KERNEL_AUTO && kernel != BP4_KERNEL_LDS && kernel != BP4_KERNEL_SOA)
+            return fail(BP4_EINVAL, "decode: kernel %d unknown", kernel);
+        soa_lanes = tune->soa_lanes;
+        soa_block = tune->soa_iter_block;
+        if (soa_lanes < 0 || soa_block < 0) return fail(BP4_EINVAL, "decode: negative soa_lanes or soa_iter_block");
         requested = tune->group_lanes;
         if (requested != 0 && requested != 4 && requested != 8 && requested != 16 && requested != 32 &&
             requested != 64 && requested != 128 && requested != 256)
             return fail(BP4_EINVAL, "decode: group_lanes %d not in {4, 8, ..., 256}", requested);
+    }
+    const bool lds_knobs = requested || lds_floor, soa_knobs = soa_lanes || soa_block;
+    if (lds_knobs && soa_knobs) return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields exclude each other");
+    if (kernel == BP4_KERNEL_AUTO)
+        kernel = lds_knobs ? BP4_KERNEL_LDS : soa_knobs ? BP4_KERNEL_SOA : auto_kernel(g, p->variant);
+    if (kernel == BP4_KERNEL_LDS && soa_knobs)
+        return fail(BP4_EINVAL, "decode: soa_lanes and soa_iter_block apply to the SOA kernel");
+    if (kernel == BP4_KERNEL_SOA) {
+        if (requested || lds_floor) return fail(BP4_EINVAL, "decode: group_lanes and lds_bytes apply to the LDS kernel");
+        const size_t need = soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, soa_lanes);
+        if (ws_bytes < need) return fail(BP4_EWORKSPACE, "decode: SOA workspace %zu < %zu bytes", ws_bytes, need);
+        hipError_t e = launch_decode_soa(g->view(dev_graph), *p, (int32_t)shots, prior_llr, synd, est, conv, iters,
+                                         q_out, mvc_out, mcv_out, ws, soa_lanes, soa_block, g->with_y,
+                                         static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "decode: SOA launch");
+        return BP4_OK;
     }
     size_t max_lds = 0;
     rc = device_max_lds(&max_lds);
@@ -402,10 +433,10 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     args.codes[0].q_out = q_out;
     args.codes[0].mvc_out = mvc_out;
     args.codes[0].mcv_out = mcv_out;
+    if ((size_t)lds_floor > max_lds) return fail(BP4_EINVAL, "decode: lds_bytes %d above the device limit", lds_floor);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_zero_u32(args.codes[0].counter, 1, s);
     if (e != hipSuccess) return hip_fail(e, "decode: zero counter");
-    if ((size_t)lds_floor > max_lds) return fail(BP4_EINVAL, "decode: lds_bytes %d above the device limit", lds_floor);
     const size_t lds = L.bytes > (size_t)lds_floor ? L.bytes : (size_t)lds_floor;
     e = launch_decode_lds(args, lds, s, nullptr);
     if (e != hipSuccess) return hip_fail(e, "decode: launch");
@@ -422,7 +453,20 @@ int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, 
     int rc = check_params(p);
     if (rc) return rc;
     if (shots < 0) return fail(BP4_EINVAL, "workspace_bytes: negative shots");
-    *bytes = kSmallWorkspace;
+    *bytes = auto_kernel(g, p->variant) == BP4_KERNEL_SOA
+                 ? soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, 0)
+                 : kSmallWorkspace;
+    return BP4_OK;
+}
+
+int bp4_soa_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, int32_t soa_lanes,
+                            size_t *bytes)
+{
+    if (!g || !bytes) return fail(BP4_EINVAL, "soa_workspace_bytes: NULL argument");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (shots < 0 || soa_lanes < 0) return fail(BP4_EINVAL, "soa_workspace_bytes: negative shots or lanes");
+    *bytes = soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, soa_lanes);
     return BP4_OK;
 }
 
@@ -502,6 +546,8 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
         if (c.shots > 0 && (!c.synd || !c.est || !c.conv || !c.iters))
             return fail(BP4_EINVAL, "decode_mixed: code %d has a NULL buffer", i);
         if (c.reserved) return fail(BP4_EINVAL, "decode_mixed: reserved field of code %d must be 0", i);
+        if (c.group_lanes == 0 && auto_kernel(c.graph, c.params.variant) == BP4_KERNEL_SOA)
+            return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d needs the large-code (SOA) kernel", i);
     }
     size_t max_lds = 0;
     int rc = device_max_lds(&max_lds);

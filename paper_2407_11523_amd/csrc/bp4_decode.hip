@@ -101,13 +101,13 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
     // Shot queue: the group leader takes the next shot index of this code.
     int shot;
     if (MW) {
-        if (r == 0) bcast[gid] = (int)atomicAdd(a.counter, 1u);
+        if (r == 0) bcast[gid] = take_shot(a.counter, a.shots);
         __syncthreads();
         shot = bcast[gid];
         __syncthreads();
     } else {
         int s0 = 0;
-        if (r == 0) s0 = (int)atomicAdd(a.counter, 1u);
+        if (r == 0) s0 = take_shot(a.counter, a.shots);
         shot = __shfl(s0, lead, 64);
     }
     if (shot < a.shots) init(shot);
@@ -223,7 +223,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
         }
         gsync();
         if (MW) {
-            if (fin && r == 0) bcast[gid] = (int)atomicAdd(a.counter, 1u);
+            if (fin && r == 0) bcast[gid] = take_shot(a.counter, a.shots);
             __syncthreads();
             if (fin) {
                 shot = bcast[gid];
@@ -231,7 +231,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
             }
         } else if (fin) {
             int s0 = 0;
-            if (r == 0) s0 = (int)atomicAdd(a.counter, 1u);
+            if (r == 0) s0 = take_shot(a.counter, a.shots);
             shot = __shfl(s0, lead, 64);
             if (shot < a.shots) init(shot);
         }

@@ -89,6 +89,20 @@ hipError_t launch_bookkeep(const GraphView &g, int32_t shots, const uint8_t *err
 hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s);
 
 size_t plain_workspace_bytes(int n, int nnz, int variant, int64_t shots);
+
+// Lanes (= shots in flight) of the SOA kernel: `requested` (0: default) capped by
+// the shot count, rounded up to whole workgroups.
+size_t soa_lanes(int64_t shots, int32_t requested);
+size_t soa_workspace_bytes(int m, int n, int nnz, int variant, int64_t shots, int32_t lanes);
+// Iterations per SOA launch between compactions of the live shots (default).
+constexpr int32_t kSoaIterBlock = 16;
+hipError_t launch_decode_soa(const GraphView &g, const bp4_params &p, int32_t shots, const float *prior,
+                             const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters, float *q_out,
+                             float *mvc_out, float *mcv_out, void *ws, int32_t lanes, int32_t iter_block,
+                             int with_y, hipStream_t s);
+// The large-code kernel is the automatic choice when even 256-lane groups need more
+// than this much LDS per workgroup (fewer than two workgroups per CU).
+constexpr size_t kLdsAutoLimit = 81920;
 hipError_t run_plain(const GraphView &g, const bp4_params &p, int32_t shots, const float *prior,
                      const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters, void *ws,
                      hipStream_t s, int32_t *iterations_run);

@@ -10,6 +10,14 @@
 
 namespace bp4 {
 
+// Next shot index from a queue head; the head can pass 2^31 near the shot limit,
+// so it is compared unsigned and saturated at `shots` (= no shot left).
+__device__ __forceinline__ int take_shot(unsigned int *head, int32_t shots)
+{
+    const unsigned got = atomicAdd(head, 1u);
+    return got < (unsigned)shots ? (int)got : shots;
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     // Lanes of one wavefront exchange data through LDS; LDS operations of a
@@ -162,6 +170,9 @@ __device__ __forceinline__ void qubit_posterior(const VariantParams &vp, int t, 
                                                 const float S[4], const float A[4], float st[3],
                                                 float acc[3], float qn[3])
 {
+    // Every kernel must round these updates identically, so no multiply-add is
+    // left to the compiler: the fused ones are written out.
+#pragma clang fp contract(off)
     const float M[3] = {S[3] + S[2], S[1] + S[2], S[1] + S[3]};
     if (vp.variant == BP4_BP) {
 #pragma unroll
@@ -169,16 +180,16 @@ __device__ __forceinline__ void qubit_posterior(const VariantParams &vp, int t, 
     } else if (vp.variant == BP4_EWAINIT) {
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
-            const float pit = t == 1 ? pi[x] : vp.alpha * pi[x] + (1.0f - vp.alpha) * st[x];
+            const float pit = t == 1 ? pi[x] : fmaf(vp.alpha, pi[x], (1.0f - vp.alpha) * st[x]);
             qn[x] = pit + M[x];
             st[x] = qn[x];
         }
     } else if (vp.variant == BP4_MOMENTUM) {
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
-            const float g = vp.gamma * acc[x] + (1.0f - vp.gamma) * (st[x] - pi[x] - M[x]);
+            const float g = fmaf(vp.gamma, acc[x], (1.0f - vp.gamma) * (st[x] - pi[x] - M[x]));
             acc[x] = g;
-            qn[x] = st[x] - vp.alpha * g;
+            qn[x] = fmaf(-vp.alpha, g, st[x]);
             st[x] = qn[x];
         }
     } else {
@@ -193,9 +204,9 @@ __device__ __forceinline__ void qubit_posterior(const VariantParams &vp, int t, 
                 if (vp.g_from_t1) acc[x] = grad * grad;
                 d = M[x];
             } else {
-                const float G2 = acc[x] + grad * grad;
+                const float G2 = fmaf(grad, grad, acc[x]);
                 acc[x] = G2;
-                d = st[x] - vp.alpha * grad / (sqrtf(G2) + vp.eps);
+                d = st[x] - (vp.alpha * grad) / (sqrtf(G2) + vp.eps);
             }
             st[x] = d;
             qn[x] = pi[x] + d;

@@ -115,6 +115,23 @@ def test_decode_rejects_bad_pointers_without_gpu(lib):
     rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
                            fake, null, null, null, fake, 256, null)
     assert rc == -1
+    tune = _lib.Tuning(0, 0, 7)                       # unknown kernel
+    rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                           fake, null, null, null, fake, 1 << 30, null)
+    assert rc == -1
+    tune = _lib.Tuning(64, 0, 2)                      # group size with the SOA kernel
+    rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                           fake, null, null, null, fake, 1 << 30, null)
+    assert rc == -1
+    tune = _lib.Tuning(0, 0, 1, 4096)                 # SOA lanes with the LDS kernel
+    rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                           fake, null, null, null, fake, 1 << 30, null)
+    assert rc == -1
+    tune = _lib.Tuning(0, 0, 2)                       # SOA workspace too small
+    rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                           fake, null, null, null, fake, 4096, null)
+    assert rc == -4
+    assert b"SOA" in lib.bp4_last_error()
     t = (ctypes.c_uint32 * 3)(2 ** 31, 2 ** 31, 1)
     rc = lib.bp4_sample(g.handle, fake, 10, 0, t, 1, 0, fake, fake, null)
     assert rc == -1
@@ -150,3 +167,48 @@ def test_mixed_and_plain_validation_without_gpu(lib):
     it = ctypes.c_int32()
     assert lib.bp4_decode_plain(g.handle, fake, ctypes.byref(cp), 1000, fake, fake, fake, fake, fake, fake, 64,
                                 null, ctypes.byref(it)) == -4
+
+
+def test_large_codes_take_the_soa_kernel(lib):
+    """Codes whose LDS image exceeds the automatic limit get the SOA kernel: its workspace
+    holds every message and qubit state per resident lane and grows with the variant."""
+    from paper_2407_11523_amd import Graph, Params
+    c = qecgen.planar(31)
+    g = Graph(c.hx, c.hz, upload=False)
+    shots = 1 << 18
+    sizes = {}
+    for v in ("bp", "ewainit", "momentum", "adagrad"):
+        prm = Params(variant=v, alpha=0.5 if v != "adagrad" else 5.0)
+        b = ctypes.c_size_t()
+        assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, 0, ctypes.byref(b)) == 0
+        sizes[v] = b.value
+        assert g.workspace_bytes(prm, shots) == b.value
+    # BP: messages (nnz + 1 slots) + decisions + syndrome bits; EWAInit adds Q; the others add a second state
+    lanes = shots
+    # two records per lane (running and packed), plus decisions
+    assert sizes["bp"] >= 2 * (7320 + 59) * lanes * 4 + 1861 * lanes
+    assert sizes["ewainit"] - sizes["bp"] >= 2 * 3 * 1861 * lanes * 4
+    assert sizes["momentum"] - sizes["ewainit"] >= 2 * 3 * 1861 * lanes * 4
+    assert sizes["adagrad"] == sizes["momentum"]
+    # fewer lanes in flight: proportionally smaller
+    b = ctypes.c_size_t()
+    prm = Params(variant="bp")
+    assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, 1 << 14, ctypes.byref(b)) == 0
+    assert b.value * 15 < sizes["bp"] < b.value * 17
+    assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, -1, ctypes.byref(b)) == -1
+    # the small codes keep the LDS kernel's 256-byte workspace
+    s = qecgen.planar(13)
+    gs = Graph(s.hx, s.hz, upload=False)
+    assert gs.workspace_bytes(Params(variant="ewainit", alpha=0.5), shots) == 256
+
+
+def test_mixed_rejects_soa_only_codes(lib):
+    from paper_2407_11523_amd import Graph, Params, _lib
+    c = qecgen.toric(32)
+    g = Graph(c.hx, c.hz, upload=False)
+    fake = ctypes.c_void_p(1 << 20)
+    arr = (_lib.CodeBatch * 1)()
+    arr[0] = _lib.CodeBatch(g.handle.value, fake.value, Params(variant="ewainit", alpha=0.5).c(), 10, fake.value,
+                            fake.value, fake.value, fake.value, fake.value, 0, 0)
+    assert lib.bp4_decode_mixed(1, arr, fake, 4096, None) == -6
+    assert b"SOA" in lib.bp4_last_error()
