@@ -47,6 +47,23 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # two-sided normal quantile for a 95% family-wise interval over the 11 codes (0.05 / 11)
 Z_FAMILY = 2.8376
 
+# Large codes with HBM-resident messages: planar d=31 and toric L=32 at p = 0.10,
+# 2^18 shots each, EWAInit-BP alpha 0.5 with iter_max 200, structure-of-arrays kernel.
+LARGE_CODES = [("planar", 31), ("toric", 32)]
+LARGE_P = 0.10
+LARGE_SHOTS = 1 << 18
+LARGE_MAX_ITER = 200
+HBM_PEAK = 8.0e12   # bytes/s
+
+
+def soa_bytes_per_shot_iteration(E, N, M):
+    """Algorithmic HBM bytes of one EWAInit iteration of one shot in the SOA kernel:
+    every message read and written on the check side and again on the qubit side
+    (16 E), the posterior Q^{(t-1)} read and Q^{(t)} written (24 N), one decision
+    byte written per qubit (N) and read per edge by the syndrome test (E), and the
+    syndrome bits read by the check pass and the test (8 ceil(M / 32))."""
+    return 17 * E + 25 * N + 8 * ((M + 31) // 32)
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -62,6 +79,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tuning-cache", default=None, help="autotuner cache file (default: the package's)")
     ap.add_argument("--no-tune", action="store_true", help="use the default lanes-per-shot pick")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-code (SOA) measurement")
+    ap.add_argument("--only-large", action="store_true", help="run only the large-code (SOA) measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -85,6 +104,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only_large:
+        print(json.dumps({"large_codes": run_large(torch, qecgen, P, dev)}), flush=True)
+        return
     thr = qecgen.thresholds(P_ERR / 3, P_ERR / 3, P_ERR / 3)
     prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=MAX_ITER)
     items = []
@@ -233,8 +255,61 @@ def main():
         out["oracle_ci"] = ci
         log(f"oracle {tot_shots / tot_t:.0f} shots/s on {threads} threads")
 
+    if not args.no_large:
+        del batch, items
+        torch.cuda.empty_cache()
+        out["large_codes"] = run_large(torch, qecgen, P, dev)
+
     out["wall_s"] = wall
     print(json.dumps(out), flush=True)
+
+
+def run_large(torch, qecgen, P, dev):
+    """Decode 2^18 shots of each large code with the SOA kernel; HBM roofline."""
+    thr = qecgen.thresholds(LARGE_P / 3, LARGE_P / 3, LARGE_P / 3)
+    prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=LARGE_MAX_ITER)
+    res = {"workload": "planar d=31 and toric L=32, depolarizing p=0.10, 2^18 shots each, EWAInit-BP "
+                       "alpha=0.5, iter_max 200, messages in HBM (structure-of-arrays kernel)",
+           "codes": {}}
+    tot_ms = tot_bytes = tot_shots = tot_eu = 0.0
+    for i, (fam, size) in enumerate(LARGE_CODES):
+        code = qecgen.make(fam, size)
+        g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
+        pr = P.prior_llr(qecgen.depolarizing_probs(code.n, LARGE_P), device=dev)
+        err, syn = P.sample(g, LARGE_SHOTS, thr, seed=qecgen.config_seed(5, i, 0))
+        ws = torch.empty(g.workspace_bytes(prm, LARGE_SHOTS), dtype=torch.uint8, device=dev)
+        P.decode(g, prm, pr, syn[:4096], kernel="soa", ws=ws)          # warm-up
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        r = P.decode(g, prm, pr, syn, kernel="soa", ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        _, counts = P.bookkeep(g, err, r["est"])
+        it_sum = int(r["iters"].to(torch.int64).sum())
+        nbytes = it_sum * soa_bytes_per_shot_iteration(g.nnz, g.n, g.m)
+        c = counts.cpu().numpy()
+        res["codes"][code.name] = {
+            "decode_ms": ms, "syndromes_per_s": LARGE_SHOTS / (ms / 1e3),
+            "edge_updates_per_s": it_sum * g.nnz / (ms / 1e3), "avg_iters": it_sum / LARGE_SHOTS,
+            "converged": float(r["conv"].float().mean()), "ler": float(c[1] + c[2]) / LARGE_SHOTS,
+            "hbm_gb_s": nbytes / (ms / 1e3) / 1e9,
+            "bytes_per_shot_iteration": soa_bytes_per_shot_iteration(g.nnz, g.n, g.m)}
+        log(f"{code.name}: decode {ms:.1f} ms, {nbytes / (ms / 1e3) / 1e9:.0f} GB/s algorithmic")
+        tot_ms += ms
+        tot_bytes += nbytes
+        tot_shots += LARGE_SHOTS
+        tot_eu += it_sum * g.nnz
+        del r, ws, err, syn
+        torch.cuda.empty_cache()
+    achieved = tot_bytes / (tot_ms / 1e3)
+    res["syndromes_per_s"] = tot_shots / (tot_ms / 1e3)
+    res["edge_updates_per_s"] = tot_eu / (tot_ms / 1e3)
+    res["roofline"] = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK, "traffic": None, "kernel": "decode_soa_kernel"}
+    return res
 
 
 if __name__ == "__main__":
