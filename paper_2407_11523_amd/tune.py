@@ -46,8 +46,10 @@ def digest(hx, hz) -> str:
 
 
 def device_key(device=None) -> str:
+    # the ISA and the CU count set the launch shapes; the marketing name varies by driver
     p = torch.cuda.get_device_properties(device)
-    return f"{p.name}:{getattr(p, 'gcnArchName', '')}:{p.multi_processor_count}"
+    arch = getattr(p, "gcnArchName", "").split(":")[0]
+    return f"{arch}:{p.multi_processor_count}cu"
 
 
 def _time(fn, reps: int = 3) -> float:
@@ -94,7 +96,7 @@ def tune_mixed(entries: Sequence, digests: Sequence[str], shots_total: Sequence[
     batch_key = device_key(dev) + "|" + "|".join(keys)
     cache = _load_cache(cache_path) if use_cache else {}
     if batch_key in cache:
-        return cache[batch_key]
+        return dict(cache[batch_key], cached=True, key=batch_key.split("|")[0])
     table = {}
     best = None
     for B in BUDGETS:
@@ -125,4 +127,4 @@ def tune_mixed(entries: Sequence, digests: Sequence[str], shots_total: Sequence[
     if save:
         cache[batch_key] = res
         _save_cache(cache, cache_path)
-    return res
+    return dict(res, cached=False, key=batch_key.split("|")[0])
