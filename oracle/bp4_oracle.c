@@ -198,6 +198,8 @@ typedef struct {
     double gamma;               /* Momentum decay */
     double eps;                 /* AdaGrad epsilon */
     double clamp;               /* message magnitude bound C (INFINITY: none) */
+    const double *alpha_t;      /* EWAInit: per-iteration discount, alpha_t[t - 1] at iteration t
+                                   (entry 0 unused), or NULL for the constant alpha */
 } or_params;
 
 typedef struct {
@@ -244,9 +246,11 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
 
         /* EWA initialisation (eq. EWAInit, Alg. 2): Pi^{(1)} = Pi^{(0)};
          * Pi^{(t)} = alpha Pi^{(0)} + (1 - alpha) Q^{(t-1)} for t > 1. */
-        if (p->variant == OR_EWAINIT && t > 1)
+        if (p->variant == OR_EWAINIT && t > 1) {
+            const double a = p->alpha_t ? p->alpha_t[t - 1] : p->alpha;
             for (int i = 0; i < 3 * n; ++i)
-                pit[i] = p->alpha * pi0[i] + (1.0 - p->alpha) * qprev[i];
+                pit[i] = a * pi0[i] + (1.0 - a) * qprev[i];
+        }
 
         /* Horizontal update (eq. h_update): for each edge (c, v), combine the
          * previous messages from all other neighbours v' of c. */

@@ -39,7 +39,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("stop_on_syndrome", ctypes.c_int32), ("adagrad_g_from_t1", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("eps", ctypes.c_double), ("clamp", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("clamp", ctypes.c_double), ("alpha_t", ctypes.c_void_p)]
 
 
 class _Outputs(ctypes.Structure):
@@ -99,11 +99,19 @@ class Params:
     gamma: float = 0.0
     eps: float = 1e-8
     clamp: float = 30.0
+    alpha_t: Optional[np.ndarray] = None   # EWAInit per-iteration discount, entry t-1 at iteration t
 
     def c(self) -> _Params:
-        return _Params(VARIANTS[self.variant], int(self.max_iter), int(bool(self.stop_on_syndrome)),
-                       int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
-                       float(self.eps), float(self.clamp))
+        cp = _Params(VARIANTS[self.variant], int(self.max_iter), int(bool(self.stop_on_syndrome)),
+                     int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
+                     float(self.eps), float(self.clamp), None)
+        if self.alpha_t is not None:
+            a = np.ascontiguousarray(self.alpha_t, dtype=np.float64)
+            if a.shape != (self.max_iter,):
+                raise ValueError("alpha_t needs one entry per iteration")
+            cp._keep = a                      # keeps the buffer alive as long as the struct
+            cp.alpha_t = a.ctypes.data
+        return cp
 
 
 # ---------------------------------------------------------------------------
