@@ -256,6 +256,44 @@ int bp4_bookkeep(const bp4_graph *g, const void *dev_graph, int64_t shots,
                  const uint8_t *err, const uint8_t *est, uint8_t *fail, int64_t *counts,
                  void *stream);
 
+/* ---- Differentiable unrolled EWAInit-BP ------------------------------------
+ * EWAInit-BP (section III, eq. EWAInit; Algorithm 2 without the early stop)
+ * run for exactly T iterations with a discount alpha_t per iteration
+ * (Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)})
+ * and learnable priors Pi^{(0)}; messages clamped to [-llr_clamp, llr_clamp]
+ * as in bp4_decode.  Loss: the mean over shots and qubits of
+ * ln(1 + sum_W e^{-Q_W^{(T)}}) + Q_{e_v}^{(T)} (Q_I = 0), the negative log of
+ * the GF(4) marginal of the sampled error e_v.  The adjoint returns its
+ * gradient with respect to alpha and Pi^{(0)}.  The forward keeps the state
+ * (messages and posteriors) every ckpt_every iterations in `saved`; the
+ * backward recomputes each segment from its checkpoint.
+ *
+ * Device buffers (caller-allocated): alpha float [T] (entry t-1 is alpha_t;
+ * entry 0 is unused), prior float [n][3] (X, Y, Z), synd uint8 [shots][m],
+ * err uint8 [shots][n] (Pauli codes), saved and ws of the sizes below.
+ * Errors: EINVAL (T < 1, ckpt_every < 1, shots < 1, llr_clamp not > 0, NULL
+ * pointers), EWORKSPACE (saved or ws too small), EHIP. */
+
+/* Bytes of the checkpoint buffer and of the workspace for these sizes. */
+int bp4_unrolled_sizes(const bp4_graph *g, int32_t T, int32_t ckpt_every, int64_t shots,
+                       size_t *saved_bytes, size_t *ws_bytes);
+
+/* Forward: writes loss dev double [1] and, if q_out is not NULL, the final
+ * posteriors Q^{(T)} dev float [shots][n][3]; fills `saved`. */
+int bp4_unrolled_forward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every,
+                         float llr_clamp, int64_t shots, const float *alpha, const float *prior,
+                         const uint8_t *synd, const uint8_t *err, double *loss, float *q_out,
+                         void *saved, size_t saved_bytes, void *ws, size_t ws_bytes, void *stream);
+
+/* Backward: with `saved` from the forward of the same inputs, writes
+ * dalpha dev double [T] = dloss * dL/dalpha_t (entry 0 is 0) and dprior dev
+ * double [n][3] = dloss * dL/dPi^{(0)}; dloss is a dev float scalar (NULL: 1). */
+int bp4_unrolled_backward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every,
+                          float llr_clamp, int64_t shots, const float *alpha, const float *prior,
+                          const uint8_t *synd, const uint8_t *err, const float *dloss,
+                          const void *saved, size_t saved_bytes, double *dalpha, double *dprior,
+                          void *ws, size_t ws_bytes, void *stream);
+
 /* Message of the calling thread's last non-OK return. */
 const char *bp4_last_error(void);
 

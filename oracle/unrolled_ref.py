@@ -126,7 +126,9 @@ def loss_and_grad(hx, hz, alpha, prior, synd, err, T: int, clamp: float = 30.0, 
     p = torch.tensor(np.asarray(prior, np.float64).reshape(tg.n, 3), requires_grad=True)
     loss, Q = forward(tg, a, p, synd, err, T, clamp)
     loss.backward()
-    return float(loss.detach()), a.grad.numpy().copy(), p.grad.numpy().copy(), Q.detach().numpy()
+    # alpha is not used at all when T = 1 (alpha_1 is unused): its gradient is then 0
+    ga = a.grad.numpy().copy() if a.grad is not None else np.zeros(a.shape)
+    return float(loss.detach()), ga, p.grad.numpy().copy(), Q.detach().numpy()
 
 
 def soft_loss(q, err):

@@ -289,3 +289,84 @@ def decode_plain(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tens
                                   _stream(dev), ctypes.byref(it)))
     res["iterations_run"] = int(it.value)
     return res
+
+
+# ---------------------------------------------------------------------------
+# Differentiable unrolled EWAInit-BP
+# ---------------------------------------------------------------------------
+
+def unrolled_sizes(g: Graph, T: int, ckpt_every: int, shots: int):
+    """(checkpoint bytes, workspace bytes) of the unrolled forward/backward."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    check(g._lib.bp4_unrolled_sizes(g.handle, int(T), int(ckpt_every), int(shots), ctypes.byref(a),
+                                    ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+class UnrolledEWAInit(torch.autograd.Function):
+    """Soft loss of T unrolled EWAInit-BP iterations (HIP forward and hand-written adjoint).
+
+    forward(alpha [T] float32, prior [n, 3] float32, graph, synd, err, T, ckpt_every, clamp)
+    returns the mean over shots and qubits of ln(1 + sum_W e^{-Q_W}) + Q_{e_v} at t = T
+    as a float64 scalar; backward gives the gradients of alpha and prior."""
+
+    @staticmethod
+    def forward(ctx, alpha, prior, g, synd, err, T, ckpt_every, clamp):
+        dev = synd.device
+        alpha = alpha.detach().to(torch.float32).contiguous()
+        prior = prior.detach().to(torch.float32).contiguous()
+        if alpha.shape != (T,) or prior.shape != (g.n, 3):
+            raise BP4Error(-1, "alpha must be [T] and prior [n, 3]")
+        synd = synd.to(torch.uint8).contiguous()
+        err = err.to(torch.uint8).contiguous()
+        shots = synd.shape[0]
+        sb, wb = unrolled_sizes(g, T, ckpt_every, shots)
+        saved = torch.empty(sb, dtype=torch.uint8, device=dev)
+        ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), int(T), int(ckpt_every), float(clamp), shots,
+                                          _ptr(alpha), _ptr(prior), _ptr(synd), _ptr(err), _ptr(loss),
+                                          ctypes.c_void_p(0), _ptr(saved), sb, _ptr(ws), wb, _stream(dev)))
+        ctx.g, ctx.T, ctx.K, ctx.clamp = g, int(T), int(ckpt_every), float(clamp)
+        ctx.bufs = (alpha, prior, synd, err, saved, ws)
+        ctx.dtypes = (alpha.dtype, prior.dtype)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, dloss):
+        alpha, prior, synd, err, saved, ws = ctx.bufs
+        g = ctx.g
+        dev = synd.device
+        dl = dloss.detach().to(device=dev, dtype=torch.float32).reshape(1).contiguous()
+        dalpha = torch.empty(ctx.T, dtype=torch.float64, device=dev)
+        dprior = torch.empty(g.n, 3, dtype=torch.float64, device=dev)
+        check(g._lib.bp4_unrolled_backward(g.handle, _ptr(g.dev), ctx.T, ctx.K, ctx.clamp, synd.shape[0],
+                                           _ptr(alpha), _ptr(prior), _ptr(synd), _ptr(err), _ptr(dl),
+                                           _ptr(saved), saved.numel(), _ptr(dalpha), _ptr(dprior), _ptr(ws),
+                                           ws.numel(), _stream(dev)))
+        ctx.bufs = None
+        return dalpha.to(ctx.dtypes[0]), dprior.to(ctx.dtypes[1]), None, None, None, None, None, None
+
+
+def unrolled_loss(g: Graph, alpha: torch.Tensor, prior: torch.Tensor, synd: torch.Tensor, err: torch.Tensor,
+                  T: int, ckpt_every: int = 8, clamp: float = 30.0) -> torch.Tensor:
+    """Differentiable soft loss of T unrolled EWAInit-BP iterations (see UnrolledEWAInit)."""
+    return UnrolledEWAInit.apply(alpha, prior, g, synd, err, T, ckpt_every, clamp)
+
+
+def unrolled_forward(g: Graph, alpha: torch.Tensor, prior: torch.Tensor, synd: torch.Tensor, err: torch.Tensor,
+                     T: int, ckpt_every: int = 8, clamp: float = 30.0, want_q: bool = False):
+    """Forward only: (loss float64 [1], Q^{(T)} [shots, n, 3] or None)."""
+    dev = synd.device
+    shots = synd.shape[0]
+    sb, wb = unrolled_sizes(g, T, ckpt_every, shots)
+    saved = torch.empty(sb, dtype=torch.uint8, device=dev)
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    q = torch.empty(shots, g.n, 3, dtype=torch.float32, device=dev) if want_q else None
+    alpha = alpha.detach().to(torch.float32).contiguous()
+    prior = prior.detach().to(torch.float32).contiguous()
+    check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), int(T), int(ckpt_every), float(clamp), shots,
+                                      _ptr(alpha), _ptr(prior), _ptr(synd.contiguous()), _ptr(err.contiguous()),
+                                      _ptr(loss), _ptr(q), _ptr(saved), sb, _ptr(ws), wb, _stream(dev)))
+    return loss, q

@@ -82,6 +82,68 @@ struct bp4_graph {
 
 extern "C" {
 
+static int unrolled_check(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t K, float clamp,
+                          int64_t shots, const float *alpha, const float *prior, const uint8_t *synd,
+                          const uint8_t *err)
+{
+    if (!g || !dev_graph) return fail(BP4_EINVAL, "unrolled: NULL graph");
+    if (T < 1 || K < 1) return fail(BP4_EINVAL, "unrolled: T %d and ckpt_every %d must be >= 1", T, K);
+    if (!(clamp > 0.0f)) return fail(BP4_EINVAL, "unrolled: llr_clamp must be > 0");
+    if (shots < 1 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "unrolled: shots %lld outside [1, 2^31)", (long long)shots);
+    if (!alpha || !prior || !synd || !err) return fail(BP4_EINVAL, "unrolled: NULL input");
+    return BP4_OK;
+}
+
+int bp4_unrolled_sizes(const bp4_graph *g, int32_t T, int32_t ckpt_every, int64_t shots, size_t *saved_bytes,
+                       size_t *ws_bytes)
+{
+    if (!g || !saved_bytes || !ws_bytes) return fail(BP4_EINVAL, "unrolled_sizes: NULL argument");
+    if (T < 1 || ckpt_every < 1) return fail(BP4_EINVAL, "unrolled_sizes: T and ckpt_every must be >= 1");
+    if (shots < 1 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "unrolled_sizes: shots out of range");
+    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
+    *saved_bytes = z.saved;
+    *ws_bytes = z.ws;
+    return BP4_OK;
+}
+
+int bp4_unrolled_forward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every, float llr_clamp,
+                         int64_t shots, const float *alpha, const float *prior, const uint8_t *synd,
+                         const uint8_t *err, double *loss, float *q_out, void *saved, size_t saved_bytes, void *ws,
+                         size_t ws_bytes, void *stream)
+{
+    int rc = unrolled_check(g, dev_graph, T, ckpt_every, llr_clamp, shots, alpha, prior, synd, err);
+    if (rc) return rc;
+    if (!loss || !saved || !ws) return fail(BP4_EINVAL, "unrolled_forward: NULL output or buffer");
+    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
+    if (saved_bytes < z.saved || ws_bytes < z.ws)
+        return fail(BP4_EWORKSPACE, "unrolled_forward: saved %zu < %zu or ws %zu < %zu bytes", saved_bytes, z.saved,
+                    ws_bytes, z.ws);
+    hipError_t e = launch_unrolled_forward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, alpha, prior,
+                                           synd, err, loss, q_out, saved, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "unrolled_forward: launch");
+    return BP4_OK;
+}
+
+int bp4_unrolled_backward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every,
+                          float llr_clamp, int64_t shots, const float *alpha, const float *prior,
+                          const uint8_t *synd, const uint8_t *err, const float *dloss, const void *saved,
+                          size_t saved_bytes, double *dalpha, double *dprior, void *ws, size_t ws_bytes,
+                          void *stream)
+{
+    int rc = unrolled_check(g, dev_graph, T, ckpt_every, llr_clamp, shots, alpha, prior, synd, err);
+    if (rc) return rc;
+    if (!dalpha || !dprior || !saved || !ws) return fail(BP4_EINVAL, "unrolled_backward: NULL output or buffer");
+    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
+    if (saved_bytes < z.saved || ws_bytes < z.ws)
+        return fail(BP4_EWORKSPACE, "unrolled_backward: saved %zu < %zu or ws %zu < %zu bytes", saved_bytes,
+                    z.saved, ws_bytes, z.ws);
+    hipError_t e = launch_unrolled_backward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, alpha,
+                                            prior, synd, err, dloss, saved, dalpha, dprior, ws,
+                                            static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "unrolled_backward: launch");
+    return BP4_OK;
+}
+
 const char *bp4_last_error(void) { return g_err.c_str(); }
 
 const char *bp4_version(void) { return "bp4 0.1 gfx950"; }

@@ -1,0 +1,485 @@
+// Unrolled EWAInit-BP over GF(4) with a fixed number T of flooding iterations
+// and no early stop, its soft loss, and the hand-written adjoint (reverse-mode
+// derivative) with respect to the per-iteration discounts alpha_t and the
+// priors Pi^{(0)}.
+//
+// Forward (section III, eq. EWAInit and Algorithm 2; check and qubit rules of
+// section II-B1): Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t)
+// Q^{(t-1)}, with the same per-node arithmetic as the decode kernels.  Loss: the
+// mean over shots and qubits of ln(1 + sum_W e^{-Q_W}) + Q_{e_v} at t = T
+// (Q_I = 0), the negative log GF(4) marginal of the sampled error.
+//
+// One lane runs one shot.  The state of a shot after iteration t is its
+// messages m_{v->c}^{(t)} (E words) and its posterior Q^{(t)} (3N words), kept
+// as a column of a per-wavefront record [wavefront][item][64 lanes] in HBM.
+// The forward keeps the state every `ckpt` iterations; the adjoint walks the
+// segments from last to first, recomputes a segment's states from its
+// checkpoint, then runs the reverse sweep through it.  Gradient sums over
+// shots are wavefront partials in FP64, reduced in a fixed order.
+#include "bp4_math.h"
+
+namespace bp4 {
+namespace {
+
+constexpr int kUnrBlock = 256;
+
+template <typename T> using konst = const __attribute__((address_space(4))) T;
+template <typename T> __device__ __forceinline__ konst<T> *as_const(const T *p) { return (konst<T> *)p; }
+
+struct UnrArgs {
+    GraphView g;
+    const float *alpha;       // [T], entry t-1 at iteration t (entry 0 unused)
+    const float *prior;       // [n][3] Pi^{(0)}
+    const uint8_t *synd;      // [shots][m]
+    const uint8_t *err;       // [shots][n] Pauli codes of the sampled errors
+    float *ckpt;              // [nseg][waves][E + 3N][64] states at t = 0, K, 2K, ...
+    float *seg;               // [K + 1][waves][E + 3N][64] states of one segment
+    float *adj;               // [waves][E + 6N][64] adjoints: m (E), Q (3N), Pi^{(0)} (3N)
+    double *partial;          // [waves][nout] per-wavefront sums
+    float *q_out;             // optional [shots][n][3] Q^{(T)}
+    int32_t shots, T, K, nseg, waves, nout;
+    float clamp;
+};
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// d phi / dx = -1 / sinh(x), x > 0 (series below 1/4, where e^x - e^-x cancels).
+__device__ __forceinline__ float dphi(float x)
+{
+    if (x < 0.25f) {
+        const float x2 = x * x;
+        return -1.0f / (x * fmaf(x2 * (1.0f / 6.0f), fmaf(x2, 0.05f, 1.0f), 1.0f));
+    }
+    const float e = hw_exp2(x * kLog2e);
+    return -2.0f / (e - 1.0f / e);
+}
+
+__device__ __forceinline__ float sigmoid(float x) { return 1.0f / (1.0f + hw_exp2(-x * kLog2e)); }
+
+// Q indices of an edge label H (1 X, 2 Z, 3 Y) and of its anticommuting pair (a, b).
+__device__ __forceinline__ void label_indices(uint32_t lab, int &h, int &a, int &b)
+{
+    h = lab == 1u ? 0 : (lab == 2u ? 2 : 1);
+    a = lab == 2u ? 0 : (lab == 1u ? 1 : 0);
+    b = lab == 2u ? 1 : 2;
+}
+
+// Soft loss of one qubit and its derivative with respect to (Q_X, Q_Y, Q_Z).
+__device__ __forceinline__ float qubit_loss(const float q[3], uint32_t e, float dq[3])
+{
+    float mx = 0.0f;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) mx = fmaxf(mx, -q[x]);
+    float ex[3];
+    float s = expf(-mx);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        ex[x] = expf(-q[x] - mx);
+        s += ex[x];
+    }
+    const int ei = e == 1u ? 0 : (e == 3u ? 1 : (e == 2u ? 2 : -1));
+#pragma unroll
+    for (int x = 0; x < 3; ++x) dq[x] = (x == ei ? 1.0f : 0.0f) - ex[x] / s;
+    return mx + logf(s) + (ei >= 0 ? q[ei] : 0.0f);
+}
+
+struct Lane {
+    size_t wave;
+    int lane;
+    size_t SI;   // items of one state
+    __device__ float *state(float *base, int slot, int waves) const
+    {
+        return base + ((size_t)slot * waves + wave) * SI * 64 + lane;
+    }
+};
+
+// m^{(0)}_{v->c} = lambda(Pi^{(0)}) clamped, Q^{(0)} = Pi^{(0)}  (eq. init).
+__device__ void init_state(const UnrArgs &a, float *st)
+{
+    konst<uint32_t> *vinfo = as_const(a.g.vinfo);
+    konst<float> *prior = as_const(a.prior);
+    const int E = a.g.nnz;
+    for (int v = 0; v < a.g.n; ++v) {
+        const uint32_t info = vinfo[v];
+        const uint32_t base = var_base(info), deg = var_deg(info);
+        const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
+        float lam[4];
+        qubit_lambdas(p3, var_labels_present(info), lam);
+        for (uint32_t j = 0; j < deg; ++j) st[(size_t)(base + j) * 64] = clampf(lam[var_lab(info, j)], a.clamp);
+        for (int x = 0; x < 3; ++x) st[(size_t)(E + 3 * v + x) * 64] = p3[x];
+    }
+}
+
+// One forward iteration t: reads the state of t-1 from `src`, writes that of t to
+// `dst` (src == dst: in place).  The check pass writes m_{c->v} into dst's message
+// items; the qubit pass turns them into m_{v->c}^{(t)} (skipped at t = T).
+__device__ void forward_iteration(const UnrArgs &a, int t, const float *src, float *dst, int shot)
+{
+    konst<uint32_t> *cedge = as_const(a.g.cedge);
+    konst<uint32_t> *vinfo = as_const(a.g.vinfo);
+    konst<float> *prior = as_const(a.prior);
+    const int m = a.g.m, n = a.g.n, E = a.g.nnz;
+    const float C = a.clamp;
+    const uint8_t *s = a.synd + (size_t)shot * m;
+    for (int c = 0; c < m; ++c) {
+        uint32_t w[4];
+        float mv[4], out[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            w[j] = cedge[kMaxCheckDeg * c + j];
+            mv[j] = edge_is_pad(w[j]) ? INFINITY : src[(size_t)edge_slot(w[j]) * 64];
+        }
+        check_update(mv, s[c] & 1u, C, out);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (!edge_is_pad(w[j])) dst[(size_t)edge_slot(w[j]) * 64] = out[j];
+    }
+    VariantParams vp;
+    vp.variant = BP4_EWAINIT;
+    vp.g_from_t1 = 0;
+    vp.alpha = a.alpha[t - 1];
+    vp.gamma = 0.0f;
+    vp.eps = 0.0f;
+    for (int v = 0; v < n; ++v) {
+        const uint32_t info = vinfo[v];
+        const uint32_t base = var_base(info), deg = var_deg(info);
+        float mc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mc[j] = (uint32_t)j < deg ? dst[(size_t)(base + j) * 64] : 0.0f;
+        float S[4], A[4];
+        label_sums(info, mc, true, false, S, A);
+        const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
+        float st[3], ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
+        for (int x = 0; x < 3; ++x) st[x] = src[(size_t)(E + 3 * v + x) * 64];
+        qubit_posterior(vp, t, p3, S, A, st, ac, qn);
+        for (int x = 0; x < 3; ++x) dst[(size_t)(E + 3 * v + x) * 64] = qn[x];
+        if (t < a.T) {
+            float lam[4];
+            qubit_lambdas(qn, var_labels_present(info), lam);
+            for (uint32_t j = 0; j < deg; ++j)
+                dst[(size_t)(base + j) * 64] = clampf(lam[var_lab(info, j)] - mc[j], C);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kUnrBlock) unrolled_forward_kernel(UnrArgs a)
+{
+    const int col = blockIdx.x * kUnrBlock + threadIdx.x;
+    Lane L;
+    L.wave = (size_t)(col >> 6);
+    L.lane = threadIdx.x & 63;
+    L.SI = (size_t)a.g.nnz + 3 * (size_t)a.g.n;
+    if ((int)L.wave >= a.waves) return;   // whole wavefront past the last shot
+    const bool have = col < a.shots;
+    const int n = a.g.n, E = a.g.nnz;
+    double loss = 0.0;
+    if (have) {
+        float *work = L.state(a.seg, 0, a.waves);
+        init_state(a, work);
+        float *ck0 = L.state(a.ckpt, 0, a.waves);
+        for (size_t i = 0; i < L.SI; ++i) ck0[i * 64] = work[i * 64];
+        for (int t = 1; t <= a.T; ++t) {
+            forward_iteration(a, t, work, work, col);
+            if (t % a.K == 0 && t < a.T) {
+                float *ck = L.state(a.ckpt, t / a.K, a.waves);
+                for (size_t i = 0; i < L.SI; ++i) ck[i * 64] = work[i * 64];
+            }
+        }
+        const uint8_t *e = a.err + (size_t)col * n;
+        for (int v = 0; v < n; ++v) {
+            float q[3], dq[3];
+            for (int x = 0; x < 3; ++x) q[x] = work[(size_t)(E + 3 * v + x) * 64];
+            loss += (double)qubit_loss(q, e[v] & 3u, dq);
+            if (a.q_out)
+                for (int x = 0; x < 3; ++x) a.q_out[((size_t)col * n + v) * 3 + x] = q[x];
+        }
+    }
+    loss = wave_sum(loss);
+    if (L.lane == 0) a.partial[L.wave * a.nout] = loss;
+}
+
+// Reverse sweep of iteration t.  cur: state t, prev: state t-1.  On entry the
+// adjoint holds dL/dm_{v->c}^{(t)} (gm) and dL/dQ^{(t)} (gQ, only the loss term
+// at t = T); on exit dL/dm_{v->c}^{(t-1)} and dL/dQ^{(t-1)}.  Returns this lane's
+// dL/dalpha_t.
+__device__ float reverse_iteration(const UnrArgs &a, int t, const float *cur, const float *prev, float *adj,
+                                   int shot)
+{
+    konst<uint32_t> *cedge = as_const(a.g.cedge);
+    konst<uint32_t> *vinfo = as_const(a.g.vinfo);
+    konst<float> *prior = as_const(a.prior);
+    const int m = a.g.m, n = a.g.n, E = a.g.nnz;
+    const float C = a.clamp;
+    float *gm = adj;
+    float *gQ = adj + (size_t)E * 64;
+    float *gP = adj + (size_t)(E + 3 * n) * 64;
+    const float al = a.alpha[t - 1];
+    float galpha = 0.0f;
+    // ---- qubit side: vertical update (t < T), then posterior and EWA prior ------
+    for (int v = 0; v < n; ++v) {
+        const uint32_t info = vinfo[v];
+        const uint32_t base = var_base(info), deg = var_deg(info);
+        float q[3], g[3];
+        for (int x = 0; x < 3; ++x) {
+            q[x] = cur[(size_t)(E + 3 * v + x) * 64];
+            g[x] = gQ[(size_t)(3 * v + x) * 64];
+        }
+        float gcv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (t < a.T) {
+            // m_{v->c} = clamp(lambda_H(Q) - m_{c->v}): lambda's partials, zero where clamped
+            for (uint32_t j = 0; j < deg; ++j) {
+                const size_t sl = (size_t)(base + j) * 64;
+                const float gj = gm[sl];
+                if (!(fabsf(cur[sl]) < C)) continue;
+                int h, ia, ib;
+                label_indices(var_lab(info, j), h, ia, ib);
+                g[h] -= gj * sigmoid(-q[h]);
+                g[ia] += gj * sigmoid(q[ib] - q[ia]);
+                g[ib] += gj * sigmoid(q[ia] - q[ib]);
+                gcv[j] = -gj;
+            }
+        }
+        // Q = Pi^{(t)} + M: each m_{c->v} enters the two components that anticommute with H
+        for (uint32_t j = 0; j < deg; ++j) {
+            int h, ia, ib;
+            label_indices(var_lab(info, j), h, ia, ib);
+            gm[(size_t)(base + j) * 64] = gcv[j] + g[ia] + g[ib];
+        }
+        // Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}  (t > 1), Pi^{(1)} = Pi^{(0)}
+        for (int x = 0; x < 3; ++x) {
+            const size_t i = (size_t)(3 * v + x) * 64;
+            if (t == 1) {
+                gP[i] += g[x];
+                gQ[i] = 0.0f;
+            } else {
+                const float p0 = prior[3 * v + x];
+                galpha = fmaf(g[x], p0 - prev[(size_t)(E + 3 * v + x) * 64], galpha);
+                gP[i] = fmaf(al, g[x], gP[i]);
+                gQ[i] = (1.0f - al) * g[x];
+            }
+        }
+    }
+    // ---- check side: m_{c->v} = clamp(sign * phi(sum_{v' != v} phi(|m_{v'->c}|))) ----
+    const uint8_t *s = a.synd + (size_t)shot * m;
+    for (int c = 0; c < m; ++c) {
+        uint32_t w[4];
+        float mv[4], f[4], gout[4];
+        uint32_t sgn[4];
+        uint32_t neg = s[c] & 1u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            w[j] = cedge[kMaxCheckDeg * c + j];
+            const bool pad = edge_is_pad(w[j]);
+            const size_t sl = (size_t)edge_slot(w[j]) * 64;
+            mv[j] = pad ? INFINITY : prev[sl];
+            gout[j] = pad ? 0.0f : gm[sl];
+            sgn[j] = mv[j] < 0.0f ? 1u : 0u;
+            neg ^= sgn[j];
+            f[j] = phi(fabsf(mv[j]));
+        }
+        const float loo[4] = {sum3_canonical(f[1], f[2], f[3]), sum3_canonical(f[0], f[2], f[3]),
+                              sum3_canonical(f[0], f[1], f[3]), sum3_canonical(f[0], f[1], f[2])};
+        float wsum[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float mag = phi(loo[j]);
+            const float sj = (neg ^ sgn[j]) ? -1.0f : 1.0f;
+            // the clamp passes the derivative only where it did not act
+            wsum[j] = (mag < C && gout[j] != 0.0f) ? gout[j] * sj * dphi(loo[j]) : 0.0f;
+        }
+        // leave-one-out sums formed directly: one term can exceed the others by many
+        // orders of magnitude (an output whose other inputs are all saturated), and
+        // subtracting it from the total would cancel the rest
+        const float others4[4] = {wsum[1] + wsum[2] + wsum[3], wsum[0] + wsum[2] + wsum[3],
+                                  wsum[0] + wsum[1] + wsum[3], wsum[0] + wsum[1] + wsum[2]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (edge_is_pad(w[k])) continue;
+            const float others = others4[k];
+            // a zero message has phi = inf: its outputs do not depend on it
+            const float gk = isinf(f[k]) ? 0.0f : (sgn[k] ? -1.0f : 1.0f) * dphi(fabsf(mv[k])) * others;
+            gm[(size_t)edge_slot(w[k]) * 64] = gk;
+        }
+    }
+    return galpha;
+}
+
+__global__ void __launch_bounds__(kUnrBlock) unrolled_backward_kernel(UnrArgs a)
+{
+    const int col = blockIdx.x * kUnrBlock + threadIdx.x;
+    Lane L;
+    L.wave = (size_t)(col >> 6);
+    L.lane = threadIdx.x & 63;
+    L.SI = (size_t)a.g.nnz + 3 * (size_t)a.g.n;
+    if ((int)L.wave >= a.waves) return;
+    const bool have = col < a.shots;
+    const int n = a.g.n, E = a.g.nnz;
+    float *adj = a.adj + L.wave * ((size_t)E + 6 * (size_t)n) * 64 + L.lane;
+    double *part = a.partial + L.wave * a.nout;
+    if (have)
+        for (size_t i = 0; i < (size_t)E + 6 * (size_t)n; ++i) adj[i * 64] = 0.0f;
+    for (int sg = a.nseg - 1; sg >= 0; --sg) {
+        const int t0 = sg * a.K;
+        const int t1 = t0 + a.K < a.T ? t0 + a.K : a.T;
+        if (have) {
+            // recompute the segment's states from its checkpoint
+            const float *ck = L.state(a.ckpt, sg, a.waves);
+            float *s0 = L.state(a.seg, 0, a.waves);
+            for (size_t i = 0; i < L.SI; ++i) s0[i * 64] = ck[i * 64];
+            for (int t = t0 + 1; t <= t1; ++t)
+                forward_iteration(a, t, L.state(a.seg, t - 1 - t0, a.waves), L.state(a.seg, t - t0, a.waves), col);
+            if (t1 == a.T) {
+                // dL/dQ^{(T)} of the soft loss (unscaled: the mean's 1/(shots n) comes last)
+                const float *sT = L.state(a.seg, t1 - t0, a.waves);
+                const uint8_t *e = a.err + (size_t)col * n;
+                for (int v = 0; v < n; ++v) {
+                    float q[3], dq[3];
+                    for (int x = 0; x < 3; ++x) q[x] = sT[(size_t)(E + 3 * v + x) * 64];
+                    qubit_loss(q, e[v] & 3u, dq);
+                    for (int x = 0; x < 3; ++x) adj[(size_t)(E + 3 * v + x) * 64] = dq[x];
+                }
+            }
+        }
+        for (int t = t1; t > t0; --t) {
+            float ga = 0.0f;
+            if (have)
+                ga = reverse_iteration(a, t, L.state(a.seg, t - t0, a.waves), L.state(a.seg, t - 1 - t0, a.waves),
+                                       adj, col);
+            const double tot = wave_sum((double)ga);
+            if (L.lane == 0) part[t - 1] = t == 1 ? 0.0 : tot;
+        }
+    }
+    // ---- initialisation: m^{(0)}_{v->c} = clamp(lambda_H(Pi^{(0)})) ----------------
+    konst<uint32_t> *vinfo = as_const(a.g.vinfo);
+    konst<float> *prior = as_const(a.prior);
+    float *gm = adj;
+    float *gP = adj + (size_t)(E + 3 * n) * 64;
+    for (int v = 0; v < n; ++v) {
+        float g[3] = {0.0f, 0.0f, 0.0f};
+        if (have) {
+            const uint32_t info = vinfo[v];
+            const uint32_t base = var_base(info), deg = var_deg(info);
+            const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
+            float lam[4];
+            qubit_lambdas(p3, var_labels_present(info), lam);
+            for (int x = 0; x < 3; ++x) g[x] = gP[(size_t)(3 * v + x) * 64];
+            for (uint32_t j = 0; j < deg; ++j) {
+                const uint32_t lab = var_lab(info, j);
+                if (!(fabsf(lam[lab]) < a.clamp)) continue;
+                const float gj = gm[(size_t)(base + j) * 64];
+                int h, ia, ib;
+                label_indices(lab, h, ia, ib);
+                g[h] -= gj * sigmoid(-p3[h]);
+                g[ia] += gj * sigmoid(p3[ib] - p3[ia]);
+                g[ib] += gj * sigmoid(p3[ia] - p3[ib]);
+            }
+        }
+        for (int x = 0; x < 3; ++x) {
+            const double tot = wave_sum((double)g[x]);
+            if (L.lane == 0) part[a.T + 3 * v + x] = tot;
+        }
+    }
+}
+
+// out[i] = scale * (*dloss) * sum over wavefronts of partial[w][i], in wavefront order.
+__global__ void __launch_bounds__(256) unrolled_reduce_kernel(const double *partial, int waves, int nout, double scale,
+                                                            const float *dloss, double *out0, int n0, double *out1)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nout) return;
+    double s = 0.0;
+    for (int w = 0; w < waves; ++w) s += partial[(size_t)w * nout + i];
+    s *= scale * (dloss ? (double)*dloss : 1.0);
+    if (i < n0) out0[i] = s;
+    else out1[i - n0] = s;
+}
+
+}  // namespace
+
+static size_t up256u(size_t x) { return (x + 255) & ~size_t(255); }
+
+UnrolledSizes unrolled_sizes(int m, int n, int nnz, int32_t T, int32_t K, int64_t shots)
+{
+    (void)m;
+    UnrolledSizes z;
+    const size_t lanes = (size_t)((shots + kUnrBlock - 1) / kUnrBlock) * kUnrBlock;
+    const size_t waves = lanes / 64;
+    const size_t SI = (size_t)nnz + 3 * (size_t)n;
+    const size_t nseg = (size_t)((T + K - 1) / K);
+    z.saved = up256u(nseg * waves * SI * 64 * 4);
+    z.ws = up256u((size_t)(K + 1) * waves * SI * 64 * 4) + up256u(waves * ((size_t)nnz + 6 * (size_t)n) * 64 * 4) +
+           up256u(waves * (size_t)(T + 3 * n) * 8);
+    return z;
+}
+
+static UnrArgs unrolled_args(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots, const float *alpha,
+                             const float *prior, const uint8_t *synd, const uint8_t *err, void *saved, void *ws,
+                             int nout)
+{
+    UnrArgs a;
+    a.g = g;
+    a.alpha = alpha;
+    a.prior = prior;
+    a.synd = synd;
+    a.err = err;
+    a.shots = shots;
+    a.T = T;
+    a.K = K;
+    a.nseg = (T + K - 1) / K;
+    a.nout = nout;
+    a.clamp = clamp;
+    a.q_out = nullptr;
+    const size_t lanes = (size_t)((shots + kUnrBlock - 1) / kUnrBlock) * kUnrBlock;
+    const size_t waves_alloc = lanes / 64;
+    const size_t SI = (size_t)g.nnz + 3 * (size_t)g.n;
+    a.ckpt = static_cast<float *>(saved);
+    char *w = static_cast<char *>(ws);
+    a.seg = reinterpret_cast<float *>(w);
+    w += up256u((size_t)(K + 1) * waves_alloc * SI * 64 * 4);
+    a.adj = reinterpret_cast<float *>(w);
+    w += up256u(waves_alloc * ((size_t)g.nnz + 6 * (size_t)g.n) * 64 * 4);
+    a.partial = reinterpret_cast<double *>(w);
+    // every allocated wavefront runs (those past the last shot contribute zeros)
+    a.waves = (int)waves_alloc;
+    return a;
+}
+
+hipError_t launch_unrolled_forward(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots,
+                                   const float *alpha, const float *prior, const uint8_t *synd, const uint8_t *err,
+                                   double *loss, float *q_out, void *saved, void *ws, hipStream_t s)
+{
+    UnrArgs a = unrolled_args(g, T, K, clamp, shots, alpha, prior, synd, err, saved, ws, 1);
+    a.q_out = q_out;
+    const unsigned blocks = (unsigned)((shots + kUnrBlock - 1) / kUnrBlock);
+    hipLaunchKernelGGL(unrolled_forward_kernel, dim3(blocks), dim3(kUnrBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double scale = 1.0 / ((double)shots * (double)g.n);
+    hipLaunchKernelGGL(unrolled_reduce_kernel, dim3(1), dim3(256), 0, s, a.partial, a.waves, 1, scale,
+                       (const float *)nullptr, loss, 1, (double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_unrolled_backward(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots,
+                                    const float *alpha, const float *prior, const uint8_t *synd, const uint8_t *err,
+                                    const float *dloss, const void *saved, double *dalpha, double *dprior, void *ws,
+                                    hipStream_t s)
+{
+    const int nout = T + 3 * g.n;
+    UnrArgs a = unrolled_args(g, T, K, clamp, shots, alpha, prior, synd, err, const_cast<void *>(saved), ws, nout);
+    const unsigned blocks = (unsigned)((shots + kUnrBlock - 1) / kUnrBlock);
+    hipLaunchKernelGGL(unrolled_backward_kernel, dim3(blocks), dim3(kUnrBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double scale = 1.0 / ((double)shots * (double)g.n);
+    hipLaunchKernelGGL(unrolled_reduce_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, a.partial, a.waves, nout,
+                       scale, dloss, dalpha, T, dprior);
+    return hipGetLastError();
+}
+
+}  // namespace bp4

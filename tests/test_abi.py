@@ -212,3 +212,34 @@ def test_mixed_rejects_soa_only_codes(lib):
                             fake.value, fake.value, fake.value, fake.value, 0, 0)
     assert lib.bp4_decode_mixed(1, arr, fake, 4096, None) == -6
     assert b"SOA" in lib.bp4_last_error()
+
+
+def test_unrolled_sizes_and_validation(lib):
+    from paper_2407_11523_amd import Graph
+    c = qecgen.planar(9)
+    g = Graph(c.hx, c.hz, upload=False)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.bp4_unrolled_sizes(g.handle, 32, 8, 1 << 16, ctypes.byref(a), ctypes.byref(b)) == 0
+    state = (544 + 3 * 145) * 4 * (1 << 16)          # messages + posteriors per shot, 65,536 shots
+    assert a.value == 4 * state                       # checkpoints at t = 0, 8, 16, 24
+    assert b.value >= 9 * state                       # one segment: its first state and 8 more
+    a2, b2 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.bp4_unrolled_sizes(g.handle, 32, 32, 1 << 16, ctypes.byref(a2), ctypes.byref(b2)) == 0
+    assert a2.value == state and b2.value > b.value   # fewer checkpoints, longer segment
+    for T, K, shots in ((0, 8, 10), (8, 0, 10), (8, 4, 0)):
+        assert lib.bp4_unrolled_sizes(g.handle, T, K, shots, ctypes.byref(a), ctypes.byref(b)) == -1
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    # undersized buffers and bad arguments fail before any launch
+    rc = lib.bp4_unrolled_forward(g.handle, fake, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, fake, null,
+                                  fake, 1024, fake, 1 << 40, null)
+    assert rc == -4
+    rc = lib.bp4_unrolled_forward(g.handle, fake, 32, 8, 0.0, 1 << 16, fake, fake, fake, fake, fake, null,
+                                  fake, 1 << 40, fake, 1 << 40, null)
+    assert rc == -1
+    rc = lib.bp4_unrolled_backward(g.handle, fake, 32, 8, 30.0, 1 << 16, fake, fake, fake, null, null, fake,
+                                   1 << 40, fake, fake, fake, 1 << 40, null)
+    assert rc == -1
+    rc = lib.bp4_unrolled_backward(g.handle, fake, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, null, fake,
+                                   1 << 40, fake, fake, fake, 64, null)
+    assert rc == -4
