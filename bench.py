@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--tuning-cache", default=None, help="autotuner cache file (default: the package's)")
     ap.add_argument("--no-tune", action="store_true", help="use the default lanes-per-shot pick")
     ap.add_argument("--no-large", action="store_true", help="skip the large-code (SOA) measurement")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the step")
+    ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/adjoint measurement")
     ap.add_argument("--only-large", action="store_true", help="run only the large-code (SOA) measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
@@ -223,6 +225,25 @@ def main():
         "ler": ler,
     }
 
+    if not args.no_graph:
+        # the same step recorded once as a HIP graph and replayed
+        snap = [(o["est"].clone(), o["iters"].clone(), it["counts"].clone()) for it, o in zip(items, batch.outs)]
+        cap = P.Captured(lambda: step(False))
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(args.steps):
+            cap.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        gms = g0.elapsed_time(g1) / args.steps
+        same = all(torch.equal(a, o["est"]) and torch.equal(b, o["iters"]) and torch.equal(c, it["counts"])
+                   for (a, b, c), it, o in zip(snap, items, batch.outs))
+        out["graph"] = {"ms_per_step": gms, "value": total_shots / (gms / 1e3), "identical_to_eager": bool(same)}
+        log(f"graph replay {gms:.2f} ms per step, identical outputs: {same}")
+        del cap
+
     if not args.no_plain:
         plain_ms = 0.0
         same = True
@@ -275,6 +296,9 @@ def main():
         out["oracle_ci"] = ci
         log(f"oracle {tot_shots / tot_t:.0f} shots/s on {threads} threads")
 
+    if not args.no_unrolled:
+        out["unrolled"] = run_unrolled(torch, qecgen, P, dev)
+
     if not args.no_large:
         del batch, items
         torch.cuda.empty_cache()
@@ -282,6 +306,39 @@ def main():
 
     out["wall_s"] = wall
     print(json.dumps(out), flush=True)
+
+
+def run_unrolled(torch, qecgen, P, dev):
+    """Unrolled EWAInit forward + adjoint: planar d=9, p=0.06, 65,536 shots, T=32, checkpoints every 8."""
+    code = qecgen.planar(9)
+    T, K, shots, p = 32, 8, 1 << 16, 0.06
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
+    err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=qecgen.config_seed(4, 0, 0))
+    alpha = torch.full((T,), ALPHA, dtype=torch.float32, device=dev, requires_grad=True)
+    prior = P.prior_llr(qecgen.depolarizing_probs(code.n, p), device=dev).clone().requires_grad_(True)
+    times = []
+    for rep in range(3):
+        alpha.grad = None
+        prior.grad = None
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        c = torch.cuda.Event(enable_timing=True)
+        a.record()
+        loss = P.unrolled_loss(g, alpha, prior, syn, err, T, K)
+        b.record()
+        loss.backward()
+        c.record()
+        torch.cuda.synchronize()
+        times.append((a.elapsed_time(b), b.elapsed_time(c)))
+    fwd, bwd = min(times, key=lambda x: x[0] + x[1])
+    eu = shots * T * g.nnz
+    log(f"unrolled: forward {fwd:.2f} ms, backward {bwd:.2f} ms")
+    return {"workload": "planar d=9, p=0.06, 65,536 shots, T=32 unrolled EWAInit iterations, checkpoints every 8, "
+                        "loss and gradients w.r.t. alpha_t and the priors",
+            "forward_ms": fwd, "backward_ms": bwd, "loss": float(loss.detach()),
+            "shots_per_s_forward_backward": shots / ((fwd + bwd) / 1e3),
+            "edge_updates_per_s_forward": eu / (fwd / 1e3),
+            "grad_alpha_norm": float(alpha.grad.norm()), "grad_prior_norm": float(prior.grad.norm())}
 
 
 def run_large(torch, qecgen, P, dev):

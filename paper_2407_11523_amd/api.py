@@ -109,6 +109,13 @@ class Graph:
         check(self._lib.bp4_workspace_bytes(self._h, ctypes.byref(cp), int(shots), ctypes.byref(b)))
         return int(b.value)
 
+    def soa_workspace_bytes(self, params: Params, shots: int, soa_lanes: int = 0) -> int:
+        b = ctypes.c_size_t()
+        cp = params.c()
+        check(self._lib.bp4_soa_workspace_bytes(self._h, ctypes.byref(cp), int(shots), int(soa_lanes),
+                                                ctypes.byref(b)))
+        return int(b.value)
+
     @property
     def handle(self):
         return self._h
@@ -175,10 +182,7 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
     cp = params.c()
     if ws is None:
         if kernel == "soa" or soa_lanes or soa_iter_block:
-            b = ctypes.c_size_t()
-            check(g._lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(cp), shots, int(soa_lanes),
-                                                 ctypes.byref(b)))
-            nbytes = int(b.value)
+            nbytes = g.soa_workspace_bytes(params, shots, soa_lanes)
         else:
             nbytes = g.workspace_bytes(params, shots)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -289,6 +293,30 @@ def decode_plain(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tens
                                   _stream(dev), ctypes.byref(it)))
     res["iterations_run"] = int(it.value)
     return res
+
+
+class Captured:
+    """Library calls recorded once as a HIP graph (torch.cuda.CUDAGraph) and replayed.
+
+    fn issues library calls on the current stream with buffers that outlive the
+    graph; inputs written into those buffers between replays are what the next
+    replay reads.  decode (both kernels, and the SOA kernel's iteration blocks with
+    their packing steps), decode_mixed, sample, bookkeep and the unrolled forward and
+    backward launch kernels only (queue heads and counters are cleared by a fill
+    kernel, never by a memset), so they can be captured; decode_plain cannot (its host
+    loop reads a device counter every iteration)."""
+
+    def __init__(self, fn, warmup: int = 1):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.result = fn()
+
+    def replay(self):
+        self.graph.replay()
+        return self.result
 
 
 # ---------------------------------------------------------------------------
