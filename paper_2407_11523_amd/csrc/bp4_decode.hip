@@ -239,7 +239,8 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
     }
 }
 
-__global__ void __launch_bounds__(kBlock)
+// At most 96 VGPRs, so five wavefronts fit per SIMD (97 would leave four).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 decode_lds_kernel(MixedArgs args)
 {
     extern __shared__ float lds[];
