@@ -35,7 +35,9 @@ constexpr int kBlock = 256;
 
 // MW: groups of 128 or 256 lanes spanning wavefronts (workgroup barriers);
 // otherwise G in {4, ..., 64} lanes inside one wavefront (wavefront-level sync).
-template <bool MW>
+// VAR: the code's variant as a compile-time constant, so the qubit update keeps only
+// its own branch.
+template <bool MW, int VAR>
 __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *bcast, int *badflag)
 {
     const int G = a.group_lanes;
@@ -54,12 +56,12 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
     uint8_t *ehat = reinterpret_cast<uint8_t *>(msg + a.ehat_off);
 
     const float C = a.clamp;
-    const int variant = a.variant;
+    constexpr int variant = VAR;
     const bool keep_q = variant != BP4_BP;
     const bool keep_acc = variant == BP4_MOMENTUM || variant == BP4_ADAGRAD;
     const bool with_y = a.with_y != 0;
     VariantParams vp;
-    vp.variant = variant;
+    vp.variant = VAR;
     vp.g_from_t1 = a.g_from_t1;
     vp.alpha = a.alpha;
     vp.gamma = a.gamma;
@@ -239,7 +241,20 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
     }
 }
 
-// At most 96 VGPRs, so five wavefronts fit per SIMD (97 would leave four).
+template <bool MW>
+__device__ __forceinline__ void run_any(const DecodeArgs &a, float *lds, int *bcast, int *badflag)
+{
+    switch (a.variant) {
+    case BP4_BP: run_code<MW, BP4_BP>(a, lds, bcast, badflag); break;
+    case BP4_MOMENTUM: run_code<MW, BP4_MOMENTUM>(a, lds, bcast, badflag); break;
+    case BP4_ADAGRAD: run_code<MW, BP4_ADAGRAD>(a, lds, bcast, badflag); break;
+    default: run_code<MW, BP4_EWAINIT>(a, lds, bcast, badflag); break;
+    }
+}
+
+// VSET: the variant every code of the launch uses, or -1 for a launch that mixes
+// variants (a switch per code).  At most 96 VGPRs, so five wavefronts fit per SIMD.
+template <int VSET>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 decode_lds_kernel(MixedArgs args)
 {
@@ -263,8 +278,15 @@ decode_lds_kernel(MixedArgs args)
         for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
         __syncthreads();
-        if (a.group_lanes > 64) run_code<true>(a, lds, bcast, badflag);
-        else run_code<false>(a, lds, bcast, badflag);
+        const bool mw = a.group_lanes > 64;
+        if (VSET < 0) {
+            if (mw) run_any<true>(a, lds, bcast, badflag);
+            else run_any<false>(a, lds, bcast, badflag);
+        } else {
+            constexpr int V = VSET < 0 ? BP4_EWAINIT : VSET;
+            if (mw) run_code<true, V>(a, lds, bcast, badflag);
+            else run_code<false, V>(a, lds, bcast, badflag);
+        }
         __syncthreads();
     }
 }
@@ -323,7 +345,8 @@ int decode_lds_pick_group(int m, int n, int nnz, int variant, size_t max_lds)
     return best;
 }
 
-hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_t s, int *grid_out)
+template <int VSET>
+static hipError_t launch_lds_kernel(const MixedArgs &args, size_t lds_bytes, hipStream_t s, int *grid_out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -331,7 +354,7 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
     int cus = 0, per_cu = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_lds_kernel, kBlock, lds_bytes);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_lds_kernel<VSET>, kBlock, lds_bytes);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long groups = 0;
@@ -344,8 +367,22 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
     if (groups < grid) grid = groups;
     if (grid < 1) grid = 1;
     if (grid_out) *grid_out = (int)grid;
-    hipLaunchKernelGGL(decode_lds_kernel, dim3((unsigned)grid), dim3(kBlock), lds_bytes, s, args);
+    hipLaunchKernelGGL(decode_lds_kernel<VSET>, dim3((unsigned)grid), dim3(kBlock), lds_bytes, s, args);
     return hipGetLastError();
+}
+
+hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_t s, int *grid_out)
+{
+    int v = args.codes[0].variant;
+    for (int i = 1; i < args.ncodes; ++i)
+        if (args.codes[i].variant != v) v = -1;
+    switch (v) {
+    case BP4_BP: return launch_lds_kernel<BP4_BP>(args, lds_bytes, s, grid_out);
+    case BP4_MOMENTUM: return launch_lds_kernel<BP4_MOMENTUM>(args, lds_bytes, s, grid_out);
+    case BP4_ADAGRAD: return launch_lds_kernel<BP4_ADAGRAD>(args, lds_bytes, s, grid_out);
+    case BP4_EWAINIT: return launch_lds_kernel<BP4_EWAINIT>(args, lds_bytes, s, grid_out);
+    default: return launch_lds_kernel<-1>(args, lds_bytes, s, grid_out);
+    }
 }
 
 }  // namespace bp4

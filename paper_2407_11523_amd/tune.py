@@ -23,8 +23,8 @@ from .api import Graph, Params, decode
 PKG = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(PKG, "tuning_cache.json")
 GROUP_SIZES = (4, 8, 16, 32, 64, 128, 256)
-# LDS per workgroup that leaves 5, 4, 3 and 2 workgroups (20, 16, 12, 8 wavefronts) per CU
-BUDGETS = (32768, 40960, 54613, 81920)
+# LDS per workgroup that leaves 7, 6, 5, 4, 3 and 2 workgroups (28 ... 8 wavefronts) per CU
+BUDGETS = (23405, 27306, 32768, 40960, 54613, 81920)
 
 
 def layout_bytes(g: Graph, params: Params, lanes: int) -> Optional[int]:
