@@ -74,6 +74,7 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
 
     uint64_t sbits = 0;
     int t = 0;
+    int par = 0;   // flag slot of this iteration (MW)
 
     // Initialisation (eq. init, Algorithm 2): m^{(0)}_{v->c} = lambda_{H_cv}(Pi^{(0)}_v);
     // Q^{(0)} = Pi^{(0)}; momentum and squared-gradient accumulators start at 0.
@@ -203,11 +204,14 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
         }
         bool sat;
         if (MW) {
-            if (bad) badflag[gid] = 1;
+            // Two flag slots per group, alternating by iteration: slot `par` is set now
+            // and read after the barrier; the other slot, last read one iteration ago
+            // (behind the barriers since), is cleared for the next iteration.
+            if (bad) badflag[par * (kBlock / 128) + gid] = 1;
             __syncthreads();
-            sat = badflag[gid] == 0;
-            __syncthreads();
-            if (r == 0) badflag[gid] = 0;
+            sat = badflag[par * (kBlock / 128) + gid] == 0;
+            if (r == 0) badflag[(par ^ 1) * (kBlock / 128) + gid] = 0;
+            par ^= 1;
         } else {
             const uint64_t ballot = __ballot(bad != 0);
             const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
@@ -223,21 +227,30 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
                 a.iters[shot] = t;
             }
         }
-        gsync();
         if (MW) {
+            // No barrier is needed before the refill: nothing reads the messages after
+            // the flag barrier, and the outputs read only the decisions, which init
+            // leaves alone.  The loop-top barrier publishes init's writes.
             if (fin && r == 0) bcast[gid] = take_shot(a.counter, a.shots);
             __syncthreads();
             if (fin) {
                 shot = bcast[gid];
                 if (shot < a.shots) init(shot);
             }
-        } else if (fin) {
-            int s0 = 0;
-            if (r == 0) s0 = take_shot(a.counter, a.shots);
-            shot = __shfl(s0, lead, 64);
-            if (shot < a.shots) init(shot);
+        } else {
+            gsync();
+            if (fin) {
+                int s0 = 0;
+                if (r == 0) s0 = take_shot(a.counter, a.shots);
+                shot = __shfl(s0, lead, 64);
+                if (shot < a.shots) init(shot);
+            }
+            gsync();
         }
-        gsync();
+    }
+    if (MW && r == 0) {   // leave both flag slots clear for the next code
+        badflag[gid] = 0;
+        badflag[kBlock / 128 + gid] = 0;
     }
 }
 
@@ -260,9 +273,9 @@ decode_lds_kernel(MixedArgs args)
 {
     extern __shared__ float lds[];
     __shared__ int bcast[kBlock / 128];
-    __shared__ int badflag[kBlock / 128];
+    __shared__ int badflag[2 * (kBlock / 128)];
     __shared__ int pending;
-    if (threadIdx.x < kBlock / 128) badflag[threadIdx.x] = 0;
+    if (threadIdx.x < 2 * (kBlock / 128)) badflag[threadIdx.x] = 0;
     for (int ci = 0; ci < args.ncodes; ++ci) {
         const DecodeArgs &a = args.codes[ci];
         // skip a code whose queue is already empty (a stale read only costs a visit)
