@@ -46,7 +46,9 @@ typedef enum {
     BP4_BP = 0,        /* traditional LLR-BP4, section II-B1 */
     BP4_MOMENTUM = 1,  /* Momentum-BP, parallel form, eqs. mombp1-mombp3 */
     BP4_ADAGRAD = 2,   /* AdaGrad-BP, eq. boost */
-    BP4_EWAINIT = 3    /* EWAInit-BP, eq. EWAInit, Algorithm 2 */
+    BP4_EWAINIT = 3,   /* EWAInit-BP, eq. EWAInit, Algorithm 2 */
+    BP4_AEWA = 4       /* AEWA-BP (appendix on adaptive MBP): EWAInit-BP restarted with the
+                          next discount of a list until the syndrome is met */
 } bp4_variant;
 
 /* Hyperparameters of one decode.
@@ -59,7 +61,14 @@ typedef enum {
  *   max_iter: iter_max >= 1.
  *   stop_on_syndrome: 1 halts a shot at the first iteration whose hard
  *          decision reproduces its syndrome (Algorithm 2); 0 runs max_iter.
- *   adagrad_g_from_t1: 1 also accumulates the squared gradient at t = 1. */
+ *   adagrad_g_from_t1: 1 also accumulates the squared gradient at t = 1.
+ *   alpha_last, alpha_steps (AEWA only): attempt k = 0 .. alpha_steps - 1 is a
+ *          fresh EWAInit decode of up to max_iter iterations with discount
+ *          alpha + (alpha_last - alpha) * k / (alpha_steps - 1) (alpha for a
+ *          single step); the first attempt that meets the syndrome is the
+ *          result, else the last one.  Both discounts in [0, 1], 1 <=
+ *          alpha_steps <= 64, stop_on_syndrome must be 1; `iters` reports the
+ *          iterations of all attempts.  Ignored by the other variants. */
 typedef struct {
     int32_t variant;
     int32_t max_iter;
@@ -69,6 +78,8 @@ typedef struct {
     float gamma;
     float eps;
     float llr_clamp;
+    float alpha_last;
+    int32_t alpha_steps;
 } bp4_params;
 
 /* Opaque host object describing one code's Tanner graph (section II-B1). */

@@ -184,7 +184,7 @@ static double clampd(double x, double c)
 /* Decoder                                                                    */
 /* ------------------------------------------------------------------------- */
 
-enum { OR_BP = 0, OR_MOMENTUM = 1, OR_ADAGRAD = 2, OR_EWAINIT = 3 };
+enum { OR_BP = 0, OR_MOMENTUM = 1, OR_ADAGRAD = 2, OR_EWAINIT = 3, OR_AEWA = 4 };
 
 /* AdaGrad gradients at or below this fraction of |D| + sum |m| count as 0. */
 #define ADAGRAD_DEADBAND 1.52587890625e-05   /* 2^-16 */
@@ -200,6 +200,8 @@ typedef struct {
     double clamp;               /* message magnitude bound C (INFINITY: none) */
     const double *alpha_t;      /* EWAInit: per-iteration discount, alpha_t[t - 1] at iteration t
                                    (entry 0 unused), or NULL for the constant alpha */
+    double alpha_last;          /* AEWA: discount of the last attempt */
+    int32_t alpha_steps;        /* AEWA: attempts; alpha_k = alpha + (alpha_last - alpha) k / (steps - 1) */
 } or_params;
 
 typedef struct {
@@ -396,6 +398,7 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
     if (m <= 0 || n <= 0 || !hx || !hz || !p || !pi0 || !synd || !est || !conv || !iters)
         return -1;
     if (p->max_iter < 1 || shots < 0) return -1;
+    if (p->variant == OR_AEWA && (p->alpha_steps < 1 || !p->stop_on_syndrome)) return -1;
     or_graph g;
     if (graph_build(m, n, hx, hz, &g)) return -1;
     or_outputs none = {0};
@@ -427,8 +430,29 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
             for (int64_t i = 0; i < shots; ++i) {
                 double *qt = o->q_trace ? o->q_trace + (size_t)i * p->max_iter * 3 * n : NULL;
                 double *mt = o->m_trace ? o->m_trace + (size_t)i * p->max_iter * 3 * n : NULL;
-                decode_one(&g, p, pi0, synd + (size_t)i * m, est + (size_t)i * n, conv + i,
-                           iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, mabs, ehat, qt, mt);
+                if (p->variant != OR_AEWA) {
+                    decode_one(&g, p, pi0, synd + (size_t)i * m, est + (size_t)i * n, conv + i,
+                               iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, mabs, ehat, qt, mt);
+                } else {
+                    /* AEWA-BP (appendix on adaptive MBP): EWAInit-BP with the discounts
+                     * alpha_0 .. alpha_{K-1}, each attempt a fresh decode, until one
+                     * satisfies the syndrome; the outputs are those of the last attempt
+                     * run and the iteration count is the total over the attempts. */
+                    or_params pk = *p;
+                    pk.variant = OR_EWAINIT;
+                    pk.alpha_t = NULL;
+                    int32_t total = 0;
+                    for (int k = 0; k < p->alpha_steps; ++k) {
+                        pk.alpha = p->alpha_steps > 1
+                                       ? p->alpha + (p->alpha_last - p->alpha) * (double)k / (double)(p->alpha_steps - 1)
+                                       : p->alpha;
+                        decode_one(&g, &pk, pi0, synd + (size_t)i * m, est + (size_t)i * n, conv + i,
+                                   iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, mabs, ehat, qt, mt);
+                        total += iters[i];
+                        if (conv[i]) break;
+                    }
+                    iters[i] = total;
+                }
                 if (o->q_out) memcpy(o->q_out + (size_t)i * 3 * n, q, sizeof(double) * 3 * n);
                 if (o->mvc_out) memcpy(o->mvc_out + (size_t)i * nnz, mvc, sizeof(double) * nnz);
                 if (o->mcv_out) memcpy(o->mcv_out + (size_t)i * nnz, mcv, sizeof(double) * nnz);

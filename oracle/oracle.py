@@ -21,8 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bp4_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-BP, MOMENTUM, ADAGRAD, EWAINIT = 0, 1, 2, 3
-VARIANTS = {"bp": BP, "momentum": MOMENTUM, "adagrad": ADAGRAD, "ewainit": EWAINIT}
+BP, MOMENTUM, ADAGRAD, EWAINIT, AEWA = 0, 1, 2, 3, 4
+VARIANTS = {"bp": BP, "momentum": MOMENTUM, "adagrad": ADAGRAD, "ewainit": EWAINIT, "aewa": AEWA}
 
 
 def build(force: bool = False) -> str:
@@ -39,7 +39,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("stop_on_syndrome", ctypes.c_int32), ("adagrad_g_from_t1", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("eps", ctypes.c_double), ("clamp", ctypes.c_double), ("alpha_t", ctypes.c_void_p)]
+                ("eps", ctypes.c_double), ("clamp", ctypes.c_double), ("alpha_t", ctypes.c_void_p),
+                ("alpha_last", ctypes.c_double), ("alpha_steps", ctypes.c_int32)]
 
 
 class _Outputs(ctypes.Structure):
@@ -100,11 +101,13 @@ class Params:
     eps: float = 1e-8
     clamp: float = 30.0
     alpha_t: Optional[np.ndarray] = None   # EWAInit per-iteration discount, entry t-1 at iteration t
+    alpha_last: float = 0.0                # AEWA: discount of the last attempt (alpha is the first)
+    alpha_steps: int = 11                  # AEWA: number of attempts
 
     def c(self) -> _Params:
         cp = _Params(VARIANTS[self.variant], int(self.max_iter), int(bool(self.stop_on_syndrome)),
                      int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
-                     float(self.eps), float(self.clamp), None)
+                     float(self.eps), float(self.clamp), None, float(self.alpha_last), int(self.alpha_steps))
         if self.alpha_t is not None:
             a = np.ascontiguousarray(self.alpha_t, dtype=np.float64)
             if a.shape != (self.max_iter,):

@@ -15,7 +15,7 @@ import torch
 
 from ._lib import BP4Error, CodeBatch as _CCodeBatch, Params as _CParams, Tuning as _CTuning, check, load
 
-VARIANTS = {"bp": 0, "momentum": 1, "adagrad": 2, "ewainit": 3}
+VARIANTS = {"bp": 0, "momentum": 1, "adagrad": 2, "ewainit": 3, "aewa": 4}
 ALLOW_ANTICOMMUTING = 1
 
 
@@ -42,11 +42,13 @@ class Params:
     gamma: float = 0.0
     eps: float = 1e-8
     llr_clamp: float = 30.0
+    alpha_last: float = 0.0   # AEWA: discount of the last attempt (alpha is the first)
+    alpha_steps: int = 11     # AEWA: number of attempts
 
     def c(self) -> _CParams:
         return _CParams(VARIANTS[self.variant], int(self.max_iter), int(bool(self.stop_on_syndrome)),
                         int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
-                        float(self.eps), float(self.llr_clamp))
+                        float(self.eps), float(self.llr_clamp), float(self.alpha_last), int(self.alpha_steps))
 
 
 class Graph:

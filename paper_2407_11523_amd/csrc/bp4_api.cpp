@@ -341,11 +341,17 @@ namespace {
 int check_params(const bp4_params *p)
 {
     if (!p) return fail(BP4_EINVAL, "params: NULL");
-    if (p->variant < BP4_BP || p->variant > BP4_EWAINIT) return fail(BP4_EINVAL, "params: variant %d", p->variant);
+    if (p->variant < BP4_BP || p->variant > BP4_AEWA) return fail(BP4_EINVAL, "params: variant %d", p->variant);
     if (p->max_iter < 1) return fail(BP4_EINVAL, "params: max_iter %d < 1", p->max_iter);
     if (!(p->llr_clamp > 0.0f) || !std::isfinite(p->llr_clamp)) return fail(BP4_EINVAL, "params: llr_clamp must be finite and > 0");
-    if (p->variant == BP4_MOMENTUM || p->variant == BP4_EWAINIT) {
+    if (p->variant == BP4_MOMENTUM || p->variant == BP4_EWAINIT || p->variant == BP4_AEWA) {
         if (!(p->alpha >= 0.0f && p->alpha <= 1.0f)) return fail(BP4_EINVAL, "params: alpha must lie in [0, 1]");
+    }
+    if (p->variant == BP4_AEWA) {
+        if (!(p->alpha_last >= 0.0f && p->alpha_last <= 1.0f))
+            return fail(BP4_EINVAL, "params: alpha_last must lie in [0, 1]");
+        if (p->alpha_steps < 1 || p->alpha_steps > 64) return fail(BP4_EINVAL, "params: alpha_steps outside [1, 64]");
+        if (!p->stop_on_syndrome) return fail(BP4_EINVAL, "params: AEWA restarts on a failed syndrome test: stop_on_syndrome must be 1");
     }
     if (p->variant == BP4_MOMENTUM && !(p->gamma >= 0.0f && p->gamma < 1.0f))
         return fail(BP4_EINVAL, "params: gamma must lie in [0, 1)");
@@ -394,6 +400,8 @@ void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, 
     a.gamma = p->gamma;
     a.eps = p->eps;
     a.clamp = p->llr_clamp;
+    a.alpha_last = p->alpha_last;
+    a.alpha_steps = p->alpha_steps;
     a.static_words = L.static_words;
     a.region_words = L.region_words;
     a.q_off = L.q_off;
@@ -665,6 +673,7 @@ int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params
     if (shots < 0 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "decode_plain: shots out of range");
     if (!prior_llr) return fail(BP4_EINVAL, "decode_plain: NULL prior");
     if (iterations_run) *iterations_run = 0;
+    if (p->variant == BP4_AEWA) return fail(BP4_EUNSUPPORTED, "decode_plain: AEWA restarts need the persistent kernels");
     if (shots == 0) return BP4_OK;
     if (!synd || !est || !conv || !iters || !ws) return fail(BP4_EINVAL, "decode_plain: NULL buffer");
     const size_t need = plain_workspace_bytes(g->n, g->nnz, p->variant, shots);

@@ -74,7 +74,9 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
 
     uint64_t sbits = 0;
     int t = 0;
-    int par = 0;   // flag slot of this iteration (MW)
+    int par = 0;       // flag slot of this iteration (MW)
+    int att = 0;       // AEWA: attempt of the current shot
+    int t_before = 0;  // AEWA: iterations of the shot's earlier attempts
 
     // Initialisation (eq. init, Algorithm 2): m^{(0)}_{v->c} = lambda_{H_cv}(Pi^{(0)}_v);
     // Q^{(0)} = Pi^{(0)}; momentum and squared-gradient accumulators start at 0.
@@ -217,15 +219,22 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
             const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
             sat = (ballot & gmask) == 0;
         }
-        const bool fin = live && ((a.stop && sat) || t >= a.max_iter);
+        // AEWA: a failed attempt restarts the shot with the next discount
+        const bool restart = VAR == BP4_AEWA && live && !sat && t >= a.max_iter && att + 1 < a.alpha_steps;
+        const bool fin = live && !restart && ((a.stop && sat) || t >= a.max_iter);
         if (fin) {
             for (int v = r; v < n; v += G) {
                 a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(ehat[v]);
             }
             if (r == 0) {
                 a.conv[shot] = sat ? 1 : 0;
-                a.iters[shot] = t;
+                a.iters[shot] = t_before + t;
             }
+        }
+        if (VAR == BP4_AEWA && (fin || restart)) {
+            t_before = restart ? t_before + t : 0;
+            att = restart ? att + 1 : 0;
+            vp.alpha = aewa_alpha(a.alpha, a.alpha_last, a.alpha_steps, att);
         }
         if (MW) {
             // No barrier is needed before the refill: nothing reads the messages after
@@ -236,6 +245,8 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
             if (fin) {
                 shot = bcast[gid];
                 if (shot < a.shots) init(shot);
+            } else if (restart) {
+                init(shot);
             }
         } else {
             gsync();
@@ -244,6 +255,8 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
                 if (r == 0) s0 = take_shot(a.counter, a.shots);
                 shot = __shfl(s0, lead, 64);
                 if (shot < a.shots) init(shot);
+            } else if (restart) {
+                init(shot);
             }
             gsync();
         }
@@ -261,6 +274,7 @@ __device__ __forceinline__ void run_any(const DecodeArgs &a, float *lds, int *bc
     case BP4_BP: run_code<MW, BP4_BP>(a, lds, bcast, badflag); break;
     case BP4_MOMENTUM: run_code<MW, BP4_MOMENTUM>(a, lds, bcast, badflag); break;
     case BP4_ADAGRAD: run_code<MW, BP4_ADAGRAD>(a, lds, bcast, badflag); break;
+    case BP4_AEWA: run_code<MW, BP4_AEWA>(a, lds, bcast, badflag); break;
     default: run_code<MW, BP4_EWAINIT>(a, lds, bcast, badflag); break;
     }
 }
@@ -394,6 +408,7 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
     case BP4_MOMENTUM: return launch_lds_kernel<BP4_MOMENTUM>(args, lds_bytes, s, grid_out);
     case BP4_ADAGRAD: return launch_lds_kernel<BP4_ADAGRAD>(args, lds_bytes, s, grid_out);
     case BP4_EWAINIT: return launch_lds_kernel<BP4_EWAINIT>(args, lds_bytes, s, grid_out);
+    case BP4_AEWA: return launch_lds_kernel<BP4_AEWA>(args, lds_bytes, s, grid_out);
     default: return launch_lds_kernel<-1>(args, lds_bytes, s, grid_out);
     }
 }

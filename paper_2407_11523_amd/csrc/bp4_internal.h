@@ -57,6 +57,8 @@ struct DecodeArgs {
     int32_t shots;
     int32_t variant, max_iter, stop, g_from_t1;
     float alpha, gamma, eps, clamp;
+    float alpha_last;        // AEWA: discount of the last attempt
+    int32_t alpha_steps;     // AEWA: attempts
     // LDS layout (words): workgroup-static part, then one region per shot group
     int32_t static_words, region_words, q_off, acc_off, ehat_off;
     int32_t group_lanes;     // lanes per shot: 4, 8, 16, 32, 64, 128 or 256

@@ -140,6 +140,13 @@ __device__ __forceinline__ void label_sums(uint32_t info, const float mc[4], boo
     A[3] = a3;
 }
 
+// Discount of AEWA attempt k: alpha + (alpha_last - alpha) k / (steps - 1).
+__device__ __forceinline__ float aewa_alpha(float alpha, float alpha_last, int steps, int k)
+{
+#pragma clang fp contract(off)
+    return steps > 1 ? alpha + (alpha_last - alpha) * ((float)k / (float)(steps - 1)) : alpha;
+}
+
 // Hyperparameters a qubit update needs (section III).
 struct VariantParams {
     int32_t variant, g_from_t1;
@@ -177,7 +184,7 @@ __device__ __forceinline__ void qubit_posterior(const VariantParams &vp, int t, 
     if (vp.variant == BP4_BP) {
 #pragma unroll
         for (int x = 0; x < 3; ++x) qn[x] = pi[x] + M[x];
-    } else if (vp.variant == BP4_EWAINIT) {
+    } else if (vp.variant == BP4_EWAINIT || vp.variant == BP4_AEWA) {
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
             const float pit = t == 1 ? pi[x] : fmaf(vp.alpha, pi[x], (1.0f - vp.alpha) * st[x]);

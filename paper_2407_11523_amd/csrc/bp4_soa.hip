@@ -61,11 +61,15 @@ struct SoaArgs {
     uint32_t *dst;            // records of the shots still live after this block
     const int32_t *src_shot;  // shot of each source column (blocks after the first)
     int32_t *dst_shot;
+    const int32_t *src_tb;    // AEWA: iterations of the shot's earlier attempts, per column
+    int32_t *dst_tb;
     const unsigned int *src_count;   // live columns (blocks after the first)
     unsigned int *dst_count;  // zeroed before the launch
     uint8_t *ehat;            // [wavefront][n][64] decision bytes
     int32_t first_shot, first_count;   // first block: shots first_shot + column
     int32_t t0, t_end, max_iter, stop, with_y;
+    int32_t fresh;            // first block of the first attempt: columns are shots first_shot + column
+    int32_t last_attempt;     // a shot that fails this attempt is finished (else it restarts)
     float clamp;
     VariantParams vp;
     SoaLayout lay;
@@ -76,7 +80,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     const int col = blockIdx.x * kSoaBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const size_t wave = (size_t)(col >> 6);
-    const int count = a.t0 == 0 ? a.first_count : (int)*a.src_count;
+    const int count = a.fresh ? a.first_count : (int)*a.src_count;
     if ((int)(wave << 6) >= count) return;   // whole wavefront idle
     const bool have = col < count;
     const int m = a.g.m, n = a.g.n;
@@ -96,10 +100,12 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
     konst<float> *prior = as_const(a.prior);
 
-    const int shot = !have ? 0 : a.t0 == 0 ? a.first_shot + col : a.src_shot[col];
+    const int shot = !have ? 0 : a.fresh ? a.first_shot + col : a.src_shot[col];
+    const int t_before = have && !a.fresh ? a.src_tb[col] : 0;   // earlier AEWA attempts
     bool done = !have;
+    int t_end_shot = 0;
 
-    if (have && a.t0 == 0) {
+    if (have && a.t0 == 0) {   // first block of an attempt: a fresh decode of the shot
         // ---- Initialisation (eq. init): syndrome bits and m_{v->c} = lambda(Pi) ----
         uint32_t word = 0;
         for (int c = 0; c < m; ++c) {
@@ -227,10 +233,11 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                 }
             }
             const bool sat = bad == 0;
-            if ((a.stop && sat) || t >= a.max_iter) {
+            t_end_shot = t;
+            if ((a.stop && sat) || (t >= a.max_iter && a.last_attempt)) {
                 for (int v = 0; v < n; ++v) a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(ehat[(size_t)v * 64]);
                 a.conv[shot] = sat ? 1 : 0;
-                a.iters[shot] = t;
+                a.iters[shot] = t_before + t;
                 done = true;
                 break;
             }
@@ -250,6 +257,8 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
         uint32_t *drec = a.dst + (size_t)(dcol >> 6) * items * 64 + (dcol & 63u);
         for (size_t i = 0; i < items; ++i) drec[i * 64] = rec[i * 64];
         a.dst_shot[dcol] = shot;
+        // a shot that ran out of iterations goes on to its next AEWA attempt
+        a.dst_tb[dcol] = t_end_shot >= a.max_iter ? t_before + t_end_shot : t_before;
     }
 }
 
@@ -266,12 +275,19 @@ size_t soa_lanes(int64_t shots, int32_t requested)
 
 static size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// The device formula of the AEWA discount, evaluated on the host in the same FP32 steps.
+static float aewa_alpha_host(float alpha, float alpha_last, int steps, int k)
+{
+#pragma clang fp contract(off)
+    return steps > 1 ? alpha + (alpha_last - alpha) * ((float)k / (float)(steps - 1)) : alpha;
+}
+
 // Workspace: two counters, two record buffers, two shot-id arrays, the decisions.
 size_t soa_workspace_bytes(int m, int n, int nnz, int variant, int64_t shots, int32_t lanes)
 {
     const size_t L = soa_lanes(shots, lanes);
     const SoaLayout lay = soa_layout(m, n, nnz, variant);
-    return 256 + 2 * up256(L * (size_t)lay.items * 4) + 2 * up256(L * 4) + up256(L * (size_t)n);
+    return 256 + 2 * up256(L * (size_t)lay.items * 4) + 4 * up256(L * 4) + up256(L * (size_t)n);
 }
 
 hipError_t launch_decode_soa(const GraphView &g, const bp4_params &p, int32_t shots, const float *prior,
@@ -293,6 +309,11 @@ hipError_t launch_decode_soa(const GraphView &g, const bp4_params &p, int32_t sh
     shot_ids[0] = reinterpret_cast<int32_t *>(w);
     w += up256(L * 4);
     shot_ids[1] = reinterpret_cast<int32_t *>(w);
+    w += up256(L * 4);
+    int32_t *tbs[2];
+    tbs[0] = reinterpret_cast<int32_t *>(w);
+    w += up256(L * 4);
+    tbs[1] = reinterpret_cast<int32_t *>(w);
     w += up256(L * 4);
     uint8_t *ehat = reinterpret_cast<uint8_t *>(w);
 
@@ -318,27 +339,36 @@ hipError_t launch_decode_soa(const GraphView &g, const bp4_params &p, int32_t sh
     a.vp.eps = p.eps;
     a.lay = lay;
     const int32_t B = iter_block > 0 ? iter_block : kSoaIterBlock;
+    // AEWA runs its attempts one after another over the shots still unsolved
+    const int32_t attempts = p.variant == BP4_AEWA ? p.alpha_steps : 1;
     for (int64_t first = 0; first < shots; first += (int64_t)L) {
         const int32_t cnt = (int32_t)((int64_t)shots - first < (int64_t)L ? (int64_t)shots - first : (int64_t)L);
         const unsigned blocks = (unsigned)((cnt + kSoaBlock - 1) / kSoaBlock);
         a.first_shot = (int32_t)first;
         a.first_count = cnt;
         int cur = 0;
-        for (int32_t t0 = 0; t0 < p.max_iter; t0 += B) {
-            a.t0 = t0;
-            a.t_end = t0 + B < p.max_iter ? t0 + B : p.max_iter;
-            a.src = recs[cur];
-            a.dst = recs[cur ^ 1];
-            a.src_shot = shot_ids[cur];
-            a.dst_shot = shot_ids[cur ^ 1];
-            a.src_count = counters + cur;
-            a.dst_count = counters + (cur ^ 1);
-            hipError_t e = launch_zero_u32(counters + (cur ^ 1), 1, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(decode_soa_kernel, dim3(blocks), dim3(kSoaBlock), 0, s, a);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            cur ^= 1;
+        for (int32_t k = 0; k < attempts; ++k) {
+            a.last_attempt = k + 1 == attempts ? 1 : 0;
+            if (p.variant == BP4_AEWA) a.vp.alpha = aewa_alpha_host(p.alpha, p.alpha_last, p.alpha_steps, k);
+            for (int32_t t0 = 0; t0 < p.max_iter; t0 += B) {
+                a.fresh = (k == 0 && t0 == 0) ? 1 : 0;
+                a.t0 = t0;
+                a.t_end = t0 + B < p.max_iter ? t0 + B : p.max_iter;
+                a.src = recs[cur];
+                a.dst = recs[cur ^ 1];
+                a.src_shot = shot_ids[cur];
+                a.dst_shot = shot_ids[cur ^ 1];
+                a.src_tb = tbs[cur];
+                a.dst_tb = tbs[cur ^ 1];
+                a.src_count = counters + cur;
+                a.dst_count = counters + (cur ^ 1);
+                hipError_t e = launch_zero_u32(counters + (cur ^ 1), 1, s);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(decode_soa_kernel, dim3(blocks), dim3(kSoaBlock), 0, s, a);
+                e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                cur ^= 1;
+            }
         }
     }
     return hipSuccess;

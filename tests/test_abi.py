@@ -243,3 +243,16 @@ def test_unrolled_sizes_and_validation(lib):
     rc = lib.bp4_unrolled_backward(g.handle, fake, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, null, fake,
                                    1 << 40, fake, fake, fake, 64, null)
     assert rc == -4
+
+
+def test_aewa_parameter_validation(lib):
+    from paper_2407_11523_amd import Graph, Params
+    g = Graph(qecgen.planar(5).hx, qecgen.planar(5).hz, upload=False)
+    ok = Params(variant="aewa", alpha=1.0, alpha_last=0.0, alpha_steps=11)
+    assert g.workspace_bytes(ok, 10) == 256
+    for bad in (Params(variant="aewa", alpha_steps=0), Params(variant="aewa", alpha_steps=65),
+                Params(variant="aewa", alpha_last=1.5), Params(variant="aewa", alpha=-0.1),
+                Params(variant="aewa", stop_on_syndrome=False)):
+        assert _err(lambda: g.workspace_bytes(bad, 10)) == "EINVAL"
+    # the other variants ignore the AEWA fields
+    assert g.workspace_bytes(Params(variant="ewainit", alpha=0.5, alpha_steps=0, alpha_last=7.0), 10) == 256
