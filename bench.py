@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the large-code (SOA) measurement")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the step")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/adjoint measurement")
+    ap.add_argument("--no-aewa", action="store_true", help="skip the AEWA-BP vs EWAInit-BP timing")
     ap.add_argument("--only-large", action="store_true", help="run only the large-code (SOA) measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
@@ -299,6 +300,10 @@ def main():
     if not args.no_unrolled:
         out["unrolled"] = run_unrolled(torch, qecgen, P, dev)
 
+    if not args.no_aewa:
+        out["aewa"] = run_aewa(torch, qecgen, P, dev)
+        out["biased_xzzx"] = run_biased(torch, qecgen, P, dev)
+
     if not args.no_large:
         del batch, items
         torch.cuda.empty_cache()
@@ -306,6 +311,80 @@ def main():
 
     out["wall_s"] = wall
     print(json.dumps(out), flush=True)
+
+
+# Table II of the paper (runtime per decode on planar codes, hardware not stated):
+# EWAInit-BP and AEWA-BP in ms at physical error rates 1e-2, 6e-2, 1e-1, 2e-1.
+PAPER_TABLE2 = {0.01: (1.1, 1.6), 0.06: (3.7, 27.9), 0.10: (7.7, 81.9), 0.20: (20.1, 240.6)}
+
+
+def run_aewa(torch, qecgen, P, dev):
+    """EWAInit-BP (alpha 0.5) and AEWA-BP (11 discounts 1 .. 0) on planar d=3, 7, 11, 2^16
+    shots each, iter_max 100, at the physical error rates of the paper's Table II."""
+    shots = 1 << 16
+    res = {"workload": "planar d=3, 7, 11, 2^16 shots each, iter_max 100, EWAInit alpha 0.5 vs AEWA 11 discounts "
+                       "from 1 to 0, at the error rates of the paper's Table II",
+           "rows": []}
+    for p in sorted(PAPER_TABLE2):
+        thr = qecgen.thresholds(p / 3, p / 3, p / 3)
+        row = {"p": p, "paper_ms": {"ewainit": PAPER_TABLE2[p][0], "aewa": PAPER_TABLE2[p][1]}}
+        tot = {"ewainit": 0.0, "aewa": 0.0}
+        for i, d in enumerate((3, 7, 11)):
+            code = qecgen.planar(d)
+            g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
+            pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p), device=dev)
+            err, syn = P.sample(g, shots, thr, seed=qecgen.config_seed(6, i, int(p * 100)))
+            for name, prm in (("ewainit", P.Params(variant="ewainit", alpha=ALPHA, max_iter=100)),
+                              ("aewa", P.Params(variant="aewa", alpha=1.0, alpha_last=0.0, alpha_steps=11,
+                                                max_iter=100))):
+                P.decode(g, prm, pr, syn[:1024])
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                r = P.decode(g, prm, pr, syn)
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b)
+                _, cnt = P.bookkeep(g, err, r["est"])
+                tot[name] += ms
+                row[f"d{d}_{name}"] = {"ms": ms, "syndromes_per_s": shots / (ms / 1e3),
+                                        "ler": float(cnt[1] + cnt[2]) / shots,
+                                        "avg_iters": float(r["iters"].float().mean())}
+        row["aewa_over_ewainit_time"] = tot["aewa"] / tot["ewainit"]
+        row["paper_aewa_over_ewainit_time"] = PAPER_TABLE2[p][1] / PAPER_TABLE2[p][0]
+        res["rows"].append(row)
+        log(f"aewa p={p}: AEWA/EWAInit time {row['aewa_over_ewainit_time']:.1f} "
+            f"(paper {row['paper_aewa_over_ewainit_time']:.1f})")
+    return res
+
+
+def run_biased(torch, qecgen, P, dev):
+    """XZZX L=5, 7, 9 under biased noise (p_Z = 2p/3, p_X = p_Y = p/6), EWAInit alpha 0.5,
+    iter_max 100, 2^16 shots per point: the LER curves and where L=5 and L=9 cross (the
+    paper reads about 10% for EWAInit under parallel scheduling)."""
+    shots = 1 << 16
+    ps = (0.06, 0.08, 0.10, 0.12, 0.14, 0.16, 0.18, 0.20)
+    prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=100)
+    ler = {}
+    for i, L in enumerate((5, 7, 9)):
+        code = qecgen.xzzx(L)
+        g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
+        ler[L] = []
+        for j, p in enumerate(ps):
+            probs = qecgen.biased_probs(code.n, p)
+            err, syn = P.sample(g, shots, qecgen.thresholds(*probs[0]), seed=qecgen.config_seed(7, i, j))
+            r = P.decode(g, prm, P.prior_llr(probs, device=dev), syn)
+            _, cnt = P.bookkeep(g, err, r["est"])
+            ler[L].append(float(cnt[1] + cnt[2]) / shots)
+    cross = None
+    for j in range(len(ps) - 1):
+        d0, d1 = ler[9][j] - ler[5][j], ler[9][j + 1] - ler[5][j + 1]
+        if d0 < 0 <= d1 or d0 <= 0 < d1:
+            cross = ps[j] + (ps[j + 1] - ps[j]) * (-d0) / (d1 - d0)
+    log(f"biased XZZX: L=5/9 LER curves cross near p = {cross}")
+    return {"workload": "XZZX L=5, 7, 9, p_Z = 2p/3, p_X = p_Y = p/6, EWAInit alpha 0.5, iter_max 100, 2^16 shots",
+            "p": list(ps), "ler": {f"L{L}": v for L, v in ler.items()}, "crossing_L5_L9": cross,
+            "paper_crossing": 0.10}
 
 
 def run_unrolled(torch, qecgen, P, dev):
