@@ -202,6 +202,7 @@ typedef struct {
                                    (entry 0 unused), or NULL for the constant alpha */
     double alpha_last;          /* AEWA: discount of the last attempt */
     int32_t alpha_steps;        /* AEWA: attempts; alpha_k = alpha + (alpha_last - alpha) k / (steps - 1) */
+    int32_t serial;             /* 0: flooding schedule (Alg. 2); 1: serial schedule (Alg. 1) */
 } or_params;
 
 typedef struct {
@@ -223,6 +224,116 @@ static int hard_decision(const double q[3])
     for (int w = 1; w < 3; ++w)
         if (q[w] < q[best]) best = w;
     return PAULI_OF_INDEX[best];
+}
+
+/* Horizontal update (eq. h_update) of edge e = (c, v): combine the current
+ * messages m_{v'->c} of the other neighbours v' of c. */
+static double check_to_qubit(const or_graph *g, const uint8_t *s, const double *mvc, int e, double C)
+{
+    const int c = g->echk[e];
+    const int e0 = g->cptr[c], e1 = g->cptr[c + 1];
+    double ssum = 0.0;
+    int neg = s[c] ? 1 : 0;
+    for (int f = e0; f < e1; ++f) {
+        if (f == e) continue;
+        ssum += phi(fabs(mvc[f]));
+        if (mvc[f] < 0.0) neg ^= 1;
+    }
+    double w = phi(ssum);
+    return clampd(neg ? -w : w, C);
+}
+
+/* Sum of incoming check messages per Pauli: M_{v,W} = sum over c in M(v) with
+ * <W, H_cv> = 1 of m_{c->v} (the sum in eqs. p_update / mombp3), and of their
+ * magnitudes. */
+static void qubit_sums(const or_graph *g, int v, const double *mcv, double *msum, double *mabs)
+{
+    for (int w = 0; w < 3; ++w) {
+        double sum = 0.0, asum = 0.0;
+        for (int k = g->vptr[v]; k < g->vptr[v + 1]; ++k) {
+            int e = g->vedge[k];
+            if (anticommute(PAULI_OF_INDEX[w], g->elab[e])) {
+                sum += mcv[e];
+                asum += fabs(mcv[e]);
+            }
+        }
+        msum[3 * v + w] = sum;
+        mabs[3 * v + w] = asum;
+    }
+}
+
+/* Posterior update of entry i = 3v + w, per variant. */
+static void posterior(const or_params *p, int t, int i, const double *pi0, const double *pit,
+                      const double *qprev, const double *msum, const double *mabs, double *q,
+                      double *acc, double *dev)
+{
+    switch (p->variant) {
+    case OR_BP:        /* eq. p_update */
+        q[i] = pi0[i] + msum[i];
+        break;
+    case OR_EWAINIT:   /* eq. p_update with Pi^{(t)} (Alg. 2) */
+        q[i] = pit[i] + msum[i];
+        break;
+    case OR_MOMENTUM: { /* eqs. mombp1, mombp2, with the gradient of eq. mombp3 */
+        double grad = qprev[i] - pi0[i] - msum[i];
+        acc[i] = p->gamma * acc[i] + (1.0 - p->gamma) * grad;
+        q[i] = qprev[i] - p->alpha * acc[i];
+        break;
+    }
+    case OR_ADAGRAD: { /* eq. boost; active from the second iteration (READING) */
+        /* Carried as the deviation D = Q - Pi^{(0)} (READING: the gradient
+         * g' = Q^{(t-1)} - Pi - sum m of eq. boost is then D^{(t-1)} - sum m,
+         * which is exactly 0 when the incoming sums repeat; the step
+         * g'/(sqrt(G)+eps) would otherwise turn rounding residue into a full
+         * step of size alpha).  READING: a gradient below the rounding
+         * resolution of its operands, |g'| <= 2^-16 (|D| + sum |m|), is 0:
+         * while G is still 0 the first adaptive step is alpha * sign(g'),
+         * so a difference of message sums that cancel exactly (opposite
+         * syndromes on a symmetric neighbourhood) must not pick a sign from
+         * rounding. */
+        double grad = dev[i] - msum[i];
+        if (fabs(grad) <= ADAGRAD_DEADBAND * (fabs(dev[i]) + mabs[i])) grad = 0.0;
+        if (t == 1) {
+            if (p->adagrad_g_from_t1) acc[i] += grad * grad;
+            dev[i] = msum[i];
+        } else {
+            acc[i] += grad * grad;
+            dev[i] = dev[i] - p->alpha * grad / (sqrt(acc[i]) + p->eps);
+        }
+        q[i] = pi0[i] + dev[i];
+        break;
+    }
+    }
+}
+
+/* Vertical update of qubit v.  BP / EWAInit (eq. v_update): lambda over the
+ * prior (Pi^{(t)} for EWAInit) plus the messages of every other check c' of v.
+ * Momentum / AdaGrad (eq. mombp5, with lambda applied as in v_update,
+ * READING): lambda over Q^{(t)} minus the original message of c. */
+static void qubit_messages(const or_graph *g, const or_params *p, int v, const double *pi0, const double *pit,
+                           const double *q, const double *mcv, double *mvc, double C)
+{
+    for (int k = g->vptr[v]; k < g->vptr[v + 1]; ++k) {
+        int e = g->vedge[k];
+        int H = g->elab[e];
+        double L[3];
+        for (int w = 0; w < 3; ++w) {
+            int W = PAULI_OF_INDEX[w];
+            if (p->variant == OR_BP || p->variant == OR_EWAINIT) {
+                double base = (p->variant == OR_BP) ? pi0[3 * v + w] : pit[3 * v + w];
+                double sum = 0.0;
+                for (int k2 = g->vptr[v]; k2 < g->vptr[v + 1]; ++k2) {
+                    int f = g->vedge[k2];
+                    if (f == e) continue;
+                    if (anticommute(W, g->elab[f])) sum += mcv[f];
+                }
+                L[w] = base + sum;
+            } else {
+                L[w] = q[3 * v + w] - (anticommute(W, H) ? mcv[e] : 0.0);
+            }
+        }
+        mvc[e] = clampd(lambda_h(H, L), C);
+    }
 }
 
 /* Decode one shot.  Work arrays are caller-provided (per thread). */
@@ -254,106 +365,25 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
                 pit[i] = a * pi0[i] + (1.0 - a) * qprev[i];
         }
 
-        /* Horizontal update (eq. h_update): for each edge (c, v), combine the
-         * previous messages from all other neighbours v' of c. */
-        for (int c = 0; c < m; ++c) {
-            int e0 = g->cptr[c], e1 = g->cptr[c + 1];
-            for (int e = e0; e < e1; ++e) {
-                double ssum = 0.0;
-                int neg = s[c] ? 1 : 0;
-                for (int f = e0; f < e1; ++f) {
-                    if (f == e) continue;
-                    ssum += phi(fabs(mvc[f]));
-                    if (mvc[f] < 0.0) neg ^= 1;
-                }
-                double w = phi(ssum);
-                mcv[e] = clampd(neg ? -w : w, C);
-            }
-        }
-
-        /* Sum of incoming check messages per Pauli: M_{v,W} = sum over c in M(v)
-         * with <W, H_cv> = 1 of m_{c->v} (the sum in eqs. p_update / mombp3). */
-        for (int v = 0; v < n; ++v) {
-            for (int w = 0; w < 3; ++w) {
-                double sum = 0.0, asum = 0.0;
+        if (!p->serial) {
+            /* Flooding ("parallel") schedule, Alg. 2: every check, then every qubit. */
+            for (int e = 0; e < nnz; ++e) mcv[e] = check_to_qubit(g, s, mvc, e, C);
+            for (int v = 0; v < n; ++v) qubit_sums(g, v, mcv, msum, mabs);
+            for (int i = 0; i < 3 * n; ++i) posterior(p, t, i, pi0, pit, qprev, msum, mabs, q, acc, dev);
+            for (int v = 0; v < n; ++v) qubit_messages(g, p, v, pi0, pit, q, mcv, mvc, C);
+        } else {
+            /* Serial schedule, Alg. 1: qubit by qubit in index order, each qubit's
+             * incoming check messages from the current messages of the check's other
+             * qubits (those earlier in the sweep already updated), then its posterior
+             * and its outgoing messages. */
+            for (int v = 0; v < n; ++v) {
                 for (int k = g->vptr[v]; k < g->vptr[v + 1]; ++k) {
-                    int e = g->vedge[k];
-                    if (anticommute(PAULI_OF_INDEX[w], g->elab[e])) {
-                        sum += mcv[e];
-                        asum += fabs(mcv[e]);
-                    }
+                    const int e = g->vedge[k];
+                    mcv[e] = check_to_qubit(g, s, mvc, e, C);
                 }
-                msum[3 * v + w] = sum;
-                mabs[3 * v + w] = asum;
-            }
-        }
-
-        /* Posterior update, per variant. */
-        for (int i = 0; i < 3 * n; ++i) {
-            switch (p->variant) {
-            case OR_BP:        /* eq. p_update */
-                q[i] = pi0[i] + msum[i];
-                break;
-            case OR_EWAINIT:   /* eq. p_update with Pi^{(t)} (Alg. 2) */
-                q[i] = pit[i] + msum[i];
-                break;
-            case OR_MOMENTUM: { /* eqs. mombp1, mombp2, with the gradient of eq. mombp3 */
-                double grad = qprev[i] - pi0[i] - msum[i];
-                acc[i] = p->gamma * acc[i] + (1.0 - p->gamma) * grad;
-                q[i] = qprev[i] - p->alpha * acc[i];
-                break;
-            }
-            case OR_ADAGRAD: { /* eq. boost; active from the second iteration (READING) */
-                /* Carried as the deviation D = Q - Pi^{(0)} (READING: the gradient
-                 * g' = Q^{(t-1)} - Pi - sum m of eq. boost is then D^{(t-1)} - sum m,
-                 * which is exactly 0 when the incoming sums repeat; the step
-                 * g'/(sqrt(G)+eps) would otherwise turn rounding residue into a full
-                 * step of size alpha).  READING: a gradient below the rounding
-                 * resolution of its operands, |g'| <= 2^-16 (|D| + sum |m|), is 0:
-                 * while G is still 0 the first adaptive step is alpha * sign(g'),
-                 * so a difference of message sums that cancel exactly (opposite
-                 * syndromes on a symmetric neighbourhood) must not pick a sign from
-                 * rounding. */
-                double grad = dev[i] - msum[i];
-                if (fabs(grad) <= ADAGRAD_DEADBAND * (fabs(dev[i]) + mabs[i])) grad = 0.0;
-                if (t == 1) {
-                    if (p->adagrad_g_from_t1) acc[i] += grad * grad;
-                    dev[i] = msum[i];
-                } else {
-                    acc[i] += grad * grad;
-                    dev[i] = dev[i] - p->alpha * grad / (sqrt(acc[i]) + p->eps);
-                }
-                q[i] = pi0[i] + dev[i];
-                break;
-            }
-            }
-        }
-
-        /* Vertical update.  BP / EWAInit (eq. v_update): lambda over the prior
-         * (Pi^{(t)} for EWAInit) plus the messages of every other check c' of v.
-         * Momentum / AdaGrad (eq. mombp5, with lambda applied as in v_update,
-         * READING): lambda over Q^{(t)} minus the original message of c. */
-        for (int v = 0; v < n; ++v) {
-            for (int k = g->vptr[v]; k < g->vptr[v + 1]; ++k) {
-                int e = g->vedge[k];
-                int H = g->elab[e];
-                double L[3];
-                for (int w = 0; w < 3; ++w) {
-                    int W = PAULI_OF_INDEX[w];
-                    if (p->variant == OR_BP || p->variant == OR_EWAINIT) {
-                        double base = (p->variant == OR_BP) ? pi0[3 * v + w] : pit[3 * v + w];
-                        double sum = 0.0;
-                        for (int k2 = g->vptr[v]; k2 < g->vptr[v + 1]; ++k2) {
-                            int f = g->vedge[k2];
-                            if (f == e) continue;
-                            if (anticommute(W, g->elab[f])) sum += mcv[f];
-                        }
-                        L[w] = base + sum;
-                    } else {
-                        L[w] = q[3 * v + w] - (anticommute(W, H) ? mcv[e] : 0.0);
-                    }
-                }
-                mvc[e] = clampd(lambda_h(H, L), C);
+                qubit_sums(g, v, mcv, msum, mabs);
+                for (int i = 3 * v; i < 3 * v + 3; ++i) posterior(p, t, i, pi0, pit, qprev, msum, mabs, q, acc, dev);
+                qubit_messages(g, p, v, pi0, pit, q, mcv, mvc, C);
             }
         }
 

@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
                 ("stop_on_syndrome", ctypes.c_int32), ("adagrad_g_from_t1", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("eps", ctypes.c_double), ("clamp", ctypes.c_double), ("alpha_t", ctypes.c_void_p),
-                ("alpha_last", ctypes.c_double), ("alpha_steps", ctypes.c_int32)]
+                ("alpha_last", ctypes.c_double), ("alpha_steps", ctypes.c_int32), ("serial", ctypes.c_int32)]
 
 
 class _Outputs(ctypes.Structure):
@@ -103,11 +103,13 @@ class Params:
     alpha_t: Optional[np.ndarray] = None   # EWAInit per-iteration discount, entry t-1 at iteration t
     alpha_last: float = 0.0                # AEWA: discount of the last attempt (alpha is the first)
     alpha_steps: int = 11                  # AEWA: number of attempts
+    serial: bool = False                   # serial schedule (Alg. 1) instead of flooding (Alg. 2)
 
     def c(self) -> _Params:
         cp = _Params(VARIANTS[self.variant], int(self.max_iter), int(bool(self.stop_on_syndrome)),
                      int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
-                     float(self.eps), float(self.clamp), None, float(self.alpha_last), int(self.alpha_steps))
+                     float(self.eps), float(self.clamp), None, float(self.alpha_last), int(self.alpha_steps),
+                     int(bool(self.serial)))
         if self.alpha_t is not None:
             a = np.ascontiguousarray(self.alpha_t, dtype=np.float64)
             if a.shape != (self.max_iter,):
