@@ -68,7 +68,14 @@ typedef enum {
  *          single step); the first attempt that meets the syndrome is the
  *          result, else the last one.  Both discounts in [0, 1], 1 <=
  *          alpha_steps <= 64, stop_on_syndrome must be 1; `iters` reports the
- *          iterations of all attempts.  Ignored by the other variants. */
+ *          iterations of all attempts.  Ignored by the other variants.
+ *   serial: 0 flooding schedule (all checks, then all qubits; Algorithm 2);
+ *          1 serial schedule (Algorithm 1: qubit by qubit in index order, each
+ *          qubit's incoming check messages from the current messages of the
+ *          check's other qubits, then its posterior and outgoing messages).
+ *          The serial schedule runs on the SOA kernel (bp4_decode chooses it;
+ *          BP4_KERNEL_LDS, bp4_decode_mixed and bp4_decode_plain answer
+ *          EUNSUPPORTED). */
 typedef struct {
     int32_t variant;
     int32_t max_iter;
@@ -80,6 +87,7 @@ typedef struct {
     float llr_clamp;
     float alpha_last;
     int32_t alpha_steps;
+    int32_t serial;
 } bp4_params;
 
 /* Opaque host object describing one code's Tanner graph (section II-B1). */

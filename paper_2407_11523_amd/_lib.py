@@ -27,7 +27,7 @@ class Params(ctypes.Structure):
                 ("stop_on_syndrome", ctypes.c_int32), ("adagrad_g_from_t1", ctypes.c_int32),
                 ("alpha", ctypes.c_float), ("gamma", ctypes.c_float),
                 ("eps", ctypes.c_float), ("llr_clamp", ctypes.c_float),
-                ("alpha_last", ctypes.c_float), ("alpha_steps", ctypes.c_int32)]
+                ("alpha_last", ctypes.c_float), ("alpha_steps", ctypes.c_int32), ("serial", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):

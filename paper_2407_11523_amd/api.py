@@ -44,11 +44,13 @@ class Params:
     llr_clamp: float = 30.0
     alpha_last: float = 0.0   # AEWA: discount of the last attempt (alpha is the first)
     alpha_steps: int = 11     # AEWA: number of attempts
+    serial: bool = False      # serial schedule (Algorithm 1) instead of flooding (Algorithm 2)
 
     def c(self) -> _CParams:
         return _CParams(VARIANTS[self.variant], int(self.max_iter), int(bool(self.stop_on_syndrome)),
                         int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
-                        float(self.eps), float(self.llr_clamp), float(self.alpha_last), int(self.alpha_steps))
+                        float(self.eps), float(self.llr_clamp), float(self.alpha_last), int(self.alpha_steps),
+                        int(bool(self.serial)))
 
 
 class Graph:

@@ -48,9 +48,10 @@ struct bp4_graph {
     std::vector<uint32_t> cedge;                 // [m][kMaxCheckDeg]
     std::vector<uint32_t> vinfo;                 // [n]
     std::vector<uint32_t> vcanon;                // [nnz]
+    std::vector<uint32_t> vchk;                  // [nnz] check of each message slot
     std::vector<uint32_t> lptr, lent;            // logicals
     // byte offsets of the sections in the device image
-    size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_lptr = 0, off_lent = 0, bytes = 0;
+    size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_vchk = 0, off_lptr = 0, off_lent = 0, bytes = 0;
 
     void layout()
     {
@@ -58,6 +59,7 @@ struct bp4_graph {
         off_cedge = o; o = align256(o + cedge.size() * 4);
         off_vinfo = o; o = align256(o + vinfo.size() * 4);
         off_vcanon = o; o = align256(o + vcanon.size() * 4);
+        off_vchk = o; o = align256(o + vchk.size() * 4);
         off_lptr = o; o = align256(o + lptr.size() * 4);
         off_lent = o; o = align256(o + (lent.empty() ? 1 : lent.size()) * 4);
         bytes = o;
@@ -70,6 +72,7 @@ struct bp4_graph {
         v.cedge = reinterpret_cast<const uint32_t *>(b + off_cedge);
         v.vinfo = reinterpret_cast<const uint32_t *>(b + off_vinfo);
         v.vcanon = reinterpret_cast<const uint32_t *>(b + off_vcanon);
+        v.vchk = reinterpret_cast<const uint32_t *>(b + off_vchk);
         v.lptr = reinterpret_cast<const uint32_t *>(b + off_lptr);
         v.lent = reinterpret_cast<const uint32_t *>(b + off_lent);
         v.m = m;
@@ -210,6 +213,8 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
         slot_of[k] = s;
         g->vcanon[s] = (uint32_t)k;
     }
+    g->vchk.assign(nnz, 0);
+    for (long s = 0; s < nnz; ++s) g->vchk[s] = (uint32_t)g->canon_chk[g->vcanon[s]];
     // commutation of the rows: only pairs sharing a qubit can anticommute
     if (!(flags & BP4_ALLOW_ANTICOMMUTING)) {
         std::vector<std::vector<std::pair<int, uint32_t>>> vchk(n);
@@ -322,6 +327,7 @@ int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stre
     std::memcpy(img.data() + g->off_cedge, g->cedge.data(), g->cedge.size() * 4);
     std::memcpy(img.data() + g->off_vinfo, g->vinfo.data(), g->vinfo.size() * 4);
     std::memcpy(img.data() + g->off_vcanon, g->vcanon.data(), g->vcanon.size() * 4);
+    std::memcpy(img.data() + g->off_vchk, g->vchk.data(), g->vchk.size() * 4);
     std::memcpy(img.data() + g->off_lptr, g->lptr.data(), g->lptr.size() * 4);
     if (!g->lent.empty()) std::memcpy(img.data() + g->off_lent, g->lent.data(), g->lent.size() * 4);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -347,6 +353,7 @@ int check_params(const bp4_params *p)
     if (p->variant == BP4_MOMENTUM || p->variant == BP4_EWAINIT || p->variant == BP4_AEWA) {
         if (!(p->alpha >= 0.0f && p->alpha <= 1.0f)) return fail(BP4_EINVAL, "params: alpha must lie in [0, 1]");
     }
+    if (p->serial != 0 && p->serial != 1) return fail(BP4_EINVAL, "params: serial must be 0 or 1");
     if (p->variant == BP4_AEWA) {
         if (!(p->alpha_last >= 0.0f && p->alpha_last <= 1.0f))
             return fail(BP4_EINVAL, "params: alpha_last must lie in [0, 1]");
@@ -475,7 +482,10 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     const bool lds_knobs = requested || lds_floor, soa_knobs = soa_lanes || soa_block;
     if (lds_knobs && soa_knobs) return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields exclude each other");
     if (kernel == BP4_KERNEL_AUTO)
-        kernel = lds_knobs ? BP4_KERNEL_LDS : soa_knobs ? BP4_KERNEL_SOA : auto_kernel(g, p->variant);
+        kernel = p->serial ? BP4_KERNEL_SOA
+                 : lds_knobs ? BP4_KERNEL_LDS : soa_knobs ? BP4_KERNEL_SOA : auto_kernel(g, p->variant);
+    if (p->serial && kernel == BP4_KERNEL_LDS)
+        return fail(BP4_EUNSUPPORTED, "decode: the serial schedule runs on the SOA kernel");
     if (kernel == BP4_KERNEL_LDS && soa_knobs)
         return fail(BP4_EINVAL, "decode: soa_lanes and soa_iter_block apply to the SOA kernel");
     if (kernel == BP4_KERNEL_SOA) {
@@ -523,7 +533,7 @@ int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, 
     int rc = check_params(p);
     if (rc) return rc;
     if (shots < 0) return fail(BP4_EINVAL, "workspace_bytes: negative shots");
-    *bytes = auto_kernel(g, p->variant) == BP4_KERNEL_SOA
+    *bytes = (p->serial || auto_kernel(g, p->variant) == BP4_KERNEL_SOA)
                  ? soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, 0)
                  : kSmallWorkspace;
     return BP4_OK;
@@ -618,6 +628,7 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
         if (c.reserved) return fail(BP4_EINVAL, "decode_mixed: reserved field of code %d must be 0", i);
         if (c.group_lanes == 0 && auto_kernel(c.graph, c.params.variant) == BP4_KERNEL_SOA)
             return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d needs the large-code (SOA) kernel", i);
+        if (c.params.serial) return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d asks for the serial schedule", i);
     }
     size_t max_lds = 0;
     int rc = device_max_lds(&max_lds);
@@ -673,6 +684,7 @@ int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params
     if (shots < 0 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "decode_plain: shots out of range");
     if (!prior_llr) return fail(BP4_EINVAL, "decode_plain: NULL prior");
     if (iterations_run) *iterations_run = 0;
+    if (p->serial) return fail(BP4_EUNSUPPORTED, "decode_plain: flooding schedule only");
     if (p->variant == BP4_AEWA) return fail(BP4_EUNSUPPORTED, "decode_plain: AEWA restarts need the persistent kernels");
     if (shots == 0) return BP4_OK;
     if (!synd || !est || !conv || !iters || !ws) return fail(BP4_EINVAL, "decode_plain: NULL buffer");

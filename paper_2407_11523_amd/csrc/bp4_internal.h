@@ -38,6 +38,7 @@ struct GraphView {
     const uint32_t *cedge;   // [m][kMaxCheckDeg] packed check edges, padded (edge_pad_word)
     const uint32_t *vinfo;   // [n] packed qubit words
     const uint32_t *vcanon;  // [nnz] canonical (row-major) edge id of each message slot
+    const uint32_t *vchk;    // [nnz] check of each message slot
     const uint32_t *lptr;    // [nlog + 1] offsets into lent
     const uint32_t *lent;    // logical supports: qubit | (Pauli << 16)
     int32_t m, n, nnz, nlog;

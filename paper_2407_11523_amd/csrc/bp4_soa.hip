@@ -70,6 +70,7 @@ struct SoaArgs {
     int32_t t0, t_end, max_iter, stop, with_y;
     int32_t fresh;            // first block of the first attempt: columns are shots first_shot + column
     int32_t last_attempt;     // a shot that fails this attempt is finished (else it restarts)
+    int32_t serial;           // serial schedule (Algorithm 1) instead of flooding
     float clamp;
     VariantParams vp;
     SoaLayout lay;
@@ -98,6 +99,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     uint8_t *ehat = a.ehat + wave * (size_t)n * 64 + lane;
     konst<uint32_t> *cedge = as_const(a.g.cedge);
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
+    konst<uint32_t> *vchk = as_const(a.g.vchk);
     konst<float> *prior = as_const(a.prior);
 
     const int shot = !have ? 0 : a.fresh ? a.first_shot + col : a.src_shot[col];
@@ -133,75 +135,132 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
 
     if (have) {
         for (int t = a.t0 + 1; t <= a.t_end; ++t) {
-            // ---- Horizontal update (eq. h_update) ----------------------------------
-            // kChunk checks at a time: all their message loads are issued before the
-            // first update, so each wavefront keeps several HBM requests in flight.
-            // Padding edges (degree-3 checks) read +inf without touching memory.
             uint32_t sw = 0;
-            for (int c0 = 0; c0 < m; c0 += kChunk) {
-                if ((c0 & 31) == 0) sw = sb[(size_t)(c0 >> 5) * 64];
-                float mv[kChunk][4];
-                uint32_t cw[kChunk][4];
-#pragma unroll
-                for (int k = 0; k < kChunk; ++k)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        cw[k][j] = c0 + k < m ? cedge[kMaxCheckDeg * (c0 + k) + j] : edge_pad_word(0);
-                        mv[k][j] = edge_is_pad(cw[k][j]) ? INFINITY : msg[(size_t)edge_slot(cw[k][j]) * 64];
-                    }
-#pragma unroll
-                for (int k = 0; k < kChunk; ++k) {
-                    if (c0 + k >= m) break;
-                    float out[4];
-                    check_update(mv[k], sw >> ((c0 + k) & 31), C, out);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (!edge_is_pad(cw[k][j])) msg[(size_t)edge_slot(cw[k][j]) * 64] = out[j];
-                }
-            }
-            // ---- Posterior, hard decision, vertical update --------------------------
-            for (int v0 = 0; v0 < n; v0 += kChunk) {
-                uint32_t info[kChunk];
-                float mc[kChunk][4], s3[kChunk][3], a3[kChunk][3];
-#pragma unroll
-                for (int k = 0; k < kChunk; ++k) {
-                    const bool in = v0 + k < n;
-                    info[k] = in ? vinfo[v0 + k] : 0u;   // degree 0 past the end
-                    const uint32_t base = var_base(info[k]), deg = var_deg(info[k]);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) mc[k][j] = (uint32_t)j < deg ? msg[(size_t)(base + j) * 64] : 0.0f;
-#pragma unroll
-                    for (int x = 0; x < 3; ++x) {
-                        s3[k][x] = keep_q && in ? st[(size_t)(3 * (v0 + k) + x) * 64] : 0.0f;
-                        a3[k][x] = keep_acc && in ? acc[(size_t)(3 * (v0 + k) + x) * 64] : 0.0f;
+            if (!a.serial) {
+                // ---- Horizontal update (eq. h_update) ----------------------------------
+                // kChunk checks at a time: all their message loads are issued before the
+                // first update, so each wavefront keeps several HBM requests in flight.
+                // Padding edges (degree-3 checks) read +inf without touching memory.
+                for (int c0 = 0; c0 < m; c0 += kChunk) {
+                    if ((c0 & 31) == 0) sw = sb[(size_t)(c0 >> 5) * 64];
+                    float mv[kChunk][4];
+                    uint32_t cw[kChunk][4];
+    #pragma unroll
+                    for (int k = 0; k < kChunk; ++k)
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            cw[k][j] = c0 + k < m ? cedge[kMaxCheckDeg * (c0 + k) + j] : edge_pad_word(0);
+                            mv[k][j] = edge_is_pad(cw[k][j]) ? INFINITY : msg[(size_t)edge_slot(cw[k][j]) * 64];
+                        }
+    #pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        if (c0 + k >= m) break;
+                        float out[4];
+                        check_update(mv[k], sw >> ((c0 + k) & 31), C, out);
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (!edge_is_pad(cw[k][j])) msg[(size_t)edge_slot(cw[k][j]) * 64] = out[j];
                     }
                 }
+                // ---- Posterior, hard decision, vertical update --------------------------
+                for (int v0 = 0; v0 < n; v0 += kChunk) {
+                    uint32_t info[kChunk];
+                    float mc[kChunk][4], s3[kChunk][3], a3[kChunk][3];
+    #pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        const bool in = v0 + k < n;
+                        info[k] = in ? vinfo[v0 + k] : 0u;   // degree 0 past the end
+                        const uint32_t base = var_base(info[k]), deg = var_deg(info[k]);
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) mc[k][j] = (uint32_t)j < deg ? msg[(size_t)(base + j) * 64] : 0.0f;
+    #pragma unroll
+                        for (int x = 0; x < 3; ++x) {
+                            s3[k][x] = keep_q && in ? st[(size_t)(3 * (v0 + k) + x) * 64] : 0.0f;
+                            a3[k][x] = keep_acc && in ? acc[(size_t)(3 * (v0 + k) + x) * 64] : 0.0f;
+                        }
+                    }
+    #pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        const int v = v0 + k;
+                        if (v >= n) break;
+                        const uint32_t base = var_base(info[k]), deg = var_deg(info[k]);
+                        float S[4], A[4];
+                        label_sums(info[k], mc[k], with_y, variant == BP4_ADAGRAD, S, A);
+                        const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
+                        float qn[3];
+                        qubit_posterior(a.vp, t, p3, S, A, s3[k], a3[k], qn);
+                        if (keep_q)
+                            for (int x = 0; x < 3; ++x) st[(size_t)(3 * v + x) * 64] = s3[k][x];
+                        if (keep_acc)
+                            for (int x = 0; x < 3; ++x) acc[(size_t)(3 * v + x) * 64] = a3[k][x];
+                        ehat[(size_t)v * 64] = (uint8_t)decision_byte(hard_decision(qn));
+                        float lam[4];
+                        qubit_lambdas(qn, var_labels_present(info[k]), lam);
+    #pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            if ((uint32_t)j >= deg) break;
+                            const float out = clampf(lam[var_lab(info[k], j)] - mc[k][j], C);
+                            msg[(size_t)(base + j) * 64] = out;
+                            if (a.mvc_out) {
+                                const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
+                                a.mvc_out[o] = out;
+                                a.mcv_out[o] = mc[k][j];
+                            }
+                        }
+                        if (a.q_out)
+                            for (int x = 0; x < 3; ++x) a.q_out[((size_t)shot * n + v) * 3 + x] = qn[x];
+                    }
+                }
+            } else {
+                // ---- Serial schedule (Algorithm 1): qubit by qubit in index order ----
+                // Each qubit's incoming m_{c->v} are formed from the current m_{v'->c}
+                // of the check's other qubits (already updated this iteration for
+                // qubits earlier in the sweep); the slots always hold m_{v->c}.
+                for (int v = 0; v < n; ++v) {
+                    const uint32_t info = vinfo[v];
+                    const uint32_t base = var_base(info), deg = var_deg(info);
+                    float mc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    for (uint32_t j = 0; j < deg; ++j) {
+                        const uint32_t slot = base + j;
+                        const uint32_t c = vchk[slot];
+                        const uint32_t sbit = (sb[(size_t)(c >> 5) * 64] >> (c & 31)) & 1u;
+                        float f[4];
+                        uint32_t neg = sbit;
 #pragma unroll
-                for (int k = 0; k < kChunk; ++k) {
-                    const int v = v0 + k;
-                    if (v >= n) break;
-                    const uint32_t base = var_base(info[k]), deg = var_deg(info[k]);
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t w = cedge[kMaxCheckDeg * c + k];
+                            // padding and this qubit's own edge take no part
+                            const float x = (edge_is_pad(w) || edge_slot(w) == slot) ? INFINITY
+                                                                                      : msg[(size_t)edge_slot(w) * 64];
+                            neg ^= x < 0.0f ? 1u : 0u;
+                            f[k] = phi(fabsf(x));
+                        }
+                        const float mag = phi((f[0] + f[1]) + (f[2] + f[3]));
+                        mc[j] = clampf(neg ? -mag : mag, C);
+                    }
                     float S[4], A[4];
-                    label_sums(info[k], mc[k], with_y, variant == BP4_ADAGRAD, S, A);
+                    label_sums(info, mc, with_y, variant == BP4_ADAGRAD, S, A);
                     const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
-                    float qn[3];
-                    qubit_posterior(a.vp, t, p3, S, A, s3[k], a3[k], qn);
+                    float s3[3] = {0.0f, 0.0f, 0.0f}, a3[3] = {0.0f, 0.0f, 0.0f}, qn[3];
                     if (keep_q)
-                        for (int x = 0; x < 3; ++x) st[(size_t)(3 * v + x) * 64] = s3[k][x];
+                        for (int x = 0; x < 3; ++x) s3[x] = st[(size_t)(3 * v + x) * 64];
                     if (keep_acc)
-                        for (int x = 0; x < 3; ++x) acc[(size_t)(3 * v + x) * 64] = a3[k][x];
+                        for (int x = 0; x < 3; ++x) a3[x] = acc[(size_t)(3 * v + x) * 64];
+                    qubit_posterior(a.vp, t, p3, S, A, s3, a3, qn);
+                    if (keep_q)
+                        for (int x = 0; x < 3; ++x) st[(size_t)(3 * v + x) * 64] = s3[x];
+                    if (keep_acc)
+                        for (int x = 0; x < 3; ++x) acc[(size_t)(3 * v + x) * 64] = a3[x];
                     ehat[(size_t)v * 64] = (uint8_t)decision_byte(hard_decision(qn));
                     float lam[4];
-                    qubit_lambdas(qn, var_labels_present(info[k]), lam);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if ((uint32_t)j >= deg) break;
-                        const float out = clampf(lam[var_lab(info[k], j)] - mc[k][j], C);
+                    qubit_lambdas(qn, var_labels_present(info), lam);
+                    for (uint32_t j = 0; j < deg; ++j) {
+                        const float out = clampf(lam[var_lab(info, j)] - mc[j], C);
                         msg[(size_t)(base + j) * 64] = out;
                         if (a.mvc_out) {
                             const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
                             a.mvc_out[o] = out;
-                            a.mcv_out[o] = mc[k][j];
+                            a.mcv_out[o] = mc[j];
                         }
                     }
                     if (a.q_out)
@@ -338,6 +397,7 @@ hipError_t launch_decode_soa(const GraphView &g, const bp4_params &p, int32_t sh
     a.vp.gamma = p.gamma;
     a.vp.eps = p.eps;
     a.lay = lay;
+    a.serial = p.serial;
     const int32_t B = iter_block > 0 ? iter_block : kSoaIterBlock;
     // AEWA runs its attempts one after another over the shots still unsolved
     const int32_t attempts = p.variant == BP4_AEWA ? p.alpha_steps : 1;
