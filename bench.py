@@ -303,6 +303,7 @@ def main():
     if not args.no_aewa:
         out["aewa"] = run_aewa(torch, qecgen, P, dev)
         out["biased_xzzx"] = run_biased(torch, qecgen, P, dev)
+        out["serial"] = run_serial(torch, qecgen, P, dev)
 
     if not args.no_large:
         del batch, items
@@ -356,6 +357,39 @@ def run_aewa(torch, qecgen, P, dev):
         log(f"aewa p={p}: AEWA/EWAInit time {row['aewa_over_ewainit_time']:.1f} "
             f"(paper {row['paper_aewa_over_ewainit_time']:.1f})")
     return res
+
+
+def run_serial(torch, qecgen, P, dev):
+    """Serial (Algorithm 1) against flooding (Algorithm 2) EWAInit, alpha 0.5, iter_max 100, on
+    toric L=4, 6, 8 with 2^16 shots at p = 0.06 ... 0.16: LER, iterations and throughput (the
+    paper reads the serial crossing at about 15%, the flooding one at about 13.6%)."""
+    shots = 1 << 16
+    ps = (0.06, 0.10, 0.14, 0.16)
+    rows = []
+    for i, L in enumerate((4, 6, 8)):
+        code = qecgen.toric(L)
+        g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
+        for j, p in enumerate(ps):
+            pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p), device=dev)
+            err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=qecgen.config_seed(8, i, j))
+            row = {"L": L, "p": p}
+            for name, serial in (("flooding", False), ("serial", True)):
+                prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=100, serial=serial)
+                P.decode(g, prm, pr, syn[:512])
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                r = P.decode(g, prm, pr, syn)
+                b.record()
+                torch.cuda.synchronize()
+                _, cnt = P.bookkeep(g, err, r["est"])
+                row[name] = {"ler": float(cnt[1] + cnt[2]) / shots, "avg_iters": float(r["iters"].float().mean()),
+                             "syndromes_per_s": shots / (a.elapsed_time(b) / 1e3)}
+            rows.append(row)
+    log("serial vs flooding: " + ", ".join(f"L{r['L']} p{r['p']}: {r['serial']['ler']:.4f}/{r['flooding']['ler']:.4f}"
+                                            for r in rows if r["p"] == 0.14))
+    return {"workload": "toric L=4, 6, 8, 2^16 shots, EWAInit alpha 0.5, iter_max 100, serial vs flooding",
+            "rows": rows}
 
 
 def run_biased(torch, qecgen, P, dev):
