@@ -142,7 +142,7 @@ def main():
         counts = torch.zeros(3, dtype=torch.int64, device=dev)
         items.append(dict(code=code, g=g, prior=pr, err=err, syn=syn, counts=counts, shots=shots,
                           seed=qecgen.config_seed(3, i, 0)))
-    # launch shape per code from the autotuner (timed on the first 2^15 syndromes of each code)
+    # launch shape per code from the autotuner (timed on the first 2^17 syndromes of each code)
     lanes = [0] * len(items)
     tuned = None
     if not args.no_tune:
@@ -154,7 +154,7 @@ def main():
                                 [tune.digest(it["code"].hx, it["code"].hz) for it in items],
                                 [it["shots"] for it in items], **kw)
         lanes = tuned["lanes"]
-        log(f"tuned lanes per shot {lanes}, LDS budget {tuned['budget']} "
+        log(f"tuned lane mappings [group_lanes, block_shots] {lanes}, LDS budget {tuned['budget']} "
             f"({'cached' if tuned['cached'] else 'measured'} for {tuned['key']})")
     batch = P.MixedBatch([(it["g"], prm, it["prior"], it["syn"], G) for it, G in zip(items, lanes)])
     total_shots = sum(it["shots"] for it in items)
@@ -218,7 +218,7 @@ def main():
                                "depolarizing p=0.08, 2^18 shots x 1:2:4 per size tier, EWAInit-BP alpha=0.5, "
                                "iter_max 100, sample + one persistent decode launch + bookkeeping per step",
                    "shots_per_step": total_shots, "codes": len(items), "shot_scale": args.scale,
-                   "lanes_per_shot": [int(x) for x in lanes]},
+                   "lane_mapping": [list(x) if isinstance(x, (list, tuple)) else [int(x), 0] for x in lanes]},
         "decode_ms": dec_ms, "edge_updates_per_s": eups, "avg_iters": iters_total / total_shots,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic("decode_lds_kernel"),

@@ -161,8 +161,14 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
                void *ws, size_t ws_bytes, void *stream);
 
 /* Launch choices of the decode kernels.  kernel: BP4_KERNEL_AUTO, _LDS or
- * _SOA (below).  group_lanes: lanes that decode one shot together in the LDS
- * kernel (4, 8, 16, 32, 64, 128 or 256; 0 picks by lane use and occupancy).
+ * _SOA (below).  Lane mapping of the LDS kernel (0 and 0: picked by lane use
+ * and occupancy): group_lanes 4, 8, 16, 32 or 64 = that many lanes of one
+ * wavefront decode one shot (lane r owns checks and qubits r, r + G, ...);
+ * block_shots S in [1, 256] (with group_lanes 0 or 256) = S shots share the
+ * 256 lanes of a workgroup, which walk the S*m check and S*n qubit items of
+ * the S shots in passes of 256 (at most 64 check items per lane);
+ * group_lanes 128 and 256 alone mean block_shots 2 and 1.  Results do not
+ * depend on the mapping.
  * lds_bytes: if larger than the code's own layout, each workgroup of the LDS
  * kernel reserves this much LDS (so a single-code launch runs at the
  * occupancy of a mixed launch that needs it; 0: the layout's size).
@@ -170,16 +176,18 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
  * a multiple of 256 and capped by the shot count); the SOA workspace grows
  * with it.  soa_iter_block: iterations per SOA launch, after which the shots
  * still running are packed onto fully populated wavefronts (0: 16); results
- * do not depend on it.  group_lanes and lds_bytes select the LDS kernel under
- * AUTO and are rejected with SOA; soa_lanes and soa_iter_block select SOA
- * under AUTO and are rejected with LDS.  reserved: 0. */
+ * do not depend on it.  group_lanes, block_shots and lds_bytes select the
+ * LDS kernel under AUTO and are rejected with SOA; soa_lanes and
+ * soa_iter_block select SOA under AUTO and are rejected with LDS.
+ * reserved: 0. */
 typedef struct {
     int32_t group_lanes;
     int32_t lds_bytes;
     int32_t kernel;
     int32_t soa_lanes;
     int32_t soa_iter_block;
-    int32_t reserved[3];
+    int32_t block_shots;
+    int32_t reserved[2];
 } bp4_tuning;
 
 /* Decode kernels.  LDS: a lane group per shot, state in LDS (small and medium
@@ -213,13 +221,15 @@ int bp4_decode_ex(const bp4_graph *g, const void *dev_graph, const bp4_params *p
                   void *ws, size_t ws_bytes, void *stream);
 
 /* LDS bytes per workgroup the LDS decode kernel needs for this code, variant
- * and group size.  Errors: EINVAL if group_lanes is not a valid size or leaves
- * more than 64 checks per lane. */
-int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int32_t group_lanes, size_t *bytes);
+ * and lane mapping (group_lanes, block_shots as in bp4_tuning; not both 0).
+ * Errors: EINVAL if the mapping is invalid or leaves more than 64 checks per
+ * lane. */
+int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int32_t group_lanes, int32_t block_shots,
+                         size_t *bytes);
 
 /* One code of a mixed batch: its graph, parameters, shots and buffers (as the
- * arguments of bp4_decode).  group_lanes as in bp4_tuning (0: automatic);
- * reserved must be 0. */
+ * arguments of bp4_decode).  group_lanes and block_shots as in bp4_tuning
+ * (both 0: automatic). */
 typedef struct {
     const bp4_graph *graph;
     const void *dev_graph;
@@ -231,7 +241,7 @@ typedef struct {
     uint8_t *conv;
     int32_t *iters;
     int32_t group_lanes;
-    int32_t reserved;
+    int32_t block_shots;
 } bp4_code_batch;
 
 #define BP4_MAX_MIXED_CODES 16
@@ -244,7 +254,7 @@ int bp4_mixed_workspace_bytes(int32_t ncodes, size_t *bytes);
  * each workgroup stages one code's graph in LDS and its lane groups pull that
  * code's shots from a queue, then the workgroup moves on to the next code
  * (largest first).  Results per code as bp4_decode; bit-identical to decoding
- * each code alone with the same group_lanes.  Errors: as bp4_decode, EINVAL
+ * each code alone with the same lane mapping.  Errors: as bp4_decode, EINVAL
  * for ncodes outside [1, BP4_MAX_MIXED_CODES]. */
 int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size_t ws_bytes,
                      void *stream);

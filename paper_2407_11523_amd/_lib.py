@@ -32,14 +32,15 @@ class Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("group_lanes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("soa_lanes", ctypes.c_int32), ("soa_iter_block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("soa_lanes", ctypes.c_int32), ("soa_iter_block", ctypes.c_int32), ("block_shots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class CodeBatch(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_void_p), ("dev_graph", ctypes.c_void_p), ("params", Params),
                 ("shots", ctypes.c_int64), ("prior_llr", ctypes.c_void_p), ("synd", ctypes.c_void_p),
                 ("est", ctypes.c_void_p), ("conv", ctypes.c_void_p), ("iters", ctypes.c_void_p),
-                ("group_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("group_lanes", ctypes.c_int32), ("block_shots", ctypes.c_int32)]
 
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -70,7 +71,8 @@ SIGNATURES = {
     "bp4_mixed_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_sz)]),
     "bp4_soa_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int32,
                                                ctypes.POINTER(_sz)]),
-    "bp4_lds_layout_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(_sz)]),
+    "bp4_lds_layout_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(_sz)]),
     "bp4_decode_mixed": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CodeBatch), _vp, _sz, _vp]),
     "bp4_plain_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64,
                                                  ctypes.POINTER(_sz)]),

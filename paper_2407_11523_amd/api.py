@@ -157,13 +157,14 @@ KERNELS = {"auto": 0, "lds": 1, "soa": 2}
 
 
 def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *, trace: bool = False,
-           group_lanes: int = 0, lds_bytes: int = 0, kernel: str = "auto", soa_lanes: int = 0,
-           soa_iter_block: int = 0, out: Optional[dict] = None,
+           group_lanes: int = 0, block_shots: int = 0, lds_bytes: int = 0, kernel: str = "auto",
+           soa_lanes: int = 0, soa_iter_block: int = 0, out: Optional[dict] = None,
            ws: Optional[torch.Tensor] = None):
     """Decode syndromes [shots][m]; returns dict(est, conv, iters[, q, mvc, mcv]).
 
-    group_lanes forces the lanes per shot of the LDS kernel (0: automatic);
-    lds_bytes reserves at least that much LDS per workgroup; kernel picks the
+    group_lanes (4..64: lanes of one wavefront per shot) or block_shots (shots
+    sharing a 256-lane workgroup) force the LDS kernel's lane mapping (0 and 0:
+    automatic); lds_bytes reserves at least that much LDS per workgroup; kernel picks the
     LDS ("lds") or structure-of-arrays ("soa") kernel ("auto": by code size);
     soa_lanes sets the shots the SOA kernel keeps in flight and soa_iter_block
     its iterations per launch (0: defaults)."""
@@ -191,14 +192,15 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
             nbytes = g.workspace_bytes(params, shots)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     res = {"est": est, "conv": conv, "iters": iters}
-    if trace or group_lanes or lds_bytes or soa_lanes or soa_iter_block or kernel != "auto":
+    if trace or group_lanes or block_shots or lds_bytes or soa_lanes or soa_iter_block or kernel != "auto":
         q = mvc = mcv = None
         if trace:
             q = torch.empty((shots, g.n, 3), dtype=torch.float32, device=dev)
             mvc = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
             mcv = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
             res.update(q=q, mvc=mvc, mcv=mcv)
-        tune = _CTuning(int(group_lanes), int(lds_bytes), KERNELS[kernel], int(soa_lanes), int(soa_iter_block))
+        tune = _CTuning(int(group_lanes), int(lds_bytes), KERNELS[kernel], int(soa_lanes), int(soa_iter_block),
+                        int(block_shots))
         check(g._lib.bp4_decode_ex(g.handle, _ptr(g.dev), ctypes.byref(cp), ctypes.byref(tune), shots,
                                    _ptr(prior), _ptr(synd), _ptr(est), _ptr(conv), _ptr(iters), _ptr(q),
                                    _ptr(mvc), _ptr(mcv), _ptr(ws), ws.numel(), _stream(dev)))
@@ -245,8 +247,9 @@ def _check_inputs(g: Graph, prior: torch.Tensor, synd: torch.Tensor):
 class MixedBatch:
     """Codes decoded together by one persistent launch (bp4_decode_mixed).
 
-    Each entry is (graph, params, prior [n][3], synd [shots][m], group_lanes); the
-    outputs are allocated once and reused by every call of run()."""
+    Each entry is (graph, params, prior [n][3], synd [shots][m], lanes), lanes =
+    group_lanes or (group_lanes, block_shots) as in decode(); the outputs are
+    allocated once and reused by every call of run()."""
 
     def __init__(self, entries, outs=None):
         self.entries = list(entries)
@@ -258,9 +261,10 @@ class MixedBatch:
             _check_inputs(g, prior, synd)
             o = _outputs(g, synd.shape[0], outs[i] if outs else None)
             self.outs.append(o)
+            G, S = (lanes if isinstance(lanes, (tuple, list)) else (lanes, 0))
             arr[i] = _CCodeBatch(g.handle.value, g.dev.data_ptr(), params.c(), synd.shape[0], prior.data_ptr(),
                                  synd.data_ptr(), o["est"].data_ptr(), o["conv"].data_ptr(),
-                                 o["iters"].data_ptr(), int(lanes), 0)
+                                 o["iters"].data_ptr(), int(G), int(S))
         self._arr = arr
         lib = load()
         b = ctypes.c_size_t()

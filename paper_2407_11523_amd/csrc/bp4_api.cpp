@@ -414,35 +414,57 @@ void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, 
     a.q_off = L.q_off;
     a.acc_off = L.acc_off;
     a.ehat_off = L.ehat_off;
+    a.syn_off = L.syn_off;
+    a.hdr_off = L.hdr_off;
     a.group_lanes = L.group_lanes;
+    a.block_shots = L.block_shots;
+    a.magic_m = (uint32_t)(((1ull << 32) + (uint64_t)g->m - 1) / (uint64_t)g->m);
+    a.magic_n = (uint32_t)(((1ull << 32) + (uint64_t)g->n - 1) / (uint64_t)g->n);
     a.with_y = g->with_y;
 }
 
-// The automatic kernel: SOA when even 256-lane groups need more than kLdsAutoLimit
-// bytes of LDS per workgroup, or the code has more than 64 checks per lane at 256.
+// The automatic kernel: SOA when even one shot per 256-lane workgroup needs more
+// than kLdsAutoLimit bytes of LDS, or the code has more than 64 checks per lane.
 int auto_kernel(const bp4_graph *g, int variant)
 {
-    if ((g->m + 255) / 256 > 64) return BP4_KERNEL_SOA;
-    return decode_lds_layout(g->m, g->n, g->nnz, variant, 256).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA
-                                                                                   : BP4_KERNEL_LDS;
+    if (!decode_lds_fits(g->m, g->n, 256, 1)) return BP4_KERNEL_SOA;
+    return decode_lds_layout(g->m, g->n, g->nnz, variant, 256, 1).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA
+                                                                                      : BP4_KERNEL_LDS;
 }
 
-// Lanes per shot for one code: the caller's choice (validated) or the default pick.
-int choose_group(const bp4_graph *g, const bp4_params *p, int32_t requested, size_t max_lds, int *G_out)
+// A requested lane mapping in range: group_lanes 0 or a power of two in [4, 256];
+// block_shots >= 0, only with group_lanes 0 or 256.
+int check_lanes(int32_t G, int32_t S, const char *who)
 {
-    int G = requested;
     if (G != 0 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64 && G != 128 && G != 256)
-        return fail(BP4_EINVAL, "decode: group_lanes %d not in {4, 8, ..., 256}", G);
-    if (G && (g->m + G - 1) / G > 64)
-        return fail(BP4_EINVAL, "decode: group_lanes %d leaves more than 64 checks per lane", G);
-    if (G > 0) {
-        if (decode_lds_layout(g->m, g->n, g->nnz, p->variant, G).bytes > max_lds)
-            return fail(BP4_EINVAL, "decode: group_lanes %d exceeds the LDS of a workgroup", G);
-    } else {
-        G = decode_lds_pick_group(g->m, g->n, g->nnz, p->variant, max_lds);
-        if (G < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the LDS kernel");
+        return fail(BP4_EINVAL, "%s: group_lanes %d not in {4, 8, ..., 256}", who, G);
+    if (S < 0 || S > 256) return fail(BP4_EINVAL, "%s: block_shots %d outside [0, 256]", who, S);
+    if (S > 0 && G != 0 && G != 256)
+        return fail(BP4_EINVAL, "%s: block_shots needs group_lanes 0 or 256", who);
+    return BP4_OK;
+}
+
+// Lane mapping for one code: the caller's choice (validated) or the default pick.
+// group_lanes 128 and 256 are block slots with 2 and 1 shots per workgroup.
+int choose_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, size_t max_lds, LaneChoice *out)
+{
+    int rc = check_lanes(G, S, "decode");
+    if (rc) return rc;
+    if (G == 0 && S == 0) {
+        *out = decode_lds_pick(g->m, g->n, g->nnz, p->variant, max_lds);
+        if (out->group_lanes < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the LDS kernel");
+        return BP4_OK;
     }
-    *G_out = G;
+    if (G > 64 || S > 0) {
+        if (S == 0) S = 256 / G;
+        G = 256;
+    }
+    if (!decode_lds_fits(g->m, g->n, G, S))
+        return fail(BP4_EINVAL, "decode: %d lanes x %d shots leave more than 64 checks per lane", G, S);
+    if (decode_lds_layout(g->m, g->n, g->nnz, p->variant, G, S).bytes > max_lds)
+        return fail(BP4_EINVAL, "decode: group_lanes %d, block_shots %d exceed the LDS of a workgroup", G, S);
+    out->group_lanes = G;
+    out->block_shots = S;
     return BP4_OK;
 }
 
@@ -462,9 +484,9 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     if ((mvc_out == nullptr) != (mcv_out == nullptr)) return fail(BP4_EINVAL, "decode: mvc_out and mcv_out go together");
     if (!ws) return fail(BP4_EINVAL, "decode: NULL workspace");
     if (ws_bytes < kSmallWorkspace) return fail(BP4_EWORKSPACE, "decode: workspace %zu < %zu bytes", ws_bytes, kSmallWorkspace);
-    int32_t requested = 0, lds_floor = 0, kernel = BP4_KERNEL_AUTO, soa_lanes = 0, soa_block = 0;
+    int32_t requested = 0, requested_S = 0, lds_floor = 0, kernel = BP4_KERNEL_AUTO, soa_lanes = 0, soa_block = 0;
     if (tune) {
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 2; ++i)
             if (tune->reserved[i]) return fail(BP4_EINVAL, "decode: reserved tuning fields must be 0");
         lds_floor = tune->lds_bytes;
         if (lds_floor < 0) return fail(BP4_EINVAL, "decode: negative lds_bytes");
@@ -475,11 +497,11 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         soa_block = tune->soa_iter_block;
         if (soa_lanes < 0 || soa_block < 0) return fail(BP4_EINVAL, "decode: negative soa_lanes or soa_iter_block");
         requested = tune->group_lanes;
-        if (requested != 0 && requested != 4 && requested != 8 && requested != 16 && requested != 32 &&
-            requested != 64 && requested != 128 && requested != 256)
-            return fail(BP4_EINVAL, "decode: group_lanes %d not in {4, 8, ..., 256}", requested);
+        requested_S = tune->block_shots;
+        rc = check_lanes(requested, requested_S, "decode");
+        if (rc) return rc;
     }
-    const bool lds_knobs = requested || lds_floor, soa_knobs = soa_lanes || soa_block;
+    const bool lds_knobs = requested || requested_S || lds_floor, soa_knobs = soa_lanes || soa_block;
     if (lds_knobs && soa_knobs) return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields exclude each other");
     if (kernel == BP4_KERNEL_AUTO)
         kernel = p->serial ? BP4_KERNEL_SOA
@@ -489,7 +511,7 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     if (kernel == BP4_KERNEL_LDS && soa_knobs)
         return fail(BP4_EINVAL, "decode: soa_lanes and soa_iter_block apply to the SOA kernel");
     if (kernel == BP4_KERNEL_SOA) {
-        if (requested || lds_floor) return fail(BP4_EINVAL, "decode: group_lanes and lds_bytes apply to the LDS kernel");
+        if (lds_knobs) return fail(BP4_EINVAL, "decode: group_lanes, block_shots and lds_bytes apply to the LDS kernel");
         const size_t need = soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, soa_lanes);
         if (ws_bytes < need) return fail(BP4_EWORKSPACE, "decode: SOA workspace %zu < %zu bytes", ws_bytes, need);
         hipError_t e = launch_decode_soa(g->view(dev_graph), *p, (int32_t)shots, prior_llr, synd, est, conv, iters,
@@ -501,10 +523,10 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     size_t max_lds = 0;
     rc = device_max_lds(&max_lds);
     if (rc) return rc;
-    int G = 0;
-    rc = choose_group(g, p, requested, max_lds, &G);
+    LaneChoice lc;
+    rc = choose_lanes(g, p, requested, requested_S, max_lds, &lc);
     if (rc) return rc;
-    const LdsLayout L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G);
+    const LdsLayout L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, lc.group_lanes, lc.block_shots);
     MixedArgs args;
     std::memset(&args, 0, sizeof args);
     args.ncodes = 1;
@@ -625,8 +647,9 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
         if (!c.prior_llr) return fail(BP4_EINVAL, "decode_mixed: code %d has a NULL prior", i);
         if (c.shots > 0 && (!c.synd || !c.est || !c.conv || !c.iters))
             return fail(BP4_EINVAL, "decode_mixed: code %d has a NULL buffer", i);
-        if (c.reserved) return fail(BP4_EINVAL, "decode_mixed: reserved field of code %d must be 0", i);
-        if (c.group_lanes == 0 && auto_kernel(c.graph, c.params.variant) == BP4_KERNEL_SOA)
+        int rcl = check_lanes(c.group_lanes, c.block_shots, "decode_mixed");
+        if (rcl) return rcl;
+        if (c.group_lanes == 0 && c.block_shots == 0 && auto_kernel(c.graph, c.params.variant) == BP4_KERNEL_SOA)
             return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d needs the large-code (SOA) kernel", i);
         if (c.params.serial) return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d asks for the serial schedule", i);
     }
@@ -648,10 +671,11 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
     unsigned int *counters = static_cast<unsigned int *>(ws);
     for (size_t k = 0; k < order.size(); ++k) {
         const bp4_code_batch &c = codes[order[k]];
-        int G = 0;
-        rc = choose_group(c.graph, &c.params, c.group_lanes, max_lds, &G);
+        LaneChoice lc;
+        rc = choose_lanes(c.graph, &c.params, c.group_lanes, c.block_shots, max_lds, &lc);
         if (rc) return rc;
-        const LdsLayout L = decode_lds_layout(c.graph->m, c.graph->n, c.graph->nnz, c.params.variant, G);
+        const LdsLayout L = decode_lds_layout(c.graph->m, c.graph->n, c.graph->nnz, c.params.variant, lc.group_lanes,
+                                              lc.block_shots);
         lds = L.bytes > lds ? L.bytes : lds;
         fill_decode_args(args.codes[k], c.graph, c.dev_graph, &c.params, c.shots, c.prior_llr, c.synd, c.est,
                          c.conv, c.iters, L, counters + k);
@@ -700,15 +724,21 @@ int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params
 
 }  // extern "C"
 
-extern "C" int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int32_t group_lanes, size_t *bytes)
+extern "C" int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int32_t group_lanes,
+                                    int32_t block_shots, size_t *bytes)
 {
     if (!g || !bytes) return fail(BP4_EINVAL, "lds_layout_bytes: NULL argument");
     int rc = check_params(p);
     if (rc) return rc;
-    const int G = group_lanes;
-    if (G != 4 && G != 8 && G != 16 && G != 32 && G != 64 && G != 128 && G != 256)
-        return fail(BP4_EINVAL, "lds_layout_bytes: group_lanes %d not in {4, 8, ..., 256}", G);
-    if ((g->m + G - 1) / G > 64) return fail(BP4_EINVAL, "lds_layout_bytes: more than 64 checks per lane");
-    *bytes = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G).bytes;
+    int G = group_lanes, S = block_shots;
+    rc = check_lanes(G, S, "lds_layout_bytes");
+    if (rc) return rc;
+    if (G == 0 && S == 0) return fail(BP4_EINVAL, "lds_layout_bytes: no lane mapping given");
+    if (G > 64 || S > 0) {
+        if (S == 0) S = 256 / G;
+        G = 256;
+    }
+    if (!decode_lds_fits(g->m, g->n, G, S)) return fail(BP4_EINVAL, "lds_layout_bytes: more than 64 checks per lane");
+    *bytes = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G, S).bytes;
     return BP4_OK;
 }

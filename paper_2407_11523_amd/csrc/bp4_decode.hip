@@ -33,12 +33,134 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// MW: groups of 128 or 256 lanes spanning wavefronts (workgroup barriers);
-// otherwise G in {4, ..., 64} lanes inside one wavefront (wavefront-level sync).
-// VAR: the code's variant as a compile-time constant, so the qubit update keeps only
-// its own branch.
-template <bool MW, int VAR>
-__device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *bcast, int *badflag)
+// ---- Per-node steps shared by the two lane mappings -------------------------------
+
+// Horizontal update (eq. h_update) of check c from the messages in `msg`; s: its
+// syndrome bit.  Padding edges read and rewrite the padding slot, which holds
+// +inf (phi(+inf) = 0 adds nothing to the sums).
+__device__ __forceinline__ void check_node(const uint32_t *s_ce, float *msg, int c, uint32_t s, float C)
+{
+    const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
+    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+    float mv[4], out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mv[j] = msg[edge_slot(w[j])];
+    check_update(mv, s, C, out);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) msg[edge_slot(w[j])] = edge_is_pad(w[j]) ? INFINITY : out[j];
+}
+
+// Syndrome test of check c against the decision bytes (Algorithm 2): nonzero if
+// the decision violates the check or some decision on it is NaN.
+__device__ __forceinline__ uint32_t test_node(const uint32_t *s_ce, const uint8_t *ehat, int c, uint32_t s)
+{
+    const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
+    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+    uint32_t par = s & 1u, any = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // <H_cv, E^_v> is bit H_cv of the decision byte (padding edges read bit 0
+        // of qubit 0's byte, which is set only if that shot already holds a NaN
+        // posterior and cannot converge)
+        const uint32_t b = ehat[edge_var(w[j])];
+        par ^= (b >> edge_lab(w[j])) & 1u;
+        any |= b;
+    }
+    return par | (any & 1u);   // bit 0: a NaN posterior never converges
+}
+
+// Initialisation of qubit v (eq. init, Algorithm 2): m^{(0)}_{v->c} =
+// lambda_{H_cv}(Pi^{(0)}_v); Q^{(0)} = Pi^{(0)}; accumulators start at 0.
+template <int VAR>
+__device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const float *s_pi, float *msg, float *qs,
+                                           float *acc, int v, float C)
+{
+    constexpr bool keep_q = VAR != BP4_BP;
+    constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
+    const uint32_t info = s_vi[v];
+    const uint32_t base = var_base(info), deg = var_deg(info);
+    const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
+    float lam[4];
+    qubit_lambdas(p3, var_labels_present(info), lam);
+    for (uint32_t j = 0; j < deg; ++j) msg[base + j] = clampf(lam[var_lab(info, j)], C);
+    float st[3], ac[3];
+    qubit_state_init(VAR, p3, st, ac);
+    if (keep_q)
+        for (int w = 0; w < 3; ++w) qs[3 * v + w] = st[w];
+    if (keep_acc)
+        for (int w = 0; w < 3; ++w) acc[3 * v + w] = ac[w];
+}
+
+// Posterior, hard decision and vertical update of qubit v at iteration t (eqs.
+// p_update, v_update and the variant's rule); `shot` indexes the optional
+// verification outputs (none are written for shot >= shots).
+template <int VAR>
+__device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *s_vi, const float *s_pi, float *msg,
+                                           float *qs, float *acc, uint8_t *ehat, int v, int t,
+                                           const VariantParams &vp, bool with_y, int shot)
+{
+    constexpr bool keep_q = VAR != BP4_BP;
+    constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
+    const float C = a.clamp;
+    const int n = a.g.n;
+    const uint32_t info = s_vi[v];
+    const uint32_t base = var_base(info), deg = var_deg(info);
+    // the words after a qubit's last slot are in the region (another qubit's
+    // slots, the padding slot or the posterior array); they are read but never
+    // used: those slots carry label 0, which the label sums skip, and no message
+    // is written for them
+    float mc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mc[j] = msg[base + j];
+    float S[4], A[4];
+    label_sums(info, mc, with_y, keep_acc && VAR == BP4_ADAGRAD, S, A);
+    const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
+    float st[3] = {0.0f, 0.0f, 0.0f}, ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
+    if (keep_q)
+        for (int x = 0; x < 3; ++x) st[x] = qs[3 * v + x];
+    if (keep_acc)
+        for (int x = 0; x < 3; ++x) ac[x] = acc[3 * v + x];
+    qubit_posterior(vp, t, p3, S, A, st, ac, qn);
+    if (keep_q)
+        for (int x = 0; x < 3; ++x) qs[3 * v + x] = st[x];
+    if (keep_acc)
+        for (int x = 0; x < 3; ++x) acc[3 * v + x] = ac[x];
+    ehat[v] = (uint8_t)decision_byte(hard_decision(qn));
+    // Vertical update (eqs. v_update / mombp5): m_{v->c} = lambda_H(Q) - m_{c->v}.
+    float lam[4];
+    qubit_lambdas(qn, var_labels_present(info), lam);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if ((uint32_t)j >= deg) continue;
+        const float out = clampf(lam[var_lab(info, j)] - mc[j], C);
+        msg[base + j] = out;
+        if (a.mvc_out && shot < a.shots) {
+            const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
+            a.mvc_out[o] = out;
+            a.mcv_out[o] = mc[j];
+        }
+    }
+    if (a.q_out && shot < a.shots)
+        for (int x = 0; x < 3; ++x) a.q_out[((size_t)shot * n + v) * 3 + x] = qn[x];
+}
+
+template <int VAR>
+__device__ __forceinline__ VariantParams variant_params(const DecodeArgs &a)
+{
+    VariantParams vp;
+    vp.variant = VAR;
+    vp.g_from_t1 = a.g_from_t1;
+    vp.alpha = a.alpha;
+    vp.gamma = a.gamma;
+    vp.eps = a.eps;
+    return vp;
+}
+
+// ---- Wave groups: G in {4, ..., 64} lanes of one wavefront per shot -----------------
+// Lane r of a group owns checks and qubits r, r + G, ...; the group's syndrome bits
+// sit in a register (bit k: check r + kG); groups synchronise at wavefront level.
+template <int VAR>
+__device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
 {
     const int G = a.group_lanes;
     const int lgG = __builtin_ctz((unsigned)G);
@@ -49,183 +171,60 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
 
     const int gid = (int)threadIdx.x >> lgG;                // group within the workgroup
     const int r = (int)threadIdx.x & (G - 1);               // rank within the group
-    const int lead = MW ? 0 : (((int)threadIdx.x & 63) >> lgG) << lgG;   // leader lane in the wavefront
+    const int lead = (((int)threadIdx.x & 63) >> lgG) << lgG;   // leader lane in the wavefront
     float *msg = lds + a.static_words + gid * a.region_words;
     float *qs = msg + a.q_off;      // [n][3] Q^{(t-1)} (AdaGrad: D = Q - Pi^{(0)})
     float *acc = msg + a.acc_off;   // [n][3] momentum g or AdaGrad G
     uint8_t *ehat = reinterpret_cast<uint8_t *>(msg + a.ehat_off);
 
     const float C = a.clamp;
-    constexpr int variant = VAR;
-    const bool keep_q = variant != BP4_BP;
-    const bool keep_acc = variant == BP4_MOMENTUM || variant == BP4_ADAGRAD;
     const bool with_y = a.with_y != 0;
-    VariantParams vp;
-    vp.variant = VAR;
-    vp.g_from_t1 = a.g_from_t1;
-    vp.alpha = a.alpha;
-    vp.gamma = a.gamma;
-    vp.eps = a.eps;
-
-    auto gsync = [&]() {
-        if (MW) __syncthreads();
-        else wave_sync();
-    };
+    VariantParams vp = variant_params<VAR>(a);
 
     uint64_t sbits = 0;
     int t = 0;
-    int par = 0;       // flag slot of this iteration (MW)
     int att = 0;       // AEWA: attempt of the current shot
     int t_before = 0;  // AEWA: iterations of the shot's earlier attempts
 
-    // Initialisation (eq. init, Algorithm 2): m^{(0)}_{v->c} = lambda_{H_cv}(Pi^{(0)}_v);
-    // Q^{(0)} = Pi^{(0)}; momentum and squared-gradient accumulators start at 0.
     auto init = [&](int s) {
         if (r == 0) msg[a.g.nnz] = INFINITY;   // padding slot
         sbits = 0;
         int k = 0;
         for (int c = r; c < m; c += G, ++k)
             if (a.synd[(size_t)s * m + c]) sbits |= 1ull << k;
-        for (int v = r; v < n; v += G) {
-            const uint32_t info = s_vi[v];
-            const uint32_t base = var_base(info), deg = var_deg(info);
-            const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
-            float lam[4];
-            qubit_lambdas(p3, var_labels_present(info), lam);
-            for (uint32_t j = 0; j < deg; ++j) msg[base + j] = clampf(lam[var_lab(info, j)], C);
-            float st[3], ac[3];
-            qubit_state_init(variant, p3, st, ac);
-            if (keep_q)
-                for (int w = 0; w < 3; ++w) qs[3 * v + w] = st[w];
-            if (keep_acc)
-                for (int w = 0; w < 3; ++w) acc[3 * v + w] = ac[w];
-        }
+        for (int v = r; v < n; v += G) init_qubit<VAR>(s_vi, s_pi, msg, qs, acc, v, C);
         t = 0;
     };
 
     // Shot queue: the group leader takes the next shot index of this code.
-    int shot;
-    if (MW) {
-        if (r == 0) bcast[gid] = take_shot(a.counter, a.shots);
-        __syncthreads();
-        shot = bcast[gid];
-        __syncthreads();
-    } else {
-        int s0 = 0;
-        if (r == 0) s0 = take_shot(a.counter, a.shots);
-        shot = __shfl(s0, lead, 64);
-    }
+    int s0 = 0;
+    if (r == 0) s0 = take_shot(a.counter, a.shots);
+    int shot = __shfl(s0, lead, 64);
     if (shot < a.shots) init(shot);
-    gsync();
+    wave_sync();
 
     for (;;) {
         const bool live = shot < a.shots;
-        if (MW ? !__syncthreads_or(live) : !__any(live)) break;
+        if (!__any(live)) break;
         if (live) {
             ++t;
-            // ---- Horizontal update (eq. h_update) ----------------------------------
-            for (int c = r; c < m; c += G) {
-                const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
-                const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
-                float mv[4], out[4];
-                // padding edges read and rewrite the padding slot, which holds +inf
-                // (phi(+inf) = 0 adds nothing to the sums)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) mv[j] = msg[edge_slot(w[j])];
-                check_update(mv, (uint32_t)(sbits >> ((c - r) >> lgG)), C, out);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) msg[edge_slot(w[j])] = edge_is_pad(w[j]) ? INFINITY : out[j];
-            }
+            for (int c = r; c < m; c += G) check_node(s_ce, msg, c, (uint32_t)(sbits >> ((c - r) >> lgG)), C);
         }
-        gsync();
-        if (live) {
-            // ---- Posterior, hard decision and vertical update ------------------------
-            for (int v = r; v < n; v += G) {
-                const uint32_t info = s_vi[v];
-                const uint32_t base = var_base(info), deg = var_deg(info);
-                // the words after a qubit's last slot are in the region (another
-                // qubit's slots, the padding slot or the posterior array); their
-                // values are read and masked to 0
-                float mc[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float x = msg[base + j];
-                    mc[j] = (uint32_t)j < deg ? x : 0.0f;
-                }
-                float S[4], A[4];
-                label_sums(info, mc, with_y, keep_acc && variant == BP4_ADAGRAD, S, A);
-                const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
-                float st[3] = {0.0f, 0.0f, 0.0f}, ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
-                if (keep_q)
-                    for (int x = 0; x < 3; ++x) st[x] = qs[3 * v + x];
-                if (keep_acc)
-                    for (int x = 0; x < 3; ++x) ac[x] = acc[3 * v + x];
-                qubit_posterior(vp, t, p3, S, A, st, ac, qn);
-                if (keep_q)
-                    for (int x = 0; x < 3; ++x) qs[3 * v + x] = st[x];
-                if (keep_acc)
-                    for (int x = 0; x < 3; ++x) acc[3 * v + x] = ac[x];
-                ehat[v] = (uint8_t)decision_byte(hard_decision(qn));
-                // Vertical update (eqs. v_update / mombp5): m_{v->c} = lambda_H(Q) - m_{c->v}.
-                float lam[4];
-                qubit_lambdas(qn, var_labels_present(info), lam);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if ((uint32_t)j >= deg) continue;
-                    const float out = clampf(lam[var_lab(info, j)] - mc[j], C);
-                    msg[base + j] = out;
-                    if (a.mvc_out) {
-                        const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
-                        a.mvc_out[o] = out;
-                        a.mcv_out[o] = mc[j];
-                    }
-                }
-                if (a.q_out)
-                    for (int x = 0; x < 3; ++x) a.q_out[((size_t)shot * n + v) * 3 + x] = qn[x];
-            }
-        }
-        gsync();
-        // ---- Syndrome test of the hard decision (Algorithm 2) -----------------------
+        wave_sync();
+        if (live)
+            for (int v = r; v < n; v += G) qubit_node<VAR>(a, s_vi, s_pi, msg, qs, acc, ehat, v, t, vp, with_y, shot);
+        wave_sync();
         uint32_t bad = 0;
-        if (live) {
-            for (int c = r; c < m; c += G) {
-                const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
-                const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
-                uint32_t par = (uint32_t)(sbits >> ((c - r) >> lgG)) & 1u, any = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    // <H_cv, E^_v> is bit H_cv of the decision byte (padding edges read
-                    // bit 0 of qubit 0's byte, which is set only if that shot already
-                    // holds a NaN posterior and cannot converge)
-                    const uint32_t b = ehat[edge_var(w[j])];
-                    par ^= (b >> edge_lab(w[j])) & 1u;
-                    any |= b;
-                }
-                bad |= par | (any & 1u);   // bit 0: a NaN posterior never converges
-            }
-        }
-        bool sat;
-        if (MW) {
-            // Two flag slots per group, alternating by iteration: slot `par` is set now
-            // and read after the barrier; the other slot, last read one iteration ago
-            // (behind the barriers since), is cleared for the next iteration.
-            if (bad) badflag[par * (kBlock / 128) + gid] = 1;
-            __syncthreads();
-            sat = badflag[par * (kBlock / 128) + gid] == 0;
-            if (r == 0) badflag[(par ^ 1) * (kBlock / 128) + gid] = 0;
-            par ^= 1;
-        } else {
-            const uint64_t ballot = __ballot(bad != 0);
-            const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
-            sat = (ballot & gmask) == 0;
-        }
+        if (live)
+            for (int c = r; c < m; c += G) bad |= test_node(s_ce, ehat, c, (uint32_t)(sbits >> ((c - r) >> lgG)));
+        const uint64_t ballot = __ballot(bad != 0);
+        const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
+        const bool sat = (ballot & gmask) == 0;
         // AEWA: a failed attempt restarts the shot with the next discount
         const bool restart = VAR == BP4_AEWA && live && !sat && t >= a.max_iter && att + 1 < a.alpha_steps;
         const bool fin = live && !restart && ((a.stop && sat) || t >= a.max_iter);
         if (fin) {
-            for (int v = r; v < n; v += G) {
-                a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(ehat[v]);
-            }
+            for (int v = r; v < n; v += G) a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(ehat[v]);
             if (r == 0) {
                 a.conv[shot] = sat ? 1 : 0;
                 a.iters[shot] = t_before + t;
@@ -236,60 +235,237 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *b
             att = restart ? att + 1 : 0;
             vp.alpha = aewa_alpha(a.alpha, a.alpha_last, a.alpha_steps, att);
         }
-        if (MW) {
-            // No barrier is needed before the refill: nothing reads the messages after
-            // the flag barrier, and the outputs read only the decisions, which init
-            // leaves alone.  The loop-top barrier publishes init's writes.
-            if (fin && r == 0) bcast[gid] = take_shot(a.counter, a.shots);
-            __syncthreads();
-            if (fin) {
-                shot = bcast[gid];
-                if (shot < a.shots) init(shot);
-            } else if (restart) {
-                init(shot);
-            }
-        } else {
-            gsync();
-            if (fin) {
-                int s0 = 0;
-                if (r == 0) s0 = take_shot(a.counter, a.shots);
-                shot = __shfl(s0, lead, 64);
-                if (shot < a.shots) init(shot);
-            } else if (restart) {
-                init(shot);
-            }
-            gsync();
+        wave_sync();
+        if (fin) {
+            s0 = 0;
+            if (r == 0) s0 = take_shot(a.counter, a.shots);
+            shot = __shfl(s0, lead, 64);
+            if (shot < a.shots) init(shot);
+        } else if (restart) {
+            init(shot);
         }
-    }
-    if (MW && r == 0) {   // leave both flag slots clear for the next code
-        badflag[gid] = 0;
-        badflag[kBlock / 128 + gid] = 0;
+        wave_sync();
     }
 }
 
-template <bool MW>
-__device__ __forceinline__ void run_any(const DecodeArgs &a, float *lds, int *bcast, int *badflag)
+// ---- Block slots: S shots share the workgroup's 256 lanes ---------------------------
+// The workgroup walks the S*m (slot, check) and S*n (slot, qubit) items of its S
+// shot slots in passes of 256 lanes, so a code whose m or n is not a multiple of
+// the lanes per shot leaves few lanes idle.  Each slot's region holds its
+// messages, posteriors, decisions, syndrome bytes and a header; every slot keeps
+// its own iteration count, and a slot whose shot stops takes the next shot from
+// the queue while the others run on.  The three phases process every slot, also
+// one without a shot (once the queue is empty): its region is only read and
+// written by its own items, and nothing from it reaches the outputs, so no phase
+// waits on a slot's header before loading its data.
+constexpr int kHdrShot = 0;     // current shot (>= shots: the slot is empty)
+constexpr int kHdrT = 1;        // iterations of the current attempt completed
+constexpr int kHdrAtt = 2;      // AEWA attempt
+constexpr int kHdrTBefore = 3;  // AEWA: iterations of the earlier attempts
+constexpr int kHdrAlpha = 4;    // AEWA: discount of the current attempt (float bits)
+constexpr int kHdrDone = 5;     // shot whose decisions are written out this round, or -1
+constexpr int kHdrFresh = 6;    // 1: the slot's state is (re)initialised this round
+constexpr int kHdrBad = 7;      // two "syndrome unmet" flags, alternating by iteration
+
+// Walk over the items (slot k, index x < d) of one lane: items tid, tid + 256, ...
+// of the flattened S*d list, advanced without integer multiplies: 256 = q d + rem,
+// so a step adds rem to x and q slots to the region offset off = k * region_words,
+// plus one carry.  The walk ends at off = S * region_words.
+struct ItemWalk {
+    uint32_t x, off;
+};
+
+__device__ __forceinline__ ItemWalk walk_start(uint32_t tid, uint32_t d, uint32_t magic, uint32_t RW)
 {
-    switch (a.variant) {
-    case BP4_BP: run_code<MW, BP4_BP>(a, lds, bcast, badflag); break;
-    case BP4_MOMENTUM: run_code<MW, BP4_MOMENTUM>(a, lds, bcast, badflag); break;
-    case BP4_ADAGRAD: run_code<MW, BP4_ADAGRAD>(a, lds, bcast, badflag); break;
-    case BP4_AEWA: run_code<MW, BP4_AEWA>(a, lds, bcast, badflag); break;
-    default: run_code<MW, BP4_EWAINIT>(a, lds, bcast, badflag); break;
+    ItemWalk w;
+    const uint32_t k = __umulhi(tid, magic);   // tid / d: exact for tid < 256 and d < 2^14
+    w.x = tid - k * d;
+    w.off = k * RW;
+    return w;
+}
+
+__device__ __forceinline__ void walk_next(ItemWalk &w, uint32_t d, uint32_t rem, uint32_t qoff, uint32_t RW)
+{
+    w.x += rem;
+    w.off += qoff;
+    if (w.x >= d) {
+        w.x -= d;
+        w.off += RW;
     }
+}
+
+template <int VAR>
+__device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *events)
+{
+    const uint32_t S = (uint32_t)a.block_shots;
+    const int m = a.g.m, n = a.g.n;
+    const int tid = (int)threadIdx.x;
+    const uint32_t *s_ce = reinterpret_cast<const uint32_t *>(lds);
+    const uint32_t *s_vi = s_ce + kMaxCheckDeg * m;
+    const float *s_pi = reinterpret_cast<const float *>(s_vi + n);
+    float *reg0 = lds + a.static_words;
+    const uint32_t RW = (uint32_t)a.region_words;
+    auto hdr = [&](uint32_t k) { return reinterpret_cast<int *>(reg0 + k * RW + a.hdr_off); };
+    const float C = a.clamp;
+    const bool with_y = a.with_y != 0;
+    VariantParams vp = variant_params<VAR>(a);
+    // item walks over checks (d = m) and qubits (d = n)
+    const uint32_t rm = kBlock % m, rn = kBlock % n;
+    const uint32_t qoffm = (kBlock / m) * RW, qoffn = (kBlock / n) * RW, end = S * RW;
+    const ItemWalk wm0 = walk_start(tid, m, a.magic_m, RW), wn0 = walk_start(tid, n, a.magic_n, RW);
+#define BP4_FOR_CHECKS(w) for (ItemWalk w = wm0; w.off < end; walk_next(w, m, rm, qoffm, RW))
+#define BP4_FOR_QUBITS(w) for (ItemWalk w = wn0; w.off < end; walk_next(w, n, rn, qoffn, RW))
+
+    bool more = false;
+    if (tid == 0) *events = 1;
+    if (tid < (int)S) {
+        int *h = hdr(tid);
+        const int s = take_shot(a.counter, a.shots);
+        h[kHdrShot] = s;
+        h[kHdrT] = 0;
+        h[kHdrAtt] = 0;
+        h[kHdrTBefore] = 0;
+        h[kHdrAlpha] = __float_as_int(a.alpha);
+        h[kHdrDone] = -1;
+        h[kHdrFresh] = s < a.shots ? 1 : 0;
+        h[kHdrBad] = 0;
+        h[kHdrBad + 1] = 0;
+        more = s < a.shots;
+    }
+    bool any_more = __syncthreads_or(more);
+    int par = 0;
+    for (;;) {
+        // outputs of the shots that stopped, initialisation of fresh slots (only in
+        // rounds where some slot stopped or restarted)
+        if (*events) {
+            BP4_FOR_QUBITS(w) {
+                float *msg = reg0 + w.off;
+                const int *h = reinterpret_cast<const int *>(msg + a.hdr_off);
+                if (h[kHdrDone] >= 0) {
+                    const uint8_t *ehat = reinterpret_cast<const uint8_t *>(msg + a.ehat_off);
+                    a.est[(size_t)h[kHdrDone] * n + w.x] = (uint8_t)decision_pauli(ehat[w.x]);
+                }
+                if (h[kHdrFresh]) init_qubit<VAR>(s_vi, s_pi, msg, msg + a.q_off, msg + a.acc_off, (int)w.x, C);
+            }
+            BP4_FOR_CHECKS(w) {
+                float *msg = reg0 + w.off;
+                const int *h = reinterpret_cast<const int *>(msg + a.hdr_off);
+                if (h[kHdrFresh]) {
+                    uint8_t *syn = reinterpret_cast<uint8_t *>(msg + a.syn_off);
+                    syn[w.x] = a.synd[(size_t)h[kHdrShot] * m + w.x];
+                }
+            }
+            if (tid < (int)S && hdr(tid)[kHdrFresh]) reg0[tid * RW + a.g.nnz] = INFINITY;   // padding slot
+        }
+        if (!any_more) break;
+        __syncthreads();
+        if (tid == 0) *events = 0;   // every lane has read it before the barrier above
+        // ---- Horizontal update (eq. h_update) ----------------------------------------
+        BP4_FOR_CHECKS(w) {
+            float *msg = reg0 + w.off;
+            const uint8_t *syn = reinterpret_cast<const uint8_t *>(msg + a.syn_off);
+            check_node(s_ce, msg, (int)w.x, syn[w.x], C);
+        }
+        __syncthreads();
+        // ---- Posterior, hard decision and vertical update ----------------------------
+        {
+            // the slot's header is read when the walk enters the slot
+            uint32_t cur = ~0u;
+            int t = 0, shot = 0;
+            BP4_FOR_QUBITS(w) {
+                float *msg = reg0 + w.off;
+                if (w.off != cur) {
+                    const int *h = reinterpret_cast<const int *>(msg + a.hdr_off);
+                    t = h[kHdrT] + 1;
+                    shot = h[kHdrShot];
+                    if (VAR == BP4_AEWA) vp.alpha = __int_as_float(h[kHdrAlpha]);
+                    cur = w.off;
+                }
+                qubit_node<VAR>(a, s_vi, s_pi, msg, msg + a.q_off, msg + a.acc_off,
+                                reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t, vp, with_y, shot);
+            }
+        }
+        __syncthreads();
+        // ---- Syndrome test of the hard decision (Algorithm 2) ---------------------------
+        {
+            // a lane ORs the results of its consecutive items of one slot and sets that
+            // slot's flag once (lanes setting one flag together serialise in LDS)
+            uint32_t bad = 0, cur = wm0.off;
+            BP4_FOR_CHECKS(w) {
+                if (w.off != cur) {
+                    if (bad) reinterpret_cast<int *>(reg0 + cur + a.hdr_off)[kHdrBad + par] = 1;
+                    bad = 0;
+                    cur = w.off;
+                }
+                const float *msg = reg0 + w.off;
+                const uint8_t *syn = reinterpret_cast<const uint8_t *>(msg + a.syn_off);
+                bad |= test_node(s_ce, reinterpret_cast<const uint8_t *>(msg + a.ehat_off), (int)w.x, syn[w.x]);
+            }
+            if (bad) reinterpret_cast<int *>(reg0 + cur + a.hdr_off)[kHdrBad + par] = 1;
+        }
+        __syncthreads();
+        // ---- Per-slot bookkeeping: stop, restart (AEWA) or continue ---------------------
+        more = false;
+        if (tid < (int)S) {
+            int *h = hdr(tid);
+            h[kHdrDone] = -1;
+            h[kHdrFresh] = 0;
+            const int shot = h[kHdrShot];
+            if (shot < a.shots) {
+                const int t = h[kHdrT] + 1;
+                const bool sat = h[kHdrBad + par] == 0;
+                const bool restart = VAR == BP4_AEWA && !sat && t >= a.max_iter && h[kHdrAtt] + 1 < a.alpha_steps;
+                const bool fin = !restart && ((a.stop && sat) || t >= a.max_iter);
+                if (fin || restart) *events = 1;
+                if (fin) {
+                    a.conv[shot] = sat ? 1 : 0;
+                    a.iters[shot] = h[kHdrTBefore] + t;
+                    h[kHdrDone] = shot;
+                    const int s = take_shot(a.counter, a.shots);
+                    h[kHdrShot] = s;
+                    h[kHdrT] = 0;
+                    h[kHdrAtt] = 0;
+                    h[kHdrTBefore] = 0;
+                    h[kHdrAlpha] = __float_as_int(a.alpha);
+                    h[kHdrFresh] = s < a.shots ? 1 : 0;
+                } else if (restart) {
+                    h[kHdrTBefore] += t;
+                    h[kHdrAtt] += 1;
+                    h[kHdrT] = 0;
+                    h[kHdrAlpha] = __float_as_int(aewa_alpha(a.alpha, a.alpha_last, a.alpha_steps, h[kHdrAtt]));
+                    h[kHdrFresh] = 1;
+                } else {
+                    h[kHdrT] = t;
+                }
+            }
+            // the other flag was last read one iteration ago: clear it for the next one
+            h[kHdrBad + (par ^ 1)] = 0;
+            more = h[kHdrShot] < a.shots;
+        }
+        par ^= 1;
+        any_more = __syncthreads_or(more);
+    }
+#undef BP4_FOR_CHECKS
+#undef BP4_FOR_QUBITS
 }
 
 // VSET: the variant every code of the launch uses, or -1 for a launch that mixes
 // variants (a switch per code).  At most 96 VGPRs, so five wavefronts fit per SIMD.
+template <int VAR>
+__device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *events)
+{
+    if (a.block_shots > 0) run_block<VAR>(a, lds, events);
+    else run_wave<VAR>(a, lds);
+}
+
 template <int VSET>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 decode_lds_kernel(MixedArgs args)
 {
-    extern __shared__ float lds[];
-    __shared__ int bcast[kBlock / 128];
-    __shared__ int badflag[2 * (kBlock / 128)];
+    // 16-byte aligned: the packed check edges are read as 16-byte vectors
+    extern __shared__ __attribute__((aligned(16))) float lds[];
     __shared__ int pending;
-    if (threadIdx.x < 2 * (kBlock / 128)) badflag[threadIdx.x] = 0;
+    __shared__ int events;   // block slots: some slot stopped or restarted this round
     for (int ci = 0; ci < args.ncodes; ++ci) {
         const DecodeArgs &a = args.codes[ci];
         // skip a code whose queue is already empty (a stale read only costs a visit)
@@ -305,14 +481,17 @@ decode_lds_kernel(MixedArgs args)
         for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
         __syncthreads();
-        const bool mw = a.group_lanes > 64;
         if (VSET < 0) {
-            if (mw) run_any<true>(a, lds, bcast, badflag);
-            else run_any<false>(a, lds, bcast, badflag);
+            switch (a.variant) {
+            case BP4_BP: run_code<BP4_BP>(a, lds, &events); break;
+            case BP4_MOMENTUM: run_code<BP4_MOMENTUM>(a, lds, &events); break;
+            case BP4_ADAGRAD: run_code<BP4_ADAGRAD>(a, lds, &events); break;
+            case BP4_AEWA: run_code<BP4_AEWA>(a, lds, &events); break;
+            default: run_code<BP4_EWAINIT>(a, lds, &events); break;
+            }
         } else {
             constexpr int V = VSET < 0 ? BP4_EWAINIT : VSET;
-            if (mw) run_code<true, V>(a, lds, bcast, badflag);
-            else run_code<false, V>(a, lds, bcast, badflag);
+            run_code<V>(a, lds, &events);
         }
         __syncthreads();
     }
@@ -320,7 +499,7 @@ decode_lds_kernel(MixedArgs args)
 
 }  // namespace
 
-LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G)
+LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S)
 {
     LdsLayout L;
     L.static_words = kMaxCheckDeg * m + n + 3 * n;
@@ -332,43 +511,71 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G)
     if (variant == BP4_MOMENTUM || variant == BP4_ADAGRAD) w += 3 * n;
     L.ehat_off = w;
     w += (n + 3) / 4;
+    if (S > 0) {                   // block slots: syndrome bytes and the slot header
+        L.syn_off = w;
+        w += (m + 3) / 4;
+        L.hdr_off = w;
+        w += kHdrBad + 2;
+    }
     // the qubit phase reads four words from each qubit's first slot: keep them inside
     if (w < nnz + 4) w = nnz + 4;
-    if ((w & 1) == 0) w += 1;   // odd stride: neighbouring groups start on other banks
+    if ((w & 1) == 0) w += 1;   // odd stride: neighbouring regions start on other banks
     L.region_words = w;
-    L.group_lanes = G;
+    L.group_lanes = S > 0 ? kBlock : G;
+    L.block_shots = S;
     L.block = kBlock;
-    L.bytes = (size_t)4 * (L.static_words + (size_t)(kBlock / G) * L.region_words);
+    const int regions = S > 0 ? S : kBlock / G;
+    L.bytes = (size_t)4 * (L.static_words + (size_t)regions * L.region_words);
     return L;
 }
 
-// Lanes per shot for a code when no tuned choice is given.  Score = lane use
-// (padding of m and n up to multiples of G) times an occupancy factor: the
-// wavefronts per CU that the LDS allows (up to 16, beyond which latency is
-// hidden) over 16.  At most 64 checks per lane; at most `max_lds` bytes of LDS
-// per workgroup.
-int decode_lds_pick_group(int m, int n, int nnz, int variant, size_t max_lds)
+// Lane use of a layout: the share of issued (lane, item) pairs that carry a check
+// or a qubit, averaged over the two phases.
+static double lane_use(int m, int n, int G, int S)
 {
-    const int cand[7] = {256, 128, 64, 32, 16, 8, 4};
+    if (S > 0) {
+        const double pc = std::ceil((double)S * m / kBlock), pv = std::ceil((double)S * n / kBlock);
+        return 0.5 * ((double)S * m / (kBlock * pc) + (double)S * n / (kBlock * pv));
+    }
+    const int kc = (m + G - 1) / G, kv = (n + G - 1) / G;
+    return 0.5 * ((double)m / (G * kc) + (double)n / (G * kv));
+}
+
+bool decode_lds_fits(int m, int n, int G, int S)
+{
+    if (S > 0) {
+        if (S > kBlock) return false;
+        if ((uint64_t)S * m * m >= (1ull << 32) || (uint64_t)S * n * n >= (1ull << 32)) return false;
+        return ((int64_t)S * m + kBlock - 1) / kBlock <= 64;
+    }
+    return G >= 4 && G <= 64 && (G & (G - 1)) == 0 && (m + G - 1) / G <= 64;
+}
+
+// Lane mapping for a code when no tuned choice is given.  Score = lane use times
+// an occupancy factor: the wavefronts per CU that the LDS allows (up to 16,
+// beyond which latency is hidden) over 16.  Candidates: block slots S = 1..16,
+// then wave groups of 64 down to 4 lanes; at most `max_lds` bytes per workgroup.
+LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds)
+{
     const double cu_lds = 160.0 * 1024.0;
-    int best = -1;
+    LaneChoice best;
     double best_score = -1.0;
-    for (int i = 0; i < 7; ++i) {
-        const int G = cand[i];
-        if ((m + G - 1) / G > 64) continue;
-        const LdsLayout L = decode_lds_layout(m, n, nnz, variant, G);
-        if (L.bytes > max_lds) continue;
-        const int kc = (m + G - 1) / G, kv = (n + G - 1) / G;
-        const double util = 0.5 * ((double)m / (G * kc) + (double)n / (G * kv));
+    auto consider = [&](int G, int S) {
+        if (!decode_lds_fits(m, n, G, S)) return;
+        const LdsLayout L = decode_lds_layout(m, n, nnz, variant, G, S);
+        if (L.bytes > max_lds) return;
         const double blocks = std::floor(cu_lds / (double)L.bytes);
         double waves = blocks * (L.block / 64);
         if (waves > 16.0) waves = 16.0;
-        const double score = util * waves / 16.0;
+        const double score = lane_use(m, n, G, S) * waves / 16.0;
         if (score > best_score * 1.02) {
             best_score = score;
-            best = G;
+            best.group_lanes = S > 0 ? kBlock : G;
+            best.block_shots = S;
         }
-    }
+    };
+    for (int S = 1; S <= 16; ++S) consider(kBlock, S);
+    for (int G = 64; G >= 4; G /= 2) consider(G, 0);
     return best;
 }
 
@@ -386,7 +593,7 @@ static hipError_t launch_lds_kernel(const MixedArgs &args, size_t lds_bytes, hip
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     long groups = 0;
     for (int i = 0; i < args.ncodes; ++i) {
-        const long gpb = kBlock / args.codes[i].group_lanes;
+        const long gpb = args.codes[i].block_shots > 0 ? args.codes[i].block_shots : kBlock / args.codes[i].group_lanes;
         const long need = (args.codes[i].shots + gpb - 1) / gpb;
         groups = need > groups ? need : groups;
     }

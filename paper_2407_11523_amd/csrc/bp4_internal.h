@@ -61,8 +61,11 @@ struct DecodeArgs {
     float alpha_last;        // AEWA: discount of the last attempt
     int32_t alpha_steps;     // AEWA: attempts
     // LDS layout (words): workgroup-static part, then one region per shot group
-    int32_t static_words, region_words, q_off, acc_off, ehat_off;
-    int32_t group_lanes;     // lanes per shot: 4, 8, 16, 32, 64, 128 or 256
+    // or shot slot
+    int32_t static_words, region_words, q_off, acc_off, ehat_off, syn_off, hdr_off;
+    int32_t group_lanes;     // wave groups: lanes per shot (4, ..., 64); block slots: 256
+    int32_t block_shots;     // block slots: shots per workgroup (0: wave groups)
+    uint32_t magic_m, magic_n;   // ceil(2^32 / m), ceil(2^32 / n): item -> slot
     int32_t with_y;          // the code has Y entries
 };
 
@@ -73,15 +76,22 @@ struct MixedArgs {
     DecodeArgs codes[kMaxMixedCodes];
 };
 
-// LDS layout of the small-code kernel for one code, variant and group size.
+// LDS layout of the small-code kernel for one code, variant and lane mapping:
+// wave groups of G lanes per shot (S = 0) or S block slots sharing 256 lanes.
 struct LdsLayout {
-    int32_t static_words = 0, region_words = 0, q_off = 0, acc_off = 0, ehat_off = 0;
-    int32_t group_lanes = 0, block = 0;
+    int32_t static_words = 0, region_words = 0, q_off = 0, acc_off = 0, ehat_off = 0, syn_off = 0, hdr_off = 0;
+    int32_t group_lanes = 0, block_shots = 0, block = 0;
     size_t bytes = 0;        // dynamic LDS bytes per workgroup
 };
+struct LaneChoice {
+    int32_t group_lanes = -1, block_shots = 0;
+};
 
-LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes);
-int decode_lds_pick_group(int m, int n, int nnz, int variant, size_t max_lds);
+LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes, int block_shots);
+// The mapping is valid for the code: G a power of two in [4, 64] with at most 64
+// checks per lane, or 1 <= S <= 256 with at most 64 check items per lane.
+bool decode_lds_fits(int m, int n, int group_lanes, int block_shots);
+LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds);
 hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_t s, int *grid_out);
 
 hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const uint32_t thr[3],

@@ -1,7 +1,8 @@
 """Autotuner of the LDS decode kernel's launch shape.
 
-For each code it times every feasible lanes-per-shot size G (4 ... 256) on a
-sample of the code's own syndromes.  In a mixed launch every workgroup reserves
+For each code it times the feasible lane mappings on a sample of the code's own
+syndromes: wave groups of G = 4 ... 64 lanes per shot, and block slots of S
+shots sharing a 256-lane workgroup (the S values of best lane use that fit).  In a mixed launch every workgroup reserves
 the largest LDS layout of the batch, which sets the occupancy of all codes, so
 the tuner times each code under each candidate LDS budget (the single-code
 launch reserves that budget too) and keeps the budget whose summed, shot-scaled
@@ -22,16 +23,42 @@ from .api import Graph, Params, decode
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(PKG, "tuning_cache.json")
-GROUP_SIZES = (4, 8, 16, 32, 64, 128, 256)
+GROUP_SIZES = (4, 8, 16, 32, 64)
+BLOCK = 256
+MAX_BLOCK_CANDS = 4
 # LDS per workgroup that leaves 7, 6, 5, 4, 3 and 2 workgroups (28 ... 8 wavefronts) per CU
 BUDGETS = (23405, 27306, 32768, 40960, 54613, 81920)
 
 
-def layout_bytes(g: Graph, params: Params, lanes: int) -> Optional[int]:
+def layout_bytes(g: Graph, params: Params, lanes: int, block_shots: int = 0) -> Optional[int]:
     b = ctypes.c_size_t()
     cp = params.c()
-    rc = load().bp4_lds_layout_bytes(g.handle, ctypes.byref(cp), int(lanes), ctypes.byref(b))
+    rc = load().bp4_lds_layout_bytes(g.handle, ctypes.byref(cp), int(lanes), int(block_shots), ctypes.byref(b))
     return int(b.value) if rc == 0 else None
+
+
+def lane_use(m: int, n: int, G: int, S: int) -> float:
+    """Share of issued (lane, item) pairs that carry a check or a qubit."""
+    def use(k):
+        if S:
+            return S * k / (BLOCK * -(-S * k // BLOCK))
+        return k / (G * -(-k // G))
+    return 0.5 * (use(m) + use(n))
+
+
+def candidates(g: Graph, params: Params, budget: int) -> List[tuple]:
+    """(G, S) mappings whose layout fits `budget`: every wave group size and the
+    block-slot counts of best lane use (ties: fewer slots)."""
+    out = [(G, 0) for G in GROUP_SIZES if (layout_bytes(g, params, G) or budget + 1) <= budget]
+    blocks = []
+    for S in range(1, BLOCK + 1):
+        lb = layout_bytes(g, params, 0, S)
+        if lb is None or lb > budget:
+            break
+        blocks.append((-lane_use(g.m, g.n, 0, S), S))
+    blocks.sort()
+    out += [(0, S) for _, S in blocks[:MAX_BLOCK_CANDS]]
+    return out
 
 
 def code_key(g: Graph, params: Params, hx_hz_digest: str) -> str:
@@ -83,17 +110,17 @@ def _save_cache(c: dict, path: str) -> None:
 
 
 def tune_mixed(entries: Sequence, digests: Sequence[str], shots_total: Sequence[int],
-               sample: int = 1 << 15, use_cache: bool = True, save: bool = True,
+               sample: int = 1 << 17, use_cache: bool = True, save: bool = True,
                cache_path: str = CACHE) -> Dict:
-    """Pick G for every code of a mixed batch.
+    """Pick the lane mapping of every code of a mixed batch.
 
     entries: (graph, params, prior, synd) per code; synd holds at least `sample`
     rows (fewer are used as they are).  shots_total: shots per code in the real
-    run (weights of the per-code times).  Returns {"lanes": [...], "budget": B,
-    "table": ...}."""
+    run (weights of the per-code times).  Returns {"lanes": [[G, S], ...],
+    "budget": B, "table": ...}."""
     dev = entries[0][0].dev.device
     keys = [code_key(g, p, d) for (g, p, _, _), d in zip(entries, digests)]
-    batch_key = device_key(dev) + "|" + "|".join(keys)
+    batch_key = device_key(dev) + ":slots|" + "|".join(keys)
     cache = _load_cache(cache_path) if use_cache else {}
     if batch_key in cache:
         return dict(cache[batch_key], cached=True, key=batch_key.split("|")[0])
@@ -106,20 +133,18 @@ def tune_mixed(entries: Sequence, digests: Sequence[str], shots_total: Sequence[
         for (g, p, prior, synd), k, S in zip(entries, keys, shots_total):
             s = synd[:min(sample, synd.shape[0])]
             cands = []
-            for G in GROUP_SIZES:
-                lb = layout_bytes(g, p, G)
-                if lb is None or lb > B:
-                    continue
-                ms = _time(lambda: decode(g, p, prior, s, group_lanes=G, lds_bytes=B))
-                cands.append((ms, G))
+            for G, BS in candidates(g, p, B):
+                ms = _time(lambda: decode(g, p, prior, s, group_lanes=G, block_shots=BS, lds_bytes=B))
+                cands.append((ms, G, BS))
             if not cands:
                 total = float("inf")
-                lanes.append(0)
+                lanes.append([0, 0])
                 continue
-            ms, G = min(cands)
-            lanes.append(G)
+            ms, G, BS = min(cands)
+            lanes.append([G, BS])
             total += ms * S / max(1, s.shape[0])
-            rows.append({"code": k, "G": G, "ms": ms, "cands": {str(g_): t for t, g_ in cands}})
+            rows.append({"code": k, "G": G, "S": BS, "ms": ms,
+                         "cands": {f"{g_}x{s_}": t for t, g_, s_ in cands}})
         table[str(B)] = {"predicted_ms": total, "codes": rows}
         if best is None or total < best[0]:
             best = (total, B, lanes)

@@ -159,9 +159,13 @@ def test_mixed_and_plain_validation_without_gpu(lib):
     g = _graph(qecgen.toric(4))
     cp = Params(variant="momentum", alpha=0.5).c()
     arr[0] = _lib.CodeBatch(g.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
-                            fake.value, 0, 1)
+                            fake.value, 0, 300)
     arr[1] = arr[0]
-    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1          # reserved field set
+    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1          # block_shots above 256
+    assert b"block_shots" in lib.bp4_last_error()
+    arr[0].group_lanes, arr[0].block_shots = 64, 2
+    arr[1] = arr[0]
+    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1          # block_shots with a wave group
     assert lib.bp4_plain_workspace_bytes(g.handle, ctypes.byref(cp), 1000, ctypes.byref(b)) == 0
     assert b.value >= 1000 * (g.nnz * 4 + 2 * 3 * g.n * 4 + g.n)
     it = ctypes.c_int32()
@@ -256,3 +260,46 @@ def test_aewa_parameter_validation(lib):
         assert _err(lambda: g.workspace_bytes(bad, 10)) == "EINVAL"
     # the other variants ignore the AEWA fields
     assert g.workspace_bytes(Params(variant="ewainit", alpha=0.5, alpha_steps=0, alpha_last=7.0), 10) == 256
+
+
+def test_lane_mapping_validation_and_layout(lib):
+    """Block slots: the layout holds S regions (each with syndrome bytes and a header),
+    group_lanes 128 / 256 alone are 2 / 1 slots, and invalid mappings are rejected
+    before anything is enqueued."""
+    from paper_2407_11523_amd import Params, _lib
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    g = _graph(qecgen.planar(9))
+    cp = Params(variant="ewainit", alpha=0.5).c()
+
+    def layout(G, S):
+        b = ctypes.c_size_t()
+        rc = lib.bp4_lds_layout_bytes(g.handle, ctypes.byref(cp), G, S, ctypes.byref(b))
+        return rc, b.value
+
+    rc1, b1 = layout(256, 0)
+    rc2, b2 = layout(0, 1)
+    assert rc1 == 0 and rc2 == 0 and b1 == b2
+    assert layout(128, 0) == layout(256, 2) == layout(0, 2)
+    region = layout(0, 2)[1] - b2
+    assert layout(0, 3)[1] == b2 + 2 * region and layout(0, 4)[1] == b2 + 3 * region
+    # a region holds the messages, posteriors, decisions, syndrome bytes and a header
+    assert region >= 4 * (g.nnz + 1 + 3 * g.n) + g.n + g.m
+    assert layout(0, 0)[0] == -1           # no mapping
+    assert layout(64, 2)[0] == -1          # block_shots with a wave group
+    assert layout(0, 257)[0] == -1
+    assert layout(48, 0)[0] == -1
+    # more than 64 check items per lane
+    big = _graph(qecgen.toric(14))
+    b = ctypes.c_size_t()
+    assert lib.bp4_lds_layout_bytes(big.handle, ctypes.byref(cp), 0, 41, ctypes.byref(b)) == 0
+    assert lib.bp4_lds_layout_bytes(big.handle, ctypes.byref(cp), 0, 42, ctypes.byref(b)) == -1
+    for G, S in ((64, 1), (0, 300), (32, 4)):
+        tune = _lib.Tuning(G, 0, 0, 0, 0, S)
+        rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                               fake, null, null, null, fake, 256, null)
+        assert rc == -1, (G, S)
+    tune = _lib.Tuning(0, 0, 2, 0, 0, 2)   # block_shots with the SOA kernel
+    rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                           fake, null, null, null, fake, 1 << 30, null)
+    assert rc == -1

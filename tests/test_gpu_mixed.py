@@ -159,8 +159,8 @@ def test_autotuner_picks_feasible_sizes(tmp_path):
         shots.append(1 << 18)
     res = tune.tune_mixed(entries, digests, shots, sample=2048, cache_path=str(tmp_path / "c.json"))
     say("tuned", res["lanes"], res["budget"])
-    for (g, p, _, _), G in zip(entries, res["lanes"]):
-        assert G in tune.GROUP_SIZES
-        assert tune.layout_bytes(g, p, G) <= res["budget"]
+    for (g, p, _, _), (G, S) in zip(entries, res["lanes"]):
+        assert (G in tune.GROUP_SIZES and S == 0) or (G == 0 and S >= 1)
+        assert tune.layout_bytes(g, p, G, S) <= res["budget"]
     again = tune.tune_mixed(entries, digests, shots, sample=2048, cache_path=str(tmp_path / "c.json"))
     assert again["lanes"] == res["lanes"]
