@@ -24,6 +24,7 @@
 // (both anticommuting LLRs drop by m, which factors out of the denominator),
 // so lambda is evaluated once per (qubit, label) instead of once per edge.
 #include <cmath>
+#include <type_traits>
 
 #include "bp4_math.h"
 
@@ -93,11 +94,12 @@ __device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const float *s_
 
 // Posterior, hard decision and vertical update of qubit v at iteration t (eqs.
 // p_update, v_update and the variant's rule); `shot` indexes the optional
-// verification outputs (none are written for shot >= shots).
-template <int VAR>
+// verification outputs (none are written for shot >= shots).  WY: the code has Y
+// labels (else every edge label is X or Z).
+template <int VAR, bool WY>
 __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *s_vi, const float *s_pi, float *msg,
                                            float *qs, float *acc, uint8_t *ehat, int v, int t,
-                                           const VariantParams &vp, bool with_y, int shot)
+                                           const VariantParams &vp, int shot)
 {
     constexpr bool keep_q = VAR != BP4_BP;
     constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
@@ -113,7 +115,7 @@ __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *
 #pragma unroll
     for (int j = 0; j < 4; ++j) mc[j] = msg[base + j];
     float S[4], A[4];
-    label_sums(info, mc, with_y, keep_acc && VAR == BP4_ADAGRAD, S, A);
+    label_sums(info, mc, WY, keep_acc && VAR == BP4_ADAGRAD, S, A);
     const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
     float st[3] = {0.0f, 0.0f, 0.0f}, ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
     if (keep_q)
@@ -125,14 +127,17 @@ __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *
         for (int x = 0; x < 3; ++x) qs[3 * v + x] = st[x];
     if (keep_acc)
         for (int x = 0; x < 3; ++x) acc[3 * v + x] = ac[x];
-    ehat[v] = (uint8_t)decision_byte(hard_decision(qn));
+    ehat[v] = (uint8_t)decision_byte_of(qn);
     // Vertical update (eqs. v_update / mombp5): m_{v->c} = lambda_H(Q) - m_{c->v}.
     float lam[4];
-    qubit_lambdas(qn, var_labels_present(info), lam);
+    qubit_lambdas(qn, var_labels_present(info) & (WY ? 0xEu : 0x6u), lam);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if ((uint32_t)j >= deg) continue;
-        const float out = clampf(lam[var_lab(info, j)] - mc[j], C);
+        const uint32_t l = var_lab(info, j);   // 1 X, 2 Z, 3 Y
+        float lsel = l == 2u ? lam[2] : lam[1];
+        if (WY) lsel = l == 3u ? lam[3] : lsel;
+        const float out = clampf(lsel - mc[j], C);
         msg[base + j] = out;
         if (a.mvc_out && shot < a.shots) {
             const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
@@ -211,8 +216,12 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
             for (int c = r; c < m; c += G) check_node(s_ce, msg, c, (uint32_t)(sbits >> ((c - r) >> lgG)), C);
         }
         wave_sync();
-        if (live)
-            for (int v = r; v < n; v += G) qubit_node<VAR>(a, s_vi, s_pi, msg, qs, acc, ehat, v, t, vp, with_y, shot);
+        if (live) {
+            if (with_y)
+                for (int v = r; v < n; v += G) qubit_node<VAR, true>(a, s_vi, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
+            else
+                for (int v = r; v < n; v += G) qubit_node<VAR, false>(a, s_vi, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
+        }
         wave_sync();
         uint32_t bad = 0;
         if (live)
@@ -368,7 +377,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
         }
         __syncthreads();
         // ---- Posterior, hard decision and vertical update ----------------------------
-        {
+        auto qubit_phase = [&](auto wy) {
             // the slot's header is read when the walk enters the slot
             uint32_t cur = ~0u;
             int t = 0, shot = 0;
@@ -381,10 +390,13 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     if (VAR == BP4_AEWA) vp.alpha = __int_as_float(h[kHdrAlpha]);
                     cur = w.off;
                 }
-                qubit_node<VAR>(a, s_vi, s_pi, msg, msg + a.q_off, msg + a.acc_off,
-                                reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t, vp, with_y, shot);
+                qubit_node<VAR, decltype(wy)::value>(a, s_vi, s_pi, msg, msg + a.q_off, msg + a.acc_off,
+                                                     reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t, vp,
+                                                     shot);
             }
-        }
+        };
+        if (with_y) qubit_phase(std::true_type{});
+        else qubit_phase(std::false_type{});
         __syncthreads();
         // ---- Syndrome test of the hard decision (Algorithm 2) ---------------------------
         {

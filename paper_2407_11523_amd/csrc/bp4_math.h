@@ -226,15 +226,9 @@ __device__ __forceinline__ void qubit_posterior(const VariantParams &vp, int t, 
 // cannot converge).
 __device__ __forceinline__ uint32_t hard_decision(const float q[3])
 {
-    uint32_t e;
-    if (q[0] > 0.0f && q[1] > 0.0f && q[2] > 0.0f) {
-        e = 0u;
-    } else {
-        int b = 0;
-        if (q[1] < q[b]) b = 1;
-        if (q[2] < q[b]) b = 2;
-        e = b == 0 ? 1u : (b == 1 ? 3u : 2u);
-    }
+    const float mn = fminf(fminf(q[0], q[1]), q[2]);
+    uint32_t e = q[0] == mn ? 1u : (q[1] == mn ? 3u : 2u);
+    if (mn > 0.0f) e = 0u;
     if (isnan(q[0]) || isnan(q[1]) || isnan(q[2])) e = 0xFFu;
     return e;
 }
@@ -243,10 +237,22 @@ __device__ __forceinline__ uint32_t hard_decision(const float q[3])
 // anticommutes with (bit L for label L = 1 X, 2 Z, 3 Y; bit 0 marks a NaN
 // posterior), bits 4-5 hold the Pauli code itself.  A check then adds
 // <H_cv, E^_v> to its parity as bit H_cv of the byte.
+//   I: 0x00, X: 0x1C (anticommutes with Z, Y), Z: 0x2A (X, Y), Y: 0x36 (X, Z), NaN: 0x01
 __device__ __forceinline__ uint32_t decision_byte(uint32_t e)
 {
     if (e == 0xFFu) return 1u;                        // NaN: never satisfies a check
-    return ((0x6AC0u >> (4u * e)) & 0xFu) | (e << 4);  // I: 0, X: {Z,Y}, Z: {X,Y}, Y: {X,Z}
+    return ((0x6AC0u >> (4u * e)) & 0xFu) | (e << 4);
+}
+
+// The decision byte straight from the posterior (same result as
+// decision_byte(hard_decision(q)), without the intermediate code).
+__device__ __forceinline__ uint32_t decision_byte_of(const float q[3])
+{
+    const float mn = fminf(fminf(q[0], q[1]), q[2]);
+    uint32_t b = q[0] == mn ? 0x1Cu : (q[1] == mn ? 0x36u : 0x2Au);
+    if (mn > 0.0f) b = 0u;
+    if (isnan(q[0]) || isnan(q[1]) || isnan(q[2])) b = 1u;
+    return b;
 }
 __device__ __forceinline__ uint32_t decision_pauli(uint32_t byte) { return byte >> 4; }
 

@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                             for (int x = 0; x < 3; ++x) st[(size_t)(3 * v + x) * 64] = s3[k][x];
                         if (keep_acc)
                             for (int x = 0; x < 3; ++x) acc[(size_t)(3 * v + x) * 64] = a3[k][x];
-                        ehat[(size_t)v * 64] = (uint8_t)decision_byte(hard_decision(qn));
+                        ehat[(size_t)v * 64] = (uint8_t)decision_byte_of(qn);
                         float lam[4];
                         qubit_lambdas(qn, var_labels_present(info[k]), lam);
     #pragma unroll
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                         for (int x = 0; x < 3; ++x) st[(size_t)(3 * v + x) * 64] = s3[x];
                     if (keep_acc)
                         for (int x = 0; x < 3; ++x) acc[(size_t)(3 * v + x) * 64] = a3[x];
-                    ehat[(size_t)v * 64] = (uint8_t)decision_byte(hard_decision(qn));
+                    ehat[(size_t)v * 64] = (uint8_t)decision_byte_of(qn);
                     float lam[4];
                     qubit_lambdas(qn, var_labels_present(info), lam);
                     for (uint32_t j = 0; j < deg; ++j) {
