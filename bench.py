@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the step")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/adjoint measurement")
     ap.add_argument("--no-aewa", action="store_true", help="skip the AEWA-BP vs EWAInit-BP timing")
+    ap.add_argument("--no-biased", action="store_true", help="skip the biased-noise XZZX curves")
+    ap.add_argument("--no-serial", action="store_true", help="skip the serial-versus-flooding comparison")
     ap.add_argument("--only-large", action="store_true", help="run only the large-code (SOA) measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
@@ -302,7 +304,9 @@ def main():
 
     if not args.no_aewa:
         out["aewa"] = run_aewa(torch, qecgen, P, dev)
+    if not args.no_biased:
         out["biased_xzzx"] = run_biased(torch, qecgen, P, dev)
+    if not args.no_serial:
         out["serial"] = run_serial(torch, qecgen, P, dev)
 
     if not args.no_large:

@@ -73,9 +73,14 @@ typedef enum {
  *          1 serial schedule (Algorithm 1: qubit by qubit in index order, each
  *          qubit's incoming check messages from the current messages of the
  *          check's other qubits, then its posterior and outgoing messages).
- *          The serial schedule runs on the SOA kernel (bp4_decode chooses it;
- *          BP4_KERNEL_LDS, bp4_decode_mixed and bp4_decode_plain answer
- *          EUNSUPPORTED). */
+ *          On the LDS kernel (the automatic choice when 64-lane groups fit)
+ *          the sweep runs level by level: a qubit's level is one more than the
+ *          highest level of an earlier qubit sharing a check with it, so the
+ *          qubits of a level are updated together with the sequential result;
+ *          wave groups of group_lanes 1, 2, 4, ..., 64 lanes per shot
+ *          (block_shots must be 0).  Large codes take the SOA kernel, one lane
+ *          per shot.  Both give the same bits.  bp4_decode_mixed and
+ *          bp4_decode_plain answer EUNSUPPORTED. */
 typedef struct {
     int32_t variant;
     int32_t max_iter;

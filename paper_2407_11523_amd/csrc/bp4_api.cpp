@@ -49,9 +49,11 @@ struct bp4_graph {
     std::vector<uint32_t> vinfo;                 // [n]
     std::vector<uint32_t> vcanon;                // [nnz]
     std::vector<uint32_t> vchk;                  // [nnz] check of each message slot
+    std::vector<uint32_t> sord, slev;            // serial order as levels (see graph_create)
     std::vector<uint32_t> lptr, lent;            // logicals
     // byte offsets of the sections in the device image
-    size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_vchk = 0, off_lptr = 0, off_lent = 0, bytes = 0;
+    size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_vchk = 0, off_sord = 0, off_slev = 0, off_lptr = 0,
+           off_lent = 0, bytes = 0;
 
     void layout()
     {
@@ -60,6 +62,8 @@ struct bp4_graph {
         off_vinfo = o; o = align256(o + vinfo.size() * 4);
         off_vcanon = o; o = align256(o + vcanon.size() * 4);
         off_vchk = o; o = align256(o + vchk.size() * 4);
+        off_sord = o; o = align256(o + sord.size() * 4);
+        off_slev = o; o = align256(o + slev.size() * 4);
         off_lptr = o; o = align256(o + lptr.size() * 4);
         off_lent = o; o = align256(o + (lent.empty() ? 1 : lent.size()) * 4);
         bytes = o;
@@ -73,6 +77,9 @@ struct bp4_graph {
         v.vinfo = reinterpret_cast<const uint32_t *>(b + off_vinfo);
         v.vcanon = reinterpret_cast<const uint32_t *>(b + off_vcanon);
         v.vchk = reinterpret_cast<const uint32_t *>(b + off_vchk);
+        v.sord = reinterpret_cast<const uint32_t *>(b + off_sord);
+        v.slev = reinterpret_cast<const uint32_t *>(b + off_slev);
+        v.nlev = (int32_t)slev.size() - 1;
         v.lptr = reinterpret_cast<const uint32_t *>(b + off_lptr);
         v.lent = reinterpret_cast<const uint32_t *>(b + off_lent);
         v.m = m;
@@ -215,6 +222,29 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
     }
     g->vchk.assign(nnz, 0);
     for (long s = 0; s < nnz; ++s) g->vchk[s] = (uint32_t)g->canon_chk[g->vcanon[s]];
+    // Serial order (Algorithm 1) as levels: level(v) = 1 + the largest level of an
+    // earlier qubit sharing a check with v (0 if none).  Qubits of one level share
+    // no check, and every neighbour of v that precedes it in index order sits on a
+    // lower level, every later one on a higher level, so sweeping the levels in
+    // order, each level's qubits in parallel, reads and writes exactly what the
+    // qubit-by-qubit sweep does.  sord: qubits by (level, index); slev: offsets.
+    {
+        std::vector<int32_t> lev(n, 0), chk_top(m, -1);
+        int32_t nlev = 0;
+        for (int v = 0; v < n; ++v) {
+            int32_t l = 0;
+            for (int32_t s = vptr[v]; s < vptr[v + 1]; ++s) l = std::max(l, chk_top[g->vchk[s]] + 1);
+            lev[v] = l;
+            for (int32_t s = vptr[v]; s < vptr[v + 1]; ++s) chk_top[g->vchk[s]] = std::max(chk_top[g->vchk[s]], l);
+            nlev = std::max(nlev, l + 1);
+        }
+        g->slev.assign(nlev + 1, 0);
+        for (int v = 0; v < n; ++v) ++g->slev[lev[v] + 1];
+        for (int l = 0; l < nlev; ++l) g->slev[l + 1] += g->slev[l];
+        std::vector<uint32_t> pos(g->slev.begin(), g->slev.end() - 1);
+        g->sord.assign(n, 0);
+        for (int v = 0; v < n; ++v) g->sord[pos[lev[v]]++] = (uint32_t)v;
+    }
     // commutation of the rows: only pairs sharing a qubit can anticommute
     if (!(flags & BP4_ALLOW_ANTICOMMUTING)) {
         std::vector<std::vector<std::pair<int, uint32_t>>> vchk(n);
@@ -328,6 +358,8 @@ int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stre
     std::memcpy(img.data() + g->off_vinfo, g->vinfo.data(), g->vinfo.size() * 4);
     std::memcpy(img.data() + g->off_vcanon, g->vcanon.data(), g->vcanon.size() * 4);
     std::memcpy(img.data() + g->off_vchk, g->vchk.data(), g->vchk.size() * 4);
+    std::memcpy(img.data() + g->off_sord, g->sord.data(), g->sord.size() * 4);
+    std::memcpy(img.data() + g->off_slev, g->slev.data(), g->slev.size() * 4);
     std::memcpy(img.data() + g->off_lptr, g->lptr.data(), g->lptr.size() * 4);
     if (!g->lent.empty()) std::memcpy(img.data() + g->off_lent, g->lent.data(), g->lent.size() * 4);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -432,6 +464,62 @@ int auto_kernel(const bp4_graph *g, int variant)
                                                                                       : BP4_KERNEL_LDS;
 }
 
+// Serial schedule on the LDS kernel: wave groups of G in {1, 2, 4, ..., 64} lanes.
+// Lane use = the share of (lane, level pass) pairs that carry a qubit of the level.
+static double serial_lane_use(const bp4_graph *g, int G)
+{
+    double used = 0.0, issued = 0.0;
+    for (size_t l = 0; l + 1 < g->slev.size(); ++l) {
+        const double w = (double)(g->slev[l + 1] - g->slev[l]);
+        used += w;
+        issued += G * std::ceil(w / G);
+    }
+    return issued > 0.0 ? used / issued : 0.0;
+}
+
+static LdsLayout serial_layout(const bp4_graph *g, int variant, int G)
+{
+    return decode_lds_serial_layout(g->m, g->n, g->nnz, (int)g->slev.size() - 1, variant, G);
+}
+
+// The serial kernel the automatic choice takes: LDS when 64-lane groups fit
+// kLdsAutoLimit, else the SOA kernel.
+int serial_auto_kernel(const bp4_graph *g, int variant)
+{
+    return serial_layout(g, variant, 64).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA : BP4_KERNEL_LDS;
+}
+
+int choose_serial_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, size_t max_lds, int *out)
+{
+    if (S != 0) return fail(BP4_EINVAL, "decode: the serial schedule runs on wave groups (block_shots must be 0)");
+    if (G != 0 && G != 1 && G != 2 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64)
+        return fail(BP4_EINVAL, "decode: serial group_lanes %d not in {1, 2, 4, ..., 64}", G);
+    if (G) {
+        if (serial_layout(g, p->variant, G).bytes > max_lds)
+            return fail(BP4_EINVAL, "decode: serial group_lanes %d exceeds the LDS of a workgroup", G);
+        *out = G;
+        return BP4_OK;
+    }
+    // default: lane use over the level passes times the occupancy the LDS allows
+    const double cu_lds = 160.0 * 1024.0;
+    double best_score = -1.0;
+    int best = -1;
+    for (int c = 64; c >= 1; c /= 2) {
+        const LdsLayout L = serial_layout(g, p->variant, c);
+        if (L.bytes > max_lds) continue;
+        double waves = std::floor(cu_lds / (double)L.bytes) * (L.block / 64);
+        if (waves > 16.0) waves = 16.0;
+        const double score = serial_lane_use(g, c) * waves / 16.0;
+        if (score > best_score * 1.02) {
+            best_score = score;
+            best = c;
+        }
+    }
+    if (best < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the serial LDS kernel");
+    *out = best;
+    return BP4_OK;
+}
+
 // A requested lane mapping in range: group_lanes 0 or a power of two in [4, 256];
 // block_shots >= 0, only with group_lanes 0 or 256.
 int check_lanes(int32_t G, int32_t S, const char *who)
@@ -498,16 +586,17 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         if (soa_lanes < 0 || soa_block < 0) return fail(BP4_EINVAL, "decode: negative soa_lanes or soa_iter_block");
         requested = tune->group_lanes;
         requested_S = tune->block_shots;
-        rc = check_lanes(requested, requested_S, "decode");
-        if (rc) return rc;
+        if (!p->serial) {
+            rc = check_lanes(requested, requested_S, "decode");
+            if (rc) return rc;
+        }
     }
     const bool lds_knobs = requested || requested_S || lds_floor, soa_knobs = soa_lanes || soa_block;
     if (lds_knobs && soa_knobs) return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields exclude each other");
     if (kernel == BP4_KERNEL_AUTO)
-        kernel = p->serial ? BP4_KERNEL_SOA
-                 : lds_knobs ? BP4_KERNEL_LDS : soa_knobs ? BP4_KERNEL_SOA : auto_kernel(g, p->variant);
-    if (p->serial && kernel == BP4_KERNEL_LDS)
-        return fail(BP4_EUNSUPPORTED, "decode: the serial schedule runs on the SOA kernel");
+        kernel = lds_knobs ? BP4_KERNEL_LDS
+                 : soa_knobs ? BP4_KERNEL_SOA
+                 : p->serial ? serial_auto_kernel(g, p->variant) : auto_kernel(g, p->variant);
     if (kernel == BP4_KERNEL_LDS && soa_knobs)
         return fail(BP4_EINVAL, "decode: soa_lanes and soa_iter_block apply to the SOA kernel");
     if (kernel == BP4_KERNEL_SOA) {
@@ -523,10 +612,18 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     size_t max_lds = 0;
     rc = device_max_lds(&max_lds);
     if (rc) return rc;
-    LaneChoice lc;
-    rc = choose_lanes(g, p, requested, requested_S, max_lds, &lc);
-    if (rc) return rc;
-    const LdsLayout L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, lc.group_lanes, lc.block_shots);
+    LdsLayout L;
+    if (p->serial) {
+        int G = 0;
+        rc = choose_serial_lanes(g, p, requested, requested_S, max_lds, &G);
+        if (rc) return rc;
+        L = serial_layout(g, p->variant, G);
+    } else {
+        LaneChoice lc;
+        rc = choose_lanes(g, p, requested, requested_S, max_lds, &lc);
+        if (rc) return rc;
+        L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, lc.group_lanes, lc.block_shots);
+    }
     MixedArgs args;
     std::memset(&args, 0, sizeof args);
     args.ncodes = 1;
@@ -535,6 +632,7 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     args.codes[0].q_out = q_out;
     args.codes[0].mvc_out = mvc_out;
     args.codes[0].mcv_out = mcv_out;
+    args.codes[0].serial = p->serial;
     if ((size_t)lds_floor > max_lds) return fail(BP4_EINVAL, "decode: lds_bytes %d above the device limit", lds_floor);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_zero_u32(args.codes[0].counter, 1, s);
@@ -555,9 +653,8 @@ int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, 
     int rc = check_params(p);
     if (rc) return rc;
     if (shots < 0) return fail(BP4_EINVAL, "workspace_bytes: negative shots");
-    *bytes = (p->serial || auto_kernel(g, p->variant) == BP4_KERNEL_SOA)
-                 ? soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, 0)
-                 : kSmallWorkspace;
+    const int k = p->serial ? serial_auto_kernel(g, p->variant) : auto_kernel(g, p->variant);
+    *bytes = k == BP4_KERNEL_SOA ? soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, 0) : kSmallWorkspace;
     return BP4_OK;
 }
 
@@ -731,6 +828,12 @@ extern "C" int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int
     int rc = check_params(p);
     if (rc) return rc;
     int G = group_lanes, S = block_shots;
+    if (p->serial) {
+        if (S != 0 || (G != 1 && G != 2 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64))
+            return fail(BP4_EINVAL, "lds_layout_bytes: the serial schedule takes group_lanes 1 ... 64 and no block_shots");
+        *bytes = serial_layout(g, p->variant, G).bytes;
+        return BP4_OK;
+    }
     rc = check_lanes(G, S, "lds_layout_bytes");
     if (rc) return rc;
     if (G == 0 && S == 0) return fail(BP4_EINVAL, "lds_layout_bytes: no lane mapping given");

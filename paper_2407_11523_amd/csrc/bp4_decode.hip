@@ -93,27 +93,21 @@ __device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const float *s_
 }
 
 // Posterior, hard decision and vertical update of qubit v at iteration t (eqs.
-// p_update, v_update and the variant's rule); `shot` indexes the optional
-// verification outputs (none are written for shot >= shots).  WY: the code has Y
-// labels (else every edge label is X or Z).
-template <int VAR, bool WY>
-__device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *s_vi, const float *s_pi, float *msg,
-                                           float *qs, float *acc, uint8_t *ehat, int v, int t,
-                                           const VariantParams &vp, int shot)
+// p_update, v_update and the variant's rule) from its incoming messages mc[j]
+// (slot order; slots j >= degree carry label 0 and are never used).  The new
+// m_{v->c} of slot base + j goes to store(slot, value).  `shot` indexes the
+// optional verification outputs (none are written for shot >= shots).  WY: the
+// code has Y labels (else every edge label is X or Z).
+template <int VAR, bool WY, typename Store>
+__device__ __forceinline__ void qubit_update(const DecodeArgs &a, const float *s_pi, uint32_t info, int v,
+                                             const float mc[4], float *qs, float *acc, uint8_t *ehat, int t,
+                                             const VariantParams &vp, int shot, Store store)
 {
     constexpr bool keep_q = VAR != BP4_BP;
     constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
     const float C = a.clamp;
     const int n = a.g.n;
-    const uint32_t info = s_vi[v];
     const uint32_t base = var_base(info), deg = var_deg(info);
-    // the words after a qubit's last slot are in the region (another qubit's
-    // slots, the padding slot or the posterior array); they are read but never
-    // used: those slots carry label 0, which the label sums skip, and no message
-    // is written for them
-    float mc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) mc[j] = msg[base + j];
     float S[4], A[4];
     label_sums(info, mc, WY, keep_acc && VAR == BP4_ADAGRAD, S, A);
     const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
@@ -131,6 +125,7 @@ __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *
     // Vertical update (eqs. v_update / mombp5): m_{v->c} = lambda_H(Q) - m_{c->v}.
     float lam[4];
     qubit_lambdas(qn, var_labels_present(info) & (WY ? 0xEu : 0x6u), lam);
+    const bool trace = a.mvc_out && shot < a.shots;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if ((uint32_t)j >= deg) continue;
@@ -138,8 +133,8 @@ __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *
         float lsel = l == 2u ? lam[2] : lam[1];
         if (WY) lsel = l == 3u ? lam[3] : lsel;
         const float out = clampf(lsel - mc[j], C);
-        msg[base + j] = out;
-        if (a.mvc_out && shot < a.shots) {
+        store(base + j, out);
+        if (trace) {
             const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
             a.mvc_out[o] = out;
             a.mcv_out[o] = mc[j];
@@ -147,6 +142,25 @@ __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *
     }
     if (a.q_out && shot < a.shots)
         for (int x = 0; x < 3; ++x) a.q_out[((size_t)shot * n + v) * 3 + x] = qn[x];
+}
+
+// Flooding qubit step: the incoming messages are the slots' m_{c->v}.
+template <int VAR, bool WY>
+__device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *s_vi, const float *s_pi, float *msg,
+                                           float *qs, float *acc, uint8_t *ehat, int v, int t,
+                                           const VariantParams &vp, int shot)
+{
+    const uint32_t info = s_vi[v];
+    const uint32_t base = var_base(info);
+    // the words after a qubit's last slot are in the region (another qubit's
+    // slots, the padding slot or the posterior array); they are read but never
+    // used: those slots carry label 0, which the label sums skip, and no message
+    // is written for them
+    float mc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mc[j] = msg[base + j];
+    qubit_update<VAR, WY>(a, s_pi, info, v, mc, qs, acc, ehat, t, vp, shot,
+                          [&](uint32_t slot, float out) { msg[slot] = out; });
 }
 
 template <int VAR>
@@ -230,6 +244,140 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
         const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
         const bool sat = (ballot & gmask) == 0;
         // AEWA: a failed attempt restarts the shot with the next discount
+        const bool restart = VAR == BP4_AEWA && live && !sat && t >= a.max_iter && att + 1 < a.alpha_steps;
+        const bool fin = live && !restart && ((a.stop && sat) || t >= a.max_iter);
+        if (fin) {
+            for (int v = r; v < n; v += G) a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(ehat[v]);
+            if (r == 0) {
+                a.conv[shot] = sat ? 1 : 0;
+                a.iters[shot] = t_before + t;
+            }
+        }
+        if (VAR == BP4_AEWA && (fin || restart)) {
+            t_before = restart ? t_before + t : 0;
+            att = restart ? att + 1 : 0;
+            vp.alpha = aewa_alpha(a.alpha, a.alpha_last, a.alpha_steps, att);
+        }
+        wave_sync();
+        if (fin) {
+            s0 = 0;
+            if (r == 0) s0 = take_shot(a.counter, a.shots);
+            shot = __shfl(s0, lead, 64);
+            if (shot < a.shots) init(shot);
+        } else if (restart) {
+            init(shot);
+        }
+        wave_sync();
+    }
+}
+
+// ---- Serial schedule (Algorithm 1) on wave groups -----------------------------------
+// One sweep visits the qubits level by level (graph image: sord, slev): the
+// qubits of a level share no check, so a group's lanes update them together and
+// the result is the qubit-by-qubit sweep's, bit for bit.  A qubit's incoming
+// m_{c->v} are formed from the current m_{v'->c} of each check's other qubits,
+// as phi((f0 + f1) + (f2 + f3)) over the check's four edge positions (this
+// qubit's edge and padding contributing 0).  The slots hold f = phi(|m_{v->c}|)
+// with the sign of m_{v->c} (the value phi would be applied to when the message
+// is read), so a message is passed through phi once, when it is written.
+// Static LDS adds the slot -> check table and the level order; the syndrome is
+// kept as bytes in the region.
+template <int VAR, bool WY>
+__device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
+{
+    const int G = a.group_lanes;
+    const int lgG = __builtin_ctz((unsigned)G);
+    const int m = a.g.m, n = a.g.n, nnz = a.g.nnz;
+    const uint32_t *s_ce = reinterpret_cast<const uint32_t *>(lds);
+    const uint32_t *s_vi = s_ce + kMaxCheckDeg * m;
+    const float *s_pi = reinterpret_cast<const float *>(s_vi + n);
+    const uint32_t *s_vchk = reinterpret_cast<const uint32_t *>(s_pi + 3 * n);
+    const uint32_t *s_ord = s_vchk + nnz;
+    const uint32_t *s_lev = s_ord + n;
+
+    const int gid = (int)threadIdx.x >> lgG;
+    const int r = (int)threadIdx.x & (G - 1);
+    const int lead = (((int)threadIdx.x & 63) >> lgG) << lgG;
+    float *fs = lds + a.static_words + gid * a.region_words;   // [nnz] signed phi(|m_{v->c}|)
+    float *qs = fs + a.q_off;
+    float *acc = fs + a.acc_off;
+    uint8_t *ehat = reinterpret_cast<uint8_t *>(fs + a.ehat_off);
+    uint8_t *syn = reinterpret_cast<uint8_t *>(fs + a.syn_off);
+
+    const float C = a.clamp;
+    VariantParams vp = variant_params<VAR>(a);
+    auto store = [&](uint32_t slot, float out) {
+        const float f = phi(fabsf(out));
+        fs[slot] = out < 0.0f ? -f : f;
+    };
+
+    int t = 0, att = 0, t_before = 0;
+    auto init = [&](int s) {
+        for (int c = r; c < m; c += G) syn[c] = a.synd[(size_t)s * m + c];
+        for (int v = r; v < n; v += G) {
+            const uint32_t info = s_vi[v];
+            const uint32_t base = var_base(info), deg = var_deg(info);
+            const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
+            float lam[4];
+            qubit_lambdas(p3, var_labels_present(info), lam);
+            for (uint32_t j = 0; j < deg; ++j) store(base + j, clampf(lam[var_lab(info, j)], C));
+            float st[3], ac[3];
+            qubit_state_init(VAR, p3, st, ac);
+            if (VAR != BP4_BP)
+                for (int w = 0; w < 3; ++w) qs[3 * v + w] = st[w];
+            if (VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD)
+                for (int w = 0; w < 3; ++w) acc[3 * v + w] = ac[w];
+        }
+        t = 0;
+    };
+
+    // one qubit of the sweep
+    auto serial_qubit = [&](int v, int shot) {
+        const uint32_t info = s_vi[v];
+        const uint32_t base = var_base(info), deg = var_deg(info);
+        float mc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (uint32_t j = 0; j < deg; ++j) {
+            const uint32_t slot = base + j;
+            const uint32_t c = s_vchk[slot];
+            const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
+            const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+            uint32_t neg = syn[c] & 1u;
+            float f[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                // padding and this qubit's own edge take no part
+                const bool skip = edge_is_pad(w[k]) || edge_slot(w[k]) == slot;
+                const float x = skip ? 0.0f : fs[edge_slot(w[k])];
+                neg ^= __float_as_uint(x) >> 31;
+                f[k] = fabsf(x);
+            }
+            const float mag = phi((f[0] + f[1]) + (f[2] + f[3]));
+            mc[j] = clampf(neg ? -mag : mag, C);
+        }
+        qubit_update<VAR, WY>(a, s_pi, info, v, mc, qs, acc, ehat, t, vp, shot, store);
+    };
+
+    int s0 = 0;
+    if (r == 0) s0 = take_shot(a.counter, a.shots);
+    int shot = __shfl(s0, lead, 64);
+    if (shot < a.shots) init(shot);
+    wave_sync();
+
+    for (;;) {
+        const bool live = shot < a.shots;
+        if (!__any(live)) break;
+        if (live) ++t;
+        for (int l = 0; l < a.g.nlev; ++l) {
+            if (live)
+                for (int i = (int)s_lev[l] + r; i < (int)s_lev[l + 1]; i += G) serial_qubit((int)s_ord[i], shot);
+            wave_sync();
+        }
+        uint32_t bad = 0;
+        if (live)
+            for (int c = r; c < m; c += G) bad |= test_node(s_ce, ehat, c, syn[c]);
+        const uint64_t ballot = __ballot(bad != 0);
+        const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
+        const bool sat = (ballot & gmask) == 0;
         const bool restart = VAR == BP4_AEWA && live && !sat && t >= a.max_iter && att + 1 < a.alpha_steps;
         const bool fin = live && !restart && ((a.stop && sat) || t >= a.max_iter);
         if (fin) {
@@ -492,8 +640,34 @@ decode_lds_kernel(MixedArgs args)
         for (int i = threadIdx.x; i < kMaxCheckDeg * m; i += kBlock) s_ce[i] = a.g.cedge[i];
         for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
+        if (VSET < 0 && a.serial) {   // slot -> check table and the level order
+            uint32_t *s_vchk = reinterpret_cast<uint32_t *>(s_pi + 3 * n);
+            uint32_t *s_ord = s_vchk + a.g.nnz;
+            uint32_t *s_lev = s_ord + n;
+            for (int i = threadIdx.x; i < a.g.nnz; i += kBlock) s_vchk[i] = a.g.vchk[i];
+            for (int i = threadIdx.x; i < n; i += kBlock) s_ord[i] = a.g.sord[i];
+            for (int i = threadIdx.x; i <= a.g.nlev; i += kBlock) s_lev[i] = a.g.slev[i];
+        }
         __syncthreads();
-        if (VSET < 0) {
+        if (VSET < 0 && a.serial) {
+            if (a.with_y) {
+                switch (a.variant) {
+                case BP4_BP: run_serial<BP4_BP, true>(a, lds); break;
+                case BP4_MOMENTUM: run_serial<BP4_MOMENTUM, true>(a, lds); break;
+                case BP4_ADAGRAD: run_serial<BP4_ADAGRAD, true>(a, lds); break;
+                case BP4_AEWA: run_serial<BP4_AEWA, true>(a, lds); break;
+                default: run_serial<BP4_EWAINIT, true>(a, lds); break;
+                }
+            } else {
+                switch (a.variant) {
+                case BP4_BP: run_serial<BP4_BP, false>(a, lds); break;
+                case BP4_MOMENTUM: run_serial<BP4_MOMENTUM, false>(a, lds); break;
+                case BP4_ADAGRAD: run_serial<BP4_ADAGRAD, false>(a, lds); break;
+                case BP4_AEWA: run_serial<BP4_AEWA, false>(a, lds); break;
+                default: run_serial<BP4_EWAINIT, false>(a, lds); break;
+                }
+            }
+        } else if (VSET < 0) {
             switch (a.variant) {
             case BP4_BP: run_code<BP4_BP>(a, lds, &events); break;
             case BP4_MOMENTUM: run_code<BP4_MOMENTUM>(a, lds, &events); break;
@@ -538,6 +712,28 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S)
     L.block = kBlock;
     const int regions = S > 0 ? S : kBlock / G;
     L.bytes = (size_t)4 * (L.static_words + (size_t)regions * L.region_words);
+    return L;
+}
+
+LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant, int G)
+{
+    LdsLayout L;
+    L.static_words = kMaxCheckDeg * m + n + 3 * n + nnz + n + nlev + 1;
+    if (L.static_words & 3) L.static_words += 4 - (L.static_words & 3);
+    int w = nnz;                   // signed phi of each m_{v->c}
+    L.q_off = w;
+    if (variant != BP4_BP) w += 3 * n;
+    L.acc_off = w;
+    if (variant == BP4_MOMENTUM || variant == BP4_ADAGRAD) w += 3 * n;
+    L.ehat_off = w;
+    w += (n + 3) / 4;
+    L.syn_off = w;
+    w += (m + 3) / 4;
+    if ((w & 1) == 0) w += 1;
+    L.region_words = w;
+    L.group_lanes = G;
+    L.block = kBlock;
+    L.bytes = (size_t)4 * (L.static_words + (size_t)(kBlock / G) * L.region_words);
     return L;
 }
 
@@ -622,6 +818,8 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
     int v = args.codes[0].variant;
     for (int i = 1; i < args.ncodes; ++i)
         if (args.codes[i].variant != v) v = -1;
+    for (int i = 0; i < args.ncodes; ++i)
+        if (args.codes[i].serial) v = -1;   // only the generic build carries the serial sweep
     switch (v) {
     case BP4_BP: return launch_lds_kernel<BP4_BP>(args, lds_bytes, s, grid_out);
     case BP4_MOMENTUM: return launch_lds_kernel<BP4_MOMENTUM>(args, lds_bytes, s, grid_out);

@@ -39,9 +39,11 @@ struct GraphView {
     const uint32_t *vinfo;   // [n] packed qubit words
     const uint32_t *vcanon;  // [nnz] canonical (row-major) edge id of each message slot
     const uint32_t *vchk;    // [nnz] check of each message slot
+    const uint32_t *sord;    // [n] qubits in serial-schedule levels (level, then index)
+    const uint32_t *slev;    // [nlev + 1] level offsets into sord
     const uint32_t *lptr;    // [nlog + 1] offsets into lent
     const uint32_t *lent;    // logical supports: qubit | (Pauli << 16)
-    int32_t m, n, nnz, nlog;
+    int32_t m, n, nnz, nlog, nlev;
 };
 
 struct DecodeArgs {
@@ -67,6 +69,7 @@ struct DecodeArgs {
     int32_t block_shots;     // block slots: shots per workgroup (0: wave groups)
     uint32_t magic_m, magic_n;   // ceil(2^32 / m), ceil(2^32 / n): item -> slot
     int32_t with_y;          // the code has Y entries
+    int32_t serial;          // serial schedule (Algorithm 1) on wave groups
 };
 
 // Codes of one persistent launch, decoded in this order (largest first).
@@ -88,6 +91,9 @@ struct LaneChoice {
 };
 
 LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes, int block_shots);
+// Serial schedule: wave groups of G in {1, ..., 64} lanes; static part adds the
+// slot -> check table and the level order, regions hold signed phi values.
+LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant, int group_lanes);
 // The mapping is valid for the code: G a power of two in [4, 64] with at most 64
 // checks per lane, or 1 <= S <= 256 with at most 64 check items per lane.
 bool decode_lds_fits(int m, int n, int group_lanes, int block_shots);

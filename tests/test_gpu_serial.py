@@ -1,4 +1,6 @@
-"""GPU: the serial schedule (Algorithm 1) on the SOA kernel against the oracle.
+"""GPU: the serial schedule (Algorithm 1) on the LDS kernel (level by level) and
+the SOA kernel against the oracle, and the two kernels against each other bit for
+bit.
 
 Bar: messages and posteriors after iteration 1 (stopping off) within the 1e-5
 bar of the flooding kernels; after iterations 2 and 3, at least 99.9% within
@@ -59,9 +61,12 @@ def test_serial_messages(variant, alpha, T):
         _, syn = O.sample(hx, hz, 700, qecgen.thresholds(*probs[0]), seed=13)
         ro = O.decode(hx, hz, O.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False,
                                        serial=True), O.prior_llr(probs), syn, want_q=True, want_msgs=True)
-        rg = P.decode(g, P.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False, serial=True),
-                      P.prior_llr(probs), torch.as_tensor(syn, device="cuda"), trace=True)
+        prm = P.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False, serial=True)
+        rg = P.decode(g, prm, P.prior_llr(probs), torch.as_tensor(syn, device="cuda"), trace=True)
+        rs = P.decode(g, prm, P.prior_llr(probs), torch.as_tensor(syn, device="cuda"), trace=True, kernel="soa")
         torch.cuda.synchronize()
+        for k in ("est", "conv", "iters", "mvc", "mcv", "q"):   # LDS levels == SOA sweep, bit for bit
+            assert torch.equal(rg[k], rs[k]), (name, variant, T, k)
         for k in ("mvc", "mcv", "q"):
             err = np.abs(np_(rg[k]).astype(np.float64) - ro[k]) / np.maximum(np.abs(ro[k]), 1.0)
             say("serial msg", name, variant, T, k, float(err.max()), float((err <= REL_TOL).mean()))
@@ -85,8 +90,11 @@ def test_serial_decisions_and_ler(make, p, variant, alpha):
     if variant == "aewa":
         kw.update(alpha_last=0.0, alpha_steps=6)
     r = P.decode(g, P.Params(**kw), P.prior_llr(qecgen.depolarizing_probs(code.n, p)), syn)
+    rs = P.decode(g, P.Params(**kw), P.prior_llr(qecgen.depolarizing_probs(code.n, p)), syn, kernel="soa")
     _, cnt = P.bookkeep(g, err, r["est"])
     torch.cuda.synchronize()
+    for k in ("est", "conv", "iters"):
+        assert torch.equal(r[k], rs[k]), k
     ro = O.decode(code.hx, code.hz, O.Params(**{k: v for k, v in kw.items()}),
                   O.prior_llr(qecgen.depolarizing_probs(code.n, p)), np_(syn))
     _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, np_(err), ro["est"])
@@ -106,8 +114,34 @@ def test_serial_rejected_where_unsupported():
     syn = torch.zeros(10, code.m, dtype=torch.uint8, device="cuda")
     pr = P.prior_llr(qecgen.depolarizing_probs(code.n, 0.05))
     prm = P.Params(variant="ewainit", alpha=0.5, serial=True)
-    for call in (lambda: P.decode(g, prm, pr, syn, kernel="lds"), lambda: P.decode_plain(g, prm, pr, syn),
-                 lambda: P.decode_mixed([(g, prm, pr, syn, 0)])):
+    for call in (lambda: P.decode_plain(g, prm, pr, syn), lambda: P.decode_mixed([(g, prm, pr, syn, 0)])):
         with pytest.raises(P.BP4Error) as e:
             call()
         assert e.value.name == "EUNSUPPORTED"
+    for kw in (dict(block_shots=2), dict(group_lanes=128), dict(group_lanes=3)):
+        with pytest.raises(P.BP4Error) as e:
+            P.decode(g, prm, pr, syn, **kw)
+        assert e.value.name == "EINVAL"
+
+
+@pytest.mark.parametrize("make", [lambda: qecgen.toric(6), lambda: qecgen.xzzx(5)])
+def test_serial_group_sizes_bitwise(make):
+    """Every serial group size (including 1 and 2 lanes per shot) and the SOA sweep
+    give the same bits; ragged shot counts."""
+    code = make()
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, 0.1))
+    for variant, kw in (("ewainit", dict(alpha=0.5)), ("aewa", dict(alpha=1.0, alpha_last=0.2, alpha_steps=4,
+                                                                   max_iter=10))):
+        prm = P.Params(variant=variant, serial=True, **dict(dict(max_iter=40), **kw))
+        for shots in (1, 257, 2000):
+            _, syn = P.sample(g, shots, qecgen.thresholds(0.1 / 3, 0.1 / 3, 0.1 / 3), seed=shots)
+            ref = P.decode(g, prm, pr, syn, kernel="soa")
+            for G in (1, 2, 4, 16, 64):
+                try:
+                    r = P.decode(g, prm, pr, syn, group_lanes=G)
+                except P.BP4Error:      # LDS exhausted at this size
+                    continue
+                torch.cuda.synchronize()
+                for k in ("est", "conv", "iters"):
+                    assert torch.equal(r[k], ref[k]), (variant, shots, G, k)
