@@ -36,13 +36,34 @@ CODES = [("planar", 5, 1), ("planar", 7, 1), ("planar", 9, 2), ("planar", 11, 4)
          ("toric", 6, 1), ("toric", 10, 2), ("toric", 14, 4),
          ("xzzx", 5, 1), ("xzzx", 9, 2), ("xzzx", 13, 4)]
 
-# Roofline of the LDS-resident decode: VALU issue.  Algorithmic work per edge
-# update (one message each way on one Tanner edge in one iteration): 4
-# transcendentals (two phi on the check side, lambda amortised over the qubit's
-# edges on the other) and 16 FP32 operations; a transcendental occupies 4 issue
-# slots, so 32 FP32 issue slots per edge update.  Peak issue: 256 CUs x 4 SIMDs
-# x 16 lanes x 2.4 GHz = 39.3e12 slots/s.
-SLOTS_PER_EDGE_UPDATE = 32
+# Roofline of the LDS-resident decode: VALU issue.  Algorithmic FP32 issue slots of
+# one EWAInit iteration of one shot, counted from the update rules: phi = 8 FP32
+# operations + one exp2 or log2; ln(1 + e^-|y|) = 4 operations + 2 transcendentals;
+# a transcendental costs TRANS_SLOTS plain FP32 issue slots (measured by
+# paper_2407_11523_amd/calib/valu_rate: exp2 1.76, log2 1.74).
+#   check of degree d: 2d phi, d sign products, 2d - 1 leave-one-out sums, d sign
+#                      applications, d clamps; syndrome test d + 1  -> 22d ops, 2d transcendentals
+#   qubit of degree d with L labels present: d + 3 label sums, 9 posterior (EWAInit),
+#                      5 hard decision, L lambdas (two softplus + 4 ops each), 2d
+#                      output subtractions and clamps               -> 3d + 17 + 12L ops, 4L transcendentals
+# so an iteration costs 25 E + 17 N + 12 sum(L) operations and 2 E + 4 sum(L)
+# transcendentals (E edges, N qubits).  Peak issue: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = 39.3e12 slots/s (the calibration measures 37.3e12 for adds).
+TRANS_SLOTS = 1.75
+
+
+def iteration_slots(code):
+    """Algorithmic FP32 issue slots of one EWAInit iteration of one shot of `code`."""
+    import numpy as np
+    lab = code.labels()
+    E = int((lab != 0).sum())
+    N = code.n
+    L = int(sum(len(set(int(x) for x in np.unique(lab[:, v])) - {0}) for v in range(N)))
+    ops = 25 * E + 17 * N + 12 * L
+    trans = 2 * E + 4 * L
+    return ops + TRANS_SLOTS * trans
+
+
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # two-sided normal quantile for a 95% family-wise interval over the 11 codes (0.05 / 11)
 Z_FAMILY = 2.8376
@@ -143,7 +164,7 @@ def main():
         syn = torch.empty((shots, code.m), dtype=torch.uint8, device=dev)
         counts = torch.zeros(3, dtype=torch.int64, device=dev)
         items.append(dict(code=code, g=g, prior=pr, err=err, syn=syn, counts=counts, shots=shots,
-                          seed=qecgen.config_seed(3, i, 0)))
+                          slots=iteration_slots(code), seed=qecgen.config_seed(3, i, 0)))
     # launch shape per code from the autotuner (timed on the first 2^17 syndromes of each code)
     lanes = [0] * len(items)
     tuned = None
@@ -198,17 +219,19 @@ def main():
     # work of the last step (every step decodes the same seeded syndromes)
     edge_updates = 0
     iters_total = 0
+    slots = 0.0
     ler = {}
     fails = {}
     for it, o in zip(items, batch.outs):
         s = int(o["iters"].to(torch.int64).sum())
         iters_total += s
         edge_updates += s * it["code"].nnz
+        slots += s * it["slots"]
         c = it["counts"].cpu().numpy()
         fails[it["code"].name] = (int(c[1] + c[2]), it["shots"])
         ler[it["code"].name] = round(float(c[1] + c[2]) / it["shots"], 6)
     eups = edge_updates / (dec_ms / 1e3)
-    achieved = edge_updates * SLOTS_PER_EDGE_UPDATE / (dec_ms / 1e3)
+    achieved = slots / (dec_ms / 1e3)
     log(f"step {ms:.2f} ms, decode {dec_ms:.2f} ms, {eups:.3e} edge-updates/s, avg iters {iters_total / total_shots:.2f}")
 
     out = {
@@ -224,7 +247,8 @@ def main():
         "decode_ms": dec_ms, "edge_updates_per_s": eups, "avg_iters": iters_total / total_shots,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic("decode_lds_kernel"),
-                     "kernel": "decode_lds_kernel", "ops_per_edge_update": SLOTS_PER_EDGE_UPDATE},
+                     "kernel": "decode_lds_kernel", "slots_per_edge_update": slots / edge_updates,
+                     "trans_slots": TRANS_SLOTS},
         "ler": ler,
     }
 

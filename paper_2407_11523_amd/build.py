@@ -56,9 +56,23 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    _build_calibration()
     if verbose:
         print("built", LIB)
     return LIB
+
+
+CALIB_SRC = os.path.join(PKG, "calib", "valu_rate.hip")
+CALIB_BIN = os.path.join(PKG, "calib", "valu_rate")
+
+
+def _build_calibration() -> None:
+    """The VALU issue-rate calibration program (measures the roofline's peaks)."""
+    cmd = [hipcc(), "-x", "hip", CALIB_SRC, "-o", CALIB_BIN + ".tmp"] + HIP_FLAGS
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the calibration program:\n{r.stdout}\n{r.stderr}")
+    os.replace(CALIB_BIN + ".tmp", CALIB_BIN)
 
 
 if __name__ == "__main__":
