@@ -609,8 +609,6 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
 #undef BP4_FOR_QUBITS
 }
 
-// VSET: the variant every code of the launch uses, or -1 for a launch that mixes
-// variants (a switch per code).  At most 96 VGPRs, so five wavefronts fit per SIMD.
 template <int VAR>
 __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *events)
 {
@@ -618,8 +616,16 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *e
     else run_wave<VAR>(a, lds);
 }
 
+// VSET: the variant every code of the launch uses, kMixedVariants for a flooding
+// launch that mixes variants (a switch per code), kSerial for the serial schedule
+// (one code, a switch on its variant).  Register budget: 72 VGPRs (seven
+// wavefronts per SIMD) for the single-variant builds that fit it without spilling,
+// 96 (five) for AdaGrad and the switching builds.
+constexpr int kMixedVariants = -1, kSerial = -2;
+constexpr int lds_kernel_waves(int vset) { return (vset < 0 || vset == BP4_ADAGRAD) ? 5 : 7; }
+
 template <int VSET>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(lds_kernel_waves(VSET))))
 decode_lds_kernel(MixedArgs args)
 {
     // 16-byte aligned: the packed check edges are read as 16-byte vectors
@@ -640,7 +646,7 @@ decode_lds_kernel(MixedArgs args)
         for (int i = threadIdx.x; i < kMaxCheckDeg * m; i += kBlock) s_ce[i] = a.g.cedge[i];
         for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
-        if (VSET < 0 && a.serial) {   // slot -> check table and the level order
+        if (VSET == kSerial) {   // slot -> check table and the level order
             uint32_t *s_vchk = reinterpret_cast<uint32_t *>(s_pi + 3 * n);
             uint32_t *s_ord = s_vchk + a.g.nnz;
             uint32_t *s_lev = s_ord + n;
@@ -649,7 +655,7 @@ decode_lds_kernel(MixedArgs args)
             for (int i = threadIdx.x; i <= a.g.nlev; i += kBlock) s_lev[i] = a.g.slev[i];
         }
         __syncthreads();
-        if (VSET < 0 && a.serial) {
+        if (VSET == kSerial) {
             if (a.with_y) {
                 switch (a.variant) {
                 case BP4_BP: run_serial<BP4_BP, true>(a, lds); break;
@@ -667,7 +673,7 @@ decode_lds_kernel(MixedArgs args)
                 default: run_serial<BP4_EWAINIT, false>(a, lds); break;
                 }
             }
-        } else if (VSET < 0) {
+        } else if (VSET == kMixedVariants) {
             switch (a.variant) {
             case BP4_BP: run_code<BP4_BP>(a, lds, &events); break;
             case BP4_MOMENTUM: run_code<BP4_MOMENTUM>(a, lds, &events); break;
@@ -818,15 +824,16 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
     int v = args.codes[0].variant;
     for (int i = 1; i < args.ncodes; ++i)
         if (args.codes[i].variant != v) v = -1;
-    for (int i = 0; i < args.ncodes; ++i)
-        if (args.codes[i].serial) v = -1;   // only the generic build carries the serial sweep
+    bool serial = false;
+    for (int i = 0; i < args.ncodes; ++i) serial = serial || args.codes[i].serial;
+    if (serial) return launch_lds_kernel<kSerial>(args, lds_bytes, s, grid_out);   // a single code
     switch (v) {
     case BP4_BP: return launch_lds_kernel<BP4_BP>(args, lds_bytes, s, grid_out);
     case BP4_MOMENTUM: return launch_lds_kernel<BP4_MOMENTUM>(args, lds_bytes, s, grid_out);
     case BP4_ADAGRAD: return launch_lds_kernel<BP4_ADAGRAD>(args, lds_bytes, s, grid_out);
     case BP4_EWAINIT: return launch_lds_kernel<BP4_EWAINIT>(args, lds_bytes, s, grid_out);
     case BP4_AEWA: return launch_lds_kernel<BP4_AEWA>(args, lds_bytes, s, grid_out);
-    default: return launch_lds_kernel<-1>(args, lds_bytes, s, grid_out);
+    default: return launch_lds_kernel<kMixedVariants>(args, lds_bytes, s, grid_out);
     }
 }
 
