@@ -82,8 +82,8 @@ HBM_PEAK = 8.0e12   # bytes/s
 # taken on: a kernel whose sources hash differently reports traffic null.
 KERNEL_SOURCES = {"decode_lds_kernel": ("bp4_decode.hip", "bp4_math.h", "bp4_internal.h"),
                   "decode_soa_kernel": ("bp4_soa.hip", "bp4_math.h", "bp4_internal.h")}
-MEASURED_TRAFFIC = {"decode_lds_kernel": ("6ade1a1695ded9ef", 4.151e9),    # mixed batch, one launch
-                    "decode_soa_kernel": ("353366fcf85bc69a", 5.268e11)}   # large codes, mean of 26 launches
+MEASURED_TRAFFIC = {"decode_lds_kernel": ("ee02ea954c7fedff", 4.019e+09),    # mixed batch, one launch
+                    "decode_soa_kernel": ("823d6d2bcc39d31f", 5.269e+11)}   # large codes, mean of 26 launches
 
 
 def measured_traffic(kernel):
