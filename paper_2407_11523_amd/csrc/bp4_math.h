@@ -31,7 +31,6 @@ __device__ __forceinline__ float clampf(float x, float c) { return __builtin_amd
 
 constexpr float kLog2e = 1.44269504088896341f;
 constexpr float kLn2 = 0.693147180559945309f;
-constexpr float kLn4 = 1.38629436111989061f;
 
 // Hardware base-2 exponential and logarithm (v_exp_f32, v_log_f32).
 __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -39,26 +38,26 @@ __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf
 
 // phi(x) = -ln tanh(x/2) = 2 atanh(e^{-x}) for x >= 0, phi(0) = inf, phi(inf) = 0;
 // 2 atanh(prod tanh(m_k/2)) = (prod sgn m_k) phi(sum phi(|m_k|)).
-//   x >= ln 4: z = e^{-x} <= 1/4 and phi = 2 z P(z^2), P(w) = atanh(sqrt w)/sqrt w;
-//   x <  ln 4: phi = ln(2/x) + u G(u), u = x^2/4, u G(u) = -ln(tanh(sqrt u)/sqrt u).
-// P and G are least-squares fits on those ranges (relative error < 1e-7 in FP32);
+//   x >= 5/4: z = e^{-x} < 0.29 and phi = 2 z P(z^2), P(w) = atanh(sqrt w)/sqrt w;
+//   x <  5/4: phi = ln(2/x) + u G(u), u = x^2/4, u G(u) = -ln(tanh(sqrt u)/sqrt u).
+// P and G are cubic minimax fits on those ranges (relative error of phi below 5e-8
+// from the fits; FP32 rounding of the exponent argument dominates at large x);
 // both forms keep full relative accuracy (no 1 - z or log(1 + tiny) cancellation).
+constexpr float kPhiSplit = 1.25f;
 __device__ __forceinline__ float phi(float x)
 {
-    if (x >= kLn4) {
+    if (x >= kPhiSplit) {
         const float z = hw_exp2(-x * kLog2e);
         const float w = z * z;
-        float p = fmaf(w, 0.12663664294804267f, 0.1419839934660223f);
-        p = fmaf(w, p, 0.2000197421889f);
-        p = fmaf(w, p, 0.3333331781245287f);
-        p = fmaf(w, p, 1.00000000019442f);
+        float p = fmaf(w, 0.16298873778648207f, 0.1989325570537775f);
+        p = fmaf(w, p, 0.3333511821226621f);
+        p = fmaf(w, p, 0.9999999533102701f);
         return (2.0f * z) * p;
     }
     const float u = 0.25f * x * x;
-    float g = fmaf(u, 0.0014921690150859843f, -0.006451527278442298f);
-    g = fmaf(u, g, 0.02182510967622784f);
-    g = fmaf(u, g, -0.07777514939719771f);
-    g = fmaf(u, g, 0.33333330803159383f);
+    float g = fmaf(u, -0.004938818690502019f, 0.021287449220304667f);
+    g = fmaf(u, g, -0.07769785638553288f);
+    g = fmaf(u, g, 0.3333296913153782f);
     return fmaf(-hw_log2(0.5f * x), kLn2, u * g);
 }
 
