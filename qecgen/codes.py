@@ -254,7 +254,82 @@ def trapping_ring() -> StabilizerCode:
     return _finish("trapping_ring", hx, hz)
 
 
-FAMILIES = {"planar": planar, "toric": toric, "xzzx": xzzx}
+def _cyclic_shift(k: int) -> np.ndarray:
+    s = np.zeros((k, k), dtype=np.uint8)
+    for i in range(k):
+        s[i, (i + 1) % k] = 1
+    return s
+
+
+def bivariate_bicycle(l: int, m: int, a_terms, b_terms, name: str = None) -> StabilizerCode:
+    """Bivariate bicycle code (Bravyi et al. 2024; section IV-C cites it).
+
+    x = S_l (x) I_m and y = I_l (x) S_m generate commuting permutation matrices
+    (S_k the k x k cyclic shift); A and B are sums of three monomials, each term a
+    pair (i, j) meaning x^i y^j.  X checks [A | B], Z checks [B^T | A^T] on 2lm
+    qubits (A and B commute, so the two kinds of checks commute)."""
+    x = np.kron(_cyclic_shift(l), np.eye(m, dtype=np.uint8))
+    y = np.kron(np.eye(l, dtype=np.uint8), _cyclic_shift(m))
+
+    def poly(terms):
+        acc = np.zeros((l * m, l * m), dtype=np.int64)
+        for i, j in terms:
+            acc += np.linalg.matrix_power(x.astype(np.int64), i) @ np.linalg.matrix_power(y.astype(np.int64), j)
+        return (acc & 1).astype(np.uint8)
+
+    A, B = poly(a_terms), poly(b_terms)
+    q = l * m
+    x_rows = np.hstack([A, B])
+    z_rows = np.hstack([B.T, A.T])
+    hx = np.vstack([x_rows, np.zeros((q, 2 * q), dtype=np.uint8)])
+    hz = np.vstack([np.zeros((q, 2 * q), dtype=np.uint8), z_rows])
+    return _finish(name or f"bb_{l}x{m}", hx, hz)
+
+
+# The published instances [[n, k, d]] -> (l, m, A, B) with A, B as (x power, y power) terms.
+BB_CODES = {
+    72: (6, 6, [(3, 0), (0, 1), (0, 2)], [(0, 3), (1, 0), (2, 0)]),      # [[72, 12, 6]]
+    90: (15, 3, [(9, 0), (0, 1), (0, 2)], [(0, 0), (2, 0), (7, 0)]),     # [[90, 8, 10]]
+    108: (9, 6, [(3, 0), (0, 1), (0, 2)], [(0, 3), (1, 0), (2, 0)]),     # [[108, 8, 10]]
+    144: (12, 6, [(3, 0), (0, 1), (0, 2)], [(0, 3), (1, 0), (2, 0)]),    # [[144, 12, 12]]
+    288: (12, 12, [(3, 0), (0, 2), (0, 7)], [(0, 3), (1, 0), (2, 0)]),   # [[288, 12, 18]]
+}
+
+
+def bb(n: int) -> StabilizerCode:
+    l, m, a_terms, b_terms = BB_CODES[n]
+    return bivariate_bicycle(l, m, a_terms, b_terms, name=f"bb_n{n}")
+
+
+def chamon(d: int) -> StabilizerCode:
+    """3D Chamon code (Bravyi, Leemhuis, Terhal 2011; section IV-C) on the periodic
+    (2d)^3 cubic lattice: qubits on the sites with even coordinate sum, one check per
+    odd site v acting as X on v +- e_x, Y on v +- e_y and Z on v +- e_z."""
+    if d < 1:
+        raise ValueError("chamon code needs d >= 1")
+    L = 2 * d
+    sites = [(a, b, c) for a in range(L) for b in range(L) for c in range(L)]
+    qubits = [s for s in sites if sum(s) % 2 == 0]
+    checks = [s for s in sites if sum(s) % 2 == 1]
+    qi = {s: i for i, s in enumerate(qubits)}
+    n, m = len(qubits), len(checks)
+    hx = np.zeros((m, n), dtype=np.uint8)
+    hz = np.zeros((m, n), dtype=np.uint8)
+    for r, (a, b, c) in enumerate(checks):
+        for da in (-1, 1):
+            v = qi[((a + da) % L, b, c)]
+            hx[r, v] = 1                              # X
+        for db in (-1, 1):
+            v = qi[(a, (b + db) % L, c)]
+            hx[r, v] = 1                              # Y = X and Z
+            hz[r, v] = 1
+        for dc in (-1, 1):
+            v = qi[(a, b, (c + dc) % L)]
+            hz[r, v] = 1                              # Z
+    return _finish(f"chamon_d{d}", hx, hz)
+
+
+FAMILIES = {"planar": planar, "toric": toric, "xzzx": xzzx, "bb": bb, "chamon": chamon}
 
 
 def make(family: str, size: int) -> StabilizerCode:
