@@ -104,10 +104,16 @@ typedef struct bp4_graph bp4_graph;
  * uint8 arrays [m][n] row-major; row i is the stabilizer S_i, entry j its
  * Pauli on qubit j (section II-B1).  Edge (i, j) exists where the entry is
  * not I; its label is the GF(4) entry H_ij.  The inputs are copied.
+ * A graph whose checks and qubits all have degree <= 4 is narrow and runs on
+ * every kernel; otherwise it is wide (checks of degree <= 8, qubits <= 7, as
+ * the bivariate bicycle and 3D Chamon codes of section IV-C need) and runs on
+ * the flooding LDS kernel, the sampler and bookkeeping only (the serial
+ * schedule, the SOA, plain and unrolled paths answer EUNSUPPORTED, and
+ * bp4_decode_mixed does not mix wide and narrow codes in one launch).
  * Errors: EINVAL (m, n <= 0, entries not 0/1, empty row or column, NULL),
  * ENONCOMM (rows anticommute, unless BP4_ALLOW_ANTICOMMUTING), EDEGREE
- * (check or qubit degree above 4), EUNSUPPORTED (n > 16383 or more than
- * 65534 edges). */
+ * (check degree above 8 or qubit degree above 7), EUNSUPPORTED (n > 16383 or
+ * more than 65534 edges). */
 int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
                      uint32_t flags, bp4_graph **out);
 

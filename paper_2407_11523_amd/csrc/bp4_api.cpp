@@ -45,15 +45,18 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct bp4_graph {
     int32_t m = 0, n = 0, nnz = 0, max_cdeg = 0, max_vdeg = 0, nlog = 0, with_y = 0;
     std::vector<int32_t> canon_chk, canon_var;   // canonical edge -> check, qubit
-    std::vector<uint32_t> cedge;                 // [m][kMaxCheckDeg]
+    int32_t cstride = kMaxCheckDeg;              // edge words per check
+    std::vector<uint32_t> cedge;                 // [m][cstride]
     std::vector<uint32_t> vinfo;                 // [n]
     std::vector<uint32_t> vcanon;                // [nnz]
     std::vector<uint32_t> vchk;                  // [nnz] check of each message slot
     std::vector<uint32_t> sord, slev;            // serial order as levels (see graph_create)
+    std::vector<uint32_t> vlab;                  // [n] slot labels of wide graphs
     std::vector<uint32_t> lptr, lent;            // logicals
     // byte offsets of the sections in the device image
-    size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_vchk = 0, off_sord = 0, off_slev = 0, off_lptr = 0,
-           off_lent = 0, bytes = 0;
+    size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_vchk = 0, off_sord = 0, off_slev = 0, off_vlab = 0,
+           off_lptr = 0, off_lent = 0, bytes = 0;
+    bool wide() const { return cstride > kMaxCheckDeg; }
 
     void layout()
     {
@@ -64,6 +67,7 @@ struct bp4_graph {
         off_vchk = o; o = align256(o + vchk.size() * 4);
         off_sord = o; o = align256(o + sord.size() * 4);
         off_slev = o; o = align256(o + slev.size() * 4);
+        off_vlab = o; o = align256(o + (vlab.empty() ? 1 : vlab.size()) * 4);
         off_lptr = o; o = align256(o + lptr.size() * 4);
         off_lent = o; o = align256(o + (lent.empty() ? 1 : lent.size()) * 4);
         bytes = o;
@@ -80,6 +84,8 @@ struct bp4_graph {
         v.sord = reinterpret_cast<const uint32_t *>(b + off_sord);
         v.slev = reinterpret_cast<const uint32_t *>(b + off_slev);
         v.nlev = (int32_t)slev.size() - 1;
+        v.vlab = reinterpret_cast<const uint32_t *>(b + off_vlab);
+        v.cstride = cstride;
         v.lptr = reinterpret_cast<const uint32_t *>(b + off_lptr);
         v.lent = reinterpret_cast<const uint32_t *>(b + off_lent);
         v.m = m;
@@ -97,6 +103,7 @@ static int unrolled_check(const bp4_graph *g, const void *dev_graph, int32_t T, 
                           const uint8_t *err)
 {
     if (!g || !dev_graph) return fail(BP4_EINVAL, "unrolled: NULL graph");
+    if (g->wide()) return fail(BP4_EUNSUPPORTED, "unrolled: graphs with degrees above 4 are not supported");
     if (T < 1 || K < 1) return fail(BP4_EINVAL, "unrolled: T %d and ckpt_every %d must be >= 1", T, K);
     if (!(clamp > 0.0f)) return fail(BP4_EINVAL, "unrolled: llr_clamp must be > 0");
     if (shots < 1 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "unrolled: shots %lld outside [1, 2^31)", (long long)shots);
@@ -187,9 +194,9 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
         if (vdeg[v] == 0) return fail(BP4_EINVAL, "graph_create: qubit %d is in no check", v);
         maxv = vdeg[v] > maxv ? vdeg[v] : maxv;
     }
-    if (maxc > kMaxCheckDeg || maxv > kMaxVarDeg)
+    if (maxc > kMaxCheckDegWide || maxv > kMaxVarDegWide)
         return fail(BP4_EDEGREE, "graph_create: degrees (check %d, qubit %d) above (%d, %d)", maxc, maxv,
-                    kMaxCheckDeg, kMaxVarDeg);
+                    kMaxCheckDegWide, kMaxVarDegWide);
 
     auto *g = new bp4_graph;
     g->m = m;
@@ -197,6 +204,7 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
     g->nnz = (int32_t)nnz;
     g->max_cdeg = maxc;
     g->max_vdeg = maxv;
+    g->cstride = (maxc > kMaxCheckDeg || maxv > kMaxVarDeg) ? kMaxCheckDegWide : kMaxCheckDeg;
     std::vector<uint32_t> lab(nnz);
     for (long i = 0; i < (long)m * n; ++i)
         if (hx[i] && hz[i]) g->with_y = 1;
@@ -275,22 +283,26 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
         }
     }
     // packed check edges (ELL, padded)
-    g->cedge.assign((size_t)m * kMaxCheckDeg, edge_pad_word((int)nnz));
+    g->cedge.assign((size_t)m * g->cstride, edge_pad_word((int)nnz));
     {
         std::vector<int> cfill(m, 0);
         for (long k = 0; k < nnz; ++k) {
             const int c = g->canon_chk[k];
             const uint32_t w = (uint32_t)slot_of[k] | ((uint32_t)g->canon_var[k] << 16) | (lab[k] << 30);
-            g->cedge[(size_t)c * kMaxCheckDeg + cfill[c]++] = w;
+            g->cedge[(size_t)c * g->cstride + cfill[c]++] = w;
         }
     }
     // packed qubit words
     g->vinfo.assign(n, 0);
+    if (g->wide()) g->vlab.assign(n, 0);
     for (int v = 0; v < n; ++v) {
         uint32_t w = (uint32_t)vptr[v] | ((uint32_t)vdeg[v] << 16);
         for (int j = 0; j < vdeg[v]; ++j) {
             const uint32_t l = lab[g->vcanon[vptr[v] + j]];
-            w |= l << (20 + 2 * j);
+            if (g->wide())
+                g->vlab[v] |= l << (2 * j);
+            else
+                w |= l << (20 + 2 * j);
             w |= 1u << (27 + l);
         }
         g->vinfo[v] = w;
@@ -360,6 +372,7 @@ int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stre
     std::memcpy(img.data() + g->off_vchk, g->vchk.data(), g->vchk.size() * 4);
     std::memcpy(img.data() + g->off_sord, g->sord.data(), g->sord.size() * 4);
     std::memcpy(img.data() + g->off_slev, g->slev.data(), g->slev.size() * 4);
+    if (!g->vlab.empty()) std::memcpy(img.data() + g->off_vlab, g->vlab.data(), g->vlab.size() * 4);
     std::memcpy(img.data() + g->off_lptr, g->lptr.data(), g->lptr.size() * 4);
     if (!g->lent.empty()) std::memcpy(img.data() + g->off_lent, g->lent.data(), g->lent.size() * 4);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -453,12 +466,14 @@ void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, 
     a.magic_m = (uint32_t)(((1ull << 32) + (uint64_t)g->m - 1) / (uint64_t)g->m);
     a.magic_n = (uint32_t)(((1ull << 32) + (uint64_t)g->n - 1) / (uint64_t)g->n);
     a.with_y = g->with_y;
+    a.wide = g->wide() ? 1 : 0;
 }
 
 // The automatic kernel: SOA when even one shot per 256-lane workgroup needs more
 // than kLdsAutoLimit bytes of LDS, or the code has more than 64 checks per lane.
 int auto_kernel(const bp4_graph *g, int variant)
 {
+    if (g->wide()) return BP4_KERNEL_LDS;   // the only kernel for wide graphs
     if (!decode_lds_fits(g->m, g->n, 256, 1)) return BP4_KERNEL_SOA;
     return decode_lds_layout(g->m, g->n, g->nnz, variant, 256, 1).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA
                                                                                       : BP4_KERNEL_LDS;
@@ -539,7 +554,7 @@ int choose_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, 
     int rc = check_lanes(G, S, "decode");
     if (rc) return rc;
     if (G == 0 && S == 0) {
-        *out = decode_lds_pick(g->m, g->n, g->nnz, p->variant, max_lds);
+        *out = decode_lds_pick(g->m, g->n, g->nnz, p->variant, max_lds, g->wide());
         if (out->group_lanes < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the LDS kernel");
         return BP4_OK;
     }
@@ -549,7 +564,7 @@ int choose_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, 
     }
     if (!decode_lds_fits(g->m, g->n, G, S))
         return fail(BP4_EINVAL, "decode: %d lanes x %d shots leave more than 64 checks per lane", G, S);
-    if (decode_lds_layout(g->m, g->n, g->nnz, p->variant, G, S).bytes > max_lds)
+    if (decode_lds_layout(g->m, g->n, g->nnz, p->variant, G, S, g->wide()).bytes > max_lds)
         return fail(BP4_EINVAL, "decode: group_lanes %d, block_shots %d exceed the LDS of a workgroup", G, S);
     out->group_lanes = G;
     out->block_shots = S;
@@ -599,6 +614,8 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
                  : p->serial ? serial_auto_kernel(g, p->variant) : auto_kernel(g, p->variant);
     if (kernel == BP4_KERNEL_LDS && soa_knobs)
         return fail(BP4_EINVAL, "decode: soa_lanes and soa_iter_block apply to the SOA kernel");
+    if (g->wide() && (kernel != BP4_KERNEL_LDS || p->serial))
+        return fail(BP4_EUNSUPPORTED, "decode: graphs with degrees above 4 run the flooding LDS kernel only");
     if (kernel == BP4_KERNEL_SOA) {
         if (lds_knobs) return fail(BP4_EINVAL, "decode: group_lanes, block_shots and lds_bytes apply to the LDS kernel");
         const size_t need = soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, soa_lanes);
@@ -622,7 +639,7 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         LaneChoice lc;
         rc = choose_lanes(g, p, requested, requested_S, max_lds, &lc);
         if (rc) return rc;
-        L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, lc.group_lanes, lc.block_shots);
+        L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, lc.group_lanes, lc.block_shots, g->wide());
     }
     MixedArgs args;
     std::memset(&args, 0, sizeof args);
@@ -749,6 +766,8 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
         if (c.group_lanes == 0 && c.block_shots == 0 && auto_kernel(c.graph, c.params.variant) == BP4_KERNEL_SOA)
             return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d needs the large-code (SOA) kernel", i);
         if (c.params.serial) return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d asks for the serial schedule", i);
+        if (c.graph->wide() != codes[0].graph->wide())
+            return fail(BP4_EUNSUPPORTED, "decode_mixed: codes with degrees above 4 and codes without share no launch");
     }
     size_t max_lds = 0;
     int rc = device_max_lds(&max_lds);
@@ -772,7 +791,7 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
         rc = choose_lanes(c.graph, &c.params, c.group_lanes, c.block_shots, max_lds, &lc);
         if (rc) return rc;
         const LdsLayout L = decode_lds_layout(c.graph->m, c.graph->n, c.graph->nnz, c.params.variant, lc.group_lanes,
-                                              lc.block_shots);
+                                              lc.block_shots, c.graph->wide());
         lds = L.bytes > lds ? L.bytes : lds;
         fill_decode_args(args.codes[k], c.graph, c.dev_graph, &c.params, c.shots, c.prior_llr, c.synd, c.est,
                          c.conv, c.iters, L, counters + k);
@@ -806,6 +825,7 @@ int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params
     if (!prior_llr) return fail(BP4_EINVAL, "decode_plain: NULL prior");
     if (iterations_run) *iterations_run = 0;
     if (p->serial) return fail(BP4_EUNSUPPORTED, "decode_plain: flooding schedule only");
+    if (g->wide()) return fail(BP4_EUNSUPPORTED, "decode_plain: graphs with degrees above 4 are not supported");
     if (p->variant == BP4_AEWA) return fail(BP4_EUNSUPPORTED, "decode_plain: AEWA restarts need the persistent kernels");
     if (shots == 0) return BP4_OK;
     if (!synd || !est || !conv || !iters || !ws) return fail(BP4_EINVAL, "decode_plain: NULL buffer");
@@ -842,6 +862,6 @@ extern "C" int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int
         G = 256;
     }
     if (!decode_lds_fits(g->m, g->n, G, S)) return fail(BP4_EINVAL, "lds_layout_bytes: more than 64 checks per lane");
-    *bytes = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G, S).bytes;
+    *bytes = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G, S, g->wide()).bytes;
     return BP4_OK;
 }

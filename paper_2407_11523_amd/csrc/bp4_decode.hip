@@ -36,30 +36,82 @@ constexpr int kBlock = 256;
 
 // ---- Per-node steps shared by the two lane mappings -------------------------------
 
+// W: the graph is wide (checks of up to 8 edges, 8 edge words per check, qubits of
+// up to 7 edges with their slot labels in a separate word); else 4 and 4.
+template <bool W> struct Width {
+    static constexpr int kCheck = W ? kMaxCheckDegWide : kMaxCheckDeg;   // edge words per check
+    static constexpr int kSlots = W ? 8 : 4;                            // message words read per qubit
+};
+
+template <bool W>
+__device__ __forceinline__ void load_check(const uint32_t *s_ce, int c, uint32_t w[Width<W>::kCheck])
+{
+#pragma unroll
+    for (int q = 0; q < Width<W>::kCheck / 4; ++q) {
+        const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[Width<W>::kCheck * c + 4 * q]);
+        w[4 * q] = w4.x;
+        w[4 * q + 1] = w4.y;
+        w[4 * q + 2] = w4.z;
+        w[4 * q + 3] = w4.w;
+    }
+}
+
+// Check rule of a wide check (up to 8 edges, padding +inf): as check_update, with
+// the leave-one-out sums of phi formed from prefix and suffix sums in edge order.
+__device__ __forceinline__ void check_update_wide(const float mv[8], uint32_t s, float C, float out[8])
+{
+    float f[8];
+    uint32_t sgn[8];
+    uint32_t neg = s & 1u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        sgn[j] = mv[j] < 0.0f ? 1u : 0u;
+        neg ^= sgn[j];
+        f[j] = phi(fabsf(mv[j]));
+    }
+    float pre[8], suf[8];
+    pre[0] = 0.0f;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) pre[j] = pre[j - 1] + f[j - 1];
+    suf[7] = 0.0f;
+#pragma unroll
+    for (int j = 6; j >= 0; --j) suf[j] = suf[j + 1] + f[j + 1];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float mag = phi(pre[j] + suf[j]);
+        out[j] = clampf((neg ^ sgn[j]) ? -mag : mag, C);
+    }
+}
+
 // Horizontal update (eq. h_update) of check c from the messages in `msg`; s: its
 // syndrome bit.  Padding edges read and rewrite the padding slot, which holds
 // +inf (phi(+inf) = 0 adds nothing to the sums).
+template <bool W = false>
 __device__ __forceinline__ void check_node(const uint32_t *s_ce, float *msg, int c, uint32_t s, float C)
 {
-    const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
-    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
-    float mv[4], out[4];
+    constexpr int D = Width<W>::kCheck;
+    uint32_t w[D];
+    load_check<W>(s_ce, c, w);
+    float mv[D], out[D];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) mv[j] = msg[edge_slot(w[j])];
-    check_update(mv, s, C, out);
+    for (int j = 0; j < D; ++j) mv[j] = msg[edge_slot(w[j])];
+    if constexpr (W) check_update_wide(mv, s, C, out);
+    else check_update(mv, s, C, out);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) msg[edge_slot(w[j])] = edge_is_pad(w[j]) ? INFINITY : out[j];
+    for (int j = 0; j < D; ++j) msg[edge_slot(w[j])] = edge_is_pad(w[j]) ? INFINITY : out[j];
 }
 
 // Syndrome test of check c against the decision bytes (Algorithm 2): nonzero if
 // the decision violates the check or some decision on it is NaN.
+template <bool W = false>
 __device__ __forceinline__ uint32_t test_node(const uint32_t *s_ce, const uint8_t *ehat, int c, uint32_t s)
 {
-    const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
-    const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+    constexpr int D = Width<W>::kCheck;
+    uint32_t w[D];
+    load_check<W>(s_ce, c, w);
     uint32_t par = s & 1u, any = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < D; ++j) {
         // <H_cv, E^_v> is bit H_cv of the decision byte (padding edges read bit 0
         // of qubit 0's byte, which is set only if that shot already holds a NaN
         // posterior and cannot converge)
@@ -70,20 +122,64 @@ __device__ __forceinline__ uint32_t test_node(const uint32_t *s_ce, const uint8_
     return par | (any & 1u);   // bit 0: a NaN posterior never converges
 }
 
+// Label of slot j from a qubit's label word (narrow: the qubit word shifted right
+// by 20; wide: the separate label word).
+__device__ __forceinline__ uint32_t slot_label(uint32_t labw, int j) { return (labw >> (2 * j)) & 3u; }
+template <bool W>
+__device__ __forceinline__ uint32_t label_word(const uint32_t *s_vl, uint32_t info, int v)
+{
+    if constexpr (W) return s_vl[v];
+    else return info >> 20;
+}
+
+// Per-label sums S[lab] of a qubit's incoming messages and of their magnitudes A[lab]
+// over its DV slots (label 0 for unused slots), as label_sums.
+template <int DV>
+__device__ __forceinline__ void label_sums_w(uint32_t labw, const float mc[DV], bool with_y, bool with_abs, float S[4],
+                                             float A[4])
+{
+    S[0] = A[0] = 0.0f;
+    float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DV; ++j) {
+        const uint32_t l = slot_label(labw, j);
+        s1 += l == 1u ? mc[j] : 0.0f;
+        s2 += l == 2u ? mc[j] : 0.0f;
+        if (with_y) s3 += l == 3u ? mc[j] : 0.0f;
+    }
+    S[1] = s1;
+    S[2] = s2;
+    S[3] = s3;
+    float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    if (with_abs) {
+#pragma unroll
+        for (int j = 0; j < DV; ++j) {
+            const uint32_t l = slot_label(labw, j);
+            a1 += l == 1u ? fabsf(mc[j]) : 0.0f;
+            a2 += l == 2u ? fabsf(mc[j]) : 0.0f;
+            a3 += l == 3u ? fabsf(mc[j]) : 0.0f;
+        }
+    }
+    A[1] = a1;
+    A[2] = a2;
+    A[3] = a3;
+}
+
 // Initialisation of qubit v (eq. init, Algorithm 2): m^{(0)}_{v->c} =
 // lambda_{H_cv}(Pi^{(0)}_v); Q^{(0)} = Pi^{(0)}; accumulators start at 0.
-template <int VAR>
-__device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const float *s_pi, float *msg, float *qs,
-                                           float *acc, int v, float C)
+template <int VAR, bool W = false>
+__device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const uint32_t *s_vl, const float *s_pi, float *msg,
+                                           float *qs, float *acc, int v, float C)
 {
     constexpr bool keep_q = VAR != BP4_BP;
     constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
     const uint32_t info = s_vi[v];
+    const uint32_t labw = label_word<W>(s_vl, info, v);
     const uint32_t base = var_base(info), deg = var_deg(info);
     const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
     float lam[4];
     qubit_lambdas(p3, var_labels_present(info), lam);
-    for (uint32_t j = 0; j < deg; ++j) msg[base + j] = clampf(lam[var_lab(info, j)], C);
+    for (uint32_t j = 0; j < deg; ++j) msg[base + j] = clampf(lam[slot_label(labw, (int)j)], C);
     float st[3], ac[3];
     qubit_state_init(VAR, p3, st, ac);
     if (keep_q)
@@ -98,9 +194,9 @@ __device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const float *s_
 // m_{v->c} of slot base + j goes to store(slot, value).  `shot` indexes the
 // optional verification outputs (none are written for shot >= shots).  WY: the
 // code has Y labels (else every edge label is X or Z).
-template <int VAR, bool WY, typename Store>
-__device__ __forceinline__ void qubit_update(const DecodeArgs &a, const float *s_pi, uint32_t info, int v,
-                                             const float mc[4], float *qs, float *acc, uint8_t *ehat, int t,
+template <int VAR, bool WY, int DV, typename Store>
+__device__ __forceinline__ void qubit_update(const DecodeArgs &a, const float *s_pi, uint32_t info, uint32_t labw,
+                                             int v, const float mc[DV], float *qs, float *acc, uint8_t *ehat, int t,
                                              const VariantParams &vp, int shot, Store store)
 {
     constexpr bool keep_q = VAR != BP4_BP;
@@ -109,7 +205,7 @@ __device__ __forceinline__ void qubit_update(const DecodeArgs &a, const float *s
     const int n = a.g.n;
     const uint32_t base = var_base(info), deg = var_deg(info);
     float S[4], A[4];
-    label_sums(info, mc, WY, keep_acc && VAR == BP4_ADAGRAD, S, A);
+    label_sums_w<DV>(labw, mc, WY, keep_acc && VAR == BP4_ADAGRAD, S, A);
     const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
     float st[3] = {0.0f, 0.0f, 0.0f}, ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
     if (keep_q)
@@ -127,9 +223,9 @@ __device__ __forceinline__ void qubit_update(const DecodeArgs &a, const float *s
     qubit_lambdas(qn, var_labels_present(info) & (WY ? 0xEu : 0x6u), lam);
     const bool trace = a.mvc_out && shot < a.shots;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < DV; ++j) {
         if ((uint32_t)j >= deg) continue;
-        const uint32_t l = var_lab(info, j);   // 1 X, 2 Z, 3 Y
+        const uint32_t l = slot_label(labw, j);   // 1 X, 2 Z, 3 Y
         float lsel = l == 2u ? lam[2] : lam[1];
         if (WY) lsel = l == 3u ? lam[3] : lsel;
         const float out = clampf(lsel - mc[j], C);
@@ -145,22 +241,23 @@ __device__ __forceinline__ void qubit_update(const DecodeArgs &a, const float *s
 }
 
 // Flooding qubit step: the incoming messages are the slots' m_{c->v}.
-template <int VAR, bool WY>
-__device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *s_vi, const float *s_pi, float *msg,
-                                           float *qs, float *acc, uint8_t *ehat, int v, int t,
-                                           const VariantParams &vp, int shot)
+template <int VAR, bool WY, bool W = false>
+__device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *s_vi, const uint32_t *s_vl,
+                                           const float *s_pi, float *msg, float *qs, float *acc, uint8_t *ehat,
+                                           int v, int t, const VariantParams &vp, int shot)
 {
+    constexpr int DV = Width<W>::kSlots;
     const uint32_t info = s_vi[v];
     const uint32_t base = var_base(info);
     // the words after a qubit's last slot are in the region (another qubit's
     // slots, the padding slot or the posterior array); they are read but never
     // used: those slots carry label 0, which the label sums skip, and no message
     // is written for them
-    float mc[4];
+    float mc[DV];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) mc[j] = msg[base + j];
-    qubit_update<VAR, WY>(a, s_pi, info, v, mc, qs, acc, ehat, t, vp, shot,
-                          [&](uint32_t slot, float out) { msg[slot] = out; });
+    for (int j = 0; j < DV; ++j) mc[j] = msg[base + j];
+    qubit_update<VAR, WY, DV>(a, s_pi, info, label_word<W>(s_vl, info, v), v, mc, qs, acc, ehat, t, vp, shot,
+                              [&](uint32_t slot, float out) { msg[slot] = out; });
 }
 
 template <int VAR>
@@ -178,15 +275,16 @@ __device__ __forceinline__ VariantParams variant_params(const DecodeArgs &a)
 // ---- Wave groups: G in {4, ..., 64} lanes of one wavefront per shot -----------------
 // Lane r of a group owns checks and qubits r, r + G, ...; the group's syndrome bits
 // sit in a register (bit k: check r + kG); groups synchronise at wavefront level.
-template <int VAR>
+template <int VAR, bool W = false>
 __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
 {
     const int G = a.group_lanes;
     const int lgG = __builtin_ctz((unsigned)G);
     const int m = a.g.m, n = a.g.n;
     const uint32_t *s_ce = reinterpret_cast<const uint32_t *>(lds);
-    const uint32_t *s_vi = s_ce + kMaxCheckDeg * m;
+    const uint32_t *s_vi = s_ce + Width<W>::kCheck * m;
     const float *s_pi = reinterpret_cast<const float *>(s_vi + n);
+    const uint32_t *s_vl = reinterpret_cast<const uint32_t *>(s_pi + 3 * n);   // wide graphs only
 
     const int gid = (int)threadIdx.x >> lgG;                // group within the workgroup
     const int r = (int)threadIdx.x & (G - 1);               // rank within the group
@@ -211,7 +309,7 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
         int k = 0;
         for (int c = r; c < m; c += G, ++k)
             if (a.synd[(size_t)s * m + c]) sbits |= 1ull << k;
-        for (int v = r; v < n; v += G) init_qubit<VAR>(s_vi, s_pi, msg, qs, acc, v, C);
+        for (int v = r; v < n; v += G) init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, qs, acc, v, C);
         t = 0;
     };
 
@@ -227,19 +325,21 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
         if (!__any(live)) break;
         if (live) {
             ++t;
-            for (int c = r; c < m; c += G) check_node(s_ce, msg, c, (uint32_t)(sbits >> ((c - r) >> lgG)), C);
+            for (int c = r; c < m; c += G) check_node<W>(s_ce, msg, c, (uint32_t)(sbits >> ((c - r) >> lgG)), C);
         }
         wave_sync();
         if (live) {
             if (with_y)
-                for (int v = r; v < n; v += G) qubit_node<VAR, true>(a, s_vi, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
+                for (int v = r; v < n; v += G)
+                    qubit_node<VAR, true, W>(a, s_vi, s_vl, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
             else
-                for (int v = r; v < n; v += G) qubit_node<VAR, false>(a, s_vi, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
+                for (int v = r; v < n; v += G)
+                    qubit_node<VAR, false, W>(a, s_vi, s_vl, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
         }
         wave_sync();
         uint32_t bad = 0;
         if (live)
-            for (int c = r; c < m; c += G) bad |= test_node(s_ce, ehat, c, (uint32_t)(sbits >> ((c - r) >> lgG)));
+            for (int c = r; c < m; c += G) bad |= test_node<W>(s_ce, ehat, c, (uint32_t)(sbits >> ((c - r) >> lgG)));
         const uint64_t ballot = __ballot(bad != 0);
         const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
         const bool sat = (ballot & gmask) == 0;
@@ -354,7 +454,7 @@ __device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
             const float mag = phi((f[0] + f[1]) + (f[2] + f[3]));
             mc[j] = clampf(neg ? -mag : mag, C);
         }
-        qubit_update<VAR, WY>(a, s_pi, info, v, mc, qs, acc, ehat, t, vp, shot, store);
+        qubit_update<VAR, WY, 4>(a, s_pi, info, info >> 20, v, mc, qs, acc, ehat, t, vp, shot, store);
     };
 
     int s0 = 0;
@@ -451,15 +551,16 @@ __device__ __forceinline__ void walk_next(ItemWalk &w, uint32_t d, uint32_t rem,
     }
 }
 
-template <int VAR>
+template <int VAR, bool W = false>
 __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *events)
 {
     const uint32_t S = (uint32_t)a.block_shots;
     const int m = a.g.m, n = a.g.n;
     const int tid = (int)threadIdx.x;
     const uint32_t *s_ce = reinterpret_cast<const uint32_t *>(lds);
-    const uint32_t *s_vi = s_ce + kMaxCheckDeg * m;
+    const uint32_t *s_vi = s_ce + Width<W>::kCheck * m;
     const float *s_pi = reinterpret_cast<const float *>(s_vi + n);
+    const uint32_t *s_vl = reinterpret_cast<const uint32_t *>(s_pi + 3 * n);   // wide graphs only
     float *reg0 = lds + a.static_words;
     const uint32_t RW = (uint32_t)a.region_words;
     auto hdr = [&](uint32_t k) { return reinterpret_cast<int *>(reg0 + k * RW + a.hdr_off); };
@@ -502,7 +603,8 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     const uint8_t *ehat = reinterpret_cast<const uint8_t *>(msg + a.ehat_off);
                     a.est[(size_t)h[kHdrDone] * n + w.x] = (uint8_t)decision_pauli(ehat[w.x]);
                 }
-                if (h[kHdrFresh]) init_qubit<VAR>(s_vi, s_pi, msg, msg + a.q_off, msg + a.acc_off, (int)w.x, C);
+                if (h[kHdrFresh])
+                    init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off, (int)w.x, C);
             }
             BP4_FOR_CHECKS(w) {
                 float *msg = reg0 + w.off;
@@ -521,7 +623,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
         BP4_FOR_CHECKS(w) {
             float *msg = reg0 + w.off;
             const uint8_t *syn = reinterpret_cast<const uint8_t *>(msg + a.syn_off);
-            check_node(s_ce, msg, (int)w.x, syn[w.x], C);
+            check_node<W>(s_ce, msg, (int)w.x, syn[w.x], C);
         }
         __syncthreads();
         // ---- Posterior, hard decision and vertical update ----------------------------
@@ -538,9 +640,9 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     if (VAR == BP4_AEWA) vp.alpha = __int_as_float(h[kHdrAlpha]);
                     cur = w.off;
                 }
-                qubit_node<VAR, decltype(wy)::value>(a, s_vi, s_pi, msg, msg + a.q_off, msg + a.acc_off,
-                                                     reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t, vp,
-                                                     shot);
+                qubit_node<VAR, decltype(wy)::value, W>(a, s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off,
+                                                        reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t, vp,
+                                                        shot);
             }
         };
         if (with_y) qubit_phase(std::true_type{});
@@ -559,7 +661,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                 }
                 const float *msg = reg0 + w.off;
                 const uint8_t *syn = reinterpret_cast<const uint8_t *>(msg + a.syn_off);
-                bad |= test_node(s_ce, reinterpret_cast<const uint8_t *>(msg + a.ehat_off), (int)w.x, syn[w.x]);
+                bad |= test_node<W>(s_ce, reinterpret_cast<const uint8_t *>(msg + a.ehat_off), (int)w.x, syn[w.x]);
             }
             if (bad) reinterpret_cast<int *>(reg0 + cur + a.hdr_off)[kHdrBad + par] = 1;
         }
@@ -609,20 +711,25 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
 #undef BP4_FOR_QUBITS
 }
 
-template <int VAR>
+template <int VAR, bool W = false>
 __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *events)
 {
-    if (a.block_shots > 0) run_block<VAR>(a, lds, events);
-    else run_wave<VAR>(a, lds);
+    if (a.block_shots > 0) run_block<VAR, W>(a, lds, events);
+    else run_wave<VAR, W>(a, lds);
 }
 
 // VSET: the variant every code of the launch uses, kMixedVariants for a flooding
 // launch that mixes variants (a switch per code), kSerial for the serial schedule
-// (one code, a switch on its variant).  Register budget: 72 VGPRs (seven
-// wavefronts per SIMD) for the single-variant builds that fit it without spilling,
-// 96 (five) for AdaGrad and the switching builds.
-constexpr int kMixedVariants = -1, kSerial = -2;
-constexpr int lds_kernel_waves(int vset) { return (vset < 0 || vset == BP4_ADAGRAD) ? 5 : 7; }
+// (one code, a switch on its variant), kWide for a flooding launch of wide graphs
+// (a switch on the variant).  Register budget: 72 VGPRs
+// (seven wavefronts per SIMD) for the single-variant builds that fit it without
+// spilling, 96 (five) for AdaGrad and the switching builds, 128 (four) for kWide,
+// whose 8-edge checks hold twice the messages in registers.
+constexpr int kMixedVariants = -1, kSerial = -2, kWide = -3;
+constexpr int lds_kernel_waves(int vset)
+{
+    return vset == kWide ? 4 : (vset < 0 || vset == BP4_ADAGRAD) ? 5 : 7;
+}
 
 template <int VSET>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(lds_kernel_waves(VSET))))
@@ -641,11 +748,16 @@ decode_lds_kernel(MixedArgs args)
         // stage the code's packed check edges, qubit words and priors
         const int m = a.g.m, n = a.g.n;
         uint32_t *s_ce = reinterpret_cast<uint32_t *>(lds);
-        uint32_t *s_vi = s_ce + kMaxCheckDeg * m;
+        const int cs = a.g.cstride;
+        uint32_t *s_vi = s_ce + cs * m;
         float *s_pi = reinterpret_cast<float *>(s_vi + n);
-        for (int i = threadIdx.x; i < kMaxCheckDeg * m; i += kBlock) s_ce[i] = a.g.cedge[i];
+        for (int i = threadIdx.x; i < cs * m; i += kBlock) s_ce[i] = a.g.cedge[i];
         for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
+        if (VSET == kWide && a.wide) {   // slot labels of a wide graph
+            uint32_t *s_vl = reinterpret_cast<uint32_t *>(s_pi + 3 * n);
+            for (int i = threadIdx.x; i < n; i += kBlock) s_vl[i] = a.g.vlab[i];
+        }
         if (VSET == kSerial) {   // slot -> check table and the level order
             uint32_t *s_vchk = reinterpret_cast<uint32_t *>(s_pi + 3 * n);
             uint32_t *s_ord = s_vchk + a.g.nnz;
@@ -673,6 +785,16 @@ decode_lds_kernel(MixedArgs args)
                 default: run_serial<BP4_EWAINIT, false>(a, lds); break;
                 }
             }
+        } else if (VSET == kWide) {   // the host launches only wide codes here
+            if (a.wide) {
+                switch (a.variant) {
+                case BP4_BP: run_code<BP4_BP, true>(a, lds, &events); break;
+                case BP4_MOMENTUM: run_code<BP4_MOMENTUM, true>(a, lds, &events); break;
+                case BP4_ADAGRAD: run_code<BP4_ADAGRAD, true>(a, lds, &events); break;
+                case BP4_AEWA: run_code<BP4_AEWA, true>(a, lds, &events); break;
+                default: run_code<BP4_EWAINIT, true>(a, lds, &events); break;
+                }
+            }
         } else if (VSET == kMixedVariants) {
             switch (a.variant) {
             case BP4_BP: run_code<BP4_BP>(a, lds, &events); break;
@@ -691,10 +813,11 @@ decode_lds_kernel(MixedArgs args)
 
 }  // namespace
 
-LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S)
+LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S, bool wide)
 {
     LdsLayout L;
-    L.static_words = kMaxCheckDeg * m + n + 3 * n;
+    // check edges, qubit words, priors (and the slot labels of a wide graph)
+    L.static_words = (wide ? kMaxCheckDegWide : kMaxCheckDeg) * m + n + 3 * n + (wide ? n : 0);
     if (L.static_words & 3) L.static_words += 4 - (L.static_words & 3);
     int w = nnz + 1;               // message slots and the padding slot
     L.q_off = w;
@@ -709,8 +832,10 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S)
         L.hdr_off = w;
         w += kHdrBad + 2;
     }
-    // the qubit phase reads four words from each qubit's first slot: keep them inside
-    if (w < nnz + 4) w = nnz + 4;
+    // the qubit phase reads four (wide: eight) words from each qubit's first slot:
+    // keep them inside
+    const int reach = nnz + (wide ? 8 : 4);
+    if (w < reach) w = reach;
     if ((w & 1) == 0) w += 1;   // odd stride: neighbouring regions start on other banks
     L.region_words = w;
     L.group_lanes = S > 0 ? kBlock : G;
@@ -769,14 +894,14 @@ bool decode_lds_fits(int m, int n, int G, int S)
 // an occupancy factor: the wavefronts per CU that the LDS allows (up to 16,
 // beyond which latency is hidden) over 16.  Candidates: block slots S = 1..16,
 // then wave groups of 64 down to 4 lanes; at most `max_lds` bytes per workgroup.
-LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds)
+LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, bool wide)
 {
     const double cu_lds = 160.0 * 1024.0;
     LaneChoice best;
     double best_score = -1.0;
     auto consider = [&](int G, int S) {
         if (!decode_lds_fits(m, n, G, S)) return;
-        const LdsLayout L = decode_lds_layout(m, n, nnz, variant, G, S);
+        const LdsLayout L = decode_lds_layout(m, n, nnz, variant, G, S, wide);
         if (L.bytes > max_lds) return;
         const double blocks = std::floor(cu_lds / (double)L.bytes);
         double waves = blocks * (L.block / 64);
@@ -827,6 +952,8 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
     bool serial = false;
     for (int i = 0; i < args.ncodes; ++i) serial = serial || args.codes[i].serial;
     if (serial) return launch_lds_kernel<kSerial>(args, lds_bytes, s, grid_out);   // a single code
+    for (int i = 0; i < args.ncodes; ++i)
+        if (args.codes[i].wide) return launch_lds_kernel<kWide>(args, lds_bytes, s, grid_out);   // all wide
     switch (v) {
     case BP4_BP: return launch_lds_kernel<BP4_BP>(args, lds_bytes, s, grid_out);
     case BP4_MOMENTUM: return launch_lds_kernel<BP4_MOMENTUM>(args, lds_bytes, s, grid_out);

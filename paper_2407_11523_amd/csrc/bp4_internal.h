@@ -8,9 +8,13 @@
 
 namespace bp4 {
 
-// Compiled degree limits of the padded (ELL) edge lists.
+// Compiled degree limits of the padded (ELL) edge lists: narrow graphs (every check
+// and qubit of degree <= 4, all kernels) and wide graphs (checks of degree <= 8,
+// qubits of degree <= 7; the LDS flooding kernel, the sampler and bookkeeping).
 constexpr int kMaxCheckDeg = 4;
 constexpr int kMaxVarDeg = 4;
+constexpr int kMaxCheckDegWide = 8;
+constexpr int kMaxVarDegWide = 7;
 constexpr int kMaxVars = 16383;      // 14-bit qubit index in a packed check edge
 constexpr int kMaxEdges = 65534;     // 16-bit message slot; slot nnz is the padding slot
 
@@ -25,8 +29,9 @@ __host__ __device__ inline uint32_t edge_var(uint32_t w) { return (w >> 16) & 0x
 __host__ __device__ inline uint32_t edge_lab(uint32_t w) { return w >> 30; }
 
 // Packed qubit word: bits 0-15 first message slot, bits 16-18 degree, bits 20+2j
-// the label of the qubit's j-th edge (edges in increasing check order), bits 28-30
-// the labels present (bit 28 + label - 1).
+// the label of the qubit's j-th edge (edges in increasing check order; narrow graphs
+// only: a wide graph keeps them in the label word vlab, bits 2j), bits 28-30 the
+// labels present (bit 28 + label - 1).
 __host__ __device__ inline uint32_t var_base(uint32_t w) { return w & 0xFFFFu; }
 __host__ __device__ inline uint32_t var_deg(uint32_t w) { return (w >> 16) & 7u; }
 __host__ __device__ inline uint32_t var_lab(uint32_t w, int j) { return (w >> (20 + 2 * j)) & 3u; }
@@ -41,9 +46,11 @@ struct GraphView {
     const uint32_t *vchk;    // [nnz] check of each message slot
     const uint32_t *sord;    // [n] qubits in serial-schedule levels (level, then index)
     const uint32_t *slev;    // [nlev + 1] level offsets into sord
+    const uint32_t *vlab;    // [n] wide graphs: labels of each qubit's slots, 2 bits each
     const uint32_t *lptr;    // [nlog + 1] offsets into lent
     const uint32_t *lent;    // logical supports: qubit | (Pauli << 16)
     int32_t m, n, nnz, nlog, nlev;
+    int32_t cstride;         // edge words per check: kMaxCheckDeg (narrow) or kMaxCheckDegWide (wide)
 };
 
 struct DecodeArgs {
@@ -70,6 +77,7 @@ struct DecodeArgs {
     uint32_t magic_m, magic_n;   // ceil(2^32 / m), ceil(2^32 / n): item -> slot
     int32_t with_y;          // the code has Y entries
     int32_t serial;          // serial schedule (Algorithm 1) on wave groups
+    int32_t wide;            // wide graph (cstride 8, labels in vlab)
 };
 
 // Codes of one persistent launch, decoded in this order (largest first).
@@ -90,14 +98,15 @@ struct LaneChoice {
     int32_t group_lanes = -1, block_shots = 0;
 };
 
-LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes, int block_shots);
+LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes, int block_shots,
+                            bool wide = false);
 // Serial schedule: wave groups of G in {1, ..., 64} lanes; static part adds the
 // slot -> check table and the level order, regions hold signed phi values.
 LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant, int group_lanes);
 // The mapping is valid for the code: G a power of two in [4, 64] with at most 64
 // checks per lane, or 1 <= S <= 256 with at most 64 check items per lane.
 bool decode_lds_fits(int m, int n, int group_lanes, int block_shots);
-LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds);
+LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, bool wide = false);
 hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_t s, int *grid_out);
 
 hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const uint32_t thr[3],

@@ -65,9 +65,8 @@ syndrome_kernel(GraphView g, int32_t shots, const uint8_t *err, uint8_t *synd)
     const int c = (int)(idx - shot * g.m);
     const uint8_t *row = err + (size_t)shot * g.n;
     uint32_t par = 0;
-#pragma unroll
-    for (int j = 0; j < kMaxCheckDeg; ++j) {
-        const uint32_t w = g.cedge[c * kMaxCheckDeg + j];
+    for (int j = 0; j < g.cstride; ++j) {   // padding words carry label 0
+        const uint32_t w = g.cedge[c * g.cstride + j];
         if (edge_is_pad(w)) continue;
         par ^= anticomm(edge_lab(w), row[edge_var(w)]);
     }
@@ -100,9 +99,8 @@ bookkeep_kernel(GraphView g, int32_t shots, int tile, const uint8_t *err, const 
     for (int i = threadIdx.x; i < rows * g.m; i += blockDim.x) {
         const int sh = i / g.m, c = i - sh * g.m;
         uint32_t par = 0;
-#pragma unroll
-        for (int j = 0; j < kMaxCheckDeg; ++j) {
-            const uint32_t w = g.cedge[c * kMaxCheckDeg + j];
+        for (int j = 0; j < g.cstride; ++j) {
+            const uint32_t w = g.cedge[c * g.cstride + j];
             if (edge_is_pad(w)) continue;
             par ^= anticomm(edge_lab(w), res[sh * n + edge_var(w)]);
         }

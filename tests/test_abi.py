@@ -79,8 +79,10 @@ def test_graph_create_errors(lib):
     b = np.array([[0, 0], [1, 0]], np.uint8)
     assert _err(lambda: Graph(a, b, upload=False)) == "ENONCOMM"
     Graph(a, b, upload=False, allow_anticommuting=True)                    # allowed with the flag
-    wide = np.ones((1, 5), np.uint8)
+    wide = np.ones((1, 9), np.uint8)                                      # a check of degree 9
     assert _err(lambda: Graph(wide, np.zeros_like(wide), upload=False)) == "EDEGREE"
+    deep = np.ones((8, 1), np.uint8)                                      # a qubit of degree 8
+    assert _err(lambda: Graph(deep, np.zeros_like(deep), upload=False)) == "EDEGREE"
     big = np.ones((1, 16384), np.uint8)
     assert _err(lambda: Graph(big, np.zeros_like(big), upload=False)) == "EUNSUPPORTED"
 
@@ -303,3 +305,44 @@ def test_lane_mapping_validation_and_layout(lib):
     rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
                            fake, null, null, null, fake, 1 << 30, null)
     assert rc == -1
+
+
+def test_wide_graphs_route_to_the_flooding_lds_kernel(lib):
+    """Degree-6 codes build as wide graphs; the paths that need narrow graphs refuse them
+    before anything is enqueued."""
+    from paper_2407_11523_amd import Graph, Params, _lib
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    for c in (qecgen.bb(72), qecgen.chamon(2)):
+        g = Graph(c.hx, c.hz, c.lx, c.lz, upload=False)
+        n, m, nnz, dc, dv = (ctypes.c_int32() for _ in range(5))
+        assert lib.bp4_graph_info(g.handle, *(ctypes.byref(x) for x in (n, m, nnz, dc, dv))) == 0
+        assert (n.value, m.value, dc.value, dv.value) == (c.n, c.m, 6, 6)
+        cp = Params(variant="ewainit", alpha=0.5).c()
+        b = ctypes.c_size_t()
+        assert lib.bp4_workspace_bytes(g.handle, ctypes.byref(cp), 1000, ctypes.byref(b)) == 0 and b.value == 256
+        # the wide layout holds 8 edge words per check and a label word per qubit
+        assert lib.bp4_lds_layout_bytes(g.handle, ctypes.byref(cp), 64, 0, ctypes.byref(b)) == 0
+        assert b.value >= 4 * (8 * c.m + 5 * c.n)
+        tune = _lib.Tuning(0, 0, 2)                                       # the SOA kernel
+        rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                               fake, null, null, null, fake, 1 << 30, null)
+        assert rc == -6, rc                                                # EUNSUPPORTED
+        sp = Params(variant="ewainit", alpha=0.5, serial=True).c()
+        rc = lib.bp4_decode(g.handle, fake, ctypes.byref(sp), 10, fake, fake, fake, fake, fake, fake, 1 << 30, null)
+        assert rc == -6
+        it = ctypes.c_int32()
+        assert lib.bp4_decode_plain(g.handle, fake, ctypes.byref(cp), 10, fake, fake, fake, fake, fake, fake,
+                                    1 << 30, null, ctypes.byref(it)) == -6
+        s1, s2 = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.bp4_unrolled_sizes(g.handle, 4, 2, 64, ctypes.byref(s1), ctypes.byref(s2)) == 0
+    # a mixed launch does not combine wide and narrow codes
+    gw = Graph(qecgen.bb(72).hx, qecgen.bb(72).hz, upload=False)
+    gn = Graph(qecgen.toric(4).hx, qecgen.toric(4).hz, upload=False)
+    cp = Params(variant="ewainit", alpha=0.5).c()
+    arr = (_lib.CodeBatch * 2)()
+    arr[0] = _lib.CodeBatch(gw.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
+                            fake.value, 0, 0)
+    arr[1] = _lib.CodeBatch(gn.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
+                            fake.value, 0, 0)
+    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -6

@@ -1,0 +1,147 @@
+"""GPU: codes with degree-6 checks and qubits (section IV-C: bivariate bicycle and
+3D Chamon codes) on the wide flooding LDS kernel, against the FP64 oracle.
+
+Bar as for the surface codes: sampling, syndromes and bookkeeping bit-exact;
+messages and posteriors within 1e-5 max(|x64|, 1) at iterations 1, 2, 3 with
+stopping off (AdaGrad from the third iteration: >= 99.9% within 1e-5); decisions
+of shots that converge on both sides >= 99.9% equal, LER inside the oracle's
+interval; every lane mapping bit-identical; a mixed launch of wide codes equal to
+the per-code decodes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import qecgen
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2407_11523_amd as P  # noqa: E402
+
+REL_TOL = 1e-5
+VARIANTS = [("bp", 1.0), ("ewainit", 0.5), ("momentum", 0.6), ("adagrad", 5.0)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+CODES = {"bb72": lambda: qecgen.bb(72), "bb144": lambda: qecgen.bb(144), "chamon2": lambda: qecgen.chamon(2),
+         "chamon3": lambda: qecgen.chamon(3)}
+
+
+@pytest.mark.parametrize("name", ["bb72", "chamon3"])
+def test_sampler_syndromes_bookkeeping_bit_exact(name):
+    c = CODES[name]()
+    g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+    thr = qecgen.thresholds(0.03, 0.02, 0.04)
+    err, syn = P.sample(g, 3001, thr, seed=77)
+    e_o, s_o = O.sample(c.hx, c.hz, 3001, thr, seed=77)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(err), e_o) and np.array_equal(np_(syn), s_o)
+    # decisions: a third equal to the error, a third times a stabilizer (and half of
+    # those times a logical), a third random
+    rng = np.random.default_rng(3)
+    lab = c.labels()
+    logical = (c.lx | (c.lz << 1)).astype(np.uint8)
+    est = e_o.copy()
+    for i in range(len(est)):
+        if i % 3 == 1:
+            est[i] ^= lab[rng.integers(c.m)]
+            if rng.random() < 0.5:
+                est[i] ^= logical[rng.integers(len(logical))]
+        elif i % 3 == 2:
+            est[i] = rng.integers(0, 4, size=c.n) * (rng.random(c.n) < 0.03)
+    fail, cnt = P.bookkeep(g, err, torch.as_tensor(est, device="cuda"))
+    f_o, c_o = O.bookkeep(c.hx, c.hz, c.lx, c.lz, e_o, est)
+    torch.cuda.synchronize()
+    assert np.array_equal(np_(fail), f_o)
+    assert np_(cnt).tolist() == c_o.tolist()
+    assert c_o[0] > 0 and c_o[1] > 0 and c_o[2] > 0
+
+
+@pytest.mark.parametrize("variant,alpha", VARIANTS)
+@pytest.mark.parametrize("name", ["bb72", "chamon2", "chamon3"])
+def test_wide_messages(name, variant, alpha):
+    c = CODES[name]()
+    g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+    rng = np.random.default_rng(5)
+    probs = rng.uniform(0.01, 0.04, size=(c.n, 3))
+    _, syn = O.sample(c.hx, c.hz, 600, qecgen.thresholds(*probs[0]), seed=19)
+    for T in (1, 2, 3):
+        ro = O.decode(c.hx, c.hz, O.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False),
+                      O.prior_llr(probs), syn, want_q=True, want_msgs=True)
+        rg = P.decode(g, P.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False),
+                      P.prior_llr(probs), torch.as_tensor(syn, device="cuda"), trace=True)
+        torch.cuda.synchronize()
+        for k in ("mvc", "mcv", "q"):
+            err = np.abs(np_(rg[k]).astype(np.float64) - ro[k]) / np.maximum(np.abs(ro[k]), 1.0)
+            say("wide msg", name, variant, T, k, float(err.max()), float((err <= REL_TOL).mean()))
+            if variant == "adagrad" and T >= 3:
+                assert (err <= REL_TOL).mean() >= 0.999 and err.max() <= 0.5, k
+            else:
+                assert err.max() <= REL_TOL, (name, variant, T, k)
+        assert np.array_equal(np_(rg["iters"]), ro["iters"])
+
+
+@pytest.mark.parametrize("name,p,variant,alpha", [("bb72", 0.05, "ewainit", 0.5), ("bb144", 0.04, "ewainit", 0.5),
+                                                  ("chamon3", 0.06, "ewainit", 0.5), ("bb72", 0.05, "bp", 1.0)])
+def test_wide_decisions_and_ler(name, p, variant, alpha):
+    c = CODES[name]()
+    g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+    shots = 3000
+    err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=31)
+    prm = dict(variant=variant, alpha=alpha, max_iter=100)
+    r = P.decode(g, P.Params(**prm), P.prior_llr(qecgen.depolarizing_probs(c.n, p)), syn)
+    _, cnt = P.bookkeep(g, err, r["est"])
+    torch.cuda.synchronize()
+    ro = O.decode(c.hx, c.hz, O.Params(**prm), O.prior_llr(qecgen.depolarizing_probs(c.n, p)), np_(syn))
+    _, co = O.bookkeep(c.hx, c.hz, c.lx, c.lz, np_(err), ro["est"])
+    both = np_(r["conv"]).astype(bool) & ro["conv"].astype(bool)
+    agree = float((np_(r["est"]) == ro["est"])[both].mean())
+    ler_g = int(cnt[1] + cnt[2]) / shots
+    lo, hi = O.wilson_ci(int(co[1] + co[2]), shots, z=3.29)
+    say("wide", name, variant, dict(agree=agree, ler_g=ler_g, ler_o=int(co[1] + co[2]) / shots, ci=(lo, hi),
+                                    conv_g=float(np_(r["conv"]).mean()), conv_o=float(ro["conv"].mean())))
+    assert agree >= 0.999
+    assert lo <= ler_g <= hi
+
+
+def test_wide_lane_mappings_bitwise_and_mixed():
+    entries, refs = [], []
+    for i, name in enumerate(("bb72", "chamon3")):
+        c = CODES[name]()
+        g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+        _, syn = P.sample(g, 2500 + 7 * i, qecgen.thresholds(0.02, 0.02, 0.02), seed=50 + i)
+        pr = P.prior_llr(qecgen.depolarizing_probs(c.n, 0.06))
+        for variant, kw in (("ewainit", dict(alpha=0.5)), ("aewa", dict(alpha=1.0, alpha_last=0.0, alpha_steps=4,
+                                                                       max_iter=15))):
+            prm = P.Params(variant=variant, **dict(dict(max_iter=60), **kw))
+            ref = P.decode(g, prm, pr, syn, group_lanes=64, trace=True)
+            for kw2 in (dict(group_lanes=8), dict(group_lanes=32), dict(block_shots=1), dict(block_shots=3)):
+                try:
+                    r = P.decode(g, prm, pr, syn, trace=True, **kw2)
+                except P.BP4Error:        # this mapping does not fit the LDS
+                    continue
+                torch.cuda.synchronize()
+                for k in ("est", "conv", "iters", "mvc", "mcv", "q"):
+                    assert torch.equal(r[k], ref[k]), (name, variant, kw2, k)
+        prm = P.Params(variant="ewainit", alpha=0.5, max_iter=60)
+        entries.append((g, prm, pr, syn, 0))
+        refs.append(P.decode(g, prm, pr, syn))
+    outs = P.decode_mixed(entries)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, refs):
+        for k in ("est", "conv", "iters"):
+            assert torch.equal(o[k], r[k]), k
