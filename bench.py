@@ -465,8 +465,9 @@ def run_qldpc(torch, qecgen, P, dev):
         code = qecgen.make(fam, size)
         g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
         row = {"code": code.name, "n": code.n, "k": code.k, "p": list(ps)}
-        for variant, alpha in (("ewainit", ALPHA), ("bp", 1.0)):
-            prm = P.Params(variant=variant, alpha=alpha, max_iter=100)
+        for variant, alpha in (("ewainit", ALPHA), ("bp", 1.0), ("aewa", 1.0)):
+            prm = P.Params(variant=variant, alpha=alpha, max_iter=100,
+                           **(dict(alpha_last=0.0, alpha_steps=11) if variant == "aewa" else {}))
             lers, rates = [], []
             for j, p in enumerate(ps):
                 err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3),
@@ -483,11 +484,23 @@ def run_qldpc(torch, qecgen, P, dev):
                 lers.append(float(cnt[1] + cnt[2]) / shots)
                 rates.append(shots / (a.elapsed_time(b) / 1e3))
             row[variant] = {"ler": lers, "syndromes_per_s": rates}
+        # the paper states no discount for these codes: EWAInit over alpha at p = 0.04
+        sweep = {}
+        err, syn = P.sample(g, shots, qecgen.thresholds(0.04 / 3, 0.04 / 3, 0.04 / 3), seed=qecgen.config_seed(9, i, 9))
+        pr = P.prior_llr(qecgen.depolarizing_probs(code.n, 0.04), device=dev)
+        for alpha in (0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
+            r = P.decode(g, P.Params(variant="ewainit", alpha=alpha, max_iter=100), pr, syn)
+            _, cnt = P.bookkeep(g, err, r["est"])
+            torch.cuda.synchronize()
+            sweep[str(alpha)] = float(cnt[1] + cnt[2]) / shots
+        row["ewainit_alpha_sweep_p0.04"] = sweep
         rows.append(row)
         log(f"{code.name}: LER EWAInit {[round(x, 4) for x in row['ewainit']['ler']]} "
-            f"BP {[round(x, 4) for x in row['bp']['ler']]}")
+            f"BP {[round(x, 4) for x in row['bp']['ler']]} AEWA {[round(x, 4) for x in row['aewa']['ler']]} "
+            f"alpha sweep p=0.04 {sweep}")
     return {"workload": "bivariate bicycle n = 72, 90, 108, 144 and 3D Chamon d = 3, 4, depolarizing p = 0.02-0.08, "
-                        "2^16 shots per point, EWAInit-BP alpha 0.5 and BP, iter_max 100",
+                        "2^16 shots per point, EWAInit-BP alpha 0.5, BP and AEWA-BP (11 discounts 1 to 0), "
+                        "iter_max 100; EWAInit over alpha at p = 0.04",
             "rows": rows}
 
 
