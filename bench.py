@@ -37,18 +37,20 @@ CODES = [("planar", 5, 1), ("planar", 7, 1), ("planar", 9, 2), ("planar", 11, 4)
          ("xzzx", 5, 1), ("xzzx", 9, 2), ("xzzx", 13, 4)]
 
 # Roofline of the LDS-resident decode: VALU issue.  Algorithmic FP32 issue slots of
-# one EWAInit iteration of one shot, counted from the update rules: phi = 8 FP32
-# operations + one exp2 or log2; ln(1 + e^-|y|) = 4 operations + 2 transcendentals;
-# a transcendental costs TRANS_SLOTS plain FP32 issue slots (measured by
-# paper_2407_11523_amd/calib/valu_rate: exp2 1.76, log2 1.74).
+# one EWAInit iteration of one shot, counted from the update rules: phi = 6 FP32
+# operations + one exp2 or log2 (a square, a cubic or quartic polynomial in it and
+# one final multiply-add, constant scalings folded into the coefficients);
+# ln(1 + e^-|y|) = 3 operations + 2 transcendentals; a transcendental costs
+# TRANS_SLOTS plain FP32 issue slots (measured by paper_2407_11523_amd/calib/valu_rate:
+# exp2 1.76, log2 1.74).
 #   check of degree d: 2d phi, d sign products, 2d - 1 leave-one-out sums, d sign
-#                      applications, d clamps; syndrome test d + 1  -> 22d ops, 2d transcendentals
+#                      applications, d clamps; syndrome test d + 1  -> 18d ops, 2d transcendentals
 #   qubit of degree d with L labels present: d + 3 label sums, 9 posterior (EWAInit),
-#                      5 hard decision, L lambdas (two softplus + 4 ops each), 2d
+#                      5 hard decision, L lambdas (two softplus + 6 ops each), 2d
 #                      output subtractions and clamps               -> 3d + 17 + 12L ops, 4L transcendentals
-# so an iteration costs 25 E + 17 N + 12 sum(L) operations and 2 E + 4 sum(L)
+# so an iteration costs 21 E + 17 N + 12 sum(L) operations and 2 E + 4 sum(L)
 # transcendentals (E edges, N qubits).  Peak issue: 256 CUs x 4 SIMDs x 16 lanes
-# x 2.4 GHz = 39.3e12 slots/s (the calibration measures 37.3e12 for adds).
+# x 2.4 GHz = 39.3e12 slots/s.
 TRANS_SLOTS = 1.75
 
 
@@ -59,7 +61,7 @@ def iteration_slots(code):
     E = int((lab != 0).sum())
     N = code.n
     L = int(sum(len(set(int(x) for x in np.unique(lab[:, v])) - {0}) for v in range(N)))
-    ops = 25 * E + 17 * N + 12 * L
+    ops = 21 * E + 17 * N + 12 * L
     trans = 2 * E + 4 * L
     return ops + TRANS_SLOTS * trans
 
@@ -82,8 +84,8 @@ HBM_PEAK = 8.0e12   # bytes/s
 # taken on: a kernel whose sources hash differently reports traffic null.
 KERNEL_SOURCES = {"decode_lds_kernel": ("bp4_decode.hip", "bp4_math.h", "bp4_internal.h"),
                   "decode_soa_kernel": ("bp4_soa.hip", "bp4_math.h", "bp4_internal.h")}
-MEASURED_TRAFFIC = {"decode_lds_kernel": ("ee02ea954c7fedff", 4.019e+09),    # mixed batch, one launch
-                    "decode_soa_kernel": ("823d6d2bcc39d31f", 5.269e+11)}   # large codes, mean of 26 launches
+MEASURED_TRAFFIC = {"decode_lds_kernel": ("bd30425fd24ae530", 4.019e+09),    # mixed batch, one launch
+                    "decode_soa_kernel": ("be385c0d228a679f", 5.272e+11)}   # large codes, mean of 26 launches
 
 
 def measured_traffic(kernel):

@@ -43,6 +43,13 @@ template <bool W> struct Width {
     static constexpr int kSlots = W ? 8 : 4;                            // message words read per qubit
 };
 
+// Message layout of the flooding kernels in LDS: slot j of qubit v at word v + j n
+// (slot-major, so the lanes of a qubit pass read and write consecutive words), then
+// the padding slot at kSlots n, which holds +inf.  The staged check edges carry
+// these positions in their slot field.
+template <bool W>
+__device__ __forceinline__ uint32_t lds_pad_slot(uint32_t n) { return Width<W>::kSlots * n; }
+
 template <bool W>
 __device__ __forceinline__ void load_check(const uint32_t *s_ce, int c, uint32_t w[Width<W>::kCheck])
 {
@@ -61,12 +68,12 @@ __device__ __forceinline__ void load_check(const uint32_t *s_ce, int c, uint32_t
 __device__ __forceinline__ void check_update_wide(const float mv[8], uint32_t s, float C, float out[8])
 {
     float f[8];
-    uint32_t sgn[8];
-    uint32_t neg = s & 1u;
+    uint32_t b[8];
+    uint32_t neg = s << 31;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        sgn[j] = mv[j] < 0.0f ? 1u : 0u;
-        neg ^= sgn[j];
+        b[j] = __float_as_uint(mv[j]);
+        neg ^= b[j];
         f[j] = phi(fabsf(mv[j]));
     }
     float pre[8], suf[8];
@@ -79,7 +86,7 @@ __device__ __forceinline__ void check_update_wide(const float mv[8], uint32_t s,
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const float mag = phi(pre[j] + suf[j]);
-        out[j] = clampf((neg ^ sgn[j]) ? -mag : mag, C);
+        out[j] = clampf(__uint_as_float(__float_as_uint(mag) ^ ((neg ^ b[j]) & 0x80000000u)), C);
     }
 }
 
@@ -169,17 +176,17 @@ __device__ __forceinline__ void label_sums_w(uint32_t labw, const float mc[DV], 
 // lambda_{H_cv}(Pi^{(0)}_v); Q^{(0)} = Pi^{(0)}; accumulators start at 0.
 template <int VAR, bool W = false>
 __device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const uint32_t *s_vl, const float *s_pi, float *msg,
-                                           float *qs, float *acc, int v, float C)
+                                           float *qs, float *acc, int v, int n, float C)
 {
     constexpr bool keep_q = VAR != BP4_BP;
     constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
     const uint32_t info = s_vi[v];
     const uint32_t labw = label_word<W>(s_vl, info, v);
-    const uint32_t base = var_base(info), deg = var_deg(info);
+    const uint32_t deg = var_deg(info);
     const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
     float lam[4];
     qubit_lambdas(p3, var_labels_present(info), lam);
-    for (uint32_t j = 0; j < deg; ++j) msg[base + j] = clampf(lam[slot_label(labw, (int)j)], C);
+    for (uint32_t j = 0; j < deg; ++j) msg[v + j * n] = clampf(lam[slot_label(labw, (int)j)], C);
     float st[3], ac[3];
     qubit_state_init(VAR, p3, st, ac);
     if (keep_q)
@@ -191,7 +198,7 @@ __device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const uint32_t 
 // Posterior, hard decision and vertical update of qubit v at iteration t (eqs.
 // p_update, v_update and the variant's rule) from its incoming messages mc[j]
 // (slot order; slots j >= degree carry label 0 and are never used).  The new
-// m_{v->c} of slot base + j goes to store(slot, value).  `shot` indexes the
+// m_{v->c} of the qubit's slot j goes to store(j, value).  `shot` indexes the
 // optional verification outputs (none are written for shot >= shots).  WY: the
 // code has Y labels (else every edge label is X or Z).
 template <int VAR, bool WY, int DV, typename Store>
@@ -229,7 +236,7 @@ __device__ __forceinline__ void qubit_update(const DecodeArgs &a, const float *s
         float lsel = l == 2u ? lam[2] : lam[1];
         if (WY) lsel = l == 3u ? lam[3] : lsel;
         const float out = clampf(lsel - mc[j], C);
-        store(base + j, out);
+        store((uint32_t)j, out);
         if (trace) {
             const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
             a.mvc_out[o] = out;
@@ -248,16 +255,14 @@ __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *
 {
     constexpr int DV = Width<W>::kSlots;
     const uint32_t info = s_vi[v];
-    const uint32_t base = var_base(info);
-    // the words after a qubit's last slot are in the region (another qubit's
-    // slots, the padding slot or the posterior array); they are read but never
-    // used: those slots carry label 0, which the label sums skip, and no message
-    // is written for them
+    const uint32_t n = (uint32_t)a.g.n;
+    // slots j >= degree are read but never used: they carry label 0, which the
+    // label sums skip, and no message is written for them
     float mc[DV];
 #pragma unroll
-    for (int j = 0; j < DV; ++j) mc[j] = msg[base + j];
+    for (int j = 0; j < DV; ++j) mc[j] = msg[v + j * n];
     qubit_update<VAR, WY, DV>(a, s_pi, info, label_word<W>(s_vl, info, v), v, mc, qs, acc, ehat, t, vp, shot,
-                              [&](uint32_t slot, float out) { msg[slot] = out; });
+                              [&](uint32_t j, float out) { msg[v + j * n] = out; });
 }
 
 template <int VAR>
@@ -304,12 +309,12 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
     int t_before = 0;  // AEWA: iterations of the shot's earlier attempts
 
     auto init = [&](int s) {
-        if (r == 0) msg[a.g.nnz] = INFINITY;   // padding slot
+        if (r == 0) msg[lds_pad_slot<W>(n)] = INFINITY;
         sbits = 0;
         int k = 0;
         for (int c = r; c < m; c += G, ++k)
             if (a.synd[(size_t)s * m + c]) sbits |= 1ull << k;
-        for (int v = r; v < n; v += G) init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, qs, acc, v, C);
+        for (int v = r; v < n; v += G) init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, qs, acc, v, n, C);
         t = 0;
     };
 
@@ -454,7 +459,8 @@ __device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
             const float mag = phi((f[0] + f[1]) + (f[2] + f[3]));
             mc[j] = clampf(neg ? -mag : mag, C);
         }
-        qubit_update<VAR, WY, 4>(a, s_pi, info, info >> 20, v, mc, qs, acc, ehat, t, vp, shot, store);
+        qubit_update<VAR, WY, 4>(a, s_pi, info, info >> 20, v, mc, qs, acc, ehat, t, vp, shot,
+                                 [&](uint32_t j, float out) { store(base + j, out); });
     };
 
     int s0 = 0;
@@ -604,7 +610,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     a.est[(size_t)h[kHdrDone] * n + w.x] = (uint8_t)decision_pauli(ehat[w.x]);
                 }
                 if (h[kHdrFresh])
-                    init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off, (int)w.x, C);
+                    init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off, (int)w.x, n, C);
             }
             BP4_FOR_CHECKS(w) {
                 float *msg = reg0 + w.off;
@@ -614,7 +620,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     syn[w.x] = a.synd[(size_t)h[kHdrShot] * m + w.x];
                 }
             }
-            if (tid < (int)S && hdr(tid)[kHdrFresh]) reg0[tid * RW + a.g.nnz] = INFINITY;   // padding slot
+            if (tid < (int)S && hdr(tid)[kHdrFresh]) reg0[tid * RW + lds_pad_slot<W>(n)] = INFINITY;
         }
         if (!any_more) break;
         __syncthreads();
@@ -721,14 +727,14 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *e
 // VSET: the variant every code of the launch uses, kMixedVariants for a flooding
 // launch that mixes variants (a switch per code), kSerial for the serial schedule
 // (one code, a switch on its variant), kWide for a flooding launch of wide graphs
-// (a switch on the variant).  Register budget: 72 VGPRs
-// (seven wavefronts per SIMD) for the single-variant builds that fit it without
+// (a switch on the variant).  Register budget: 80 VGPRs
+// (six wavefronts per SIMD) for the single-variant builds, which fit it without
 // spilling, 96 (five) for AdaGrad and the switching builds, 128 (four) for kWide,
 // whose 8-edge checks hold twice the messages in registers.
 constexpr int kMixedVariants = -1, kSerial = -2, kWide = -3;
 constexpr int lds_kernel_waves(int vset)
 {
-    return vset == kWide ? 4 : (vset < 0 || vset == BP4_ADAGRAD) ? 5 : 7;
+    return vset == kWide ? 4 : (vset < 0 || vset == BP4_ADAGRAD) ? 5 : 6;
 }
 
 template <int VSET>
@@ -751,7 +757,23 @@ decode_lds_kernel(MixedArgs args)
         const int cs = a.g.cstride;
         uint32_t *s_vi = s_ce + cs * m;
         float *s_pi = reinterpret_cast<float *>(s_vi + n);
-        for (int i = threadIdx.x; i < cs * m; i += kBlock) s_ce[i] = a.g.cedge[i];
+        if (VSET == kSerial) {
+            for (int i = threadIdx.x; i < cs * m; i += kBlock) s_ce[i] = a.g.cedge[i];
+        } else {
+            // slot field -> slot-major position v + j n (j: the edge's rank among its
+            // qubit's slots); padding -> the padding slot.  kSlots n < 2^16: the
+            // layout holds kSlots n message words in LDS.
+            constexpr bool W = VSET == kWide;
+            for (int i = threadIdx.x; i < cs * m; i += kBlock) {
+                const uint32_t w = a.g.cedge[i];
+                uint32_t slot = lds_pad_slot<W>((uint32_t)n);
+                if (!edge_is_pad(w)) {
+                    const uint32_t v = edge_var(w);
+                    slot = v + (edge_slot(w) - var_base(a.g.vinfo[v])) * (uint32_t)n;
+                }
+                s_ce[i] = (w & ~0xFFFFu) | slot;
+            }
+        }
         for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
         if (VSET == kWide && a.wide) {   // slot labels of a wide graph
@@ -819,7 +841,7 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S, bo
     // check edges, qubit words, priors (and the slot labels of a wide graph)
     L.static_words = (wide ? kMaxCheckDegWide : kMaxCheckDeg) * m + n + 3 * n + (wide ? n : 0);
     if (L.static_words & 3) L.static_words += 4 - (L.static_words & 3);
-    int w = nnz + 1;               // message slots and the padding slot
+    int w = (wide ? 8 : 4) * n + 1;   // slot-major message slots and the padding slot
     L.q_off = w;
     if (variant != BP4_BP) w += 3 * n;
     L.acc_off = w;
@@ -832,10 +854,6 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S, bo
         L.hdr_off = w;
         w += kHdrBad + 2;
     }
-    // the qubit phase reads four (wide: eight) words from each qubit's first slot:
-    // keep them inside
-    const int reach = nnz + (wide ? 8 : 4);
-    if (w < reach) w = reach;
     if ((w & 1) == 0) w += 1;   // odd stride: neighbouring regions start on other banks
     L.region_words = w;
     L.group_lanes = S > 0 ? kBlock : G;

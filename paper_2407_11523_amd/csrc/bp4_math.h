@@ -38,27 +38,30 @@ __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf
 
 // phi(x) = -ln tanh(x/2) = 2 atanh(e^{-x}) for x >= 0, phi(0) = inf, phi(inf) = 0;
 // 2 atanh(prod tanh(m_k/2)) = (prod sgn m_k) phi(sum phi(|m_k|)).
-//   x >= 5/4: z = e^{-x} < 0.29 and phi = 2 z P(z^2), P(w) = atanh(sqrt w)/sqrt w;
-//   x <  5/4: phi = ln(2/x) + u G(u), u = x^2/4, u G(u) = -ln(tanh(sqrt u)/sqrt u).
-// P and G are cubic minimax fits on those ranges (relative error of phi below 5e-8
-// from the fits; FP32 rounding of the exponent argument dominates at large x);
-// both forms keep full relative accuracy (no 1 - z or log(1 + tiny) cancellation).
+//   x >= 5/4: z = e^{-x} < 0.29 and phi = z Q(z^2), Q(w) = 2 atanh(sqrt w)/sqrt w;
+//   x <  5/4: phi = -ln x + H(x^2), H(v) = ln 2 - ln(tanh(s)/s) at s = sqrt(v)/2.
+// Q is a cubic and H a quartic with H(0) = ln 2, minimax fits on those ranges
+// (relative error of phi below 2e-7 from the fits and FP32 rounding, up to
+// x = 20; beyond, the rounding of the exponent argument dominates); both forms
+// keep full relative accuracy (no 1 - z or log(1 + tiny) cancellation).  Six
+// FP32 operations and one transcendental either way.
 constexpr float kPhiSplit = 1.25f;
 __device__ __forceinline__ float phi(float x)
 {
     if (x >= kPhiSplit) {
         const float z = hw_exp2(-x * kLog2e);
         const float w = z * z;
-        float p = fmaf(w, 0.16298873778648207f, 0.1989325570537775f);
-        p = fmaf(w, p, 0.3333511821226621f);
-        p = fmaf(w, p, 0.9999999533102701f);
-        return (2.0f * z) * p;
+        float q = fmaf(w, 0.32597747557296414f, 0.397865114107555f);
+        q = fmaf(w, q, 0.6667023642453243f);
+        q = fmaf(w, q, 1.9999999066205403f);
+        return z * q;
     }
-    const float u = 0.25f * x * x;
-    float g = fmaf(u, -0.004938818690502019f, 0.021287449220304667f);
-    g = fmaf(u, g, -0.07769785638553288f);
-    g = fmaf(u, g, 0.3333296913153782f);
-    return fmaf(-hw_log2(0.5f * x), kLn2, u * g);
+    const float v = x * x;
+    float h = fmaf(v, -1.929226050977351e-05f, 0.0003326163940672604f);
+    h = fmaf(v, h, -0.004856116024095805f);
+    h = fmaf(v, h, 0.08333242282884455f);
+    h = fmaf(v, h, kLn2);
+    return fmaf(-hw_log2(x), kLn2, h);
 }
 
 // ln(1 + e^{-|y|}): the correction term of a two-term log-sum-exp.
@@ -269,25 +272,29 @@ __device__ __forceinline__ void qubit_lambdas(const float q[3], uint32_t present
 
 // Check-node update (eq. h_update) of one check of degree <= 4 given its incoming
 // messages mv[j] (padding: +inf) and syndrome bit s: outputs out[j] for j < 4.
+// The sign of each output is the XOR of the syndrome bit and the other inputs'
+// sign bits (a -0 input counts as negative: its own phi is +inf, so the only
+// outputs it changes are zeros, whose sign it flips).
 __device__ __forceinline__ void check_update(const float mv[4], uint32_t s, float C, float out[4])
 {
+    constexpr uint32_t kSign = 0x80000000u;
     float f[4];
-    uint32_t sgn[4];
-    uint32_t neg = s & 1u;
+    uint32_t b[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        sgn[j] = mv[j] < 0.0f ? 1u : 0u;
-        neg ^= sgn[j];
+        b[j] = __float_as_uint(mv[j]);
         f[j] = phi(fabsf(mv[j]));
     }
+    const uint32_t neg = b[0] ^ b[1] ^ b[2] ^ b[3] ^ (s << 31);   // sign bit: product of all signs
     // leave-one-out sums of phi, formed directly (no subtraction) and in value order,
     // so equal multisets of inputs give bitwise equal outputs
     const float loo[4] = {sum3_canonical(f[1], f[2], f[3]), sum3_canonical(f[0], f[2], f[3]),
                           sum3_canonical(f[0], f[1], f[3]), sum3_canonical(f[0], f[1], f[2])};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float mag = phi(loo[j]);
-        out[j] = clampf((neg ^ sgn[j]) ? -mag : mag, C);
+        const float mag = phi(loo[j]);   // >= 0 (or NaN)
+        const uint32_t sgn = (neg ^ b[j]) & kSign;
+        out[j] = clampf(__uint_as_float(__float_as_uint(mag) ^ sgn), C);
     }
 }
 

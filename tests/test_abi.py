@@ -285,8 +285,9 @@ def test_lane_mapping_validation_and_layout(lib):
     assert layout(128, 0) == layout(256, 2) == layout(0, 2)
     region = layout(0, 2)[1] - b2
     assert layout(0, 3)[1] == b2 + 2 * region and layout(0, 4)[1] == b2 + 3 * region
-    # a region holds the messages, posteriors, decisions, syndrome bytes and a header
-    assert region >= 4 * (g.nnz + 1 + 3 * g.n) + g.n + g.m
+    # a region holds the messages (four slot-major slots per qubit and the padding
+    # slot), posteriors, decisions, syndrome bytes and a header
+    assert region >= 4 * (4 * g.n + 1 + 3 * g.n) + g.n + g.m
     assert layout(0, 0)[0] == -1           # no mapping
     assert layout(64, 2)[0] == -1          # block_shots with a wave group
     assert layout(0, 257)[0] == -1
