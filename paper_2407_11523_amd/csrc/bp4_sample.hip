@@ -55,22 +55,85 @@ sample_errors_kernel(int32_t n, int32_t shots, int64_t shot0, uint32_t t0, uint3
     }
 }
 
-// One thread per (shot, check): s_c = sum over the check's edges of <H_cv, E_v> mod 2.
-__global__ void __launch_bounds__(256)
-syndrome_kernel(GraphView g, int32_t shots, const uint8_t *err, uint8_t *synd)
+// Tiles of shots: a workgroup stages `rows` consecutive shots' bytes of one or two
+// [shots][n] arrays in LDS (XOR of the two when both are given), as 4-byte words
+// where the source is aligned and single bytes at the two ends.  dst[i] for
+// i < rows * n holds byte first * n + i.
+__device__ __forceinline__ void stage_rows(uint8_t *dst, const uint8_t *a, const uint8_t *b, size_t first_byte,
+                                           int len)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)shots * g.m) return;
-    const int64_t shot = idx / g.m;
-    const int c = (int)(idx - shot * g.m);
-    const uint8_t *row = err + (size_t)shot * g.n;
-    uint32_t par = 0;
-    for (int j = 0; j < g.cstride; ++j) {   // padding words carry label 0
-        const uint32_t w = g.cedge[c * g.cstride + j];
-        if (edge_is_pad(w)) continue;
-        par ^= anticomm(edge_lab(w), row[edge_var(w)]);
+    const uint8_t *pa = a + first_byte;
+    const uint8_t *pb = b ? b + first_byte : nullptr;
+    // bytes before the first 4-byte boundary of the source, then whole words, then the rest
+    int head = (int)((4u - (uint32_t)((uintptr_t)pa & 3u)) & 3u);
+    if (head > len) head = len;
+    const int words = (len - head) >> 2;
+    for (int i = threadIdx.x; i < head; i += blockDim.x) dst[i] = pb ? (uint8_t)(pa[i] ^ pb[i]) : pa[i];
+    const uint32_t *wa = reinterpret_cast<const uint32_t *>(pa + head);
+    const bool b_aligned = pb && (((uintptr_t)(pb + head) & 3u) == 0);
+    for (int i = threadIdx.x; i < words; i += blockDim.x) {
+        uint32_t v = wa[i];
+        if (pb) {
+            if (b_aligned) {
+                v ^= reinterpret_cast<const uint32_t *>(pb + head)[i];
+            } else {
+                const uint8_t *q = pb + head + 4 * i;
+                v ^= (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) | ((uint32_t)q[3] << 24);
+            }
+        }
+        uint8_t *d = dst + head + 4 * i;
+        d[0] = (uint8_t)v;
+        d[1] = (uint8_t)(v >> 8);
+        d[2] = (uint8_t)(v >> 16);
+        d[3] = (uint8_t)(v >> 24);
     }
-    synd[idx] = (uint8_t)par;
+    for (int i = head + 4 * words + (int)threadIdx.x; i < len; i += blockDim.x)
+        dst[i] = pb ? (uint8_t)(pa[i] ^ pb[i]) : pa[i];
+}
+
+// Symplectic product of check c with the Pauli row `row` (bytes per qubit): the
+// check's edge words are read as 16-byte vectors; padding words carry label 0.
+__device__ __forceinline__ uint32_t check_parity(const GraphView &g, int c, const uint8_t *row)
+{
+    uint32_t par = 0;
+    for (int q = 0; q < g.cstride; q += 4) {
+        const uint4 w4 = *reinterpret_cast<const uint4 *>(g.cedge + (size_t)c * g.cstride + q);
+        const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (!edge_is_pad(w[j])) par ^= anticomm(edge_lab(w[j]), row[edge_var(w[j])]);
+    }
+    return par;
+}
+
+// Walk over the (shot, check) items of a tile: item tid, tid + B, ... of the
+// flattened rows * m list, advanced by carries instead of a division per item.
+struct RowWalk {
+    int sh, c;
+};
+
+// Syndromes of a tile of shots: s_c = sum over the check's edges of <H_cv, E_v> mod 2.
+__global__ void __launch_bounds__(256)
+syndrome_kernel(GraphView g, int32_t shots, int tile, const uint8_t *err, uint8_t *synd)
+{
+    extern __shared__ uint8_t rows_lds[];   // [tile][n]
+    const int64_t first = (int64_t)blockIdx.x * tile;
+    const int rows = (int)((shots - first) < tile ? (shots - first) : tile);
+    const int n = g.n, m = g.m;
+    stage_rows(rows_lds, err, nullptr, (size_t)first * n, rows * n);
+    __syncthreads();
+    uint8_t *out = synd + (size_t)first * m;
+    const int B = (int)blockDim.x, q = B / m, rem = B - q * m;
+    RowWalk w{(int)threadIdx.x / m, (int)threadIdx.x % m};
+    for (; w.sh < rows;) {
+        out[w.sh * m + w.c] = (uint8_t)check_parity(g, w.c, rows_lds + w.sh * n);
+        w.sh += q;
+        w.c += rem;
+        if (w.c >= m) {
+            w.c -= m;
+            w.sh += 1;
+        }
+    }
 }
 
 // Bookkeeping: a block takes a tile of shots, stages R = E^ xor E in LDS, then
@@ -87,24 +150,33 @@ bookkeep_kernel(GraphView g, int32_t shots, int tile, const uint8_t *err, const 
     __shared__ unsigned int cnt[3];
     const int64_t first = (int64_t)blockIdx.x * tile;
     const int rows = (int)((shots - first) < tile ? (shots - first) : tile);
-    const int n = g.n;
-    for (int i = threadIdx.x; i < rows * n; i += blockDim.x) {
-        const size_t off = (size_t)first * n + i;
-        res[i] = (err[off] ^ est[off]) & 3u;
-    }
+    const int n = g.n, m = g.m;
+    // bit 0: x part, bit 1: z part of the residual (decision bytes hold only those)
+    stage_rows(res, err, est, (size_t)first * n, rows * n);
     for (int i = threadIdx.x; i < rows; i += blockDim.x) flags[i] = 0;
     if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
     __syncthreads();
     // residual syndrome: "detected" when R anticommutes with a stabilizer
-    for (int i = threadIdx.x; i < rows * g.m; i += blockDim.x) {
-        const int sh = i / g.m, c = i - sh * g.m;
-        uint32_t par = 0;
-        for (int j = 0; j < g.cstride; ++j) {
-            const uint32_t w = g.cedge[c * g.cstride + j];
-            if (edge_is_pad(w)) continue;
-            par ^= anticomm(edge_lab(w), res[sh * n + edge_var(w)]);
+    {
+        const int B = (int)blockDim.x, q = B / m, rem = B - q * m;
+        RowWalk w{(int)threadIdx.x / m, (int)threadIdx.x % m};
+        uint32_t bad = 0;
+        int cur = w.sh;
+        for (; w.sh < rows;) {
+            if (w.sh != cur) {
+                if (bad) atomicOr(&flags[cur], 1u);
+                bad = 0;
+                cur = w.sh;
+            }
+            bad |= check_parity(g, w.c, res + w.sh * n);
+            w.sh += q;
+            w.c += rem;
+            if (w.c >= m) {
+                w.c -= m;
+                w.sh += 1;
+            }
         }
-        if (par) atomicOr(&flags[sh], 1u);
+        if (bad && cur < rows) atomicOr(&flags[cur], 1u);
     }
     // logical class: "undetected" when R anticommutes with a logical operator
     for (int i = threadIdx.x; i < rows * g.nlog; i += blockDim.x) {
@@ -145,10 +217,14 @@ hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const
                        g.n, shots, shot0, thr[0], thr[1], thr[2], seed, stream_id, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t work2 = (int64_t)shots * g.m;
-    if (work2 == 0) return hipSuccess;
-    hipLaunchKernelGGL(syndrome_kernel, dim3((unsigned)((work2 + 255) / 256)), dim3(256), 0, s,
-                       g, shots, err, synd);
+    if (g.m == 0) return hipSuccess;
+    // shots per workgroup: their error rows fill at most 16 KB of LDS
+    int tile = 16384 / (g.n > 0 ? g.n : 1);
+    if (tile > 64) tile = 64;
+    if (tile < 1) tile = 1;
+    const int64_t blocks = ((int64_t)shots + tile - 1) / tile;
+    hipLaunchKernelGGL(syndrome_kernel, dim3((unsigned)blocks), dim3(256), (size_t)tile * g.n, s, g, shots, tile,
+                       err, synd);
     return hipGetLastError();
 }
 

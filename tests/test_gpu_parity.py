@@ -122,6 +122,35 @@ def test_bookkeep_bit_exact(make):
     assert cnt_o[2] > 0 and cnt_o[1] > 0 and cnt_o[0] > 0
 
 
+def test_sample_and_bookkeep_on_unaligned_views():
+    """Rows that start off a 4-byte boundary (slices of a caller's buffers): the
+    staged row copies of the syndrome and bookkeeping kernels take their byte path
+    at both ends and for an unaligned second operand; results stay bit-exact."""
+    code = qecgen.planar(5)   # n = 41, m = 40
+    say("unaligned views", code.name)
+    g = gpu_graph(code)
+    shots = 1000
+    thr = qecgen.thresholds(0.03, 0.02, 0.05)
+    ebuf = torch.zeros(shots + 1, code.n, dtype=torch.uint8, device="cuda")
+    sbuf = torch.zeros(shots * code.m + 3, dtype=torch.uint8, device="cuda")
+    err = ebuf[1:]                                   # starts 41 bytes in
+    syn = sbuf[3:].view(shots, code.m)               # starts 3 bytes in
+    P.sample(g, shots, thr, seed=77, stream_id=1, err=err, synd=syn)
+    torch.cuda.synchronize()
+    e0, s0 = O.sample(code.hx, code.hz, shots, thr, seed=77, stream=1, shot0=0)
+    assert np.array_equal(np_(err), e0) and np.array_equal(np_(syn), s0)
+    rng = np.random.default_rng(5)
+    est = e0 ^ (rng.integers(0, 4, size=e0.shape) * (rng.random(e0.shape) < 0.02)).astype(np.uint8)
+    est_buf = torch.zeros(shots + 2, code.n, dtype=torch.uint8, device="cuda")
+    est_buf[2:] = torch.as_tensor(est, device="cuda")
+    fail_g, cnt_g = P.bookkeep(g, err, est_buf[2:])  # 82 bytes in: 2-byte aligned
+    torch.cuda.synchronize()
+    fail_o, cnt_o = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e0, est)
+    assert np.array_equal(np_(fail_g), fail_o)
+    assert np_(cnt_g).tolist() == cnt_o.tolist()
+    assert cnt_o[1] > 0 and cnt_o[0] > 0
+
+
 # ---------------------------------------------------------------------------
 # Messages at iterations 1..5 (stopping off) against FP64
 # ---------------------------------------------------------------------------
