@@ -7,11 +7,15 @@
 // (scalar loads).
 //
 // Iteration blocks: a launch runs the live shots through at most `iter_block`
-// iterations.  Shots that stop are written out; the others append their column
-// to a second record buffer, densely, so the next launch runs only live shots
-// on fully populated wavefronts instead of idling lanes behind the shots that
-// run to the iteration limit.  The arithmetic of a shot does not depend on its
-// column, so results do not depend on the block length or the compaction order.
+// iterations.  Shots that stop are written out; the others move their column to
+// a second record buffer, densely, so the next launch runs only live shots on
+// fully populated wavefronts instead of idling lanes behind the shots that run
+// to the iteration limit.  With the flooding schedule the move costs no extra
+// traffic: the shots entering a launch's last iteration take their new column
+// first, and that iteration reads the old column and writes the new one; a shot
+// that stops in it leaves a hole (shot id -1) that the next launch skips.  The
+// arithmetic of a shot does not depend on its column, so results do not depend
+// on the block length or the compaction order.
 //
 // Paper: Chen, Yi, Liang, Wang, "Improved Belief Propagation Decoding
 // Algorithms for Surface Codes", section II-B1 (eqs. init, h_update,
@@ -83,7 +87,8 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     const size_t wave = (size_t)(col >> 6);
     const int count = a.fresh ? a.first_count : (int)*a.src_count;
     if ((int)(wave << 6) >= count) return;   // whole wavefront idle
-    const bool have = col < count;
+    const int src_shot = col < count && !a.fresh ? a.src_shot[col] : 0;
+    const bool have = col < count && src_shot >= 0;   // -1: a hole left by the last block
     const int m = a.g.m, n = a.g.n;
     const int variant = a.vp.variant;
     const bool keep_q = variant != BP4_BP;
@@ -102,10 +107,14 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     konst<uint32_t> *vchk = as_const(a.g.vchk);
     konst<float> *prior = as_const(a.prior);
 
-    const int shot = !have ? 0 : a.fresh ? a.first_shot + col : a.src_shot[col];
+    const int shot = !have ? 0 : a.fresh ? a.first_shot + col : src_shot;
     const int t_before = have && !a.fresh ? a.src_tb[col] : 0;   // earlier AEWA attempts
     bool done = !have;
     int t_end_shot = 0;
+    // the iteration's writes: the source record, or in a launch's last iteration the
+    // shot's column of the next block's records
+    float *wmsg = msg, *wst = st, *wacc = acc;
+    int64_t moved = -1;   // column taken in the next block's records
 
     if (have && a.t0 == 0) {   // first block of an attempt: a fresh decode of the shot
         // ---- Initialisation (eq. init): syndrome bits and m_{v->c} = lambda(Pi) ----
@@ -136,6 +145,23 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     if (have) {
         for (int t = a.t0 + 1; t <= a.t_end; ++t) {
             uint32_t sw = 0;
+            if (!a.serial && t == a.t_end && t < a.max_iter) {
+                // last iteration of the block for the shots still here (t is the same
+                // for every active lane): take the new columns, one atomic per wavefront
+                const uint64_t live = __ballot(1);
+                const int leader = __ffsll((long long)live) - 1;
+                unsigned b0 = 0;
+                if (lane == leader) b0 = atomicAdd(a.dst_count, (unsigned)__popcll(live));
+                b0 = (unsigned)__shfl((int)b0, leader, 64);
+                const unsigned dcol = b0 + (unsigned)__popcll(live & ((1ull << lane) - 1ull));
+                uint32_t *drec = a.dst + (size_t)(dcol >> 6) * items * 64 + (dcol & 63u);
+                wmsg = reinterpret_cast<float *>(drec);
+                wst = reinterpret_cast<float *>(drec + (size_t)a.lay.st_off * 64);
+                wacc = reinterpret_cast<float *>(drec + (size_t)a.lay.acc_off * 64);
+                uint32_t *dsb = drec + (size_t)a.lay.sb_off * 64;
+                for (int k = 0; k < (m + 31) / 32; ++k) dsb[(size_t)k * 64] = sb[(size_t)k * 64];
+                moved = dcol;
+            }
             if (!a.serial) {
                 // ---- Horizontal update (eq. h_update) ----------------------------------
                 // kChunk checks at a time: all their message loads are issued before the
@@ -159,7 +185,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                         check_update(mv[k], sw >> ((c0 + k) & 31), C, out);
     #pragma unroll
                         for (int j = 0; j < 4; ++j)
-                            if (!edge_is_pad(cw[k][j])) msg[(size_t)edge_slot(cw[k][j]) * 64] = out[j];
+                            if (!edge_is_pad(cw[k][j])) wmsg[(size_t)edge_slot(cw[k][j]) * 64] = out[j];
                     }
                 }
                 // ---- Posterior, hard decision, vertical update --------------------------
@@ -172,7 +198,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                         info[k] = in ? vinfo[v0 + k] : 0u;   // degree 0 past the end
                         const uint32_t base = var_base(info[k]), deg = var_deg(info[k]);
     #pragma unroll
-                        for (int j = 0; j < 4; ++j) mc[k][j] = (uint32_t)j < deg ? msg[(size_t)(base + j) * 64] : 0.0f;
+                        for (int j = 0; j < 4; ++j) mc[k][j] = (uint32_t)j < deg ? wmsg[(size_t)(base + j) * 64] : 0.0f;
     #pragma unroll
                         for (int x = 0; x < 3; ++x) {
                             s3[k][x] = keep_q && in ? st[(size_t)(3 * (v0 + k) + x) * 64] : 0.0f;
@@ -190,9 +216,9 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                         float qn[3];
                         qubit_posterior(a.vp, t, p3, S, A, s3[k], a3[k], qn);
                         if (keep_q)
-                            for (int x = 0; x < 3; ++x) st[(size_t)(3 * v + x) * 64] = s3[k][x];
+                            for (int x = 0; x < 3; ++x) wst[(size_t)(3 * v + x) * 64] = s3[k][x];
                         if (keep_acc)
-                            for (int x = 0; x < 3; ++x) acc[(size_t)(3 * v + x) * 64] = a3[k][x];
+                            for (int x = 0; x < 3; ++x) wacc[(size_t)(3 * v + x) * 64] = a3[k][x];
                         ehat[(size_t)v * 64] = (uint8_t)decision_byte_of(qn);
                         float lam[4];
                         qubit_lambdas(qn, var_labels_present(info[k]), lam);
@@ -200,7 +226,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                         for (int j = 0; j < 4; ++j) {
                             if ((uint32_t)j >= deg) break;
                             const float out = clampf(lam[var_lab(info[k], j)] - mc[k][j], C);
-                            msg[(size_t)(base + j) * 64] = out;
+                            wmsg[(size_t)(base + j) * 64] = out;
                             if (a.mvc_out) {
                                 const size_t o = (size_t)shot * a.g.nnz + a.g.vcanon[base + j];
                                 a.mvc_out[o] = out;
@@ -297,6 +323,7 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
                 for (int v = 0; v < n; ++v) a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(ehat[(size_t)v * 64]);
                 a.conv[shot] = sat ? 1 : 0;
                 a.iters[shot] = t_before + t;
+                if (moved >= 0) a.dst_shot[moved] = -1;   // its new column stays a hole
                 done = true;
                 break;
             }
@@ -304,6 +331,13 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     }
 
     // ---- Survivors: append their columns to the next block's records ------------
+    if (moved >= 0) {   // already written there by the block's last iteration
+        if (!done) {
+            a.dst_shot[moved] = shot;
+            a.dst_tb[moved] = t_before;
+        }
+        return;
+    }
     const uint64_t mask = __ballot(!done);
     if (mask == 0) return;
     const unsigned cnt = (unsigned)__popcll(mask);
@@ -313,8 +347,12 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
     base = (unsigned)__shfl((int)base, leader, 64);
     if (!done) {
         const unsigned dcol = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-        uint32_t *drec = a.dst + (size_t)(dcol >> 6) * items * 64 + (dcol & 63u);
-        for (size_t i = 0; i < items; ++i) drec[i * 64] = rec[i * 64];
+        // a shot at the end of an AEWA attempt restarts from the syndrome and the
+        // priors: its record is not needed
+        if (t_end_shot < a.max_iter) {
+            uint32_t *drec = a.dst + (size_t)(dcol >> 6) * items * 64 + (dcol & 63u);
+            for (size_t i = 0; i < items; ++i) drec[i * 64] = rec[i * 64];
+        }
         a.dst_shot[dcol] = shot;
         // a shot that ran out of iterations goes on to its next AEWA attempt
         a.dst_tb[dcol] = t_end_shot >= a.max_iter ? t_before + t_end_shot : t_before;

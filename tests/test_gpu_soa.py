@@ -169,6 +169,25 @@ def test_soa_block_length_and_lanes_do_not_change_results():
             assert torch.equal(ref[k], r[k]), (block, lanes, k)
 
 
+def test_soa_moved_columns_keep_every_message():
+    """Blocks of 3 iterations without stopping: the last iteration of each block
+    writes the shots' new columns; messages and posteriors after 10 iterations
+    equal the LDS kernel's bit for bit (AdaGrad keeps a second state array)."""
+    code = qecgen.planar(7)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    p = 0.1
+    _, syn = P.sample(g, 3000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=19)
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    for variant, alpha in (("ewainit", 0.5), ("adagrad", 5.0)):
+        prm = P.Params(variant=variant, alpha=alpha, max_iter=10, stop_on_syndrome=False)
+        a = _run(g, prm, pr, syn, "lds", trace=True)
+        b = P.decode(g, prm, pr, syn, kernel="soa", trace=True, soa_iter_block=3, soa_lanes=1024)
+        torch.cuda.synchronize()
+        say("soa moved columns", variant)
+        for k in ("q", "mvc", "mcv", "est", "conv", "iters"):
+            assert torch.equal(a[k], b[k]), (variant, k)
+
+
 def test_soa_workspace_checked():
     code = qecgen.planar(5)
     g = P.Graph(code.hx, code.hz, code.lx, code.lz)
