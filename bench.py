@@ -76,7 +76,7 @@ LARGE_CODES = [("planar", 31), ("toric", 32)]
 LARGE_P = 0.10
 LARGE_SHOTS = 1 << 18
 LARGE_MAX_ITER = 200
-SOA_ITER_BLOCK = 16   # the library's default iterations per SOA launch
+SOA_ITER_BLOCK = 24   # the library's default iterations per SOA launch
 HBM_PEAK = 8.0e12   # bytes/s
 
 # HBM traffic per launch from rocprofv3 counters (2 x FETCH_SIZE + WRITE_SIZE, the
@@ -84,8 +84,8 @@ HBM_PEAK = 8.0e12   # bytes/s
 # taken on: a kernel whose sources hash differently reports traffic null.
 KERNEL_SOURCES = {"decode_lds_kernel": ("bp4_decode.hip", "bp4_math.h", "bp4_internal.h"),
                   "decode_soa_kernel": ("bp4_soa.hip", "bp4_math.h", "bp4_internal.h")}
-MEASURED_TRAFFIC = {"decode_lds_kernel": ("bd30425fd24ae530", 4.019e+09),    # mixed batch, one launch
-                    "decode_soa_kernel": ("be385c0d228a679f", 5.272e+11)}   # large codes, mean of 26 launches
+MEASURED_TRAFFIC = {"decode_lds_kernel": ("1d2ceffcc16218c3", 4.019e+09),    # mixed batch, one launch
+                    "decode_soa_kernel": ("fa2dc08f7c843211", 7.453e+11)}   # large codes, mean of 18 launches
 
 
 def measured_traffic(kernel):

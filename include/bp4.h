@@ -186,7 +186,7 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
  * soa_lanes: shots the SOA kernel keeps in flight (0: 262,144; rounded up to
  * a multiple of 256 and capped by the shot count); the SOA workspace grows
  * with it.  soa_iter_block: iterations per SOA launch, after which the shots
- * still running are packed onto fully populated wavefronts (0: 16); results
+ * still running are packed onto fully populated wavefronts (0: 24); results
  * do not depend on it.  group_lanes, block_shots and lds_bytes select the
  * LDS kernel under AUTO and are rejected with SOA; soa_lanes and
  * soa_iter_block select SOA under AUTO and are rejected with LDS.

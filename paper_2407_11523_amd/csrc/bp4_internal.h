@@ -123,7 +123,7 @@ size_t plain_workspace_bytes(int n, int nnz, int variant, int64_t shots);
 size_t soa_lanes(int64_t shots, int32_t requested);
 size_t soa_workspace_bytes(int m, int n, int nnz, int variant, int64_t shots, int32_t lanes);
 // Iterations per SOA launch between compactions of the live shots (default).
-constexpr int32_t kSoaIterBlock = 16;
+constexpr int32_t kSoaIterBlock = 24;
 hipError_t launch_decode_soa(const GraphView &g, const bp4_params &p, int32_t shots, const float *prior,
                              const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters, float *q_out,
                              float *mvc_out, float *mcv_out, void *ws, int32_t lanes, int32_t iter_block,
