@@ -168,7 +168,7 @@ def main():
         counts = torch.zeros(3, dtype=torch.int64, device=dev)
         items.append(dict(code=code, g=g, prior=pr, err=err, syn=syn, counts=counts, shots=shots,
                           slots=iteration_slots(code), seed=qecgen.config_seed(3, i, 0)))
-    # launch shape per code from the autotuner (timed on the first 2^17 syndromes of each code)
+    # launch shape per code from the autotuner (timed on up to 2^20 syndromes of each code)
     lanes = [0] * len(items)
     tuned = None
     if not args.no_tune:

@@ -175,11 +175,11 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
  * _SOA (below).  Lane mapping of the LDS kernel (0 and 0: picked by lane use
  * and occupancy): group_lanes 4, 8, 16, 32 or 64 = that many lanes of one
  * wavefront decode one shot (lane r owns checks and qubits r, r + G, ...);
- * block_shots S in [1, 256] (with group_lanes 0 or 256) = S shots share the
- * 256 lanes of a workgroup, which walk the S*m check and S*n qubit items of
- * the S shots in passes of 256 (at most 64 check items per lane);
- * group_lanes 128 and 256 alone mean block_shots 2 and 1.  Results do not
- * depend on the mapping.
+ * block_shots S in [1, 512] (with group_lanes 0 or 512) = S shots share the
+ * 512 lanes of a workgroup, which walk the S*m check and S*n qubit items of
+ * the S shots in passes of 512 (at most 64 check items per lane);
+ * group_lanes 128, 256 and 512 alone mean block_shots 4, 2 and 1.  Results do
+ * not depend on the mapping.
  * lds_bytes: if larger than the code's own layout, each workgroup of the LDS
  * kernel reserves this much LDS (so a single-code launch runs at the
  * occupancy of a mixed launch that needs it; 0: the layout's size).
@@ -204,7 +204,7 @@ typedef struct {
 /* Decode kernels.  LDS: a lane group per shot, state in LDS (small and medium
  * codes).  SOA: one lane per shot, messages and state in HBM as
  * structure-of-arrays [slot][lane] (large codes).  AUTO picks SOA when even
- * 256-lane groups would need more than 80 KB of LDS per workgroup. */
+ * one shot per workgroup would need more than 80 KB of LDS. */
 enum { BP4_KERNEL_AUTO = 0, BP4_KERNEL_LDS = 1, BP4_KERNEL_SOA = 2 };
 
 /* Device workspace bytes of the SOA kernel for `shots` shots with soa_lanes

@@ -163,7 +163,7 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
     """Decode syndromes [shots][m]; returns dict(est, conv, iters[, q, mvc, mcv]).
 
     group_lanes (4..64: lanes of one wavefront per shot) or block_shots (shots
-    sharing a 256-lane workgroup) force the LDS kernel's lane mapping (0 and 0:
+    sharing a 512-lane workgroup) force the LDS kernel's lane mapping (0 and 0:
     automatic); lds_bytes reserves at least that much LDS per workgroup; kernel picks the
     LDS ("lds") or structure-of-arrays ("soa") kernel ("auto": by code size);
     soa_lanes sets the shots the SOA kernel keeps in flight and soa_iter_block

@@ -469,13 +469,13 @@ void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, 
     a.wide = g->wide() ? 1 : 0;
 }
 
-// The automatic kernel: SOA when even one shot per 256-lane workgroup needs more
-// than kLdsAutoLimit bytes of LDS, or the code has more than 64 checks per lane.
+// The automatic kernel: SOA when even one shot per workgroup needs more than
+// kLdsAutoLimit bytes of LDS, or the code has more than 64 checks per lane.
 int auto_kernel(const bp4_graph *g, int variant)
 {
     if (g->wide()) return BP4_KERNEL_LDS;   // the only kernel for wide graphs
-    if (!decode_lds_fits(g->m, g->n, 256, 1)) return BP4_KERNEL_SOA;
-    return decode_lds_layout(g->m, g->n, g->nnz, variant, 256, 1).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA
+    if (!decode_lds_fits(g->m, g->n, kLdsBlock, 1)) return BP4_KERNEL_SOA;
+    return decode_lds_layout(g->m, g->n, g->nnz, variant, kLdsBlock, 1).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA
                                                                                       : BP4_KERNEL_LDS;
 }
 
@@ -535,20 +535,20 @@ int choose_serial_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int3
     return BP4_OK;
 }
 
-// A requested lane mapping in range: group_lanes 0 or a power of two in [4, 256];
-// block_shots >= 0, only with group_lanes 0 or 256.
+// A requested lane mapping in range: group_lanes 0 or a power of two in
+// [4, kLdsBlock]; block_shots in [0, kLdsBlock], only with group_lanes 0 or kLdsBlock.
 int check_lanes(int32_t G, int32_t S, const char *who)
 {
-    if (G != 0 && G != 4 && G != 8 && G != 16 && G != 32 && G != 64 && G != 128 && G != 256)
-        return fail(BP4_EINVAL, "%s: group_lanes %d not in {4, 8, ..., 256}", who, G);
-    if (S < 0 || S > 256) return fail(BP4_EINVAL, "%s: block_shots %d outside [0, 256]", who, S);
-    if (S > 0 && G != 0 && G != 256)
-        return fail(BP4_EINVAL, "%s: block_shots needs group_lanes 0 or 256", who);
+    if (G != 0 && (G < 4 || G > kLdsBlock || (G & (G - 1)) != 0))
+        return fail(BP4_EINVAL, "%s: group_lanes %d not in {4, 8, ..., %d}", who, G, kLdsBlock);
+    if (S < 0 || S > kLdsBlock) return fail(BP4_EINVAL, "%s: block_shots %d outside [0, %d]", who, S, kLdsBlock);
+    if (S > 0 && G != 0 && G != kLdsBlock)
+        return fail(BP4_EINVAL, "%s: block_shots needs group_lanes 0 or %d", who, kLdsBlock);
     return BP4_OK;
 }
 
 // Lane mapping for one code: the caller's choice (validated) or the default pick.
-// group_lanes 128 and 256 are block slots with 2 and 1 shots per workgroup.
+// group_lanes 128, 256 and 512 are block slots with 4, 2 and 1 shots per workgroup.
 int choose_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, size_t max_lds, LaneChoice *out)
 {
     int rc = check_lanes(G, S, "decode");
@@ -559,8 +559,8 @@ int choose_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, 
         return BP4_OK;
     }
     if (G > 64 || S > 0) {
-        if (S == 0) S = 256 / G;
-        G = 256;
+        if (S == 0) S = kLdsBlock / G;
+        G = kLdsBlock;
     }
     if (!decode_lds_fits(g->m, g->n, G, S))
         return fail(BP4_EINVAL, "decode: %d lanes x %d shots leave more than 64 checks per lane", G, S);
@@ -858,8 +858,8 @@ extern "C" int bp4_lds_layout_bytes(const bp4_graph *g, const bp4_params *p, int
     if (rc) return rc;
     if (G == 0 && S == 0) return fail(BP4_EINVAL, "lds_layout_bytes: no lane mapping given");
     if (G > 64 || S > 0) {
-        if (S == 0) S = 256 / G;
-        G = 256;
+        if (S == 0) S = kLdsBlock / G;
+        G = kLdsBlock;
     }
     if (!decode_lds_fits(g->m, g->n, G, S)) return fail(BP4_EINVAL, "lds_layout_bytes: more than 64 checks per lane");
     *bytes = decode_lds_layout(g->m, g->n, g->nnz, p->variant, G, S, g->wide()).bytes;

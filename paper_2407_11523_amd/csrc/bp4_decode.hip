@@ -1,8 +1,8 @@
 // Flooding-schedule LLR belief propagation over GF(4) for gfx950: the persistent
 // LDS-resident kernel for small and medium codes, decoding one or many codes in
 // a single launch.  A group of G lanes decodes one shot at a time (G <= 64:
-// groups inside one wavefront; G = 128 or 256: groups spanning wavefronts of a
-// 256-lane workgroup).  The shot's messages, posteriors and accumulators live in
+// groups inside one wavefront), or S shots share a 512-lane workgroup (block
+// slots).  The shot's messages, posteriors and accumulators live in
 // LDS; a code's Tanner graph and priors are staged once per workgroup in LDS and
 // shared by all of its groups.  Groups pull shots from the code's queue and
 // refill as soon as their shot stops, so the heavy tail of iteration counts
@@ -32,7 +32,11 @@ namespace bp4 {
 
 namespace {
 
-constexpr int kBlock = 256;
+// Lanes per workgroup: eight wavefronts, so the code's staged graph is shared by
+// twice the shots of a 256-lane workgroup at the same LDS per wavefront (three
+// workgroups per CU, 24 wavefronts).  Measured on the mixed batch of surface
+// codes: 512 lanes 192 ms, 256 lanes 201 ms, 768 lanes 201 ms.
+constexpr int kBlock = kLdsBlock;
 
 // ---- Per-node steps shared by the two lane mappings -------------------------------
 
@@ -511,9 +515,9 @@ __device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
     }
 }
 
-// ---- Block slots: S shots share the workgroup's 256 lanes ---------------------------
+// ---- Block slots: S shots share the workgroup's 512 lanes ---------------------------
 // The workgroup walks the S*m (slot, check) and S*n (slot, qubit) items of its S
-// shot slots in passes of 256 lanes, so a code whose m or n is not a multiple of
+// shot slots in passes of 512 lanes, so a code whose m or n is not a multiple of
 // the lanes per shot leaves few lanes idle.  Each slot's region holds its
 // messages, posteriors, decisions, syndrome bytes and a header; every slot keeps
 // its own iteration count, and a slot whose shot stops takes the next shot from
@@ -530,8 +534,9 @@ constexpr int kHdrDone = 5;     // shot whose decisions are written out this rou
 constexpr int kHdrFresh = 6;    // 1: the slot's state is (re)initialised this round
 constexpr int kHdrBad = 7;      // two "syndrome unmet" flags, alternating by iteration
 
-// Walk over the items (slot k, index x < d) of one lane: items tid, tid + 256, ...
-// of the flattened S*d list, advanced without integer multiplies: 256 = q d + rem,
+// Walk over the items (slot k, index x < d) of one lane: items tid, tid + B, ...
+// (B = kBlock) of the flattened S*d list, advanced without integer multiplies:
+// B = q d + rem,
 // so a step adds rem to x and q slots to the region offset off = k * region_words,
 // plus one carry.  The walk ends at off = S * region_words.
 struct ItemWalk {
@@ -541,7 +546,7 @@ struct ItemWalk {
 __device__ __forceinline__ ItemWalk walk_start(uint32_t tid, uint32_t d, uint32_t magic, uint32_t RW)
 {
     ItemWalk w;
-    const uint32_t k = __umulhi(tid, magic);   // tid / d: exact for tid < 256 and d < 2^14
+    const uint32_t k = __umulhi(tid, magic);   // tid / d: exact for tid < 2^9 and d < 2^14
     w.x = tid - k * d;
     w.off = k * RW;
     return w;
@@ -909,9 +914,10 @@ bool decode_lds_fits(int m, int n, int G, int S)
 }
 
 // Lane mapping for a code when no tuned choice is given.  Score = lane use times
-// an occupancy factor: the wavefronts per CU that the LDS allows (up to 16,
-// beyond which latency is hidden) over 16.  Candidates: block slots S = 1..16,
-// then wave groups of 64 down to 4 lanes; at most `max_lds` bytes per workgroup.
+// an occupancy factor: the wavefronts per CU that the LDS allows (up to 24, the
+// register limit of the single-variant builds) over 24.  Candidates: block slots
+// S = 1..64, then wave groups of 64 down to 4 lanes; at most `max_lds` bytes per
+// workgroup.
 LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, bool wide)
 {
     const double cu_lds = 160.0 * 1024.0;
@@ -923,15 +929,15 @@ LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, b
         if (L.bytes > max_lds) return;
         const double blocks = std::floor(cu_lds / (double)L.bytes);
         double waves = blocks * (L.block / 64);
-        if (waves > 16.0) waves = 16.0;
-        const double score = lane_use(m, n, G, S) * waves / 16.0;
+        if (waves > 24.0) waves = 24.0;
+        const double score = lane_use(m, n, G, S) * waves / 24.0;
         if (score > best_score * 1.02) {
             best_score = score;
             best.group_lanes = S > 0 ? kBlock : G;
             best.block_shots = S;
         }
     };
-    for (int S = 1; S <= 16; ++S) consider(kBlock, S);
+    for (int S = 1; S <= 64; ++S) consider(kBlock, S);
     for (int G = 64; G >= 4; G /= 2) consider(G, 0);
     return best;
 }

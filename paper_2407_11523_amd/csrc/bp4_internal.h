@@ -14,6 +14,9 @@ namespace bp4 {
 constexpr int kMaxCheckDeg = 4;
 constexpr int kMaxVarDeg = 4;
 constexpr int kMaxCheckDegWide = 8;
+// Lanes per workgroup of the LDS kernel (block slots share them; group_lanes 128,
+// 256 and 512 mean 4, 2 and 1 block slots).
+constexpr int kLdsBlock = 512;
 constexpr int kMaxVarDegWide = 7;
 constexpr int kMaxVars = 16383;      // 14-bit qubit index in a packed check edge
 constexpr int kMaxEdges = 65534;     // 16-bit message slot; slot nnz is the padding slot

@@ -2,7 +2,7 @@
 
 For each code it times the feasible lane mappings on a sample of the code's own
 syndromes: wave groups of G = 4 ... 64 lanes per shot, and block slots of S
-shots sharing a 256-lane workgroup (the S values of best lane use that fit).  In a mixed launch every workgroup reserves
+shots sharing a 512-lane workgroup (the S values of best lane use that fit).  In a mixed launch every workgroup reserves
 the largest LDS layout of the batch, which sets the occupancy of all codes, so
 the tuner times each code under each candidate LDS budget (the single-code
 launch reserves that budget too) and keeps the budget whose summed, shot-scaled
@@ -24,10 +24,12 @@ from .api import Graph, Params, decode
 PKG = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(PKG, "tuning_cache.json")
 GROUP_SIZES = (4, 8, 16, 32, 64)
-BLOCK = 256
+BLOCK = 512
 MAX_BLOCK_CANDS = 4
-# LDS per workgroup that leaves 7, 6, 5, 4, 3 and 2 workgroups (28 ... 8 wavefronts) per CU
-BUDGETS = (23405, 27306, 32768, 40960, 54613, 81920)
+# LDS per 512-lane workgroup that leaves 4, 3 and 2 workgroups per CU: 160 KiB / k
+# rounded down to 2 KiB, since LDS is allocated in granules (budgets of 54,613 and
+# 54,272 bytes held only two workgroups; layouts up to 51,452 bytes held three)
+BUDGETS = (40960, 53248, 81920)
 
 
 def layout_bytes(g: Graph, params: Params, lanes: int, block_shots: int = 0) -> Optional[int]:
@@ -110,7 +112,7 @@ def _save_cache(c: dict, path: str) -> None:
 
 
 def tune_mixed(entries: Sequence, digests: Sequence[str], shots_total: Sequence[int],
-               sample: int = 1 << 17, use_cache: bool = True, save: bool = True,
+               sample: int = 1 << 20, use_cache: bool = True, save: bool = True,
                cache_path: str = CACHE) -> Dict:
     """Pick the lane mapping of every code of a mixed batch.
 
@@ -120,7 +122,7 @@ def tune_mixed(entries: Sequence, digests: Sequence[str], shots_total: Sequence[
     "budget": B, "table": ...}."""
     dev = entries[0][0].dev.device
     keys = [code_key(g, p, d) for (g, p, _, _), d in zip(entries, digests)]
-    batch_key = device_key(dev) + ":slots|" + "|".join(keys)
+    batch_key = device_key(dev) + ":slots512|" + "|".join(keys)
     cache = _load_cache(cache_path) if use_cache else {}
     if batch_key in cache:
         return dict(cache[batch_key], cached=True, key=batch_key.split("|")[0])

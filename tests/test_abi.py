@@ -161,9 +161,9 @@ def test_mixed_and_plain_validation_without_gpu(lib):
     g = _graph(qecgen.toric(4))
     cp = Params(variant="momentum", alpha=0.5).c()
     arr[0] = _lib.CodeBatch(g.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
-                            fake.value, 0, 300)
+                            fake.value, 0, 600)
     arr[1] = arr[0]
-    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1          # block_shots above 256
+    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1          # block_shots above 512
     assert b"block_shots" in lib.bp4_last_error()
     arr[0].group_lanes, arr[0].block_shots = 64, 2
     arr[1] = arr[0]
@@ -266,8 +266,8 @@ def test_aewa_parameter_validation(lib):
 
 def test_lane_mapping_validation_and_layout(lib):
     """Block slots: the layout holds S regions (each with syndrome bytes and a header),
-    group_lanes 128 / 256 alone are 2 / 1 slots, and invalid mappings are rejected
-    before anything is enqueued."""
+    group_lanes 128 / 256 / 512 alone are 4 / 2 / 1 slots of a 512-lane workgroup, and
+    invalid mappings are rejected before anything is enqueued."""
     from paper_2407_11523_amd import Params, _lib
     null = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(1 << 20)
@@ -279,10 +279,11 @@ def test_lane_mapping_validation_and_layout(lib):
         rc = lib.bp4_lds_layout_bytes(g.handle, ctypes.byref(cp), G, S, ctypes.byref(b))
         return rc, b.value
 
-    rc1, b1 = layout(256, 0)
+    rc1, b1 = layout(512, 0)
     rc2, b2 = layout(0, 1)
     assert rc1 == 0 and rc2 == 0 and b1 == b2
-    assert layout(128, 0) == layout(256, 2) == layout(0, 2)
+    assert layout(256, 0) == layout(512, 2) == layout(0, 2)
+    assert layout(128, 0) == layout(0, 4)
     region = layout(0, 2)[1] - b2
     assert layout(0, 3)[1] == b2 + 2 * region and layout(0, 4)[1] == b2 + 3 * region
     # a region holds the messages (four slot-major slots per qubit and the padding
@@ -290,14 +291,15 @@ def test_lane_mapping_validation_and_layout(lib):
     assert region >= 4 * (4 * g.n + 1 + 3 * g.n) + g.n + g.m
     assert layout(0, 0)[0] == -1           # no mapping
     assert layout(64, 2)[0] == -1          # block_shots with a wave group
-    assert layout(0, 257)[0] == -1
+    assert layout(0, 513)[0] == -1
+    assert layout(1024, 0)[0] == -1
     assert layout(48, 0)[0] == -1
-    # more than 64 check items per lane
+    # more than 64 check items per lane (392 checks: 83 shots fit 64 x 512 items)
     big = _graph(qecgen.toric(14))
     b = ctypes.c_size_t()
-    assert lib.bp4_lds_layout_bytes(big.handle, ctypes.byref(cp), 0, 41, ctypes.byref(b)) == 0
-    assert lib.bp4_lds_layout_bytes(big.handle, ctypes.byref(cp), 0, 42, ctypes.byref(b)) == -1
-    for G, S in ((64, 1), (0, 300), (32, 4)):
+    assert lib.bp4_lds_layout_bytes(big.handle, ctypes.byref(cp), 0, 83, ctypes.byref(b)) == 0
+    assert lib.bp4_lds_layout_bytes(big.handle, ctypes.byref(cp), 0, 84, ctypes.byref(b)) == -1
+    for G, S in ((64, 1), (0, 600), (32, 4)):
         tune = _lib.Tuning(G, 0, 0, 0, 0, S)
         rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(cp), ctypes.byref(tune), 10, fake, fake, fake, fake,
                                fake, null, null, null, fake, 256, null)

@@ -1,4 +1,4 @@
-"""GPU: block slots of the LDS kernel (S shots sharing the 256 lanes of a workgroup,
+"""GPU: block slots of the LDS kernel (S shots sharing the 512 lanes of a workgroup,
 which walk the flattened (slot, check) and (slot, qubit) items).
 
 The per-node arithmetic is the wave groups' own, so every slot count must give
