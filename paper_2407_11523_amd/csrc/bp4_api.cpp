@@ -549,12 +549,13 @@ int check_lanes(int32_t G, int32_t S, const char *who)
 
 // Lane mapping for one code: the caller's choice (validated) or the default pick.
 // group_lanes 128, 256 and 512 are block slots with 4, 2 and 1 shots per workgroup.
-int choose_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, size_t max_lds, LaneChoice *out)
+int choose_lanes(const bp4_graph *g, const bp4_params *p, int32_t G, int32_t S, size_t max_lds, LaneChoice *out,
+                 int64_t shots = 0)
 {
     int rc = check_lanes(G, S, "decode");
     if (rc) return rc;
     if (G == 0 && S == 0) {
-        *out = decode_lds_pick(g->m, g->n, g->nnz, p->variant, max_lds, g->wide());
+        *out = decode_lds_pick(g->m, g->n, g->nnz, p->variant, max_lds, g->wide(), shots);
         if (out->group_lanes < 0) return fail(BP4_EUNSUPPORTED, "decode: code too large for the LDS kernel");
         return BP4_OK;
     }
@@ -637,7 +638,7 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         L = serial_layout(g, p->variant, G);
     } else {
         LaneChoice lc;
-        rc = choose_lanes(g, p, requested, requested_S, max_lds, &lc);
+        rc = choose_lanes(g, p, requested, requested_S, max_lds, &lc, shots);
         if (rc) return rc;
         L = decode_lds_layout(g->m, g->n, g->nnz, p->variant, lc.group_lanes, lc.block_shots, g->wide());
     }
@@ -788,7 +789,7 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
     for (size_t k = 0; k < order.size(); ++k) {
         const bp4_code_batch &c = codes[order[k]];
         LaneChoice lc;
-        rc = choose_lanes(c.graph, &c.params, c.group_lanes, c.block_shots, max_lds, &lc);
+        rc = choose_lanes(c.graph, &c.params, c.group_lanes, c.block_shots, max_lds, &lc, c.shots);
         if (rc) return rc;
         const LdsLayout L = decode_lds_layout(c.graph->m, c.graph->n, c.graph->nnz, c.params.variant, lc.group_lanes,
                                               lc.block_shots, c.graph->wide());

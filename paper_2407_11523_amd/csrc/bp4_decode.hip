@@ -580,13 +580,17 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
     VariantParams vp = variant_params<VAR>(a);
     // item walks over checks (d = m) and qubits (d = n)
     const uint32_t rm = kBlock % m, rn = kBlock % n;
-    const uint32_t qoffm = (kBlock / m) * RW, qoffn = (kBlock / n) * RW, end = S * RW;
+    const uint32_t qoffm = (kBlock / m) * RW, qoffn = (kBlock / n) * RW;
+    uint32_t end = S * RW;   // the walks cover the active slots 0 .. events[1] - 1
     const ItemWalk wm0 = walk_start(tid, m, a.magic_m, RW), wn0 = walk_start(tid, n, a.magic_n, RW);
 #define BP4_FOR_CHECKS(w) for (ItemWalk w = wm0; w.off < end; walk_next(w, m, rm, qoffm, RW))
 #define BP4_FOR_QUBITS(w) for (ItemWalk w = wn0; w.off < end; walk_next(w, n, rn, qoffn, RW))
 
     bool more = false;
-    if (tid == 0) *events = 1;
+    if (tid == 0) {
+        events[0] = 1;
+        events[1] = (int)S;
+    }
     if (tid < (int)S) {
         int *h = hdr(tid);
         const int s = take_shot(a.counter, a.shots);
@@ -600,6 +604,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
         h[kHdrBad] = 0;
         h[kHdrBad + 1] = 0;
         more = s < a.shots;
+        if (!more) events[3] = 1;
     }
     bool any_more = __syncthreads_or(more);
     int par = 0;
@@ -627,9 +632,48 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
             }
             if (tid < (int)S && hdr(tid)[kHdrFresh]) reg0[tid * RW + lds_pad_slot<W>(n)] = INFINITY;
         }
+        if (events[3]) {   // some slot was left without a shot (the queue is empty)
+            // Compaction: once the queue is empty, a slot left without a shot takes
+            // the region of the last active slot, so the phases walk only the active
+            // slots and the tail of a workgroup (its last long-running shots) costs
+            // their items, not S slots' worth
+            __syncthreads();
+            for (;;) {
+                if (tid == 0) {
+                    int na = events[1], hole = -1;
+                    while (na > 0 && hdr((uint32_t)(na - 1))[kHdrShot] >= a.shots) --na;
+                    for (int k = 0; k + 1 < na; ++k)
+                        if (hdr((uint32_t)k)[kHdrShot] >= a.shots) {
+                            hole = k;
+                            break;
+                        }
+                    events[1] = na;
+                    events[2] = hole;
+                }
+                __syncthreads();
+                const int hole = events[2], na = events[1];
+                if (hole < 0) break;
+                const float *src = reg0 + (uint32_t)(na - 1) * RW;
+                float *dst = reg0 + (uint32_t)hole * RW;
+                for (uint32_t i = (uint32_t)tid; i < RW; i += kBlock) dst[i] = src[i];
+                __syncthreads();
+                if (tid == 0) {   // the vacated slot is empty
+                    int *h = hdr((uint32_t)(na - 1));
+                    h[kHdrShot] = a.shots;
+                    h[kHdrDone] = -1;
+                    h[kHdrFresh] = 0;
+                    events[1] = na - 1;
+                }
+                __syncthreads();
+            }
+            end = (uint32_t)events[1] * RW;
+        }
         if (!any_more) break;
         __syncthreads();
-        if (tid == 0) *events = 0;   // every lane has read it before the barrier above
+        if (tid == 0) {   // every lane has read them before the barrier above
+            events[0] = 0;
+            events[3] = 0;
+        }
         // ---- Horizontal update (eq. h_update) ----------------------------------------
         BP4_FOR_CHECKS(w) {
             float *msg = reg0 + w.off;
@@ -701,6 +745,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     h[kHdrTBefore] = 0;
                     h[kHdrAlpha] = __float_as_int(a.alpha);
                     h[kHdrFresh] = s < a.shots ? 1 : 0;
+                    if (s >= a.shots) events[3] = 1;
                 } else if (restart) {
                     h[kHdrTBefore] += t;
                     h[kHdrAtt] += 1;
@@ -749,11 +794,16 @@ decode_lds_kernel(MixedArgs args)
     // 16-byte aligned: the packed check edges are read as 16-byte vectors
     extern __shared__ __attribute__((aligned(16))) float lds[];
     __shared__ int pending;
-    __shared__ int events;   // block slots: some slot stopped or restarted this round
+    // block slots: [0] some slot stopped or restarted this round, [1] active slots,
+    // [2] a slot to refill by compaction, [3] some slot was left without a shot
+    __shared__ int events[4];
     for (int ci = 0; ci < args.ncodes; ++ci) {
         const DecodeArgs &a = args.codes[ci];
         // skip a code whose queue is already empty (a stale read only costs a visit)
-        if (threadIdx.x == 0) pending = __hip_atomic_load(a.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)a.shots;
+        if (threadIdx.x == 0) {
+            pending = __hip_atomic_load(a.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)a.shots;
+            events[3] = 0;
+        }
         __syncthreads();
         if (!pending) continue;
         // stage the code's packed check edges, qubit words and priors
@@ -815,24 +865,24 @@ decode_lds_kernel(MixedArgs args)
         } else if (VSET == kWide) {   // the host launches only wide codes here
             if (a.wide) {
                 switch (a.variant) {
-                case BP4_BP: run_code<BP4_BP, true>(a, lds, &events); break;
-                case BP4_MOMENTUM: run_code<BP4_MOMENTUM, true>(a, lds, &events); break;
-                case BP4_ADAGRAD: run_code<BP4_ADAGRAD, true>(a, lds, &events); break;
-                case BP4_AEWA: run_code<BP4_AEWA, true>(a, lds, &events); break;
-                default: run_code<BP4_EWAINIT, true>(a, lds, &events); break;
+                case BP4_BP: run_code<BP4_BP, true>(a, lds, events); break;
+                case BP4_MOMENTUM: run_code<BP4_MOMENTUM, true>(a, lds, events); break;
+                case BP4_ADAGRAD: run_code<BP4_ADAGRAD, true>(a, lds, events); break;
+                case BP4_AEWA: run_code<BP4_AEWA, true>(a, lds, events); break;
+                default: run_code<BP4_EWAINIT, true>(a, lds, events); break;
                 }
             }
         } else if (VSET == kMixedVariants) {
             switch (a.variant) {
-            case BP4_BP: run_code<BP4_BP>(a, lds, &events); break;
-            case BP4_MOMENTUM: run_code<BP4_MOMENTUM>(a, lds, &events); break;
-            case BP4_ADAGRAD: run_code<BP4_ADAGRAD>(a, lds, &events); break;
-            case BP4_AEWA: run_code<BP4_AEWA>(a, lds, &events); break;
-            default: run_code<BP4_EWAINIT>(a, lds, &events); break;
+            case BP4_BP: run_code<BP4_BP>(a, lds, events); break;
+            case BP4_MOMENTUM: run_code<BP4_MOMENTUM>(a, lds, events); break;
+            case BP4_ADAGRAD: run_code<BP4_ADAGRAD>(a, lds, events); break;
+            case BP4_AEWA: run_code<BP4_AEWA>(a, lds, events); break;
+            default: run_code<BP4_EWAINIT>(a, lds, events); break;
             }
         } else {
             constexpr int V = VSET < 0 ? BP4_EWAINIT : VSET;
-            run_code<V>(a, lds, &events);
+            run_code<V>(a, lds, events);
         }
         __syncthreads();
     }
@@ -917,28 +967,46 @@ bool decode_lds_fits(int m, int n, int G, int S)
 // an occupancy factor: the wavefronts per CU that the LDS allows (up to 24, the
 // register limit of the single-variant builds) over 24.  Candidates: block slots
 // S = 1..64, then wave groups of 64 down to 4 lanes; at most `max_lds` bytes per
-// workgroup.
-LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, bool wide)
+// workgroup.  Among block-slot mappings within 2 % of the best score the most
+// slots win (each barrier of an iteration then covers more passes of items), up
+// to the count that still lets the resident workgroups (three per CU on 256 CUs)
+// cycle through `shots` at least 12 times, since a batch of few rounds waits on
+// the tail of its last round.
+LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, bool wide, int64_t shots)
 {
     const double cu_lds = 160.0 * 1024.0;
-    LaneChoice best;
-    double best_score = -1.0;
-    auto consider = [&](int G, int S) {
-        if (!decode_lds_fits(m, n, G, S)) return;
+    auto score_of = [&](int G, int S) {
+        if (!decode_lds_fits(m, n, G, S)) return -1.0;
         const LdsLayout L = decode_lds_layout(m, n, nnz, variant, G, S, wide);
-        if (L.bytes > max_lds) return;
-        const double blocks = std::floor(cu_lds / (double)L.bytes);
+        if (L.bytes > max_lds) return -1.0;
+        // LDS is allocated in granules: a layout occupies its size rounded up to 2 KB
+        const double blocks = std::floor(cu_lds / (double)((L.bytes + 2047) / 2048 * 2048));
         double waves = blocks * (L.block / 64);
         if (waves > 24.0) waves = 24.0;
-        const double score = lane_use(m, n, G, S) * waves / 24.0;
-        if (score > best_score * 1.02) {
-            best_score = score;
-            best.group_lanes = S > 0 ? kBlock : G;
-            best.block_shots = S;
-        }
+        return lane_use(m, n, G, S) * waves / 24.0;
     };
-    for (int S = 1; S <= 64; ++S) consider(kBlock, S);
-    for (int G = 64; G >= 4; G /= 2) consider(G, 0);
+    int64_t cap = shots > 0 ? shots / (2 * 3 * 256) : 64;
+    if (cap < 1) cap = 1;
+    if (cap > 64) cap = 64;
+    LaneChoice best;
+    double best_score = -1.0;
+    for (int S = 1; S <= cap; ++S) best_score = std::max(best_score, score_of(kBlock, S));
+    for (int G = 64; G >= 4; G /= 2) {
+        const double sc = score_of(G, 0);
+        if (sc > best_score * 1.02) {
+            best_score = sc;
+            best.group_lanes = G;
+            best.block_shots = 0;
+        }
+    }
+    if (best.group_lanes > 0 && best.block_shots == 0 && best_score > 0.0) return best;   // a wave group won
+    for (int S = (int)cap; S >= 1; --S) {
+        if (best_score > 0.0 && score_of(kBlock, S) >= best_score * 0.98) {
+            best.group_lanes = kBlock;
+            best.block_shots = S;
+            return best;
+        }
+    }
     return best;
 }
 

@@ -109,7 +109,7 @@ LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant,
 // The mapping is valid for the code: G a power of two in [4, 64] with at most 64
 // checks per lane, or 1 <= S <= 256 with at most 64 check items per lane.
 bool decode_lds_fits(int m, int n, int group_lanes, int block_shots);
-LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, bool wide = false);
+LaneChoice decode_lds_pick(int m, int n, int nnz, int variant, size_t max_lds, bool wide = false, int64_t shots = 0);
 hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_t s, int *grid_out);
 
 hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const uint32_t thr[3],
