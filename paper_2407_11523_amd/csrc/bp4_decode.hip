@@ -777,14 +777,15 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *e
 // VSET: the variant every code of the launch uses, kMixedVariants for a flooding
 // launch that mixes variants (a switch per code), kSerial for the serial schedule
 // (one code, a switch on its variant), kWide for a flooding launch of wide graphs
-// (a switch on the variant).  Register budget: 80 VGPRs
-// (six wavefronts per SIMD) for the single-variant builds, which fit it without
-// spilling, 96 (five) for AdaGrad and the switching builds, 128 (four) for kWide,
-// whose 8-edge checks hold twice the messages in registers.
+// (a switch on the variant).  Register budget: 80 VGPRs (six wavefronts per
+// SIMD: three 512-lane workgroups per CU) for every build but kWide, 128 (four)
+// for kWide, whose 8-edge checks hold twice the messages in registers.  The
+// AdaGrad and switching builds spill 12-13 registers at 80 and still ran an
+// AdaGrad batch 19 % faster than at 96 VGPRs, where only two workgroups fit.
 constexpr int kMixedVariants = -1, kSerial = -2, kWide = -3;
 constexpr int lds_kernel_waves(int vset)
 {
-    return vset == kWide ? 4 : (vset < 0 || vset == BP4_ADAGRAD) ? 5 : 6;
+    return vset == kWide ? 4 : 6;
 }
 
 template <int VSET>
