@@ -118,14 +118,31 @@ __global__ void __launch_bounds__(kSoaBlock) decode_soa_kernel(SoaArgs a)
 
     if (have && a.t0 == 0) {   // first block of an attempt: a fresh decode of the shot
         // ---- Initialisation (eq. init): syndrome bits and m_{v->c} = lambda(Pi) ----
+        const uint8_t *srow = a.synd + (size_t)shot * m;
         uint32_t word = 0;
-        for (int c = 0; c < m; ++c) {
-            word |= (uint32_t)(a.synd[(size_t)shot * m + c] & 1u) << (c & 31);
-            if ((c & 31) == 31 || c == m - 1) {
-                sb[(size_t)(c >> 5) * 64] = word;
-                word = 0;
+        int c = 0;
+        if ((m & 3) == 0 && ((uintptr_t)a.synd & 3u) == 0) {
+            // rows start on 4-byte boundaries: four syndrome bytes per load (bit 0 of
+            // each byte, at bits 0, 8, 16, 24 of the word)
+            for (; c < m; c += 4) {
+                const uint32_t x = *reinterpret_cast<const uint32_t *>(srow + c);
+                const uint32_t nib = (x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u);
+                word |= nib << (c & 31);
+                if (((c + 4) & 31) == 0) {
+                    sb[(size_t)(c >> 5) * 64] = word;
+                    word = 0;
+                }
+            }
+        } else {
+            for (; c < m; ++c) {
+                word |= (uint32_t)(srow[c] & 1u) << (c & 31);
+                if ((c & 31) == 31) {
+                    sb[(size_t)(c >> 5) * 64] = word;
+                    word = 0;
+                }
             }
         }
+        if (m & 31) sb[(size_t)((m - 1) >> 5) * 64] = word;   // the last, partial word
         for (int v = 0; v < n; ++v) {
             const uint32_t info = vinfo[v];
             const uint32_t base = var_base(info), deg = var_deg(info);
