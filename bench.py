@@ -84,8 +84,8 @@ HBM_PEAK = 8.0e12   # bytes/s
 # taken on: a kernel whose sources hash differently reports traffic null.
 KERNEL_SOURCES = {"decode_lds_kernel": ("bp4_decode.hip", "bp4_math.h", "bp4_internal.h"),
                   "decode_soa_kernel": ("bp4_soa.hip", "bp4_math.h", "bp4_internal.h")}
-MEASURED_TRAFFIC = {"decode_lds_kernel": ("3f7a20e8b3954723", 3.917e+09),    # mixed batch, one launch
-                    "decode_soa_kernel": ("38700eee5ae9f043", 7.454e+11)}   # large codes, mean of 18 launches
+MEASURED_TRAFFIC = {"decode_lds_kernel": ("954398d2577431de", 3.917e+09),    # mixed batch, one launch
+                    "decode_soa_kernel": ("463af61095e7f716", 7.433e+11)}   # large codes, mean of 18 launches
 
 
 def measured_traffic(kernel):
