@@ -114,3 +114,23 @@ def test_mixed_launch_with_block_slots():
     for i, (o, r) in enumerate(zip(outs, ref)):
         for k in ("est", "conv", "iters"):
             assert torch.equal(o[k], r[k]), (i, k)
+
+
+@pytest.mark.parametrize("variant,kw", [("ewainit", dict(alpha=0.5)),
+                                        ("aewa", dict(alpha=1.0, alpha_last=0.0, alpha_steps=4, max_iter=30))])
+def test_compacted_slots_keep_their_state(variant, kw):
+    """Once the queue is empty, a slot left without a shot takes the region of the
+    last active slot.  With early stopping the shots end at different iterations,
+    so shots still running are moved mid-decode; their final messages and
+    posteriors (traced after their last iteration) equal a wave-group decode bit for
+    bit.  24 slots per workgroup and 1,500 shots: most of the decode is tail."""
+    c = qecgen.planar(7)
+    g, syn, pr = setup(c.hx, c.hz, c.lx, c.lz, 0.12, 1500, 29)
+    prm = P.Params(variant=variant, **dict(dict(max_iter=60), **kw))
+    ref = P.decode(g, prm, pr, syn, group_lanes=16, trace=True)
+    r = P.decode(g, prm, pr, syn, block_shots=24, trace=True)
+    torch.cuda.synchronize()
+    say("compacted slots", variant, float(r["iters"].float().mean()), int(r["iters"].max()))
+    assert int(r["iters"].max()) > 2 * int(r["iters"].min())   # shots end at different iterations
+    for k in ("est", "conv", "iters", "q", "mvc", "mcv"):
+        assert torch.equal(r[k], ref[k]), (variant, k)
