@@ -294,6 +294,32 @@ def main():
                                  "bit_identical": bool(same)}
         log(f"plain per-code decode {plain_ms:.1f} ms -> mixed is {plain_ms / dec_ms:.1f}x")
 
+        # the mixed launch's own kernel run one code at a time (same lane mappings and
+        # LDS budget): separates the batching gain from the kernel gain
+        lds_ms = 0.0
+        same = True
+        for it, o, lane in zip(items, batch.outs, lanes):
+            G, S = (lane if isinstance(lane, (list, tuple)) else (lane, 0))
+            kw = dict(group_lanes=G, block_shots=S)
+            if tuned is not None:
+                kw["lds_bytes"] = tuned["budget"]
+            P.decode(it["g"], prm, it["prior"], it["syn"][:4096], **kw)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            r = P.decode(it["g"], prm, it["prior"], it["syn"], **kw)
+            b.record()
+            torch.cuda.synchronize()
+            lds_ms += a.elapsed_time(b)
+            same = same and torch.equal(r["est"], o["est"]) and torch.equal(r["iters"], o["iters"])
+            del r
+        out["lds_per_code"] = {"decode_ms": lds_ms, "value": total_shots / (lds_ms / 1e3), "unit": "syndromes/s",
+                               "batching_gain": lds_ms / dec_ms, "kernel_gain": plain_ms / lds_ms,
+                               "bit_identical": bool(same)}
+        log(f"LDS kernel per code {lds_ms:.1f} ms: batching gain {lds_ms / dec_ms:.2f}x, "
+            f"kernel gain over plain {plain_ms / lds_ms:.1f}x")
+
     if not args.no_cpu:
         from oracle import oracle as O
         O.build()
