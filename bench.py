@@ -326,6 +326,7 @@ def main():
         threads = min(16, os.cpu_count() or 1)
         tot_shots = 0
         tot_t = 0.0
+        tot_eu = 0
         in_ci = True
         ci = {}
         for it in items:
@@ -338,6 +339,7 @@ def main():
                           nthreads=threads)
             tot_t += time.perf_counter() - t
             tot_shots += k
+            tot_eu += int(ro["iters"].astype(np.int64).sum()) * int((code.labels() != 0).sum())
             _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
             # Wilson interval at family-wise 95% over the codes (Bonferroni: z for 0.05 / ncodes)
             lo, hi = O.wilson_ci(int(co[1] + co[2]), k, z=Z_FAMILY)
@@ -348,6 +350,14 @@ def main():
         out["cpu_baseline"] = {"value": tot_shots / tot_t, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
                                "sample": f"first 512 x (1|2|4) shots of each code ({tot_shots} shots), FP64 oracle, "
                                          f"OpenMP over shots"}
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        out["oracle_host"] = {"cpu_model": model, "logical_cpus": os.cpu_count(), "threads": threads,
+                              "us_per_shot": tot_t / tot_shots * 1e6, "edge_updates_per_s": tot_eu / tot_t}
         out["ler_in_oracle_ci"] = bool(in_ci)
         out["oracle_ci"] = ci
         log(f"oracle {tot_shots / tot_t:.0f} shots/s on {threads} threads")
