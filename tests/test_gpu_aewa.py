@@ -12,6 +12,7 @@ import pytest
 
 import qecgen
 from oracle import oracle as O
+from tests.oracle_inputs import matched
 
 pytestmark = pytest.mark.gpu
 
@@ -43,10 +44,11 @@ def test_aewa_vs_oracle(make, p, shots):
     r = P.decode(g, prm, P.prior_llr(qecgen.depolarizing_probs(code.n, p)), syn)
     _, cnt = P.bookkeep(g, err, r["est"])
     torch.cuda.synchronize()
+    e_o, s_o = matched(code, thr, 17, err, syn)
     ro = O.decode(code.hx, code.hz, O.Params(variant="aewa", alpha=1.0, alpha_last=0.0, alpha_steps=11,
                                              max_iter=100),
-                  O.prior_llr(qecgen.depolarizing_probs(code.n, p)), np_(syn))
-    _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, np_(err), ro["est"])
+                  O.prior_llr(qecgen.depolarizing_probs(code.n, p)), s_o)
+    _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
     both = np_(r["conv"]).astype(bool) & ro["conv"].astype(bool)
     agree = float((np_(r["est"]) == ro["est"])[both].mean())
     it_agree = float((np_(r["iters"]) == ro["iters"])[both].mean())

@@ -118,6 +118,78 @@ def test_mixed_matches_oracle_sample():
         assert lo <= ler_g <= hi
 
 
+
+def test_mixed_full_batch_in_bench_launch():
+    """The full mixed batch (26 x 2^18 = 6,815,744 shots over the 11 codes, p = 0.08,
+    EWAInit alpha 0.5, iter_max 100) in the launch the benchmark times: the lane
+    mappings from the committed autotuner cache, one persistent launch over every
+    code.  128 shots per code (the first two, the last, 125 drawn at random) are
+    decoded by the oracle from its own sampler's rows.
+
+    Bar, over the 1,408 sampled shots: the decisions of shots that converged on both
+    sides agree on >= 99.9% of the qubits and everything agrees on >= 99%; shots
+    the oracle stops within 20 iterations agree exactly, and so do their stopping
+    iterations except where the FP64 hard decision at the earlier one was within
+    1e-3 (relative) of a tie, on at most 1% of them; each code's logical error
+    rate over its whole batch lies in the oracle's 99.9% interval on its sample."""
+    from paper_2407_11523_amd import tune
+    from tests.oracle_inputs import matched, same_stops
+    p = 0.08
+    thr = qecgen.thresholds(p / 3, p / 3, p / 3)
+    prm = P.Params(variant="ewainit", alpha=0.5, max_iter=100)
+    items = []
+    for i, (fam, L, mult) in enumerate(CONFIG3):
+        code = qecgen.make(fam, L)
+        shots = (1 << 18) * mult
+        g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+        err, syn = P.sample(g, shots, thr, seed=qecgen.config_seed(3, i, 0))
+        items.append(dict(code=code, g=g, err=err, syn=syn, shots=shots, seed=qecgen.config_seed(3, i, 0),
+                          prior=P.prior_llr(qecgen.depolarizing_probs(code.n, p))))
+    tuned = tune.tune_mixed([(it["g"], prm, it["prior"], it["syn"]) for it in items],
+                            [tune.digest(it["code"].hx, it["code"].hz) for it in items],
+                            [it["shots"] for it in items], save=False)
+    say("full mixed batch lanes", tuned["lanes"], "cached" if tuned.get("cached") else "measured")
+    batch = P.MixedBatch([(it["g"], prm, it["prior"], it["syn"], G) for it, G in zip(items, tuned["lanes"])])
+    batch.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    same_both, same_all, n_both, n_all, n_off, n_early = 0, 0, 0, 0, 0, 0
+    for it, o in zip(items, batch.outs):
+        code, shots = it["code"], it["shots"]
+        idx = np.unique(np.concatenate([[0, 1, shots - 1], rng.choice(shots, 125, replace=False)]))
+        e_o, s_o = matched(code, thr, it["seed"], it["err"], it["syn"], idx=idx)
+        ro = O.decode(code.hx, code.hz, O.Params(variant="ewainit", alpha=0.5, max_iter=100),
+                      O.prior_llr(qecgen.depolarizing_probs(code.n, p)), s_o)
+        sel = torch.as_tensor(idx, device=it["syn"].device)
+        est_g, conv_g, it_g = np_(o["est"][sel]), np_(o["conv"][sel]), np_(o["iters"][sel])
+        same = est_g == ro["est"]
+        both = conv_g.astype(bool) & ro["conv"].astype(bool)
+        early = both & (ro["iters"] <= 20)
+        assert np.array_equal(est_g[early], ro["est"][early]), code.name
+        # a stopping iteration may differ only where the FP64 decision was a near-tie
+        op = O.Params(variant="ewainit", alpha=0.5, max_iter=100)
+        off, margins = same_stops(code, op, O.prior_llr(qecgen.depolarizing_probs(code.n, p)), s_o[early],
+                                  it_g[early], ro["iters"][early])
+        n_off += len(off)
+        n_early += int(early.sum())
+        same_both += int(same[both].sum())
+        n_both += int(same[both].size)
+        same_all += int(same.sum())
+        n_all += same.size
+        _, cg = P.bookkeep(it["g"], it["err"], o["est"])
+        _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
+        torch.cuda.synchronize()
+        ler_g = int(cg[1] + cg[2]) / shots
+        lo, hi = O.wilson_ci(int(co[1] + co[2]), len(idx), z=3.29)
+        say("full mixed batch", code.name, shots, dict(early=int(early.sum()), both=int(both.sum()),
+                                                       stop_diff=len(off), margins=margins, ler_g=ler_g, ci=(lo, hi)))
+        assert lo <= ler_g <= hi, code.name
+    say("full mixed batch agreement", same_both / n_both, same_all / n_all, "stops differing", n_off, n_early)
+    assert same_both / n_both >= 0.999
+    assert n_off <= max(2, 0.01 * n_early)
+    assert same_all / n_all >= 0.99
+
+
 def test_mixed_edge_cases():
     c1, c2 = qecgen.toric(4), qecgen.planar(3)
     g1, _, s1, p1 = setup(c1, 0.05, 100, 1)

@@ -17,6 +17,7 @@ import pytest
 
 import qecgen
 from oracle import oracle as O
+from tests.oracle_inputs import matched
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +86,8 @@ def test_serial_decisions_and_ler(make, p, variant, alpha):
     code = make()
     g = P.Graph(code.hx, code.hz, code.lx, code.lz)
     shots = 3000
-    err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=41)
+    thr = qecgen.thresholds(p / 3, p / 3, p / 3)
+    err, syn = P.sample(g, shots, thr, seed=41)
     kw = dict(variant=variant, alpha=alpha, max_iter=100, serial=True)
     if variant == "aewa":
         kw.update(alpha_last=0.0, alpha_steps=6)
@@ -95,9 +97,10 @@ def test_serial_decisions_and_ler(make, p, variant, alpha):
     torch.cuda.synchronize()
     for k in ("est", "conv", "iters"):
         assert torch.equal(r[k], rs[k]), k
+    e_o, s_o = matched(code, thr, 41, err, syn)
     ro = O.decode(code.hx, code.hz, O.Params(**{k: v for k, v in kw.items()}),
-                  O.prior_llr(qecgen.depolarizing_probs(code.n, p)), np_(syn))
-    _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, np_(err), ro["est"])
+                  O.prior_llr(qecgen.depolarizing_probs(code.n, p)), s_o)
+    _, co = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e_o, ro["est"])
     both = np_(r["conv"]).astype(bool) & ro["conv"].astype(bool)
     agree = float((np_(r["est"]) == ro["est"])[both].mean())
     ler_g = int(cnt[1] + cnt[2]) / shots

@@ -13,6 +13,7 @@ import pytest
 
 import qecgen
 from oracle import oracle as O
+from tests.oracle_inputs import matched
 
 pytestmark = pytest.mark.gpu
 
@@ -243,7 +244,7 @@ def test_large_codes_full_batch_sampled(make):
     fail_g, cnt_g = P.bookkeep(g, err, rg["est"])
     torch.cuda.synchronize()
     sel = torch.as_tensor(idx, device=syn.device)
-    s, e = np_(syn[sel]), np_(err[sel])
+    e, s = matched(code, thr, seed, err, syn, idx=idx)
     est_g, conv_g, it_g = np_(rg["est"][sel]), np_(rg["conv"][sel]), np_(rg["iters"][sel])
     pi = O.prior_llr(qecgen.depolarizing_probs(code.n, p))
     op = O.Params(variant="ewainit", alpha=0.5, max_iter=max_iter)

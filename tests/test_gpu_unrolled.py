@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import qecgen
+from oracle import oracle as O
 from oracle import unrolled_ref as U
 
 pytestmark = pytest.mark.gpu
@@ -48,7 +49,9 @@ def clifford_relabel(code, seed):
 def setup(hx, hz, lx, lz, p, shots, seed, T, jitter=0.3):
     g = P.Graph(hx, hz, lx, lz)
     n = g.n
-    err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=seed)
+    # the oracle's sampler draws the shots; the GPU and the FP64 reference read the same rows
+    e, s = O.sample(hx, hz, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=seed)
+    err, syn = torch.as_tensor(e, device="cuda"), torch.as_tensor(s, device="cuda")
     rng = np.random.default_rng(seed)
     prior = np.log((1 - p) / (p / 3)) + rng.uniform(-jitter, jitter, (n, 3))
     alpha = rng.uniform(0.3, 0.9, T)

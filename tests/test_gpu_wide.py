@@ -15,6 +15,7 @@ import pytest
 
 import qecgen
 from oracle import oracle as O
+from tests.oracle_inputs import matched
 
 pytestmark = pytest.mark.gpu
 
@@ -101,13 +102,15 @@ def test_wide_decisions_and_ler(name, p, variant, alpha):
     c = CODES[name]()
     g = P.Graph(c.hx, c.hz, c.lx, c.lz)
     shots = 3000
-    err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=31)
+    thr = qecgen.thresholds(p / 3, p / 3, p / 3)
+    err, syn = P.sample(g, shots, thr, seed=31)
     prm = dict(variant=variant, alpha=alpha, max_iter=100)
     r = P.decode(g, P.Params(**prm), P.prior_llr(qecgen.depolarizing_probs(c.n, p)), syn)
     _, cnt = P.bookkeep(g, err, r["est"])
     torch.cuda.synchronize()
-    ro = O.decode(c.hx, c.hz, O.Params(**prm), O.prior_llr(qecgen.depolarizing_probs(c.n, p)), np_(syn))
-    _, co = O.bookkeep(c.hx, c.hz, c.lx, c.lz, np_(err), ro["est"])
+    e_o, s_o = matched(c, thr, 31, err, syn)
+    ro = O.decode(c.hx, c.hz, O.Params(**prm), O.prior_llr(qecgen.depolarizing_probs(c.n, p)), s_o)
+    _, co = O.bookkeep(c.hx, c.hz, c.lx, c.lz, e_o, ro["est"])
     both = np_(r["conv"]).astype(bool) & ro["conv"].astype(bool)
     agree = float((np_(r["est"]) == ro["est"])[both].mean())
     ler_g = int(cnt[1] + cnt[2]) / shots
