@@ -9,9 +9,12 @@
 // mean over shots and qubits of ln(1 + sum_W e^{-Q_W}) + Q_{e_v} at t = T
 // (Q_I = 0), the negative log GF(4) marginal of the sampled error.
 //
-// One lane runs one shot.  The state of a shot after iteration t is its
-// messages m_{v->c}^{(t)} (E words) and its posterior Q^{(t)} (3N words), kept
-// as a column of a per-wavefront record [wavefront][item][64 lanes] in HBM.
+// A workgroup of kUnrWaves wavefronts runs a chunk of 64 shots, one shot per
+// lane column: wavefront g takes the checks and the qubits whose index is g
+// modulo kUnrWaves, with a workgroup barrier between the check and the qubit
+// pass.  The state of a shot after iteration t is its messages m_{v->c}^{(t)}
+// (E words) and its posterior Q^{(t)} (3N words), kept as a column of a
+// per-chunk record [chunk][item][64 columns] in HBM.
 // The forward keeps the state every `ckpt` iterations; the adjoint walks the
 // segments from last to first, recomputes a segment's states from its
 // checkpoint, then runs the reverse sweep through it.  Gradient sums over
@@ -21,7 +24,9 @@
 namespace bp4 {
 namespace {
 
-constexpr int kUnrBlock = 256;
+constexpr int kUnrWaves = 8;                // wavefronts sharing one chunk of 64 shots
+constexpr int kUnrBlock = 64 * kUnrWaves;
+constexpr int kUnrRound = 256;               // records are allocated for shots rounded up to this
 
 template <typename T> using konst = const __attribute__((address_space(4))) T;
 template <typename T> __device__ __forceinline__ konst<T> *as_const(const T *p) { return (konst<T> *)p; }
@@ -35,7 +40,7 @@ struct UnrArgs {
     float *ckpt;              // [nseg][waves][E + 3N][64] states at t = 0, K, 2K, ...
     float *seg;               // [K + 1][waves][E + 3N][64] states of one segment
     float *adj;               // [waves][E + 6N][64] adjoints: m (E), Q (3N), Pi^{(0)} (3N)
-    double *partial;          // [waves][nout] per-wavefront sums
+    double *partial;          // [waves][nout] per-chunk sums
     float *q_out;             // optional [shots][n][3] Q^{(T)}
     int32_t shots, T, K, nseg, waves, nout;
     float clamp;
@@ -89,36 +94,82 @@ __device__ __forceinline__ float qubit_loss(const float q[3], uint32_t e, float 
 }
 
 struct Lane {
-    size_t wave;
-    int lane;
-    size_t SI;   // items of one state
+    size_t wave;  // chunk of 64 shots (the workgroup)
+    int lane;     // column of the shot in the chunk
+    int part;     // wavefront of the workgroup: nodes part, part + kUnrWaves, ...
+    bool have;    // the column holds a shot
+    size_t SI;    // items of one state
     __device__ float *state(float *base, int slot, int waves) const
     {
         return base + ((size_t)slot * waves + wave) * SI * 64 + lane;
     }
 };
 
-// m^{(0)}_{v->c} = lambda(Pi^{(0)}) clamped, Q^{(0)} = Pi^{(0)}  (eq. init).
-__device__ void init_state(const UnrArgs &a, float *st)
+__device__ __forceinline__ Lane lane_of(const UnrArgs &a)
 {
+    Lane L;
+    L.wave = blockIdx.x;
+    L.lane = threadIdx.x & 63;
+    L.part = threadIdx.x >> 6;
+    L.have = (int64_t)L.wave * 64 + L.lane < a.shots;
+    L.SI = (size_t)a.g.nnz + 3 * (size_t)a.g.n;
+    return L;
+}
+
+// Copy of a column's first `items` words, split over the workgroup's wavefronts.
+__device__ void copy_column(const Lane &L, float *dst, const float *src, size_t items)
+{
+    if (L.have)
+        for (size_t i = L.part; i < items; i += kUnrWaves) dst[i * 64] = src[i * 64];
+}
+
+// Sum over the workgroup of one double per wavefront, in wavefront order; the
+// result is valid in thread 0 only.  sh: kUnrWaves doubles of LDS.
+__device__ double block_sum(double x, double *sh)
+{
+    x = wave_sum(x);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kUnrWaves; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// m^{(0)}_{v->c} = lambda(Pi^{(0)}) clamped, Q^{(0)} = Pi^{(0)}  (eq. init), written
+// to st and ck.
+__device__ void init_state(const UnrArgs &a, const Lane &L, float *st, float *ck)
+{
+    if (!L.have) return;
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
     konst<float> *prior = as_const(a.prior);
     const int E = a.g.nnz;
-    for (int v = 0; v < a.g.n; ++v) {
+    for (int v = L.part; v < a.g.n; v += kUnrWaves) {
         const uint32_t info = vinfo[v];
         const uint32_t base = var_base(info), deg = var_deg(info);
         const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
         float lam[4];
         qubit_lambdas(p3, var_labels_present(info), lam);
-        for (uint32_t j = 0; j < deg; ++j) st[(size_t)(base + j) * 64] = clampf(lam[var_lab(info, j)], a.clamp);
-        for (int x = 0; x < 3; ++x) st[(size_t)(E + 3 * v + x) * 64] = p3[x];
+        for (uint32_t j = 0; j < deg; ++j) {
+            const float mj = clampf(lam[var_lab(info, j)], a.clamp);
+            st[(size_t)(base + j) * 64] = mj;
+            ck[(size_t)(base + j) * 64] = mj;
+        }
+        for (int x = 0; x < 3; ++x) {
+            st[(size_t)(E + 3 * v + x) * 64] = p3[x];
+            ck[(size_t)(E + 3 * v + x) * 64] = p3[x];
+        }
     }
 }
 
 // One forward iteration t: reads the state of t-1 from `src`, writes that of t to
 // `dst` (src == dst: in place).  The check pass writes m_{c->v} into dst's message
-// items; the qubit pass turns them into m_{v->c}^{(t)} (skipped at t = T).
-__device__ void forward_iteration(const UnrArgs &a, int t, const float *src, float *dst, int shot)
+// items; the qubit pass turns them into m_{v->c}^{(t)} (skipped at t = T).  Each
+// message and posterior item belongs to one check and one qubit, so the passes
+// need only the workgroup barrier between them and the one at the end.  Called by
+// every thread of the workgroup.
+__device__ void forward_iteration(const UnrArgs &a, const Lane &L, int t, const float *src, float *dst, int shot)
 {
     konst<uint32_t> *cedge = as_const(a.g.cedge);
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
@@ -126,7 +177,7 @@ __device__ void forward_iteration(const UnrArgs &a, int t, const float *src, flo
     const int m = a.g.m, n = a.g.n, E = a.g.nnz;
     const float C = a.clamp;
     const uint8_t *s = a.synd + (size_t)shot * m;
-    for (int c = 0; c < m; ++c) {
+    for (int c = L.part; L.have && c < m; c += kUnrWaves) {
         uint32_t w[4];
         float mv[4], out[4];
 #pragma unroll
@@ -139,13 +190,14 @@ __device__ void forward_iteration(const UnrArgs &a, int t, const float *src, flo
         for (int j = 0; j < 4; ++j)
             if (!edge_is_pad(w[j])) dst[(size_t)edge_slot(w[j]) * 64] = out[j];
     }
+    __syncthreads();
     VariantParams vp;
     vp.variant = BP4_EWAINIT;
     vp.g_from_t1 = 0;
     vp.alpha = a.alpha[t - 1];
     vp.gamma = 0.0f;
     vp.eps = 0.0f;
-    for (int v = 0; v < n; ++v) {
+    for (int v = L.part; L.have && v < n; v += kUnrWaves) {
         const uint32_t info = vinfo[v];
         const uint32_t base = var_base(info), deg = var_deg(info);
         float mc[4];
@@ -165,33 +217,30 @@ __device__ void forward_iteration(const UnrArgs &a, int t, const float *src, flo
                 dst[(size_t)(base + j) * 64] = clampf(lam[var_lab(info, j)] - mc[j], C);
         }
     }
+    __syncthreads();
 }
 
 __global__ void __launch_bounds__(kUnrBlock) unrolled_forward_kernel(UnrArgs a)
 {
-    const int col = blockIdx.x * kUnrBlock + threadIdx.x;
-    Lane L;
-    L.wave = (size_t)(col >> 6);
-    L.lane = threadIdx.x & 63;
-    L.SI = (size_t)a.g.nnz + 3 * (size_t)a.g.n;
-    if ((int)L.wave >= a.waves) return;   // whole wavefront past the last shot
-    const bool have = col < a.shots;
+    __shared__ double sh[kUnrWaves];
+    const Lane L = lane_of(a);
+    if ((int)L.wave >= a.waves) return;   // the whole workgroup: no such chunk
+    const int col = (int)L.wave * 64 + L.lane;
     const int n = a.g.n, E = a.g.nnz;
-    double loss = 0.0;
-    if (have) {
-        float *work = L.state(a.seg, 0, a.waves);
-        init_state(a, work);
-        float *ck0 = L.state(a.ckpt, 0, a.waves);
-        for (size_t i = 0; i < L.SI; ++i) ck0[i * 64] = work[i * 64];
-        for (int t = 1; t <= a.T; ++t) {
-            forward_iteration(a, t, work, work, col);
-            if (t % a.K == 0 && t < a.T) {
-                float *ck = L.state(a.ckpt, t / a.K, a.waves);
-                for (size_t i = 0; i < L.SI; ++i) ck[i * 64] = work[i * 64];
-            }
+    float *work = L.state(a.seg, 0, a.waves);
+    init_state(a, L, work, L.state(a.ckpt, 0, a.waves));
+    __syncthreads();
+    for (int t = 1; t <= a.T; ++t) {
+        forward_iteration(a, L, t, work, work, col);
+        if (t % a.K == 0 && t < a.T) {
+            copy_column(L, L.state(a.ckpt, t / a.K, a.waves), work, L.SI);
+            __syncthreads();              // the next check pass rewrites work in place
         }
+    }
+    double loss = 0.0;
+    if (L.have) {
         const uint8_t *e = a.err + (size_t)col * n;
-        for (int v = 0; v < n; ++v) {
+        for (int v = L.part; v < n; v += kUnrWaves) {
             float q[3], dq[3];
             for (int x = 0; x < 3; ++x) q[x] = work[(size_t)(E + 3 * v + x) * 64];
             loss += (double)qubit_loss(q, e[v] & 3u, dq);
@@ -199,16 +248,19 @@ __global__ void __launch_bounds__(kUnrBlock) unrolled_forward_kernel(UnrArgs a)
                 for (int x = 0; x < 3; ++x) a.q_out[((size_t)col * n + v) * 3 + x] = q[x];
         }
     }
-    loss = wave_sum(loss);
-    if (L.lane == 0) a.partial[L.wave * a.nout] = loss;
+    loss = block_sum(loss, sh);
+    if (threadIdx.x == 0) a.partial[L.wave * a.nout] = loss;
 }
 
 // Reverse sweep of iteration t.  cur: state t, prev: state t-1.  On entry the
 // adjoint holds dL/dm_{v->c}^{(t)} (gm) and dL/dQ^{(t)} (gQ, only the loss term
-// at t = T); on exit dL/dm_{v->c}^{(t-1)} and dL/dQ^{(t-1)}.  Returns this lane's
-// dL/dalpha_t.
-__device__ float reverse_iteration(const UnrArgs &a, int t, const float *cur, const float *prev, float *adj,
-                                   int shot)
+// at t = T); on exit dL/dm_{v->c}^{(t-1)} and dL/dQ^{(t-1)}.  Every message and
+// posterior adjoint belongs to one qubit and one check, so the qubit side and the
+// check side need only the workgroup barrier between them and the one at the end.
+// Called by every thread of the workgroup; returns the workgroup's dL/dalpha_t in
+// thread 0.
+__device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, const float *cur, const float *prev,
+                                    float *adj, int shot, double *sh)
 {
     konst<uint32_t> *cedge = as_const(a.g.cedge);
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
@@ -221,7 +273,7 @@ __device__ float reverse_iteration(const UnrArgs &a, int t, const float *cur, co
     const float al = a.alpha[t - 1];
     float galpha = 0.0f;
     // ---- qubit side: vertical update (t < T), then posterior and EWA prior ------
-    for (int v = 0; v < n; ++v) {
+    for (int v = L.part; L.have && v < n; v += kUnrWaves) {
         const uint32_t info = vinfo[v];
         const uint32_t base = var_base(info), deg = var_deg(info);
         float q[3], g[3];
@@ -264,9 +316,10 @@ __device__ float reverse_iteration(const UnrArgs &a, int t, const float *cur, co
             }
         }
     }
+    const double galpha_sum = block_sum((double)galpha, sh);   // also the barrier between the sides
     // ---- check side: m_{c->v} = clamp(sign * phi(sum_{v' != v} phi(|m_{v'->c}|))) ----
     const uint8_t *s = a.synd + (size_t)shot * m;
-    for (int c = 0; c < m; ++c) {
+    for (int c = L.part; L.have && c < m; c += kUnrWaves) {
         uint32_t w[4];
         float mv[4], f[4], gout[4];
         uint32_t sgn[4];
@@ -306,62 +359,57 @@ __device__ float reverse_iteration(const UnrArgs &a, int t, const float *cur, co
             gm[(size_t)edge_slot(w[k]) * 64] = gk;
         }
     }
-    return galpha;
+    __syncthreads();
+    return galpha_sum;
 }
 
 __global__ void __launch_bounds__(kUnrBlock) unrolled_backward_kernel(UnrArgs a)
 {
-    const int col = blockIdx.x * kUnrBlock + threadIdx.x;
-    Lane L;
-    L.wave = (size_t)(col >> 6);
-    L.lane = threadIdx.x & 63;
-    L.SI = (size_t)a.g.nnz + 3 * (size_t)a.g.n;
-    if ((int)L.wave >= a.waves) return;
-    const bool have = col < a.shots;
+    __shared__ double sh[kUnrWaves];
+    const Lane L = lane_of(a);
+    if ((int)L.wave >= a.waves) return;   // the whole workgroup: no such chunk
+    const int col = (int)L.wave * 64 + L.lane;
     const int n = a.g.n, E = a.g.nnz;
     float *adj = a.adj + L.wave * ((size_t)E + 6 * (size_t)n) * 64 + L.lane;
     double *part = a.partial + L.wave * a.nout;
-    if (have)
-        for (size_t i = 0; i < (size_t)E + 6 * (size_t)n; ++i) adj[i * 64] = 0.0f;
+    if (L.have)
+        for (size_t i = L.part; i < (size_t)E + 6 * (size_t)n; i += kUnrWaves) adj[i * 64] = 0.0f;
+    __syncthreads();
     for (int sg = a.nseg - 1; sg >= 0; --sg) {
         const int t0 = sg * a.K;
         const int t1 = t0 + a.K < a.T ? t0 + a.K : a.T;
-        if (have) {
-            // recompute the segment's states from its checkpoint
-            const float *ck = L.state(a.ckpt, sg, a.waves);
-            float *s0 = L.state(a.seg, 0, a.waves);
-            for (size_t i = 0; i < L.SI; ++i) s0[i * 64] = ck[i * 64];
-            for (int t = t0 + 1; t <= t1; ++t)
-                forward_iteration(a, t, L.state(a.seg, t - 1 - t0, a.waves), L.state(a.seg, t - t0, a.waves), col);
-            if (t1 == a.T) {
-                // dL/dQ^{(T)} of the soft loss (unscaled: the mean's 1/(shots n) comes last)
-                const float *sT = L.state(a.seg, t1 - t0, a.waves);
-                const uint8_t *e = a.err + (size_t)col * n;
-                for (int v = 0; v < n; ++v) {
-                    float q[3], dq[3];
-                    for (int x = 0; x < 3; ++x) q[x] = sT[(size_t)(E + 3 * v + x) * 64];
-                    qubit_loss(q, e[v] & 3u, dq);
-                    for (int x = 0; x < 3; ++x) adj[(size_t)(E + 3 * v + x) * 64] = dq[x];
-                }
+        // recompute the segment's states from its checkpoint
+        copy_column(L, L.state(a.seg, 0, a.waves), L.state(a.ckpt, sg, a.waves), L.SI);
+        __syncthreads();
+        for (int t = t0 + 1; t <= t1; ++t)
+            forward_iteration(a, L, t, L.state(a.seg, t - 1 - t0, a.waves), L.state(a.seg, t - t0, a.waves), col);
+        if (t1 == a.T && L.have) {
+            // dL/dQ^{(T)} of the soft loss (unscaled: the mean's 1/(shots n) comes last)
+            const float *sT = L.state(a.seg, t1 - t0, a.waves);
+            const uint8_t *e = a.err + (size_t)col * n;
+            for (int v = L.part; v < n; v += kUnrWaves) {
+                float q[3], dq[3];
+                for (int x = 0; x < 3; ++x) q[x] = sT[(size_t)(E + 3 * v + x) * 64];
+                qubit_loss(q, e[v] & 3u, dq);
+                for (int x = 0; x < 3; ++x) adj[(size_t)(E + 3 * v + x) * 64] = dq[x];
             }
         }
+        __syncthreads();
         for (int t = t1; t > t0; --t) {
-            float ga = 0.0f;
-            if (have)
-                ga = reverse_iteration(a, t, L.state(a.seg, t - t0, a.waves), L.state(a.seg, t - 1 - t0, a.waves),
-                                       adj, col);
-            const double tot = wave_sum((double)ga);
-            if (L.lane == 0) part[t - 1] = t == 1 ? 0.0 : tot;
+            const double tot = reverse_iteration(a, L, t, L.state(a.seg, t - t0, a.waves),
+                                                 L.state(a.seg, t - 1 - t0, a.waves), adj, col, sh);
+            if (threadIdx.x == 0) part[t - 1] = t == 1 ? 0.0 : tot;
         }
     }
     // ---- initialisation: m^{(0)}_{v->c} = clamp(lambda_H(Pi^{(0)})) ----------------
+    // qubit v is one wavefront's, so its sums run over that wavefront's 64 columns
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
     konst<float> *prior = as_const(a.prior);
     float *gm = adj;
     float *gP = adj + (size_t)(E + 3 * n) * 64;
-    for (int v = 0; v < n; ++v) {
+    for (int v = L.part; v < n; v += kUnrWaves) {
         float g[3] = {0.0f, 0.0f, 0.0f};
-        if (have) {
+        if (L.have) {
             const uint32_t info = vinfo[v];
             const uint32_t base = var_base(info), deg = var_deg(info);
             const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
@@ -407,7 +455,7 @@ UnrolledSizes unrolled_sizes(int m, int n, int nnz, int32_t T, int32_t K, int64_
 {
     (void)m;
     UnrolledSizes z;
-    const size_t lanes = (size_t)((shots + kUnrBlock - 1) / kUnrBlock) * kUnrBlock;
+    const size_t lanes = (size_t)((shots + kUnrRound - 1) / kUnrRound) * kUnrRound;
     const size_t waves = lanes / 64;
     const size_t SI = (size_t)nnz + 3 * (size_t)n;
     const size_t nseg = (size_t)((T + K - 1) / K);
@@ -434,7 +482,7 @@ static UnrArgs unrolled_args(const GraphView &g, int32_t T, int32_t K, float cla
     a.nout = nout;
     a.clamp = clamp;
     a.q_out = nullptr;
-    const size_t lanes = (size_t)((shots + kUnrBlock - 1) / kUnrBlock) * kUnrBlock;
+    const size_t lanes = (size_t)((shots + kUnrRound - 1) / kUnrRound) * kUnrRound;
     const size_t waves_alloc = lanes / 64;
     const size_t SI = (size_t)g.nnz + 3 * (size_t)g.n;
     a.ckpt = static_cast<float *>(saved);
@@ -444,7 +492,7 @@ static UnrArgs unrolled_args(const GraphView &g, int32_t T, int32_t K, float cla
     a.adj = reinterpret_cast<float *>(w);
     w += up256u(waves_alloc * ((size_t)g.nnz + 6 * (size_t)g.n) * 64 * 4);
     a.partial = reinterpret_cast<double *>(w);
-    // every allocated wavefront runs (those past the last shot contribute zeros)
+    // every allocated chunk runs (those past the last shot contribute zeros)
     a.waves = (int)waves_alloc;
     return a;
 }
@@ -455,8 +503,7 @@ hipError_t launch_unrolled_forward(const GraphView &g, int32_t T, int32_t K, flo
 {
     UnrArgs a = unrolled_args(g, T, K, clamp, shots, alpha, prior, synd, err, saved, ws, 1);
     a.q_out = q_out;
-    const unsigned blocks = (unsigned)((shots + kUnrBlock - 1) / kUnrBlock);
-    hipLaunchKernelGGL(unrolled_forward_kernel, dim3(blocks), dim3(kUnrBlock), 0, s, a);
+    hipLaunchKernelGGL(unrolled_forward_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = 1.0 / ((double)shots * (double)g.n);
@@ -472,8 +519,7 @@ hipError_t launch_unrolled_backward(const GraphView &g, int32_t T, int32_t K, fl
 {
     const int nout = T + 3 * g.n;
     UnrArgs a = unrolled_args(g, T, K, clamp, shots, alpha, prior, synd, err, const_cast<void *>(saved), ws, nout);
-    const unsigned blocks = (unsigned)((shots + kUnrBlock - 1) / kUnrBlock);
-    hipLaunchKernelGGL(unrolled_backward_kernel, dim3(blocks), dim3(kUnrBlock), 0, s, a);
+    hipLaunchKernelGGL(unrolled_backward_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = 1.0 / ((double)shots * (double)g.n);
