@@ -363,44 +363,56 @@ __device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, cons
     return galpha_sum;
 }
 
-__global__ void __launch_bounds__(kUnrBlock) unrolled_backward_kernel(UnrArgs a)
+// Adjoint, part 1 for segment sg: recompute the segment's states from its
+// checkpoint; for the last segment first clear the adjoint record and seed it
+// with dL/dQ^{(T)} of the soft loss (unscaled: the mean's 1/(shots n) comes last).
+__global__ void __launch_bounds__(kUnrBlock) unrolled_recompute_kernel(UnrArgs a, int sg)
+{
+    const Lane L = lane_of(a);
+    if ((int)L.wave >= a.waves) return;   // the whole workgroup: no such chunk
+    const int col = (int)L.wave * 64 + L.lane;
+    const int n = a.g.n, E = a.g.nnz;
+    const int t0 = sg * a.K;
+    const int t1 = t0 + a.K < a.T ? t0 + a.K : a.T;
+    float *adj = a.adj + L.wave * ((size_t)E + 6 * (size_t)n) * 64 + L.lane;
+    copy_column(L, L.state(a.seg, 0, a.waves), L.state(a.ckpt, sg, a.waves), L.SI);
+    __syncthreads();
+    for (int t = t0 + 1; t <= t1; ++t)
+        forward_iteration(a, L, t, L.state(a.seg, t - 1 - t0, a.waves), L.state(a.seg, t - t0, a.waves), col);
+    if (t1 != a.T) return;
+    if (L.have)
+        for (size_t i = L.part; i < (size_t)E + 6 * (size_t)n; i += kUnrWaves) adj[i * 64] = 0.0f;
+    __syncthreads();                      // other wavefronts cleared some of the items written below
+    if (!L.have) return;
+    const float *sT = L.state(a.seg, t1 - t0, a.waves);
+    const uint8_t *e = a.err + (size_t)col * n;
+    for (int v = L.part; v < n; v += kUnrWaves) {
+        float q[3], dq[3];
+        for (int x = 0; x < 3; ++x) q[x] = sT[(size_t)(E + 3 * v + x) * 64];
+        qubit_loss(q, e[v] & 3u, dq);
+        for (int x = 0; x < 3; ++x) adj[(size_t)(E + 3 * v + x) * 64] = dq[x];
+    }
+}
+
+// Adjoint, part 2 for segment sg: the reverse sweep t = t1 ... t0+1 over the
+// recomputed states, then (sg = 0) the initial messages' contribution.
+__global__ void __launch_bounds__(kUnrBlock) unrolled_reverse_kernel(UnrArgs a, int sg)
 {
     __shared__ double sh[kUnrWaves];
     const Lane L = lane_of(a);
     if ((int)L.wave >= a.waves) return;   // the whole workgroup: no such chunk
     const int col = (int)L.wave * 64 + L.lane;
     const int n = a.g.n, E = a.g.nnz;
+    const int t0 = sg * a.K;
+    const int t1 = t0 + a.K < a.T ? t0 + a.K : a.T;
     float *adj = a.adj + L.wave * ((size_t)E + 6 * (size_t)n) * 64 + L.lane;
     double *part = a.partial + L.wave * a.nout;
-    if (L.have)
-        for (size_t i = L.part; i < (size_t)E + 6 * (size_t)n; i += kUnrWaves) adj[i * 64] = 0.0f;
-    __syncthreads();
-    for (int sg = a.nseg - 1; sg >= 0; --sg) {
-        const int t0 = sg * a.K;
-        const int t1 = t0 + a.K < a.T ? t0 + a.K : a.T;
-        // recompute the segment's states from its checkpoint
-        copy_column(L, L.state(a.seg, 0, a.waves), L.state(a.ckpt, sg, a.waves), L.SI);
-        __syncthreads();
-        for (int t = t0 + 1; t <= t1; ++t)
-            forward_iteration(a, L, t, L.state(a.seg, t - 1 - t0, a.waves), L.state(a.seg, t - t0, a.waves), col);
-        if (t1 == a.T && L.have) {
-            // dL/dQ^{(T)} of the soft loss (unscaled: the mean's 1/(shots n) comes last)
-            const float *sT = L.state(a.seg, t1 - t0, a.waves);
-            const uint8_t *e = a.err + (size_t)col * n;
-            for (int v = L.part; v < n; v += kUnrWaves) {
-                float q[3], dq[3];
-                for (int x = 0; x < 3; ++x) q[x] = sT[(size_t)(E + 3 * v + x) * 64];
-                qubit_loss(q, e[v] & 3u, dq);
-                for (int x = 0; x < 3; ++x) adj[(size_t)(E + 3 * v + x) * 64] = dq[x];
-            }
-        }
-        __syncthreads();
-        for (int t = t1; t > t0; --t) {
-            const double tot = reverse_iteration(a, L, t, L.state(a.seg, t - t0, a.waves),
-                                                 L.state(a.seg, t - 1 - t0, a.waves), adj, col, sh);
-            if (threadIdx.x == 0) part[t - 1] = t == 1 ? 0.0 : tot;
-        }
+    for (int t = t1; t > t0; --t) {
+        const double tot = reverse_iteration(a, L, t, L.state(a.seg, t - t0, a.waves),
+                                             L.state(a.seg, t - 1 - t0, a.waves), adj, col, sh);
+        if (threadIdx.x == 0) part[t - 1] = t == 1 ? 0.0 : tot;
     }
+    if (sg != 0) return;
     // ---- initialisation: m^{(0)}_{v->c} = clamp(lambda_H(Pi^{(0)})) ----------------
     // qubit v is one wavefront's, so its sums run over that wavefront's 64 columns
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
@@ -519,7 +531,10 @@ hipError_t launch_unrolled_backward(const GraphView &g, int32_t T, int32_t K, fl
 {
     const int nout = T + 3 * g.n;
     UnrArgs a = unrolled_args(g, T, K, clamp, shots, alpha, prior, synd, err, const_cast<void *>(saved), ws, nout);
-    hipLaunchKernelGGL(unrolled_backward_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a);
+    for (int sg = a.nseg - 1; sg >= 0; --sg) {
+        hipLaunchKernelGGL(unrolled_recompute_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a, sg);
+        hipLaunchKernelGGL(unrolled_reverse_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a, sg);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = 1.0 / ((double)shots * (double)g.n);
