@@ -395,8 +395,12 @@ __global__ void __launch_bounds__(kUnrBlock) unrolled_recompute_kernel(UnrArgs a
 }
 
 // Adjoint, part 2 for segment sg: the reverse sweep t = t1 ... t0+1 over the
-// recomputed states, then (sg = 0) the initial messages' contribution.
-__global__ void __launch_bounds__(kUnrBlock) unrolled_reverse_kernel(UnrArgs a, int sg)
+// recomputed states, then (sg = 0) the initial messages' contribution.  Held to
+// 64 VGPRs (8 wavefronts per SIMD): the few values that spill cost less than the
+// latency hidden by the extra wavefronts (96 VGPRs without spills: 5 per SIMD,
+// 17% slower).
+__global__ void __launch_bounds__(kUnrBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+unrolled_reverse_kernel(UnrArgs a, int sg)
 {
     __shared__ double sh[kUnrWaves];
     const Lane L = lane_of(a);
