@@ -98,3 +98,59 @@ def test_soa_iteration_block_graph_replays_match_eager():
             assert torch.equal(got[k], r[k]), (rep, k)
         assert torch.equal(other["iters"], r["iters"][:100])
         say("soa replay", rep, float(got["iters"].float().mean()))
+
+
+def test_unrolled_forward_backward_graph_replays_match_eager():
+    """The unrolled forward and its adjoint (two kernels per checkpoint segment plus
+    the reductions) captured once; each replay's loss and gradients equal an eager
+    autograd pass over the same shots bit for bit."""
+    import ctypes
+
+    import numpy as np
+    from paper_2407_11523_amd import api as A
+    c = qecgen.planar(5)
+    T, K, shots, p = 10, 3, 1000, 0.08
+    g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+    thr = qecgen.thresholds(p / 3, p / 3, p / 3)
+    rng = np.random.default_rng(3)
+    alpha = torch.tensor(rng.uniform(0.3, 0.9, T), dtype=torch.float32, device="cuda")
+    prior = torch.tensor(np.log((1 - p) / (p / 3)) + rng.uniform(-0.3, 0.3, (c.n, 3)), dtype=torch.float32,
+                         device="cuda")
+    err = torch.empty((shots, c.n), dtype=torch.uint8, device="cuda")
+    syn = torch.empty((shots, c.m), dtype=torch.uint8, device="cuda")
+    sb, wb = A.unrolled_sizes(g, T, K, shots)
+    saved = torch.empty(sb, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    dl = torch.ones(1, dtype=torch.float32, device="cuda")
+    dalpha = torch.empty(T, dtype=torch.float64, device="cuda")
+    dprior = torch.empty(c.n, 3, dtype=torch.float64, device="cuda")
+    lib = g._lib
+
+    def run():
+        s = A._stream(syn.device)
+        A.check(lib.bp4_unrolled_forward(g.handle, A._ptr(g.dev), T, K, 30.0, shots, A._ptr(alpha), A._ptr(prior),
+                                         A._ptr(syn), A._ptr(err), A._ptr(loss), ctypes.c_void_p(0), A._ptr(saved),
+                                         sb, A._ptr(ws), wb, s))
+        A.check(lib.bp4_unrolled_backward(g.handle, A._ptr(g.dev), T, K, 30.0, shots, A._ptr(alpha), A._ptr(prior),
+                                          A._ptr(syn), A._ptr(err), A._ptr(dl), A._ptr(saved), sb, A._ptr(dalpha),
+                                          A._ptr(dprior), A._ptr(ws), wb, s))
+
+    P.sample(g, shots, thr, 30, err=err, synd=syn)
+    cap = P.Captured(run)
+    for rep, seed in enumerate((31, 32, 33)):
+        P.sample(g, shots, thr, seed, err=err, synd=syn)
+        P.decode(g, P.Params(), prior, syn[:100])        # unrelated eager work between replays
+        torch.cuda.synchronize()
+        cap.replay()
+        torch.cuda.synchronize()
+        got = (loss.clone(), dalpha.clone(), dprior.clone())
+        a = alpha.clone().requires_grad_(True)
+        pr = prior.clone().requires_grad_(True)
+        ref = P.unrolled_loss(g, a, pr, syn, err, T, K)
+        ref.backward()
+        torch.cuda.synchronize()
+        assert torch.equal(got[0][0], ref.detach()), rep
+        assert torch.equal(got[1].to(torch.float32), a.grad), rep
+        assert torch.equal(got[2].to(torch.float32), pr.grad), rep
+        say("unrolled replay", rep, float(got[0][0]))
