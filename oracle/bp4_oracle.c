@@ -186,9 +186,6 @@ static double clampd(double x, double c)
 
 enum { OR_BP = 0, OR_MOMENTUM = 1, OR_ADAGRAD = 2, OR_EWAINIT = 3, OR_AEWA = 4 };
 
-/* AdaGrad gradients at or below this fraction of |D| + sum |m| count as 0. */
-#define ADAGRAD_DEADBAND 1.52587890625e-05   /* 2^-16 */
-
 typedef struct {
     int32_t variant;            /* OR_BP, OR_MOMENTUM, OR_ADAGRAD, OR_EWAINIT */
     int32_t max_iter;           /* iter_max >= 1 */
@@ -244,27 +241,22 @@ static double check_to_qubit(const or_graph *g, const uint8_t *s, const double *
 }
 
 /* Sum of incoming check messages per Pauli: M_{v,W} = sum over c in M(v) with
- * <W, H_cv> = 1 of m_{c->v} (the sum in eqs. p_update / mombp3), and of their
- * magnitudes. */
-static void qubit_sums(const or_graph *g, int v, const double *mcv, double *msum, double *mabs)
+ * <W, H_cv> = 1 of m_{c->v} (the sum in eqs. p_update / mombp3). */
+static void qubit_sums(const or_graph *g, int v, const double *mcv, double *msum)
 {
     for (int w = 0; w < 3; ++w) {
-        double sum = 0.0, asum = 0.0;
+        double sum = 0.0;
         for (int k = g->vptr[v]; k < g->vptr[v + 1]; ++k) {
             int e = g->vedge[k];
-            if (anticommute(PAULI_OF_INDEX[w], g->elab[e])) {
-                sum += mcv[e];
-                asum += fabs(mcv[e]);
-            }
+            if (anticommute(PAULI_OF_INDEX[w], g->elab[e])) sum += mcv[e];
         }
         msum[3 * v + w] = sum;
-        mabs[3 * v + w] = asum;
     }
 }
 
 /* Posterior update of entry i = 3v + w, per variant. */
 static void posterior(const or_params *p, int t, int i, const double *pi0, const double *pit,
-                      const double *qprev, const double *msum, const double *mabs, double *q,
+                      const double *qprev, const double *msum, double *q,
                       double *acc, double *dev)
 {
     switch (p->variant) {
@@ -283,16 +275,8 @@ static void posterior(const or_params *p, int t, int i, const double *pi0, const
     case OR_ADAGRAD: { /* eq. boost; active from the second iteration (READING) */
         /* Carried as the deviation D = Q - Pi^{(0)} (READING: the gradient
          * g' = Q^{(t-1)} - Pi - sum m of eq. boost is then D^{(t-1)} - sum m,
-         * which is exactly 0 when the incoming sums repeat; the step
-         * g'/(sqrt(G)+eps) would otherwise turn rounding residue into a full
-         * step of size alpha).  READING: a gradient below the rounding
-         * resolution of its operands, |g'| <= 2^-16 (|D| + sum |m|), is 0:
-         * while G is still 0 the first adaptive step is alpha * sign(g'),
-         * so a difference of message sums that cancel exactly (opposite
-         * syndromes on a symmetric neighbourhood) must not pick a sign from
-         * rounding. */
+         * which is exactly 0 when the incoming sums repeat). */
         double grad = dev[i] - msum[i];
-        if (fabs(grad) <= ADAGRAD_DEADBAND * (fabs(dev[i]) + mabs[i])) grad = 0.0;
         if (t == 1) {
             if (p->adagrad_g_from_t1) acc[i] += grad * grad;
             dev[i] = msum[i];
@@ -340,7 +324,7 @@ static void qubit_messages(const or_graph *g, const or_params *p, int v, const d
 static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
                        const uint8_t *s, uint8_t *est, uint8_t *conv_out, int32_t *iters_out,
                        double *mvc, double *mcv, double *q, double *qprev, double *pit,
-                       double *acc, double *dev, double *msum, double *mabs, int *ehat,
+                       double *acc, double *dev, double *msum, int *ehat,
                        double *q_trace, double *m_trace)
 {
     const int n = g->n, m = g->m, nnz = g->nnz;
@@ -368,8 +352,8 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
         if (!p->serial) {
             /* Flooding ("parallel") schedule, Alg. 2: every check, then every qubit. */
             for (int e = 0; e < nnz; ++e) mcv[e] = check_to_qubit(g, s, mvc, e, C);
-            for (int v = 0; v < n; ++v) qubit_sums(g, v, mcv, msum, mabs);
-            for (int i = 0; i < 3 * n; ++i) posterior(p, t, i, pi0, pit, qprev, msum, mabs, q, acc, dev);
+            for (int v = 0; v < n; ++v) qubit_sums(g, v, mcv, msum);
+            for (int i = 0; i < 3 * n; ++i) posterior(p, t, i, pi0, pit, qprev, msum, q, acc, dev);
             for (int v = 0; v < n; ++v) qubit_messages(g, p, v, pi0, pit, q, mcv, mvc, C);
         } else {
             /* Serial schedule, Alg. 1: qubit by qubit in index order, each qubit's
@@ -381,8 +365,8 @@ static void decode_one(const or_graph *g, const or_params *p, const double *pi0,
                     const int e = g->vedge[k];
                     mcv[e] = check_to_qubit(g, s, mvc, e, C);
                 }
-                qubit_sums(g, v, mcv, msum, mabs);
-                for (int i = 3 * v; i < 3 * v + 3; ++i) posterior(p, t, i, pi0, pit, qprev, msum, mabs, q, acc, dev);
+                qubit_sums(g, v, mcv, msum);
+                for (int i = 3 * v; i < 3 * v + 3; ++i) posterior(p, t, i, pi0, pit, qprev, msum, q, acc, dev);
                 qubit_messages(g, p, v, pi0, pit, q, mcv, mvc, C);
             }
         }
@@ -450,9 +434,8 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
         double *acc = malloc(sizeof(double) * 3 * n);
         double *dev = malloc(sizeof(double) * 3 * n);
         double *msum = malloc(sizeof(double) * 3 * n);
-        double *mabs = malloc(sizeof(double) * 3 * n);
         int *ehat = malloc(sizeof(int) * n);
-        if (!mvc || !mcv || !q || !qprev || !pit || !acc || !dev || !msum || !mabs || !ehat) {
+        if (!mvc || !mcv || !q || !qprev || !pit || !acc || !dev || !msum || !ehat) {
 #pragma omp atomic write
             rc = -1;
         } else {
@@ -462,7 +445,7 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
                 double *mt = o->m_trace ? o->m_trace + (size_t)i * p->max_iter * 3 * n : NULL;
                 if (p->variant != OR_AEWA) {
                     decode_one(&g, p, pi0, synd + (size_t)i * m, est + (size_t)i * n, conv + i,
-                               iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, mabs, ehat, qt, mt);
+                               iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, ehat, qt, mt);
                 } else {
                     /* AEWA-BP (appendix on adaptive MBP): EWAInit-BP with the discounts
                      * alpha_0 .. alpha_{K-1}, each attempt a fresh decode, until one
@@ -477,7 +460,7 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
                                        ? p->alpha + (p->alpha_last - p->alpha) * (double)k / (double)(p->alpha_steps - 1)
                                        : p->alpha;
                         decode_one(&g, &pk, pi0, synd + (size_t)i * m, est + (size_t)i * n, conv + i,
-                                   iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, mabs, ehat, qt, mt);
+                                   iters + i, mvc, mcv, q, qprev, pit, acc, dev, msum, ehat, qt, mt);
                         total += iters[i];
                         if (conv[i]) break;
                     }
@@ -488,7 +471,7 @@ int or_decode(int m, int n, const uint8_t *hx, const uint8_t *hz, const or_param
                 if (o->mcv_out) memcpy(o->mcv_out + (size_t)i * nnz, mcv, sizeof(double) * nnz);
             }
         }
-        free(mvc); free(mcv); free(q); free(qprev); free(pit); free(acc); free(dev); free(msum); free(mabs); free(ehat);
+        free(mvc); free(mcv); free(q); free(qprev); free(pit); free(acc); free(dev); free(msum); free(ehat);
     }
     graph_free(&g);
     return rc;

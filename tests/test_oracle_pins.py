@@ -362,7 +362,7 @@ def test_momentum_alpha_one_identity():
 
 def test_adagrad_step_invariants():
     # eq. boost: each adaptive step has magnitude alpha |g'| / (sqrt(G) + eps) <= alpha, and the
-    # first adaptive step (t = 2, G = g'^2) is alpha |g'| / (|g'| + eps).
+    # first adaptive step (t = 2, G = g'^2) is alpha |g'| / (|g'| + eps), for every gradient.
     code, _, syn, pi = _toric_batch(shots=16)
     T, a = 10, 5.0
     r = O.decode(code.hx, code.hz, O.Params(variant="adagrad", alpha=a, max_iter=T,
@@ -372,17 +372,107 @@ def test_adagrad_step_invariants():
     steps = np.abs(np.diff(Q, axis=1))
     assert np.all(steps <= a * (1 + 1e-12))
     gp = M[:, 0] - M[:, 1]          # Q^{(1)} - Pi - M^{(2)} with Q^{(1)} = Pi + M^{(1)}
-    big = np.abs(gp) > 1e-3         # far above the sub-resolution deadband
-    assert big.mean() > 0.3
+    assert (np.abs(gp) > 1e-3).mean() > 0.3
     step = np.abs(Q[:, 1] - Q[:, 0])
-    assert np.allclose(step[big], (a * np.abs(gp) / (np.abs(gp) + 1e-8))[big], rtol=1e-9, atol=1e-9)
-    # a gradient that vanishes (exactly, or below the rounding resolution) gives no step
-    assert np.all(step[np.abs(gp) < 1e-12] == 0)
+    assert np.allclose(step, a * np.abs(gp) / (np.abs(gp) + 1e-8), rtol=1e-9, atol=1e-9)
+    # a gradient that vanishes gives no step, bit for bit
+    assert np.all(step[gp == 0] == 0)
     # accumulating G from t = 1 gives a smaller first adaptive step
     r2 = O.decode(code.hx, code.hz, O.Params(variant="adagrad", alpha=a, max_iter=T, stop_on_syndrome=False,
                                              adagrad_g_from_t1=True), pi, syn, want_trace=True)
     s2 = np.abs(r2["q_trace"][:, 1] - r2["q_trace"][:, 0])
     assert np.all(s2 <= np.abs(Q[:, 1] - Q[:, 0]) + 1e-12)
+
+
+def prob_bp4_optim(hx, hz, probs, s, T, variant, alpha, gamma=0.0, eps=1e-8, g_from_t1=False):
+    """Probability-domain quaternary BP whose posterior follows a library optimiser.
+
+    Check messages are the explicit sums over neighbour configurations of
+    ``prob_bp4``.  M_{v,W} = sum_c ln(r_{c->v}(I) / r_{c->v}(W)) is the LLR form of
+    the product of the incoming check messages.  Momentum-BP (eqs. mombp1-3) and
+    AdaGrad-BP (eq. boost) treat Q - Pi - M as the gradient of the posterior; here
+    torch.optim.SGD (heavy ball with dampening gamma, i.e. g = gamma g + (1 - gamma)
+    grad, Q -= alpha g, momentum buffer starting at 0) and torch.optim.Adagrad
+    (G += grad^2, Q -= alpha grad / (sqrt(G) + eps)) take that step.  AdaGrad's first
+    iteration is the plain BP posterior with G = 0 (or G = grad^2 with
+    ``g_from_t1``).  The outgoing message divides the check's own incoming
+    message out of the posterior (probability form of lambda(Q - m_{c->v})).
+    Returns Q^{(t)} for t = 1..T.
+    """
+    torch = pytest.importorskip("torch")
+    m, n = hx.shape
+    lab = (hx | (hz << 1)).astype(int)
+    edges = [(c, v) for c in range(m) for v in range(n) if lab[c, v]]
+    p0 = np.column_stack([1 - probs.sum(1), probs[:, 0], probs[:, 2], probs[:, 1]])
+    q = {e: p0[e[1]].copy() for e in edges}
+    pi = torch.tensor(np.log(p0[:, [0]]) - np.log(p0[:, [1, 3, 2]]), dtype=torch.float64)
+    Q = pi.clone().requires_grad_(True)
+    if variant == "momentum":
+        opt = torch.optim.SGD([Q], lr=alpha, momentum=gamma, dampening=gamma)
+        opt.state[Q]["momentum_buffer"] = torch.zeros_like(Q)
+    else:
+        opt = torch.optim.Adagrad([Q], lr=alpha, eps=eps, initial_accumulator_value=0.0)
+    out = []
+    for t in range(1, T + 1):
+        r = {}
+        for (c, v) in edges:
+            others = [u for u in range(n) if lab[c, u] and u != v]
+            rv = np.zeros(4)
+            for P in range(4):
+                tot = 0.0
+                for conf in itertools.product(range(4), repeat=len(others)):
+                    par = COMM[lab[c, v], P]
+                    w = 1.0
+                    for u, Pu in zip(others, conf):
+                        par ^= COMM[lab[c, u], Pu]
+                        w *= q[(c, u)][Pu]
+                    if par == s[c]:
+                        tot += w
+                rv[P] = tot
+            r[(c, v)] = rv / rv.sum()
+        M = np.zeros((n, 3))
+        for (c, v) in edges:
+            M[v] += np.log(r[(c, v)][0]) - np.log(r[(c, v)][[1, 3, 2]])
+        M = torch.tensor(M)
+        with torch.no_grad():
+            if variant == "adagrad" and t == 1:
+                if g_from_t1:
+                    opt.state[Q]["sum"].copy_((Q - pi - M) ** 2)
+                Q.copy_(pi + M)
+            else:
+                Q.grad = (Q - pi - M).detach().clone()
+                opt.step()
+        Qn = Q.detach().numpy().copy()
+        post = np.column_stack([np.ones(n), np.exp(-Qn[:, 0]), np.exp(-Qn[:, 2]), np.exp(-Qn[:, 1])])
+        post /= post.sum(1, keepdims=True)
+        for (c, v) in edges:
+            qq = post[v] / r[(c, v)]
+            q[(c, v)] = qq / qq.sum()
+        out.append(Qn)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("make", [lambda: qecgen.planar(3), lambda: qecgen.toric(3),
+                                  lambda: qecgen.xzzx(3)])
+@pytest.mark.parametrize("variant,alpha,gamma,g1", [("momentum", 0.7, 0.3, False), ("momentum", 0.5, 0.7, False),
+                                                    ("adagrad", 5.0, 0.0, False), ("adagrad", 1.0, 0.0, False),
+                                                    ("adagrad", 5.0, 0.0, True)])
+def test_optimiser_posteriors_probability_domain(make, variant, alpha, gamma, g1):
+    # Momentum-BP with gamma != 0 and AdaGrad-BP on graphs with cycles, Y labels and
+    # non-uniform priors, against probability-domain BP driven by torch's SGD / Adagrad.
+    code = make()
+    rng = np.random.default_rng(5)
+    hx, hz, _ = clifford_relabel(code, rng)
+    probs = rng.uniform(0.005, 0.04, size=(code.n, 3))
+    e = np.zeros(code.n, np.uint8)
+    e[rng.choice(code.n, 2, replace=False)] = rng.integers(1, 4, size=2)
+    s = syndrome_np(hx, hz, e)[0]
+    T = 8
+    want = prob_bp4_optim(hx, hz, probs, s, T, variant, alpha, gamma, g_from_t1=g1)
+    r = O.decode(hx, hz, O.Params(variant=variant, max_iter=T, stop_on_syndrome=False, clamp=math.inf,
+                                  alpha=alpha, gamma=gamma, adagrad_g_from_t1=g1),
+                 O.prior_llr(probs), s[None], want_trace=True)
+    assert np.allclose(r["q_trace"][0], want, rtol=1e-11, atol=1e-11)
 
 
 # ---------------------------------------------------------------------------
