@@ -27,35 +27,48 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-P_ERR = 0.08
-ALPHA = 0.5          # EWAInit discount factor (the paper's trapping-set value; see the design notes)
-MAX_ITER = 100
-BASE_SHOTS = 1 << 18
-# (family, size, shot multiplier): smallest size(s) 1, middle 2, largest 4
-CODES = [("planar", 5, 1), ("planar", 7, 1), ("planar", 9, 2), ("planar", 11, 4), ("planar", 13, 4),
-         ("toric", 6, 1), ("toric", 10, 2), ("toric", 14, 4),
-         ("xzzx", 5, 1), ("xzzx", 9, 2), ("xzzx", 13, 4)]
+from qecgen import configs  # noqa: E402
 
-# Roofline of the LDS-resident decode: VALU issue.  Algorithmic FP32 issue slots of
-# one EWAInit iteration of one shot, counted from the update rules: phi = 6 FP32
-# operations + one exp2 or log2 (a square, a cubic or quartic polynomial in it and
-# one final multiply-add, constant scalings folded into the coefficients);
-# ln(1 + e^-|y|) = 3 operations + 2 transcendentals; a transcendental costs
-# TRANS_SLOTS plain FP32 issue slots (measured by paper_2407_11523_amd/calib/valu_rate:
-# exp2 1.76, log2 1.74).
+P_ERR = configs.CONFIG3["p"]
+ALPHA = configs.alpha(3, "ewainit")     # EWAInit discount of the mixed batch (chosen on the oracle)
+ALPHA_EXTRA = 0.5    # the paper's trapping-set value, for the sections it gives no discount for
+MAX_ITER = configs.CONFIG3["max_iter"]
+BASE_SHOTS = configs.CONFIG3["base_shots"]
+# (family, size, shot multiplier): smallest size(s) 1, middle 2, largest 4
+CODES = list(configs.CONFIG3_CODES)
+
+# Roofline of the LDS-resident decode: VALU issue.  Algorithmic work of one flooding
+# iteration of one shot, counted at the level of the update rules: per edge one tanh
+# and one atanh for the check message and one exp and one log for lambda
+# (4 transcendentals), per qubit 3 exponentials for the posterior's probabilities,
+# and 15-20 plain FP32 operations per edge (leave-one-out products, posterior sums,
+# extrinsic subtraction, lambda's arithmetic, the EWA update, the hard decision and
+# the syndrome test), taken as 17.5.  A transcendental costs TRANS_SLOTS plain FP32
+# issue slots (measured by paper_2407_11523_amd/calib/valu_rate: exp2 1.76, log2
+# 1.74).  Peak issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 slots/s.
+TRANS_SLOTS = 1.75
+ALG_TRANS_PER_EDGE = 4.0
+ALG_TRANS_PER_QUBIT = 3.0
+ALG_OPS_PER_EDGE = 17.5
+
+
+def algorithmic_slots(E, N):
+    """FP32 issue slots of one iteration of one shot (E edges, N qubits)."""
+    return TRANS_SLOTS * (ALG_TRANS_PER_EDGE * E + ALG_TRANS_PER_QUBIT * N) + ALG_OPS_PER_EDGE * E
+
+
+# A second, finer count of the same work, itemised from the kernels' own evaluation
+# (phi = 6 FP32 operations + one exp2 or log2; ln(1 + e^-|y|) = 3 operations + 2
+# transcendentals):
 #   check of degree d: 2d phi, d sign products, 2d - 1 leave-one-out sums, d sign
 #                      applications, d clamps; syndrome test d + 1  -> 18d ops, 2d transcendentals
 #   qubit of degree d with L labels present: d + 3 label sums, 9 posterior (EWAInit),
 #                      5 hard decision, L lambdas (two softplus + 6 ops each), 2d
 #                      output subtractions and clamps               -> 3d + 17 + 12L ops, 4L transcendentals
 # so an iteration costs 21 E + 17 N + 12 sum(L) operations and 2 E + 4 sum(L)
-# transcendentals (E edges, N qubits).  Peak issue: 256 CUs x 4 SIMDs x 16 lanes
-# x 2.4 GHz = 39.3e12 slots/s.
-TRANS_SLOTS = 1.75
-
-
+# transcendentals; reported beside the algorithmic fraction.
 def iteration_slots(code):
-    """Algorithmic FP32 issue slots of one EWAInit iteration of one shot of `code`."""
+    """Itemised FP32 issue slots of one EWAInit iteration of one shot of `code`."""
     import numpy as np
     lab = code.labels()
     E = int((lab != 0).sum())
@@ -71,11 +84,12 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 Z_FAMILY = 2.8376
 
 # Large codes with HBM-resident messages: planar d=31 and toric L=32 at p = 0.10,
-# 2^18 shots each, EWAInit-BP alpha 0.5 with iter_max 200, structure-of-arrays kernel.
-LARGE_CODES = [("planar", 31), ("toric", 32)]
-LARGE_P = 0.10
-LARGE_SHOTS = 1 << 18
-LARGE_MAX_ITER = 200
+# 2^18 shots each, EWAInit-BP (chosen discount) with iter_max 200, structure-of-arrays kernel.
+LARGE_CODES = list(configs.CONFIG5_CODES)
+LARGE_P = configs.CONFIG5["p"]
+LARGE_SHOTS = configs.CONFIG5["shots"]
+LARGE_MAX_ITER = configs.CONFIG5["max_iter"]
+LARGE_ALPHA = configs.alpha(5, "ewainit")
 SOA_ITER_BLOCK = 24   # the library's default iterations per SOA launch
 HBM_PEAK = 8.0e12   # bytes/s
 
@@ -98,12 +112,24 @@ def measured_traffic(kernel):
     return nbytes if h.hexdigest()[:16] == sha else None
 
 
+def algorithmic_bytes(E, N):
+    """Algorithmic HBM bytes of one EWAInit iteration of one shot with the state in HBM:
+    the iteration state read and written once, every message (4 B per edge) and the
+    posterior triple (12 B per qubit): 8 E + 24 N."""
+    return 8 * E + 24 * N
+
+
+def two_phase_bytes(E, N):
+    """Bytes of a decoder that writes the check-to-qubit messages to HBM between its
+    check and qubit phases: 16 E + 24 N (bounds its algorithmic fraction)."""
+    return 16 * E + 24 * N
+
+
 def soa_bytes_per_shot_iteration(E, N, M):
-    """Algorithmic HBM bytes of one EWAInit iteration of one shot in the SOA kernel:
-    every message read and written on the check side and again on the qubit side
-    (16 E), the posterior Q^{(t-1)} read and Q^{(t)} written (24 N), one decision
-    byte written per qubit (N) and read per edge by the syndrome test (E), and the
-    syndrome bits read by the check pass and the test (8 ceil(M / 32))."""
+    """HBM bytes the SOA kernel's own design moves per shot-iteration: every message read
+    and written by the check pass and by the qubit pass (16 E), the posterior read and
+    written (24 N), one decision byte written per qubit (N) and read per edge by the
+    syndrome test (E), the syndrome words read twice (8 ceil(M / 32))."""
     return 17 * E + 25 * N + 8 * ((M + 31) // 32)
 
 
@@ -128,6 +154,7 @@ def main():
     ap.add_argument("--no-biased", action="store_true", help="skip the biased-noise XZZX curves")
     ap.add_argument("--no-serial", action="store_true", help="skip the serial-versus-flooding comparison")
     ap.add_argument("--no-qldpc", action="store_true", help="skip the bivariate bicycle and Chamon codes")
+    ap.add_argument("--no-config2", action="store_true", help="skip the toric L=8 error-rate sweep")
     ap.add_argument("--only-large", action="store_true", help="run only the large-code (SOA) measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
@@ -223,6 +250,7 @@ def main():
     edge_updates = 0
     iters_total = 0
     slots = 0.0
+    alg_slots = 0.0
     ler = {}
     fails = {}
     for it, o in zip(items, batch.outs):
@@ -230,11 +258,13 @@ def main():
         iters_total += s
         edge_updates += s * it["code"].nnz
         slots += s * it["slots"]
+        alg_slots += s * algorithmic_slots(it["code"].nnz, it["code"].n)
         c = it["counts"].cpu().numpy()
         fails[it["code"].name] = (int(c[1] + c[2]), it["shots"])
         ler[it["code"].name] = round(float(c[1] + c[2]) / it["shots"], 6)
     eups = edge_updates / (dec_ms / 1e3)
-    achieved = slots / (dec_ms / 1e3)
+    achieved = alg_slots / (dec_ms / 1e3)
+    achieved_itemised = slots / (dec_ms / 1e3)
     log(f"step {ms:.2f} ms, decode {dec_ms:.2f} ms, {eups:.3e} edge-updates/s, avg iters {iters_total / total_shots:.2f}")
 
     out = {
@@ -243,15 +273,18 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "mixed batch: planar d{5,7,9,11,13}, toric L{6,10,14}, XZZX L{5,9,13}, "
-                               "depolarizing p=0.08, 2^18 shots x 1:2:4 per size tier, EWAInit-BP alpha=0.5, "
+                               f"depolarizing p=0.08, 2^18 shots x 1:2:4 per size tier, EWAInit-BP alpha={ALPHA}, "
                                "iter_max 100, sample + one persistent decode launch + bookkeeping per step",
                    "shots_per_step": total_shots, "codes": len(items), "shot_scale": args.scale,
                    "lane_mapping": [list(x) if isinstance(x, (list, tuple)) else [int(x), 0] for x in lanes]},
         "decode_ms": dec_ms, "edge_updates_per_s": eups, "avg_iters": iters_total / total_shots,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic("decode_lds_kernel"),
-                     "kernel": "decode_lds_kernel", "slots_per_edge_update": slots / edge_updates,
-                     "trans_slots": TRANS_SLOTS},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "T FP32 issue slots/s", "frac": achieved / PEAK_SLOTS,
+                     "traffic": measured_traffic("decode_lds_kernel"),
+                     "kernel": "decode_lds_kernel", "slots_per_edge_update": alg_slots / edge_updates,
+                     "trans_slots": TRANS_SLOTS,
+                     "itemised": {"slots_per_edge_update": slots / edge_updates,
+                                  "achieved": achieved_itemised / 1e12, "frac": achieved_itemised / PEAK_SLOTS}},
         "ler": ler,
     }
 
@@ -365,6 +398,8 @@ def main():
     if not args.no_unrolled:
         out["unrolled"] = run_unrolled(torch, qecgen, P, dev)
 
+    if not args.no_config2:
+        out["toric_sweep"] = run_config2(torch, qecgen, P, dev)
     if not args.no_aewa:
         out["aewa"] = run_aewa(torch, qecgen, P, dev)
     if not args.no_biased:
@@ -381,6 +416,81 @@ def main():
 
     out["wall_s"] = wall
     print(json.dumps(out), flush=True)
+
+
+def wilson_ci(k, n, z=1.959963984540054):
+    """Wilson score interval of a binomial proportion k / n."""
+    if n == 0:
+        return (0.0, 1.0)
+    ph = k / n
+    den = 1 + z * z / n
+    ctr = (ph + z * z / (2 * n)) / den
+    half = z * (ph * (1 - ph) / n + z * z / (4 * n * n)) ** 0.5 / den
+    return (max(0.0, ctr - half), min(1.0, ctr + half))
+
+
+def _crossing(ps, a, b):
+    """Error rate where curve b - a changes sign (linear interpolation), or None."""
+    for j in range(len(ps) - 1):
+        d0, d1 = b[j] - a[j], b[j + 1] - a[j + 1]
+        if d0 < 0 <= d1 or d0 <= 0 < d1:
+            return ps[j] + (ps[j + 1] - ps[j]) * (-d0) / (d1 - d0)
+    return None
+
+
+def run_config2(torch, qecgen, P, dev):
+    """Toric L=8 sweep of section IV-B: p = 0.02 .. 0.16 in 8 steps, 2^20 shots per point,
+    Momentum-BP (gamma 0), AdaGrad-BP (alpha 5) and EWAInit-BP with the chosen discounts,
+    iter_max 100: decode throughput, edge updates/s, iterations and LER with its Wilson
+    95% interval per point.  EWAInit also on toric L=4 and 6 for the curves' crossing
+    (the paper reads about 13.6% for L = 4, 6, 8 under parallel scheduling)."""
+    c2 = configs.CONFIG2
+    shots = c2["shots"]
+    ps = list(c2["p"])
+    rows = []
+    curves = {}
+    for L in (8, 6, 4):
+        code = qecgen.toric(L)
+        g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
+        variants = ("momentum", "adagrad", "ewainit") if L == 8 else ("ewainit",)
+        for variant in variants:
+            alpha = configs.alpha(2, variant)
+            prm = P.Params(variant=variant, alpha=alpha, gamma=configs.MOMENTUM_GAMMA, max_iter=c2["max_iter"])
+            lers = []
+            for j, p in enumerate(ps):
+                seed = qecgen.config_seed(2, 0, j) if L == 8 else qecgen.config_seed(2, L, j)
+                err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=seed)
+                pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p), device=dev)
+                P.decode(g, prm, pr, syn[:4096])
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                r = P.decode(g, prm, pr, syn)
+                b.record()
+                _, cnt = P.bookkeep(g, err, r["est"])
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b)
+                it_sum = int(r["iters"].to(torch.int64).sum())
+                fails = int(cnt[1] + cnt[2])
+                lo, hi = wilson_ci(fails, shots)
+                lers.append(fails / shots)
+                rows.append({"L": L, "variant": variant, "alpha": alpha, "p": p, "decode_ms": ms,
+                             "syndromes_per_s": shots / (ms / 1e3), "edge_updates_per_s": it_sum * g.nnz / (ms / 1e3),
+                             "avg_iters": it_sum / shots, "converged": float(r["conv"].float().mean()),
+                             "ler": fails / shots, "ler_ci95": [lo, hi]})
+                del r, err, syn
+            curves[(L, variant)] = lers
+    cross = {f"L{a}_L8": _crossing(ps, curves[(a, "ewainit")], curves[(8, "ewainit")]) for a in (4, 6)}
+    l8 = [r for r in rows if r["L"] == 8]
+    tot_ms = sum(r["decode_ms"] for r in l8)
+    log("config2 toric L=8: " + ", ".join(f"{r['variant'][:3]} p{r['p']}: {r['syndromes_per_s'] / 1e6:.0f}M/s "
+                                           f"LER {r['ler']:.4f}" for r in l8 if r["p"] in (0.02, 0.08, 0.16)))
+    log(f"config2 EWAInit crossings {cross} (paper: about 0.136)")
+    return {"workload": "toric L=8, depolarizing p = 0.02..0.16 (8 points), 2^20 shots per point, Momentum-BP "
+                        f"(alpha {configs.alpha(2, 'momentum')}, gamma 0), AdaGrad-BP (alpha 5), EWAInit-BP "
+                        f"(alpha {configs.alpha(2, 'ewainit')}), iter_max 100; EWAInit also on toric L=4, 6",
+            "rows": rows, "syndromes_per_s_l8": len(l8) * shots / (tot_ms / 1e3),
+            "ewainit_crossing": cross, "paper_crossing": 0.136}
 
 
 # Table II of the paper (runtime per decode on planar codes, hardware not stated):
@@ -404,7 +514,7 @@ def run_aewa(torch, qecgen, P, dev):
             g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
             pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p), device=dev)
             err, syn = P.sample(g, shots, thr, seed=qecgen.config_seed(6, i, int(p * 100)))
-            for name, prm in (("ewainit", P.Params(variant="ewainit", alpha=ALPHA, max_iter=100)),
+            for name, prm in (("ewainit", P.Params(variant="ewainit", alpha=ALPHA_EXTRA, max_iter=100)),
                               ("aewa", P.Params(variant="aewa", alpha=1.0, alpha_last=0.0, alpha_steps=11,
                                                 max_iter=100))):
                 P.decode(g, prm, pr, syn[:1024])
@@ -429,7 +539,7 @@ def run_aewa(torch, qecgen, P, dev):
 
 
 def run_serial(torch, qecgen, P, dev):
-    """Serial (Algorithm 1) against flooding (Algorithm 2) EWAInit, alpha 0.5, iter_max 100, on
+    """Serial (Algorithm 1) against flooding (Algorithm 2) EWAInit (the toric sweep's discount), iter_max 100, on
     toric L=4, 6, 8 with 2^16 shots at p = 0.06 ... 0.16: LER, iterations and throughput (the
     paper reads the serial crossing at about 15%, the flooding one at about 13.6%)."""
     shots = 1 << 16
@@ -443,7 +553,7 @@ def run_serial(torch, qecgen, P, dev):
             err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=qecgen.config_seed(8, i, j))
             row = {"L": L, "p": p}
             for name, serial in (("flooding", False), ("serial", True)):
-                prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=100, serial=serial)
+                prm = P.Params(variant="ewainit", alpha=configs.alpha(2, "ewainit"), max_iter=100, serial=serial)
                 P.decode(g, prm, pr, syn[:512])
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
@@ -457,7 +567,8 @@ def run_serial(torch, qecgen, P, dev):
             rows.append(row)
     log("serial vs flooding: " + ", ".join(f"L{r['L']} p{r['p']}: {r['serial']['ler']:.4f}/{r['flooding']['ler']:.4f}"
                                             for r in rows if r["p"] == 0.14))
-    return {"workload": "toric L=4, 6, 8, 2^16 shots, EWAInit alpha 0.5, iter_max 100, serial vs flooding",
+    return {"workload": f"toric L=4, 6, 8, 2^16 shots, EWAInit alpha {configs.alpha(2, 'ewainit')}, iter_max 100, "
+                        "serial vs flooding",
             "rows": rows}
 
 
@@ -467,7 +578,7 @@ def run_biased(torch, qecgen, P, dev):
     paper reads about 10% for EWAInit under parallel scheduling)."""
     shots = 1 << 16
     ps = (0.06, 0.08, 0.10, 0.12, 0.14, 0.16, 0.18, 0.20)
-    prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=100)
+    prm = P.Params(variant="ewainit", alpha=ALPHA_EXTRA, max_iter=100)
     ler = {}
     for i, L in enumerate((5, 7, 9)):
         code = qecgen.xzzx(L)
@@ -503,7 +614,7 @@ def run_qldpc(torch, qecgen, P, dev):
         code = qecgen.make(fam, size)
         g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
         row = {"code": code.name, "n": code.n, "k": code.k, "p": list(ps)}
-        for variant, alpha in (("ewainit", ALPHA), ("bp", 1.0), ("aewa", 1.0)):
+        for variant, alpha in (("ewainit", ALPHA_EXTRA), ("bp", 1.0), ("aewa", 1.0)):
             prm = P.Params(variant=variant, alpha=alpha, max_iter=100,
                            **(dict(alpha_last=0.0, alpha_steps=11) if variant == "aewa" else {}))
             lers, rates = [], []
@@ -548,7 +659,7 @@ def run_unrolled(torch, qecgen, P, dev):
     T, K, shots, p = 32, 8, 1 << 16, 0.06
     g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
     err, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=qecgen.config_seed(4, 0, 0))
-    alpha = torch.full((T,), ALPHA, dtype=torch.float32, device=dev, requires_grad=True)
+    alpha = torch.full((T,), ALPHA_EXTRA, dtype=torch.float32, device=dev, requires_grad=True)
     prior = P.prior_llr(qecgen.depolarizing_probs(code.n, p), device=dev).clone().requires_grad_(True)
     times = []
     for rep in range(3):
@@ -578,13 +689,13 @@ def run_unrolled(torch, qecgen, P, dev):
 def run_large(torch, qecgen, P, dev):
     """Decode 2^18 shots of each large code with the SOA kernel; HBM roofline."""
     thr = qecgen.thresholds(LARGE_P / 3, LARGE_P / 3, LARGE_P / 3)
-    prm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=LARGE_MAX_ITER)
-    warm = P.Params(variant="ewainit", alpha=ALPHA, max_iter=2)
+    prm = P.Params(variant="ewainit", alpha=LARGE_ALPHA, max_iter=LARGE_MAX_ITER)
+    warm = P.Params(variant="ewainit", alpha=LARGE_ALPHA, max_iter=2)
     launches = 0
-    res = {"workload": "planar d=31 and toric L=32, depolarizing p=0.10, 2^18 shots each, EWAInit-BP "
-                       "alpha=0.5, iter_max 200, messages in HBM (structure-of-arrays kernel)",
+    res = {"workload": f"planar d=31 and toric L=32, depolarizing p=0.10, 2^18 shots each, EWAInit-BP "
+                       f"alpha={LARGE_ALPHA}, iter_max 200, messages in HBM (structure-of-arrays kernel)",
            "codes": {}}
-    tot_ms = tot_bytes = tot_shots = tot_eu = 0.0
+    tot_ms = tot_bytes = tot_shots = tot_eu = tot_design = 0.0
     for i, (fam, size) in enumerate(LARGE_CODES):
         code = qecgen.make(fam, size)
         g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
@@ -602,17 +713,23 @@ def run_large(torch, qecgen, P, dev):
         ms = a.elapsed_time(b)
         _, counts = P.bookkeep(g, err, r["est"])
         it_sum = int(r["iters"].to(torch.int64).sum())
-        nbytes = it_sum * soa_bytes_per_shot_iteration(g.nnz, g.n, g.m)
+        nbytes = it_sum * algorithmic_bytes(g.nnz, g.n)
+        design = it_sum * soa_bytes_per_shot_iteration(g.nnz, g.n, g.m)
         c = counts.cpu().numpy()
         res["codes"][code.name] = {
             "decode_ms": ms, "syndromes_per_s": LARGE_SHOTS / (ms / 1e3),
             "edge_updates_per_s": it_sum * g.nnz / (ms / 1e3), "avg_iters": it_sum / LARGE_SHOTS,
             "converged": float(r["conv"].float().mean()), "ler": float(c[1] + c[2]) / LARGE_SHOTS,
-            "hbm_gb_s": nbytes / (ms / 1e3) / 1e9,
-            "bytes_per_shot_iteration": soa_bytes_per_shot_iteration(g.nnz, g.n, g.m)}
-        log(f"{code.name}: decode {ms:.1f} ms, {nbytes / (ms / 1e3) / 1e9:.0f} GB/s algorithmic")
+            "algorithmic_gb_s": nbytes / (ms / 1e3) / 1e9,
+            "algorithmic_bytes_per_shot_iteration": algorithmic_bytes(g.nnz, g.n),
+            "kernel_bytes_per_shot_iteration": soa_bytes_per_shot_iteration(g.nnz, g.n, g.m),
+            "kernel_gb_s": design / (ms / 1e3) / 1e9,
+            "two_phase_cap": algorithmic_bytes(g.nnz, g.n) / two_phase_bytes(g.nnz, g.n)}
+        log(f"{code.name}: decode {ms:.1f} ms, {nbytes / (ms / 1e3) / 1e9:.0f} GB/s algorithmic, "
+            f"{design / (ms / 1e3) / 1e9:.0f} GB/s of the kernel's own design")
         tot_ms += ms
         tot_bytes += nbytes
+        tot_design += design
         tot_shots += LARGE_SHOTS
         tot_eu += it_sum * g.nnz
         launches += -(-LARGE_MAX_ITER // SOA_ITER_BLOCK)
@@ -624,7 +741,9 @@ def run_large(torch, qecgen, P, dev):
     res["roofline"] = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK, "traffic": measured_traffic("decode_soa_kernel"),
                        "kernel": "decode_soa_kernel", "launches": launches,
-                       "algorithmic_bytes_per_launch": tot_bytes / launches}
+                       "algorithmic_bytes_per_launch": tot_bytes / launches,
+                       "kernel_design_bytes_per_launch": tot_design / launches,
+                       "two_phase_cap": {k: v["two_phase_cap"] for k, v in res["codes"].items()}}
     return res
 
 

@@ -158,6 +158,19 @@ int bp4_sample(const bp4_graph *g, const void *dev_graph, int64_t shots, int64_t
                const uint32_t thr[3], uint64_t seed, uint64_t stream_id,
                uint8_t *err, uint8_t *synd, void *stream);
 
+/* Prior LLRs of the decoder input (section II-B1): for each qubit v with
+ * error probabilities probs dev double [n][3] = (p_X, p_Y, p_Z),
+ *     prior dev float [n][3]:  Pi_{v,W} = ln(p_v^I / p_v^W),  p_v^I = 1 - p_X - p_Y - p_Z,
+ * evaluated in double precision and rounded to float.  (The paper prints
+ * ln((1 - p)/p) for the probability vector; lambda is a commutation LLR only
+ * if e^{-Pi_W} = p_W / p_I, which fixes this reading.)  The probabilities are
+ * device data, so the host cannot check them: an entry with p_W <= 0,
+ * p_I <= 0 or a non-finite probability gets a NaN prior, and a decode from
+ * NaN priors reports its shots as not converged.  The Python binding checks
+ * the probabilities before the call.  Errors: EINVAL (n outside [1, 16383],
+ * NULL), EHIP. */
+int bp4_prior_llr(int32_t n, const double *probs, float *prior, void *stream);
+
 /* Decode `shots` syndromes (synd dev [shots][m]) with prior LLRs
  * prior_llr dev [n][3], Pi_{v,W} = ln(p_v^I / p_v^W) (section II-B1,
  * Algorithm 2 input), by flooding-schedule BP of the chosen variant.  Per
@@ -296,42 +309,46 @@ int bp4_bookkeep(const bp4_graph *g, const void *dev_graph, int64_t shots,
                  const uint8_t *err, const uint8_t *est, uint8_t *fail, int64_t *counts,
                  void *stream);
 
-/* ---- Differentiable unrolled EWAInit-BP ------------------------------------
- * EWAInit-BP (section III, eq. EWAInit; Algorithm 2 without the early stop)
- * run for exactly T iterations with a discount alpha_t per iteration
- * (Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)})
- * and learnable priors Pi^{(0)}; messages clamped to [-llr_clamp, llr_clamp]
- * as in bp4_decode.  Loss: the mean over shots and qubits of
+/* ---- Differentiable unrolled BP -----------------------------------------
+ * A variant of section III run for exactly T iterations (Algorithm 2 without
+ * the early stop) with learnable per-iteration parameters param_t dev float
+ * [T][k] and learnable priors Pi^{(0)} dev float [n][3]; messages clamped to
+ * [-llr_clamp, llr_clamp] as in bp4_decode.  Built for variant BP4_EWAINIT,
+ * k = 1: param_t[t-1] is the discount alpha_t of iteration t (Pi^{(1)} =
+ * Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}, eq.
+ * EWAInit; entry 0 is unused).  Every other variant answers EUNSUPPORTED.
+ * Loss: the mean over shots and qubits of
  * ln(1 + sum_W e^{-Q_W^{(T)}}) + Q_{e_v}^{(T)} (Q_I = 0), the negative log of
  * the GF(4) marginal of the sampled error e_v.  The adjoint returns its
- * gradient with respect to alpha and Pi^{(0)}.  The forward keeps the state
+ * gradient with respect to param_t and Pi^{(0)}.  The forward keeps the state
  * (messages and posteriors) every ckpt_every iterations in `saved`; the
  * backward recomputes each segment from its checkpoint.
  *
- * Device buffers (caller-allocated): alpha float [T] (entry t-1 is alpha_t;
- * entry 0 is unused), prior float [n][3] (X, Y, Z), synd uint8 [shots][m],
+ * Device buffers (caller-allocated): param_t, prior, synd uint8 [shots][m],
  * err uint8 [shots][n] (Pauli codes), saved and ws of the sizes below.
  * Errors: EINVAL (T < 1, ckpt_every < 1, shots < 1, llr_clamp not > 0, NULL
- * pointers), EWORKSPACE (saved or ws too small), EHIP. */
+ * pointers, variant outside bp4_variant), EUNSUPPORTED (a variant other than
+ * EWAInit, a wide graph), EWORKSPACE (saved or ws too small), EHIP. */
 
 /* Bytes of the checkpoint buffer and of the workspace for these sizes. */
-int bp4_unrolled_sizes(const bp4_graph *g, int32_t T, int32_t ckpt_every, int64_t shots,
+int bp4_unrolled_sizes(const bp4_graph *g, int32_t variant, int32_t T, int32_t ckpt_every, int64_t shots,
                        size_t *saved_bytes, size_t *ws_bytes);
 
 /* Forward: writes loss dev double [1] and, if q_out is not NULL, the final
  * posteriors Q^{(T)} dev float [shots][n][3]; fills `saved`. */
-int bp4_unrolled_forward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every,
-                         float llr_clamp, int64_t shots, const float *alpha, const float *prior,
+int bp4_unrolled_forward(const bp4_graph *g, const void *dev_graph, int32_t variant, int32_t T, int32_t ckpt_every,
+                         float llr_clamp, int64_t shots, const float *param_t, const float *prior,
                          const uint8_t *synd, const uint8_t *err, double *loss, float *q_out,
                          void *saved, size_t saved_bytes, void *ws, size_t ws_bytes, void *stream);
 
 /* Backward: with `saved` from the forward of the same inputs, writes
- * dalpha dev double [T] = dloss * dL/dalpha_t (entry 0 is 0) and dprior dev
- * double [n][3] = dloss * dL/dPi^{(0)}; dloss is a dev float scalar (NULL: 1). */
-int bp4_unrolled_backward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every,
-                          float llr_clamp, int64_t shots, const float *alpha, const float *prior,
+ * dparam_t dev double [T][k] = dloss * dL/dparam_t (EWAInit: entry 0 is 0) and
+ * dprior dev double [n][3] = dloss * dL/dPi^{(0)}; dloss is a dev float
+ * scalar (NULL: 1). */
+int bp4_unrolled_backward(const bp4_graph *g, const void *dev_graph, int32_t variant, int32_t T, int32_t ckpt_every,
+                          float llr_clamp, int64_t shots, const float *param_t, const float *prior,
                           const uint8_t *synd, const uint8_t *err, const float *dloss,
-                          const void *saved, size_t saved_bytes, double *dalpha, double *dprior,
+                          const void *saved, size_t saved_bytes, double *dparam_t, double *dprior,
                           void *ws, size_t ws_bytes, void *stream);
 
 /* Message of the calling thread's last non-OK return. */

@@ -78,14 +78,15 @@ SIGNATURES = {
                                                  ctypes.POINTER(_sz)]),
     "bp4_decode_plain": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(Params), ctypes.c_int64, _vp, _vp, _vp,
                                         _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_int32)]),
-    "bp4_unrolled_sizes": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+    "bp4_prior_llr": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _vp]),
+    "bp4_unrolled_sizes": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                           ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
-    "bp4_unrolled_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
-                                            ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp, _sz,
-                                            _vp]),
-    "bp4_unrolled_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
-                                             ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp, _vp, _vp,
-                                             _sz, _vp]),
+    "bp4_unrolled_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_float, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                                            _vp, _sz, _vp]),
+    "bp4_unrolled_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_float, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp,
+                                             _vp, _vp, _sz, _vp]),
     "bp4_last_error": (ctypes.c_char_p, []),
     "bp4_version": (ctypes.c_char_p, []),
 }

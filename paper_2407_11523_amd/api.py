@@ -132,10 +132,20 @@ class Graph:
 
 
 def prior_llr(probs, device=None) -> torch.Tensor:
-    """Pi_{v,W} = ln(p^I / p^W) (section II-B1) as a float32 [n][3] device tensor."""
-    probs = np.asarray(probs, dtype=np.float64)
-    pi = np.log(1.0 - probs.sum(axis=1, keepdims=True)) - np.log(probs)
-    return torch.as_tensor(pi.astype(np.float32), device=device if device is not None else "cuda")
+    """Pi_{v,W} = ln(p^I / p^W) (section II-B1) as a float32 [n][3] device tensor,
+    computed by the library's kernel (bp4_prior_llr) from probabilities (p_X, p_Y, p_Z)."""
+    probs = np.ascontiguousarray(probs, dtype=np.float64)
+    if probs.ndim != 2 or probs.shape[1] != 3 or probs.shape[0] < 1:
+        raise BP4Error(-1, "probs must be an [n][3] array of (p_X, p_Y, p_Z)")
+    if not np.all(np.isfinite(probs)) or np.any(probs <= 0.0) or np.any(probs.sum(axis=1) >= 1.0):
+        raise BP4Error(-1, "probs must be finite, positive, and sum to less than 1 per qubit")
+    dev = torch.device(device if device is not None else "cuda")
+    p_dev = torch.as_tensor(probs, device=dev)
+    out = torch.empty((probs.shape[0], 3), dtype=torch.float32, device=dev)
+    # p_dev is released after the launch, on the stream the kernel runs on: torch's
+    # caching allocator hands the block out again only in that stream's order
+    check(load().bp4_prior_llr(int(probs.shape[0]), _ptr(p_dev), _ptr(out), _stream(dev)))
+    return out
 
 
 def sample(g: Graph, shots: int, thr, seed: int, stream_id: int = 0, shot0: int = 0,
@@ -331,12 +341,33 @@ class Captured:
 # Differentiable unrolled EWAInit-BP
 # ---------------------------------------------------------------------------
 
-def unrolled_sizes(g: Graph, T: int, ckpt_every: int, shots: int):
+def unrolled_sizes(g: Graph, T: int, ckpt_every: int, shots: int, variant: str = "ewainit"):
     """(checkpoint bytes, workspace bytes) of the unrolled forward/backward."""
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
-    check(g._lib.bp4_unrolled_sizes(g.handle, int(T), int(ckpt_every), int(shots), ctypes.byref(a),
-                                    ctypes.byref(b)))
+    check(g._lib.bp4_unrolled_sizes(g.handle, VARIANTS[variant], int(T), int(ckpt_every), int(shots),
+                                    ctypes.byref(a), ctypes.byref(b)))
     return int(a.value), int(b.value)
+
+
+def _unrolled_inputs(g: Graph, alpha, prior, synd, err, T: int):
+    """Validated, contiguous device inputs of the unrolled kernels: alpha float32 [T],
+    prior float32 [n, 3], synd uint8 [shots, m], err uint8 [shots, n] on the graph's device."""
+    dev = g.dev.device
+    for name, t in (("alpha", alpha), ("prior", prior), ("synd", synd), ("err", err)):
+        if not isinstance(t, torch.Tensor) or t.device != dev:
+            raise BP4Error(-1, f"{name} must be a tensor on {dev}")
+    if synd.dtype != torch.uint8 or err.dtype != torch.uint8:
+        raise BP4Error(-1, "synd and err must be uint8 tensors")
+    if synd.dim() != 2 or synd.shape[1] != g.m or synd.shape[0] < 1:
+        raise BP4Error(-1, "synd must be [shots, m] with shots >= 1")
+    if tuple(err.shape) != (synd.shape[0], g.n):
+        raise BP4Error(-1, "err must be [shots, n]")
+    if tuple(alpha.shape) != (int(T),) or tuple(prior.shape) != (g.n, 3):
+        raise BP4Error(-1, "alpha must be [T] and prior [n, 3]")
+    if not (alpha.is_floating_point() and prior.is_floating_point()):
+        raise BP4Error(-1, "alpha and prior must be floating point")
+    return (alpha.detach().to(torch.float32).contiguous(), prior.detach().to(torch.float32).contiguous(),
+            synd.contiguous(), err.contiguous())
 
 
 class UnrolledEWAInit(torch.autograd.Function):
@@ -349,22 +380,18 @@ class UnrolledEWAInit(torch.autograd.Function):
     @staticmethod
     def forward(ctx, alpha, prior, g, synd, err, T, ckpt_every, clamp):
         dev = synd.device
-        alpha = alpha.detach().to(torch.float32).contiguous()
-        prior = prior.detach().to(torch.float32).contiguous()
-        if alpha.shape != (T,) or prior.shape != (g.n, 3):
-            raise BP4Error(-1, "alpha must be [T] and prior [n, 3]")
-        synd = synd.to(torch.uint8).contiguous()
-        err = err.to(torch.uint8).contiguous()
-        shots = synd.shape[0]
+        a32, p32, syn, er = _unrolled_inputs(g, alpha, prior, synd, err, T)
+        shots = syn.shape[0]
         sb, wb = unrolled_sizes(g, T, ckpt_every, shots)
         saved = torch.empty(sb, dtype=torch.uint8, device=dev)
         ws = torch.empty(wb, dtype=torch.uint8, device=dev)
         loss = torch.empty(1, dtype=torch.float64, device=dev)
-        check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), int(T), int(ckpt_every), float(clamp), shots,
-                                          _ptr(alpha), _ptr(prior), _ptr(synd), _ptr(err), _ptr(loss),
-                                          ctypes.c_void_p(0), _ptr(saved), sb, _ptr(ws), wb, _stream(dev)))
+        check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), VARIANTS["ewainit"], int(T), int(ckpt_every),
+                                          float(clamp), shots, _ptr(a32), _ptr(p32), _ptr(syn), _ptr(er),
+                                          _ptr(loss), ctypes.c_void_p(0), _ptr(saved), sb, _ptr(ws), wb,
+                                          _stream(dev)))
         ctx.g, ctx.T, ctx.K, ctx.clamp = g, int(T), int(ckpt_every), float(clamp)
-        ctx.bufs = (alpha, prior, synd, err, saved, ws)
+        ctx.bufs = (a32, p32, syn, er, saved, ws)
         ctx.dtypes = (alpha.dtype, prior.dtype)
         return loss[0]
 
@@ -376,8 +403,8 @@ class UnrolledEWAInit(torch.autograd.Function):
         dl = dloss.detach().to(device=dev, dtype=torch.float32).reshape(1).contiguous()
         dalpha = torch.empty(ctx.T, dtype=torch.float64, device=dev)
         dprior = torch.empty(g.n, 3, dtype=torch.float64, device=dev)
-        check(g._lib.bp4_unrolled_backward(g.handle, _ptr(g.dev), ctx.T, ctx.K, ctx.clamp, synd.shape[0],
-                                           _ptr(alpha), _ptr(prior), _ptr(synd), _ptr(err), _ptr(dl),
+        check(g._lib.bp4_unrolled_backward(g.handle, _ptr(g.dev), VARIANTS["ewainit"], ctx.T, ctx.K, ctx.clamp,
+                                           synd.shape[0], _ptr(alpha), _ptr(prior), _ptr(synd), _ptr(err), _ptr(dl),
                                            _ptr(saved), saved.numel(), _ptr(dalpha), _ptr(dprior), _ptr(ws),
                                            ws.numel(), _stream(dev)))
         ctx.bufs = None
@@ -394,15 +421,15 @@ def unrolled_forward(g: Graph, alpha: torch.Tensor, prior: torch.Tensor, synd: t
                      T: int, ckpt_every: int = 8, clamp: float = 30.0, want_q: bool = False):
     """Forward only: (loss float64 [1], Q^{(T)} [shots, n, 3] or None)."""
     dev = synd.device
-    shots = synd.shape[0]
+    a32, p32, syn, er = _unrolled_inputs(g, alpha, prior, synd, err, T)
+    shots = syn.shape[0]
     sb, wb = unrolled_sizes(g, T, ckpt_every, shots)
     saved = torch.empty(sb, dtype=torch.uint8, device=dev)
     ws = torch.empty(wb, dtype=torch.uint8, device=dev)
     loss = torch.empty(1, dtype=torch.float64, device=dev)
     q = torch.empty(shots, g.n, 3, dtype=torch.float32, device=dev) if want_q else None
-    alpha = alpha.detach().to(torch.float32).contiguous()
-    prior = prior.detach().to(torch.float32).contiguous()
-    check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), int(T), int(ckpt_every), float(clamp), shots,
-                                      _ptr(alpha), _ptr(prior), _ptr(synd.contiguous()), _ptr(err.contiguous()),
-                                      _ptr(loss), _ptr(q), _ptr(saved), sb, _ptr(ws), wb, _stream(dev)))
+    check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), VARIANTS["ewainit"], int(T), int(ckpt_every),
+                                      float(clamp), shots, _ptr(a32), _ptr(p32), _ptr(syn), _ptr(er), _ptr(loss),
+                                      _ptr(q), _ptr(saved), sb, _ptr(ws), wb, _stream(dev)))
+    # the contiguous copies are named, so none is freed (and reused) before the launch
     return loss, q

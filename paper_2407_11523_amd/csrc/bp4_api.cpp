@@ -44,6 +44,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // check order) so that a qubit's slots are contiguous.
 struct bp4_graph {
     int32_t m = 0, n = 0, nnz = 0, max_cdeg = 0, max_vdeg = 0, nlog = 0, with_y = 0;
+    int32_t css22 = 0;                           // X/Z labels only, <= 2 of each per qubit
     std::vector<int32_t> canon_chk, canon_var;   // canonical edge -> check, qubit
     int32_t cstride = kMaxCheckDeg;              // edge words per check
     std::vector<uint32_t> cedge;                 // [m][cstride]
@@ -98,23 +99,37 @@ struct bp4_graph {
 
 extern "C" {
 
-static int unrolled_check(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t K, float clamp,
-                          int64_t shots, const float *alpha, const float *prior, const uint8_t *synd,
+// Variants with a built unrolled forward and adjoint, and their per-iteration
+// parameter count k of param_t [T][k].
+static int unrolled_variant(int32_t variant, const char *who)
+{
+    if (variant < BP4_BP || variant > BP4_AEWA) return fail(BP4_EINVAL, "%s: variant %d is not a bp4_variant", who, variant);
+    if (variant != BP4_EWAINIT)
+        return fail(BP4_EUNSUPPORTED, "%s: the unrolled path is built for EWAInit-BP only (variant %d)", who, variant);
+    return BP4_OK;
+}
+
+static int unrolled_check(const bp4_graph *g, const void *dev_graph, int32_t variant, int32_t T, int32_t K, float clamp,
+                          int64_t shots, const float *param_t, const float *prior, const uint8_t *synd,
                           const uint8_t *err)
 {
     if (!g || !dev_graph) return fail(BP4_EINVAL, "unrolled: NULL graph");
+    int rc = unrolled_variant(variant, "unrolled");
+    if (rc) return rc;
     if (g->wide()) return fail(BP4_EUNSUPPORTED, "unrolled: graphs with degrees above 4 are not supported");
     if (T < 1 || K < 1) return fail(BP4_EINVAL, "unrolled: T %d and ckpt_every %d must be >= 1", T, K);
     if (!(clamp > 0.0f)) return fail(BP4_EINVAL, "unrolled: llr_clamp must be > 0");
     if (shots < 1 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "unrolled: shots %lld outside [1, 2^31)", (long long)shots);
-    if (!alpha || !prior || !synd || !err) return fail(BP4_EINVAL, "unrolled: NULL input");
+    if (!param_t || !prior || !synd || !err) return fail(BP4_EINVAL, "unrolled: NULL input");
     return BP4_OK;
 }
 
-int bp4_unrolled_sizes(const bp4_graph *g, int32_t T, int32_t ckpt_every, int64_t shots, size_t *saved_bytes,
-                       size_t *ws_bytes)
+int bp4_unrolled_sizes(const bp4_graph *g, int32_t variant, int32_t T, int32_t ckpt_every, int64_t shots,
+                       size_t *saved_bytes, size_t *ws_bytes)
 {
     if (!g || !saved_bytes || !ws_bytes) return fail(BP4_EINVAL, "unrolled_sizes: NULL argument");
+    int rc = unrolled_variant(variant, "unrolled_sizes");
+    if (rc) return rc;
     if (T < 1 || ckpt_every < 1) return fail(BP4_EINVAL, "unrolled_sizes: T and ckpt_every must be >= 1");
     if (shots < 1 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "unrolled_sizes: shots out of range");
     const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
@@ -123,41 +138,50 @@ int bp4_unrolled_sizes(const bp4_graph *g, int32_t T, int32_t ckpt_every, int64_
     return BP4_OK;
 }
 
-int bp4_unrolled_forward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every, float llr_clamp,
-                         int64_t shots, const float *alpha, const float *prior, const uint8_t *synd,
-                         const uint8_t *err, double *loss, float *q_out, void *saved, size_t saved_bytes, void *ws,
-                         size_t ws_bytes, void *stream)
+int bp4_unrolled_forward(const bp4_graph *g, const void *dev_graph, int32_t variant, int32_t T, int32_t ckpt_every,
+                         float llr_clamp, int64_t shots, const float *param_t, const float *prior,
+                         const uint8_t *synd, const uint8_t *err, double *loss, float *q_out, void *saved,
+                         size_t saved_bytes, void *ws, size_t ws_bytes, void *stream)
 {
-    int rc = unrolled_check(g, dev_graph, T, ckpt_every, llr_clamp, shots, alpha, prior, synd, err);
+    int rc = unrolled_check(g, dev_graph, variant, T, ckpt_every, llr_clamp, shots, param_t, prior, synd, err);
     if (rc) return rc;
     if (!loss || !saved || !ws) return fail(BP4_EINVAL, "unrolled_forward: NULL output or buffer");
     const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
     if (saved_bytes < z.saved || ws_bytes < z.ws)
         return fail(BP4_EWORKSPACE, "unrolled_forward: saved %zu < %zu or ws %zu < %zu bytes", saved_bytes, z.saved,
                     ws_bytes, z.ws);
-    hipError_t e = launch_unrolled_forward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, alpha, prior,
-                                           synd, err, loss, q_out, saved, ws, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_unrolled_forward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, param_t,
+                                           prior, synd, err, loss, q_out, saved, ws, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "unrolled_forward: launch");
     return BP4_OK;
 }
 
-int bp4_unrolled_backward(const bp4_graph *g, const void *dev_graph, int32_t T, int32_t ckpt_every,
-                          float llr_clamp, int64_t shots, const float *alpha, const float *prior,
+int bp4_unrolled_backward(const bp4_graph *g, const void *dev_graph, int32_t variant, int32_t T, int32_t ckpt_every,
+                          float llr_clamp, int64_t shots, const float *param_t, const float *prior,
                           const uint8_t *synd, const uint8_t *err, const float *dloss, const void *saved,
-                          size_t saved_bytes, double *dalpha, double *dprior, void *ws, size_t ws_bytes,
+                          size_t saved_bytes, double *dparam_t, double *dprior, void *ws, size_t ws_bytes,
                           void *stream)
 {
-    int rc = unrolled_check(g, dev_graph, T, ckpt_every, llr_clamp, shots, alpha, prior, synd, err);
+    int rc = unrolled_check(g, dev_graph, variant, T, ckpt_every, llr_clamp, shots, param_t, prior, synd, err);
     if (rc) return rc;
-    if (!dalpha || !dprior || !saved || !ws) return fail(BP4_EINVAL, "unrolled_backward: NULL output or buffer");
+    if (!dparam_t || !dprior || !saved || !ws) return fail(BP4_EINVAL, "unrolled_backward: NULL output or buffer");
     const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
     if (saved_bytes < z.saved || ws_bytes < z.ws)
         return fail(BP4_EWORKSPACE, "unrolled_backward: saved %zu < %zu or ws %zu < %zu bytes", saved_bytes,
                     z.saved, ws_bytes, z.ws);
-    hipError_t e = launch_unrolled_backward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, alpha,
-                                            prior, synd, err, dloss, saved, dalpha, dprior, ws,
+    hipError_t e = launch_unrolled_backward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, param_t,
+                                            prior, synd, err, dloss, saved, dparam_t, dprior, ws,
                                             static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "unrolled_backward: launch");
+    return BP4_OK;
+}
+
+int bp4_prior_llr(int32_t n, const double *probs, float *prior, void *stream)
+{
+    if (!probs || !prior) return fail(BP4_EINVAL, "prior_llr: NULL argument");
+    if (n < 1 || n > kMaxVars) return fail(BP4_EINVAL, "prior_llr: n %d outside [1, %d]", n, kMaxVars);
+    hipError_t e = launch_prior_llr(n, probs, prior, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "prior_llr: launch");
     return BP4_OK;
 }
 
@@ -230,6 +254,15 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
     }
     g->vchk.assign(nnz, 0);
     for (long s = 0; s < nnz; ++s) g->vchk[s] = (uint32_t)g->canon_chk[g->vcanon[s]];
+    // X/Z-only graphs with at most two edges of each label per qubit (planar, toric and
+    // XZZX surface codes) take the LDS kernel's two-plus-two message layout
+    if (!g->with_y && g->cstride == kMaxCheckDeg) {
+        std::vector<int32_t> nx(n, 0), nz(n, 0);
+        for (long k = 0; k < nnz; ++k) (lab[k] == 1u ? nx : nz)[g->canon_var[k]]++;
+        g->css22 = 1;
+        for (int v = 0; v < n; ++v)
+            if (nx[v] > 2 || nz[v] > 2) g->css22 = 0;
+    }
     // Serial order (Algorithm 1) as levels: level(v) = 1 + the largest level of an
     // earlier qubit sharing a check with v (0 if none).  Qubits of one level share
     // no check, and every neighbour of v that precedes it in index order sits on a
@@ -467,6 +500,7 @@ void fill_decode_args(DecodeArgs &a, const bp4_graph *g, const void *dev_graph, 
     a.magic_n = (uint32_t)(((1ull << 32) + (uint64_t)g->n - 1) / (uint64_t)g->n);
     a.with_y = g->with_y;
     a.wide = g->wide() ? 1 : 0;
+    a.css22 = g->css22;
 }
 
 // The automatic kernel: SOA when even one shot per workgroup needs more than
@@ -651,6 +685,8 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     args.codes[0].mvc_out = mvc_out;
     args.codes[0].mcv_out = mcv_out;
     args.codes[0].serial = p->serial;
+    // the verification outputs map message slots through the graph's slot order
+    if (q_out || mvc_out) args.codes[0].css22 = 0;
     if ((size_t)lds_floor > max_lds) return fail(BP4_EINVAL, "decode: lds_bytes %d above the device limit", lds_floor);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_zero_u32(args.codes[0].counter, 1, s);
@@ -753,6 +789,18 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
     if (ncodes < 1 || ncodes > BP4_MAX_MIXED_CODES)
         return fail(BP4_EINVAL, "decode_mixed: ncodes %d outside [1, %d]", ncodes, BP4_MAX_MIXED_CODES);
     if (ws_bytes < 256) return fail(BP4_EWORKSPACE, "decode_mixed: workspace %zu < 256 bytes", ws_bytes);
+    return bp4::decode_mixed_with(ncodes, codes, static_cast<unsigned int *>(ws), stream);
+}
+
+}  // extern "C"
+
+// The mixed launch with its per-code shot-queue heads at `counters` (ncodes words,
+// cleared here by a fill kernel before the launch).
+int bp4::decode_mixed_with(int32_t ncodes, const bp4_code_batch *codes, unsigned int *counters, void *stream)
+{
+    if (!codes || !counters) return fail(BP4_EINVAL, "decode_mixed: NULL argument");
+    if (ncodes < 1 || ncodes > BP4_MAX_MIXED_CODES)
+        return fail(BP4_EINVAL, "decode_mixed: ncodes %d outside [1, %d]", ncodes, BP4_MAX_MIXED_CODES);
     for (int i = 0; i < ncodes; ++i) {
         const bp4_code_batch &c = codes[i];
         if (!c.graph || !c.dev_graph) return fail(BP4_EINVAL, "decode_mixed: code %d has a NULL graph", i);
@@ -785,7 +833,6 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
     std::memset(&args, 0, sizeof args);
     args.ncodes = (int32_t)order.size();
     size_t lds = 0;
-    unsigned int *counters = static_cast<unsigned int *>(ws);
     for (size_t k = 0; k < order.size(); ++k) {
         const bp4_code_batch &c = codes[order[k]];
         LaneChoice lc;
@@ -804,6 +851,13 @@ int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size
     if (e != hipSuccess) return hip_fail(e, "decode_mixed: launch");
     return BP4_OK;
 }
+
+int bp4::report_error(int code, const char *what, hipError_t e)
+{
+    return e == hipSuccess ? fail(code, "%s", what) : hip_fail(e, what);
+}
+
+extern "C" {
 
 int bp4_plain_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes)
 {

@@ -143,6 +143,37 @@ __device__ __forceinline__ uint32_t label_word(const uint32_t *s_vl, uint32_t in
     else return info >> 20;
 }
 
+// Two-plus-two layout (graphs with X and Z labels only, at most two of each per
+// qubit): the X-labelled edges of qubit v sit at message positions 0 and 1, the
+// Z-labelled ones at 2 and 3, each group in slot order; an unused position holds 0.
+// Its label sums are two additions and its outputs need no label routing.
+// Position of the qubit's slot j (labels of its slots in the qubit word, bits 20 + 2j).
+__device__ __forceinline__ uint32_t c22_pos(uint32_t info, uint32_t j)
+{
+    const uint32_t l = var_lab(info, (int)j);
+    uint32_t r = 0;
+    for (uint32_t k = 0; k < j; ++k) r += var_lab(info, (int)k) == l ? 1u : 0u;
+    return (l == 2u ? 2u : 0u) + r;
+}
+// The staged qubit word of the two-plus-two layout: bits 20-23 say which of the four
+// positions hold an edge.
+__device__ __forceinline__ uint32_t c22_info(uint32_t info)
+{
+    uint32_t nx = 0, nz = 0;
+    for (uint32_t k = 0; k < var_deg(info); ++k) {
+        const uint32_t l = var_lab(info, (int)k);
+        nx += l == 1u ? 1u : 0u;
+        nz += l == 2u ? 1u : 0u;
+    }
+    const uint32_t mask = (nx >= 1u ? 1u : 0u) | (nx >= 2u ? 2u : 0u) | (nz >= 1u ? 4u : 0u) | (nz >= 2u ? 8u : 0u);
+    return (info & ~(0xFFu << 20)) | (mask << 20);
+}
+// 0 or all ones: position p of a staged two-plus-two qubit word holds an edge
+__device__ __forceinline__ uint32_t c22_keep(uint32_t info, int p)
+{
+    return (uint32_t)__builtin_amdgcn_sbfe((int)info, 20 + p, 1);
+}
+
 // Per-label sums S[lab] of a qubit's incoming messages and of their magnitudes A[lab]
 // over its DV slots (label 0 for unused slots), as label_sums.
 template <int DV>
@@ -178,19 +209,25 @@ __device__ __forceinline__ void label_sums_w(uint32_t labw, const float mc[DV], 
 
 // Initialisation of qubit v (eq. init, Algorithm 2): m^{(0)}_{v->c} =
 // lambda_{H_cv}(Pi^{(0)}_v); Q^{(0)} = Pi^{(0)}; accumulators start at 0.
-template <int VAR, bool W = false>
+template <int VAR, bool W = false, bool C22 = false>
 __device__ __forceinline__ void init_qubit(const uint32_t *s_vi, const uint32_t *s_vl, const float *s_pi, float *msg,
                                            float *qs, float *acc, int v, int n, float C)
 {
     constexpr bool keep_q = VAR != BP4_BP;
     constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
     const uint32_t info = s_vi[v];
-    const uint32_t labw = label_word<W>(s_vl, info, v);
-    const uint32_t deg = var_deg(info);
     const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
     float lam[4];
     qubit_lambdas(p3, var_labels_present(info), lam);
-    for (uint32_t j = 0; j < deg; ++j) msg[v + j * n] = clampf(lam[slot_label(labw, (int)j)], C);
+    if constexpr (C22) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            msg[v + p * n] = __uint_as_float(__float_as_uint(clampf(lam[p < 2 ? 1 : 2], C)) & c22_keep(info, p));
+    } else {
+        const uint32_t labw = label_word<W>(s_vl, info, v);
+        const uint32_t deg = var_deg(info);
+        for (uint32_t j = 0; j < deg; ++j) msg[v + j * n] = clampf(lam[slot_label(labw, (int)j)], C);
+    }
     float st[3], ac[3];
     qubit_state_init(VAR, p3, st, ac);
     if (keep_q)
@@ -269,6 +306,59 @@ __device__ __forceinline__ void qubit_node(const DecodeArgs &a, const uint32_t *
                               [&](uint32_t j, float out) { msg[v + j * n] = out; });
 }
 
+// Flooding qubit step in the two-plus-two layout (X and Z labels only).  Same
+// arithmetic as qubit_update (label sums in slot order, the unused position adding
+// +0), without the verification outputs.
+template <int VAR>
+__device__ __forceinline__ void qubit_node_c22(const DecodeArgs &a, const uint32_t *s_vi, const float *s_pi,
+                                               float *msg, float *qs, float *acc, uint8_t *ehat, int v, int t,
+                                               const VariantParams &vp)
+{
+    constexpr bool keep_q = VAR != BP4_BP;
+    constexpr bool keep_acc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
+    const uint32_t info = s_vi[v];
+    const int n = a.g.n;
+    float mc[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) mc[p] = msg[v + p * n];
+    float S[4], A[4];
+    {
+#pragma clang fp contract(off)
+        S[0] = A[0] = 0.0f;
+        S[1] = mc[0] + mc[1];
+        S[2] = mc[2] + mc[3];
+        S[3] = 0.0f;
+        A[3] = 0.0f;
+        if (VAR == BP4_ADAGRAD) {
+            A[1] = fabsf(mc[0]) + fabsf(mc[1]);
+            A[2] = fabsf(mc[2]) + fabsf(mc[3]);
+        } else {
+            A[1] = A[2] = 0.0f;
+        }
+    }
+    const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
+    float st[3] = {0.0f, 0.0f, 0.0f}, ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
+    if (keep_q)
+        for (int x = 0; x < 3; ++x) st[x] = qs[3 * v + x];
+    if (keep_acc)
+        for (int x = 0; x < 3; ++x) ac[x] = acc[3 * v + x];
+    qubit_posterior(vp, t, p3, S, A, st, ac, qn);
+    if (keep_q)
+        for (int x = 0; x < 3; ++x) qs[3 * v + x] = st[x];
+    if (keep_acc)
+        for (int x = 0; x < 3; ++x) acc[3 * v + x] = ac[x];
+    ehat[v] = (uint8_t)decision_byte_of(qn);
+    // Vertical update (eqs. v_update / mombp5): m_{v->c} = lambda_H(Q) - m_{c->v}
+    float lam[4];
+    qubit_lambdas(qn, var_labels_present(info) & 0x6u, lam);
+    const float C = a.clamp;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const float out = clampf(lam[p < 2 ? 1 : 2] - mc[p], C);
+        msg[v + p * n] = __uint_as_float(__float_as_uint(out) & c22_keep(info, p));
+    }
+}
+
 template <int VAR>
 __device__ __forceinline__ VariantParams variant_params(const DecodeArgs &a)
 {
@@ -284,7 +374,7 @@ __device__ __forceinline__ VariantParams variant_params(const DecodeArgs &a)
 // ---- Wave groups: G in {4, ..., 64} lanes of one wavefront per shot -----------------
 // Lane r of a group owns checks and qubits r, r + G, ...; the group's syndrome bits
 // sit in a register (bit k: check r + kG); groups synchronise at wavefront level.
-template <int VAR, bool W = false>
+template <int VAR, bool W = false, bool C22 = false>
 __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
 {
     const int G = a.group_lanes;
@@ -318,7 +408,7 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
         int k = 0;
         for (int c = r; c < m; c += G, ++k)
             if (a.synd[(size_t)s * m + c]) sbits |= 1ull << k;
-        for (int v = r; v < n; v += G) init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, qs, acc, v, n, C);
+        for (int v = r; v < n; v += G) init_qubit<VAR, W, C22>(s_vi, s_vl, s_pi, msg, qs, acc, v, n, C);
         t = 0;
     };
 
@@ -338,12 +428,15 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
         }
         wave_sync();
         if (live) {
-            if (with_y)
+            if constexpr (C22) {
+                for (int v = r; v < n; v += G) qubit_node_c22<VAR>(a, s_vi, s_pi, msg, qs, acc, ehat, v, t, vp);
+            } else if (with_y) {
                 for (int v = r; v < n; v += G)
                     qubit_node<VAR, true, W>(a, s_vi, s_vl, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
-            else
+            } else {
                 for (int v = r; v < n; v += G)
                     qubit_node<VAR, false, W>(a, s_vi, s_vl, s_pi, msg, qs, acc, ehat, v, t, vp, shot);
+            }
         }
         wave_sync();
         uint32_t bad = 0;
@@ -562,7 +655,7 @@ __device__ __forceinline__ void walk_next(ItemWalk &w, uint32_t d, uint32_t rem,
     }
 }
 
-template <int VAR, bool W = false>
+template <int VAR, bool W = false, bool C22 = false>
 __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *events)
 {
     const uint32_t S = (uint32_t)a.block_shots;
@@ -620,7 +713,7 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     a.est[(size_t)h[kHdrDone] * n + w.x] = (uint8_t)decision_pauli(ehat[w.x]);
                 }
                 if (h[kHdrFresh])
-                    init_qubit<VAR, W>(s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off, (int)w.x, n, C);
+                    init_qubit<VAR, W, C22>(s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off, (int)w.x, n, C);
             }
             BP4_FOR_CHECKS(w) {
                 float *msg = reg0 + w.off;
@@ -695,13 +788,17 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
                     if (VAR == BP4_AEWA) vp.alpha = __int_as_float(h[kHdrAlpha]);
                     cur = w.off;
                 }
-                qubit_node<VAR, decltype(wy)::value, W>(a, s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off,
-                                                        reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t, vp,
-                                                        shot);
+                if constexpr (C22)
+                    qubit_node_c22<VAR>(a, s_vi, s_pi, msg, msg + a.q_off, msg + a.acc_off,
+                                        reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t, vp);
+                else
+                    qubit_node<VAR, decltype(wy)::value, W>(a, s_vi, s_vl, s_pi, msg, msg + a.q_off, msg + a.acc_off,
+                                                            reinterpret_cast<uint8_t *>(msg + a.ehat_off), (int)w.x, t,
+                                                            vp, shot);
             }
         };
-        if (with_y) qubit_phase(std::true_type{});
-        else qubit_phase(std::false_type{});
+        if (C22 || !with_y) qubit_phase(std::false_type{});
+        else qubit_phase(std::true_type{});
         __syncthreads();
         // ---- Syndrome test of the hard decision (Algorithm 2) ---------------------------
         {
@@ -767,9 +864,18 @@ __device__ __forceinline__ void run_block(const DecodeArgs &a, float *lds, int *
 #undef BP4_FOR_QUBITS
 }
 
-template <int VAR, bool W = false>
+// C22OK: the build takes the two-plus-two layout for codes that allow it (the
+// single-variant builds; the variant-switching build would hold both paths' registers).
+template <int VAR, bool W = false, bool C22OK = false>
 __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *events)
 {
+    if constexpr (!W && C22OK) {
+        if (a.css22) {
+            if (a.block_shots > 0) run_block<VAR, false, true>(a, lds, events);
+            else run_wave<VAR, false, true>(a, lds);
+            return;
+        }
+    }
     if (a.block_shots > 0) run_block<VAR, W>(a, lds, events);
     else run_wave<VAR, W>(a, lds);
 }
@@ -819,18 +925,26 @@ decode_lds_kernel(MixedArgs args)
             // slot field -> slot-major position v + j n (j: the edge's rank among its
             // qubit's slots); padding -> the padding slot.  kSlots n < 2^16: the
             // layout holds kSlots n message words in LDS.
+            // Two-plus-two layout: position = 2 [Z label] + rank among the qubit's slots
+            // of the same label.
             constexpr bool W = VSET == kWide;
+            const bool c22 = VSET >= 0 && a.css22;
             for (int i = threadIdx.x; i < cs * m; i += kBlock) {
                 const uint32_t w = a.g.cedge[i];
                 uint32_t slot = lds_pad_slot<W>((uint32_t)n);
                 if (!edge_is_pad(w)) {
                     const uint32_t v = edge_var(w);
-                    slot = v + (edge_slot(w) - var_base(a.g.vinfo[v])) * (uint32_t)n;
+                    const uint32_t info = a.g.vinfo[v];
+                    const uint32_t j = edge_slot(w) - var_base(info);
+                    slot = v + (c22 ? c22_pos(info, j) : j) * (uint32_t)n;
                 }
                 s_ce[i] = (w & ~0xFFFFu) | slot;
             }
         }
-        for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
+        if (VSET >= 0 && a.css22)
+            for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = c22_info(a.g.vinfo[i]);
+        else
+            for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
         if (VSET == kWide && a.wide) {   // slot labels of a wide graph
             uint32_t *s_vl = reinterpret_cast<uint32_t *>(s_pi + 3 * n);
@@ -883,7 +997,7 @@ decode_lds_kernel(MixedArgs args)
             }
         } else {
             constexpr int V = VSET < 0 ? BP4_EWAINIT : VSET;
-            run_code<V>(a, lds, events);
+            run_code<V, false, true>(a, lds, events);
         }
         __syncthreads();
     }

@@ -81,6 +81,9 @@ struct DecodeArgs {
     int32_t with_y;          // the code has Y entries
     int32_t serial;          // serial schedule (Algorithm 1) on wave groups
     int32_t wide;            // wide graph (cstride 8, labels in vlab)
+    int32_t css22;           // X/Z labels only, at most two of each per qubit: the LDS
+                             // kernel keeps a qubit's X messages at positions 0-1 and its Z
+                             // messages at 2-3 (unused positions hold 0)
 };
 
 // Codes of one persistent launch, decoded in this order (largest first).
@@ -118,6 +121,13 @@ hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const
 hipError_t launch_bookkeep(const GraphView &g, int32_t shots, const uint8_t *err,
                            const uint8_t *est, uint8_t *fail, int64_t *counts, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s);
+// bp4_decode_mixed with its shot-queue heads at `counters` (device, >= ncodes words):
+// validates, clears the heads with a fill kernel and launches.  Returns a BP4_ code.
+int decode_mixed_with(int32_t ncodes, const bp4_code_batch *codes, unsigned int *counters, void *stream);
+// Records the calling thread's error message (with the HIP error's text unless e is
+// hipSuccess) and returns `code`.
+int report_error(int code, const char *what, hipError_t e = hipSuccess);
+hipError_t launch_prior_llr(int32_t n, const double *probs, float *prior, hipStream_t s);
 
 size_t plain_workspace_bytes(int n, int nnz, int variant, int64_t shots);
 

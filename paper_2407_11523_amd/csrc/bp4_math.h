@@ -1,5 +1,5 @@
 // Device arithmetic of one flooding BP iteration, shared by every decode kernel:
-// the check-node function phi, the commutation LLR lambda, value-ordered sums.
+// the check-node function phi, the commutation LLR lambda, leave-one-out sums.
 //
 // Paper: Chen, Yi, Liang, Wang, "Improved Belief Propagation Decoding
 // Algorithms for Surface Codes", section II-B1 (eqs. init, h_update, v_update,
@@ -86,18 +86,42 @@ __device__ __forceinline__ float lambda_lab(uint32_t lab, const float q[3])
     return lambda_sp(q[h], qa, qb, softplus_neg_abs(q[h]), softplus_neg_abs(qa - qb));
 }
 
-// Sum of three non-negative values in an order fixed by their values:
-// (min + median) + max, so the result depends only on the multiset.
+// Sum of three non-negative values in an order fixed by their values,
+// (min + median) + max, so the result depends only on the multiset: a check whose
+// inputs are a permutation of another check's gives bitwise equal outputs, and
+// exact symmetries of a syndrome survive FP32 rounding.  Non-negative floats order
+// like their bit patterns as unsigned integers, so the order comes from integer
+// min / max (the median is the XOR of the three values, their minimum and their
+// maximum) instead of floating-point compares.
 __device__ __forceinline__ float sum3_canonical(float a, float b, float c)
 {
-    const float lo = fminf(fminf(a, b), c);
-    const float hi = fmaxf(fmaxf(a, b), c);
-    const float mid = __builtin_amdgcn_fmed3f(a, b, c);
-    return (lo + mid) + hi;
+    const uint32_t ua = __float_as_uint(a), ub = __float_as_uint(b), uc = __float_as_uint(c);
+    const uint32_t lo = min(min(ua, ub), uc), hi = max(max(ua, ub), uc);
+    const uint32_t mid = ua ^ ub ^ uc ^ lo ^ hi;
+    return (__uint_as_float(lo) + __uint_as_float(mid)) + __uint_as_float(hi);
 }
 
-// AdaGrad gradients at or below this fraction of |D| + sum |m| count as 0.
-constexpr float kAdaGradDeadband = 1.52587890625e-05f;   // 2^-16
+// Leave-one-out sums of four non-negative values: loo[j] sums the three values other
+// than f[j], formed directly (no subtraction) in value order.
+__device__ __forceinline__ void loo4(const float f[4], float loo[4])
+{
+#pragma clang fp contract(off)
+    loo[0] = sum3_canonical(f[1], f[2], f[3]);
+    loo[1] = sum3_canonical(f[0], f[2], f[3]);
+    loo[2] = sum3_canonical(f[0], f[1], f[3]);
+    loo[3] = sum3_canonical(f[0], f[1], f[2]);
+}
+
+// AdaGrad gradients at or below this fraction of |D| + sum |m| count as 0: FP32
+// cannot resolve their sign, and eq. boost's first adaptive step is about
+// alpha sign(g').  2^-20 is about eight FP32 roundings of the operands; against
+// the FP64 evaluation of eq. boost it kept more entries within 1e-5 than 2^-16,
+// and far more than 2^-24 or no threshold (rounding residue of sums that are
+// equal in exact arithmetic then takes a full step).
+#ifndef BP4_ADAGRAD_DEADBAND
+#define BP4_ADAGRAD_DEADBAND 9.5367431640625e-07f   // 2^-20
+#endif
+constexpr float kAdaGradDeadband = BP4_ADAGRAD_DEADBAND;
 
 // 1 iff single-qubit Paulis a, b (codes) anticommute.
 __device__ __forceinline__ uint32_t anticomm(uint32_t a, uint32_t b)
@@ -288,8 +312,8 @@ __device__ __forceinline__ void check_update(const float mv[4], uint32_t s, floa
     const uint32_t neg = b[0] ^ b[1] ^ b[2] ^ b[3] ^ (s << 31);   // sign bit: product of all signs
     // leave-one-out sums of phi, formed directly (no subtraction) and in value order,
     // so equal multisets of inputs give bitwise equal outputs
-    const float loo[4] = {sum3_canonical(f[1], f[2], f[3]), sum3_canonical(f[0], f[2], f[3]),
-                          sum3_canonical(f[0], f[1], f[3]), sum3_canonical(f[0], f[1], f[2])};
+    float loo[4];
+    loo4(f, loo);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const float mag = phi(loo[j]);   // >= 0 (or NaN)

@@ -1,6 +1,7 @@
 // Error sampling, syndromes and logical-error bookkeeping on the GPU (integer
 // work, bit-exact).  Section IV of the paper: i.i.d. Pauli errors per qubit;
-// success iff the residual E^ E lies in the stabilizer group.
+// success iff the residual E^ E lies in the stabilizer group.  Also the prior
+// LLRs of the noise model (section II-B1).
 #include "bp4_internal.h"
 
 namespace bp4 {
@@ -205,7 +206,29 @@ __global__ void zero_u32_kernel(unsigned int *p, int count)
     if (i < count) p[i] = 0u;
 }
 
+// Prior LLRs of section II-B1, one thread per qubit: Pi_W = ln p_I - ln p_W with
+// p_I = 1 - (p_X + p_Y + p_Z), in double precision, rounded to float once.  An
+// impossible entry (p_W <= 0, p_I <= 0, or a non-finite probability) is NaN.
+__global__ void __launch_bounds__(256) prior_llr_kernel(int32_t n, const double *probs, float *prior)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const double px = probs[3 * v], py = probs[3 * v + 1], pz = probs[3 * v + 2];
+    const double pi = 1.0 - ((px + py) + pz);
+    const bool ok = isfinite(px) && isfinite(py) && isfinite(pz) && px > 0.0 && py > 0.0 && pz > 0.0 && pi > 0.0;
+    const double lpi = log(pi);
+    prior[3 * v] = ok ? (float)(lpi - log(px)) : __builtin_nanf("");
+    prior[3 * v + 1] = ok ? (float)(lpi - log(py)) : __builtin_nanf("");
+    prior[3 * v + 2] = ok ? (float)(lpi - log(pz)) : __builtin_nanf("");
+}
+
 }  // namespace
+
+hipError_t launch_prior_llr(int32_t n, const double *probs, float *prior, hipStream_t s)
+{
+    hipLaunchKernelGGL(prior_llr_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, probs, prior);
+    return hipGetLastError();
+}
 
 hipError_t launch_sample(const GraphView &g, int32_t shots, int64_t shot0, const uint32_t thr[3],
                          uint64_t seed, uint64_t stream_id, uint8_t *err, uint8_t *synd,

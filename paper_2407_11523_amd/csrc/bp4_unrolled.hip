@@ -335,8 +335,8 @@ __device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, cons
             neg ^= sgn[j];
             f[j] = phi(fabsf(mv[j]));
         }
-        const float loo[4] = {sum3_canonical(f[1], f[2], f[3]), sum3_canonical(f[0], f[2], f[3]),
-                              sum3_canonical(f[0], f[1], f[3]), sum3_canonical(f[0], f[1], f[2])};
+        float loo[4];
+        loo4(f, loo);   // the forward check rule's sums, bit for bit
         float wsum[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {

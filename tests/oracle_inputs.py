@@ -32,25 +32,3 @@ def matched(code, thr, seed, err_gpu, syn_gpu, idx=None):
     assert np.array_equal(gs, s), "GPU syndromes differ from the oracle's sampler"
     assert np.array_equal(ge, e), "GPU errors differ from the oracle's sampler"
     return e, s
-
-
-def decision_margin(code, params, pi0, syn_row, t):
-    """Smallest distance, over the qubits, of the oracle's FP64 posterior LLRs at
-    iteration t from a change of the hard decision (section II-B1: identity when
-    every LLR is positive, else the smallest one).  An FP32 decoder can only take
-    a different decision where this is at rounding level."""
-    r = O.decode(code.hx, code.hz, params, pi0, syn_row.reshape(1, -1), want_trace=True)
-    q = np.sort(r["q_trace"][0, t - 1], axis=1)
-    margin = np.where(q[:, 0] > 0, q[:, 0], np.minimum(-q[:, 0], q[:, 1] - q[:, 0]))
-    scale = np.maximum(1.0, np.abs(q).max(axis=1))
-    return float((margin / scale).min())
-
-
-def same_stops(code, params, pi0, syn, it_a, it_b, rel=1e-3):
-    """Shots whose stopping iterations differ are accepted only where the FP64
-    decision at the earlier of the two iterations is within `rel` of a tie.
-    Returns the indices of the differing shots and their margins."""
-    bad = np.nonzero(it_a != it_b)[0]
-    margins = [decision_margin(code, params, pi0, syn[i], int(min(it_a[i], it_b[i]))) for i in bad]
-    assert all(m <= rel for m in margins), (bad, margins)
-    return bad, margins

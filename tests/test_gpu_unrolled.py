@@ -172,8 +172,6 @@ def test_config4_planar_d9_full_batch():
     ra, rp = compare(gas, ga64), compare(gps, gp64)
     say("config4 subset", dict(loss32=Ls, loss64=L64, alpha=ra, prior=rp, ref_seconds=time.perf_counter() - t0))
     assert abs(Ls - L64) <= 1e-5 * abs(L64)
-    if ra[0] <= 1e-4 and rp[0] <= 1e-4:
-        return
     _, q32 = P.unrolled_forward(g, torch.tensor(alpha, dtype=torch.float32, device="cuda"),
                                 torch.tensor(prior, dtype=torch.float32, device="cuda"), syn[:sub], err[:sub], T, K,
                                 want_q=True)
@@ -184,6 +182,16 @@ def test_config4_planar_d9_full_batch():
     Lk, gak, gpk = gpu_loss_grad(g, alpha, prior, syn[:sub][sel], err[:sub][sel], T, K)
     Lk64, gak64, gpk64, _ = U.loss_and_grad(c.hx, c.hz, alpha, prior, syn_s[keep], err_s[keep], T, 30.0, tg=tg)
     rak, rpk = compare(gak, gak64), compare(gpk, gpk64)
-    say("config4 agreeing shots", dict(excluded=excluded, alpha=rak, prior=rpk))
+    # both figures are reported: all shots (norm-wise, per element) and the shots whose FP32
+    # and FP64 forwards agree (reading C23)
+    say("config4 gradient errors", dict(all_shots=dict(alpha=ra, prior=rp),
+                                        agreeing_shots=dict(excluded=excluded, alpha=rak, prior=rpk)))
+    if ra[0] <= 1e-4 and rp[0] <= 1e-4 and ra[1] <= 1e-4 and rp[1] <= 1e-4:
+        return
+    # Norm-wise the agreeing shots meet 1e-4.  Per element, a gradient entry that is a
+    # small sum of per-shot terms of both signs carries their FP32 rounding relative to
+    # the sum of their magnitudes: measured 5e-4 (against the floor of 1% of the largest
+    # entry), so the per-element bar there is 1e-3.
     assert excluded <= 0.1
-    assert rak[0] <= 1e-4 and rpk[0] <= 1e-4
+    for rel_norm, rel_elem in (rak, rpk):
+        assert rel_norm <= 1e-4 and rel_elem <= 1e-3
