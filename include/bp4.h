@@ -283,6 +283,18 @@ int bp4_mixed_workspace_bytes(int32_t ncodes, size_t *bytes);
 int bp4_decode_mixed(int32_t ncodes, const bp4_code_batch *codes, void *ws, size_t ws_bytes,
                      void *stream);
 
+/* bp4_decode_mixed for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * launch, inputs, outputs and results, but its scratch memory, the per-code
+ * shot-queue heads, is a 256-byte array inside the library's code object (one per
+ * GPU, held until the process ends) instead of a caller workspace, and the call
+ * allocates nothing.  The heads are cleared by a fill kernel on `stream` before each
+ * launch.  Every call on one GPU shares that array: calls that overlap on one GPU
+ * (different streams, or threads) race and must not be issued.  Errors: as
+ * bp4_decode_mixed; EINVAL for ncodes outside [1, BP4_MAX_MIXED_CODES] (the
+ * array's limit), EHIP if the array's device address cannot be obtained. */
+int bp4_decode_mixed_noalloc(int32_t ncodes, const bp4_code_batch *codes, void *stream);
+
 /* Device workspace bytes of bp4_decode_plain: messages, per-qubit state and
  * hard decisions of every shot in HBM. */
 int bp4_plain_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes);

@@ -74,6 +74,7 @@ SIGNATURES = {
     "bp4_lds_layout_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(_sz)]),
     "bp4_decode_mixed": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CodeBatch), _vp, _sz, _vp]),
+    "bp4_decode_mixed_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CodeBatch), _vp]),
     "bp4_plain_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64,
                                                  ctypes.POINTER(_sz)]),
     "bp4_decode_plain": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(Params), ctypes.c_int64, _vp, _vp, _vp,
