@@ -113,3 +113,22 @@ def adagrad_report(err_q, win):
                 outside_max=float(err_q[~win].max()) if (~win).any() else 0.0,
                 inside_frac_1e5=float((err_q[win] <= REL_TOL).mean()) if win.any() else 1.0,
                 all_frac_1e5=float((err_q <= REL_TOL).mean()))
+
+
+def early_agreement(est_gpu, conv_gpu, ro, rp):
+    """Shots both sides converged on within EARLY_ITERS iterations whose decisions
+    differ, for the GPU against the oracle and for the oracle against its own run
+    with perturbed priors (on the shots that run covers), and the bar: the GPU's
+    share may exceed the oracle's own by a 3-sigma binomial margin (taken at a
+    share of at least 1e-4)."""
+    k = len(rp["est"])
+    e_g = conv_gpu.astype(bool) & ro["conv"].astype(bool) & (ro["iters"] <= EARLY_ITERS)
+    e_s = rp["conv"].astype(bool) & ro["conv"][:k].astype(bool) & (ro["iters"][:k] <= EARLY_ITERS)
+    diff_g = int((~np.all(est_gpu[e_g] == ro["est"][e_g], axis=1)).sum())
+    diff_s = int((~np.all(rp["est"][e_s] == ro["est"][:k][e_s], axis=1)).sum())
+    share_g = diff_g / max(1, int(e_g.sum()))
+    share_s = diff_s / max(1, int(e_s.sum()))
+    q = max(share_s, 1e-4)
+    bar = share_s + Z_MARGIN * math.sqrt(q * (1 - q) / max(1, int(e_g.sum())))
+    return dict(early=int(e_g.sum()), early_diff=diff_g, early_share=share_g, early_self_share=share_s,
+                early_bar=bar, early_ok=share_g <= bar)
