@@ -19,7 +19,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bp4_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# BP4_ORACLE_SANITIZE=1: the AddressSanitizer + UndefinedBehaviorSanitizer build (the
+# process must preload gcc's libasan and libubsan)
+_SANITIZE = os.environ.get("BP4_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined", "-g"]
 
 BP, MOMENTUM, ADAGRAD, EWAINIT, AEWA = 0, 1, 2, 3, 4
 VARIANTS = {"bp": BP, "momentum": MOMENTUM, "adagrad": ADAGRAD, "ewainit": EWAINIT, "aewa": AEWA}
@@ -30,7 +34,8 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-Wextra"] + (SANITIZE_FLAGS if _SANITIZE else []) +
+                              ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libbp4.so")
+# BP4_SANITIZE=1: the library whose host ABI layer is built with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload clang's ASan runtime)
+LIB_PATH = os.path.join(PKG, "libbp4_san.so" if os.environ.get("BP4_SANITIZE") == "1" else "libbp4.so")
 
 BP4_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENONCOMM", -3: "EDEGREE", -4: "EWORKSPACE", -5: "EHIP", -6: "EUNSUPPORTED"}

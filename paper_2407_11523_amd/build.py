@@ -62,6 +62,49 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SAN_LIB = os.path.join(PKG, "libbp4_san.so")
+# host code of the ABI layer only: the device code objects are the regular ones
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined", "-g"]
+
+
+def build_sanitized() -> str:
+    """libbp4_san.so: bp4_api.cpp (argument checks, graph construction, launch set-up)
+    with AddressSanitizer and UndefinedBehaviorSanitizer, linked with the regular
+    kernel objects; loaded with BP4_SANITIZE=1 and clang's ASan runtime preloaded."""
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        if src == "bp4_api.cpp":
+            obj = os.path.join(BUILD, "bp4_api_san.o")
+            cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + HIP_FLAGS + SAN_FLAGS
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"hipcc failed for the sanitized {src}:\n{r.stdout}\n{r.stderr}")
+            objs.append(obj)
+        else:
+            obj = os.path.join(BUILD, src + ".o")
+            if not os.path.exists(obj):
+                _compile(src)
+            objs.append(obj)
+    tmp = SAN_LIB + ".tmp"
+    r = subprocess.run([hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs,
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed for the sanitized library:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
+def asan_runtime() -> str:
+    """clang's ASan runtime of the ROCm toolchain (preloaded for the sanitized library)."""
+    import glob
+    cands = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not cands:
+        raise RuntimeError("no libclang_rt.asan-x86_64.so under /opt/rocm/llvm")
+    return cands[-1]
+
+
 CALIB_SRC = os.path.join(PKG, "calib", "valu_rate.hip")
 CALIB_BIN = os.path.join(PKG, "calib", "valu_rate")
 
