@@ -90,16 +90,15 @@ LARGE_P = configs.CONFIG5["p"]
 LARGE_SHOTS = configs.CONFIG5["shots"]
 LARGE_MAX_ITER = configs.CONFIG5["max_iter"]
 LARGE_ALPHA = configs.alpha(5, "ewainit")
-SOA_ITER_BLOCK = 24   # the library's default iterations per SOA launch
 HBM_PEAK = 8.0e12   # bytes/s
 
 # HBM traffic per launch from rocprofv3 counters (2 x FETCH_SIZE + WRITE_SIZE, the
 # factors read off a 1 GiB device copy), valid only for the kernel sources they were
 # taken on: a kernel whose sources hash differently reports traffic null.
 KERNEL_SOURCES = {"decode_lds_kernel": ("bp4_decode.hip", "bp4_math.h", "bp4_internal.h"),
-                  "decode_soa_kernel": ("bp4_soa.hip", "bp4_math.h", "bp4_internal.h")}
-MEASURED_TRAFFIC = {"decode_lds_kernel": ("954398d2577431de", 3.917e+09),    # mixed batch, one launch
-                    "decode_soa_kernel": ("463af61095e7f716", 7.433e+11)}   # large codes, mean of 18 launches
+                  "decode_gather_kernel": ("bp4_gather.hip", "bp4_gather.h", "bp4_math.h", "bp4_internal.h")}
+MEASURED_TRAFFIC = {"decode_lds_kernel": ("8db27d3ffb1bb416", 3.910e+09),    # mixed batch, one launch
+                    "decode_gather_kernel": ("0000000000000000", 0.0)}      # large codes, mean of 2 launches
 
 
 def measured_traffic(kernel):
@@ -125,14 +124,6 @@ def two_phase_bytes(E, N):
     return 16 * E + 24 * N
 
 
-def soa_bytes_per_shot_iteration(E, N, M):
-    """HBM bytes the SOA kernel's own design moves per shot-iteration: every message read
-    and written by the check pass and by the qubit pass (16 E), the posterior read and
-    written (24 N), one decision byte written per qubit (N) and read per edge by the
-    syndrome test (E), the syndrome words read twice (8 ceil(M / 32))."""
-    return 17 * E + 25 * N + 8 * ((M + 31) // 32)
-
-
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -147,7 +138,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tuning-cache", default=None, help="autotuner cache file (default: the package's)")
     ap.add_argument("--no-tune", action="store_true", help="use the default lanes-per-shot pick")
-    ap.add_argument("--no-large", action="store_true", help="skip the large-code (SOA) measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-code (HBM kernels) measurement")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the step")
     ap.add_argument("--no-unrolled", action="store_true", help="skip the unrolled forward/adjoint measurement")
     ap.add_argument("--no-aewa", action="store_true", help="skip the AEWA-BP vs EWAInit-BP timing")
@@ -155,7 +146,7 @@ def main():
     ap.add_argument("--no-serial", action="store_true", help="skip the serial-versus-flooding comparison")
     ap.add_argument("--no-qldpc", action="store_true", help="skip the bivariate bicycle and Chamon codes")
     ap.add_argument("--no-config2", action="store_true", help="skip the toric L=8 error-rate sweep")
-    ap.add_argument("--only-large", action="store_true", help="run only the large-code (SOA) measurement")
+    ap.add_argument("--only-large", action="store_true", help="run only the large-code (HBM kernels) measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -687,65 +678,79 @@ def run_unrolled(torch, qecgen, P, dev):
 
 
 def run_large(torch, qecgen, P, dev):
-    """Decode 2^18 shots of each large code with the SOA kernel; HBM roofline."""
+    """Decode 2^18 shots of each large code with the single-pass HBM kernel (the automatic
+    choice) and, on the same syndromes, with the two-phase SOA kernel; HBM roofline of
+    the single-pass kernel."""
     thr = qecgen.thresholds(LARGE_P / 3, LARGE_P / 3, LARGE_P / 3)
     prm = P.Params(variant="ewainit", alpha=LARGE_ALPHA, max_iter=LARGE_MAX_ITER)
     warm = P.Params(variant="ewainit", alpha=LARGE_ALPHA, max_iter=2)
-    launches = 0
     res = {"workload": f"planar d=31 and toric L=32, depolarizing p=0.10, 2^18 shots each, EWAInit-BP "
-                       f"alpha={LARGE_ALPHA}, iter_max 200, messages in HBM (structure-of-arrays kernel)",
+                       f"alpha={LARGE_ALPHA}, iter_max 200, messages in HBM (single-pass kernel; the two-phase "
+                       f"structure-of-arrays kernel timed on the same syndromes)",
            "codes": {}}
-    tot_ms = tot_bytes = tot_shots = tot_eu = tot_design = 0.0
+    tot = {"gather": 0.0, "soa": 0.0}
+    tot_bytes = tot_shots = tot_eu = 0.0
     for i, (fam, size) in enumerate(LARGE_CODES):
         code = qecgen.make(fam, size)
         g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
         pr = P.prior_llr(qecgen.depolarizing_probs(code.n, LARGE_P), device=dev)
         err, syn = P.sample(g, LARGE_SHOTS, thr, seed=qecgen.config_seed(5, i, 0))
-        ws = torch.empty(g.workspace_bytes(prm, LARGE_SHOTS), dtype=torch.uint8, device=dev)
-        P.decode(g, warm, pr, syn[:256], kernel="soa", ws=ws)          # warm-up (loads the code object)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        r = P.decode(g, prm, pr, syn, kernel="soa", ws=ws)
-        b.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b)
+        row = {}
+        results = {}
+        for kernel in ("gather", "soa"):
+            nbytes_ws = (g.gather_workspace_bytes(prm, LARGE_SHOTS) if kernel == "gather"
+                         else g.soa_workspace_bytes(prm, LARGE_SHOTS))
+            ws = torch.empty(nbytes_ws, dtype=torch.uint8, device=dev)
+            P.decode(g, warm, pr, syn[:256], kernel=kernel, ws=ws)          # warm-up (loads the code object)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            r = P.decode(g, prm, pr, syn, kernel=kernel, ws=ws)
+            b.record()
+            torch.cuda.synchronize()
+            row[kernel + "_ms"] = a.elapsed_time(b)
+            results[kernel] = r
+            del ws
+            torch.cuda.empty_cache()
+        r = results["gather"]
+        same = all(torch.equal(r[k], results["soa"][k]) for k in ("est", "conv", "iters"))
+        ms = row["gather_ms"]
         _, counts = P.bookkeep(g, err, r["est"])
         it_sum = int(r["iters"].to(torch.int64).sum())
         nbytes = it_sum * algorithmic_bytes(g.nnz, g.n)
-        design = it_sum * soa_bytes_per_shot_iteration(g.nnz, g.n, g.m)
         c = counts.cpu().numpy()
         res["codes"][code.name] = {
-            "decode_ms": ms, "syndromes_per_s": LARGE_SHOTS / (ms / 1e3),
+            "decode_ms": ms, "soa_decode_ms": row["soa_ms"], "speedup_vs_soa": row["soa_ms"] / ms,
+            "bitwise_equal_to_soa": same,
+            "syndromes_per_s": LARGE_SHOTS / (ms / 1e3),
             "edge_updates_per_s": it_sum * g.nnz / (ms / 1e3), "avg_iters": it_sum / LARGE_SHOTS,
             "converged": float(r["conv"].float().mean()), "ler": float(c[1] + c[2]) / LARGE_SHOTS,
             "algorithmic_gb_s": nbytes / (ms / 1e3) / 1e9,
+            "soa_algorithmic_gb_s": nbytes / (row["soa_ms"] / 1e3) / 1e9,
             "algorithmic_bytes_per_shot_iteration": algorithmic_bytes(g.nnz, g.n),
-            "kernel_bytes_per_shot_iteration": soa_bytes_per_shot_iteration(g.nnz, g.n, g.m),
-            "kernel_gb_s": design / (ms / 1e3) / 1e9,
-            "two_phase_cap": algorithmic_bytes(g.nnz, g.n) / two_phase_bytes(g.nnz, g.n)}
-        log(f"{code.name}: decode {ms:.1f} ms, {nbytes / (ms / 1e3) / 1e9:.0f} GB/s algorithmic, "
-            f"{design / (ms / 1e3) / 1e9:.0f} GB/s of the kernel's own design")
-        tot_ms += ms
+            "algorithmic_bytes_per_launch": nbytes,
+            "soa_two_phase_cap": algorithmic_bytes(g.nnz, g.n) / two_phase_bytes(g.nnz, g.n)}
+        log(f"{code.name}: single-pass {ms:.1f} ms ({nbytes / (ms / 1e3) / 1e9:.0f} GB/s algorithmic), "
+            f"two-phase SOA {row['soa_ms']:.1f} ms, bitwise equal {same}")
+        for k in tot:
+            tot[k] += row[k + "_ms"]
         tot_bytes += nbytes
-        tot_design += design
         tot_shots += LARGE_SHOTS
         tot_eu += it_sum * g.nnz
-        launches += -(-LARGE_MAX_ITER // SOA_ITER_BLOCK)
-        del r, ws, err, syn
+        del r, results, err, syn
         torch.cuda.empty_cache()
-    achieved = tot_bytes / (tot_ms / 1e3)
-    res["syndromes_per_s"] = tot_shots / (tot_ms / 1e3)
-    res["edge_updates_per_s"] = tot_eu / (tot_ms / 1e3)
+    launches = len(LARGE_CODES)   # one persistent launch per code
+    achieved = tot_bytes / (tot["gather"] / 1e3)
+    res["syndromes_per_s"] = tot_shots / (tot["gather"] / 1e3)
+    res["edge_updates_per_s"] = tot_eu / (tot["gather"] / 1e3)
+    res["soa_syndromes_per_s"] = tot_shots / (tot["soa"] / 1e3)
     res["roofline"] = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK, "traffic": measured_traffic("decode_soa_kernel"),
-                       "kernel": "decode_soa_kernel", "launches": launches,
+                       "frac": achieved / HBM_PEAK, "traffic": measured_traffic("decode_gather_kernel"),
+                       "kernel": "decode_gather_kernel", "launches": launches,
                        "algorithmic_bytes_per_launch": tot_bytes / launches,
-                       "kernel_design_bytes_per_launch": tot_design / launches,
-                       "two_phase_cap": {k: v["two_phase_cap"] for k, v in res["codes"].items()}}
+                       "soa_frac": tot_bytes / (tot["soa"] / 1e3) / HBM_PEAK}
     return res
-
 
 if __name__ == "__main__":
     main()

@@ -142,8 +142,9 @@ void bp4_graph_destroy(bp4_graph *g);
 int bp4_graph_edges(const bp4_graph *g, int32_t *check, int32_t *qubit);
 
 /* Device workspace bytes bp4_decode needs for `shots` shots with the automatic
- * kernel choice (a queue counter for the LDS kernel; lane-resident message and
- * state arrays for the SOA kernel). */
+ * kernel choice (a queue counter for the LDS kernel; the column records of the
+ * single-pass HBM kernel, or the lane-resident message and state arrays of the
+ * SOA kernel where that one applies: serial schedule, AEWA). */
 int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes);
 
 /* Sample i.i.d. Pauli errors and their syndromes (section IV: each qubit is
@@ -184,8 +185,8 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
                uint8_t *est, uint8_t *conv, int32_t *iters,
                void *ws, size_t ws_bytes, void *stream);
 
-/* Launch choices of the decode kernels.  kernel: BP4_KERNEL_AUTO, _LDS or
- * _SOA (below).  Lane mapping of the LDS kernel (0 and 0: picked by lane use
+/* Launch choices of the decode kernels.  kernel: BP4_KERNEL_AUTO, _LDS, _SOA
+ * or _GATHER (below).  Lane mapping of the LDS kernel (0 and 0: picked by lane use
  * and occupancy): group_lanes 4, 8, 16, 32 or 64 = that many lanes of one
  * wavefront decode one shot (lane r owns checks and qubits r, r + G, ...);
  * block_shots S in [1, 512] (with group_lanes 0 or 512) = S shots share the
@@ -200,10 +201,12 @@ int bp4_decode(const bp4_graph *g, const void *dev_graph, const bp4_params *p, i
  * a multiple of 256 and capped by the shot count); the SOA workspace grows
  * with it.  soa_iter_block: iterations per SOA launch, after which the shots
  * still running are packed onto fully populated wavefronts (0: 24); results
- * do not depend on it.  group_lanes, block_shots and lds_bytes select the
- * LDS kernel under AUTO and are rejected with SOA; soa_lanes and
- * soa_iter_block select SOA under AUTO and are rejected with LDS.
- * reserved: 0. */
+ * do not depend on it.  gather_waves: wavefronts per workgroup of the
+ * single-pass HBM kernel, 4, 8 or 16 (0: 16; 64 shots per workgroup, 32
+ * wavefronts per CU); results do not depend on it.  group_lanes, block_shots
+ * and lds_bytes select the LDS kernel under AUTO, soa_lanes and
+ * soa_iter_block the SOA kernel, gather_waves the single-pass HBM kernel;
+ * each group is rejected with the other kernels.  reserved: 0. */
 typedef struct {
     int32_t group_lanes;
     int32_t lds_bytes;
@@ -211,14 +214,23 @@ typedef struct {
     int32_t soa_lanes;
     int32_t soa_iter_block;
     int32_t block_shots;
-    int32_t reserved[2];
+    int32_t gather_waves;
+    int32_t reserved;
 } bp4_tuning;
 
 /* Decode kernels.  LDS: a lane group per shot, state in LDS (small and medium
  * codes).  SOA: one lane per shot, messages and state in HBM as
- * structure-of-arrays [slot][lane] (large codes).  AUTO picks SOA when even
- * one shot per workgroup would need more than 80 KB of LDS. */
-enum { BP4_KERNEL_AUTO = 0, BP4_KERNEL_LDS = 1, BP4_KERNEL_SOA = 2 };
+ * structure-of-arrays [slot][lane], a check pass and a qubit pass per
+ * iteration, the shots still running packed between launches (large codes;
+ * every variant, both schedules, the verification outputs).  GATHER: one
+ * lane per shot, 64 shots per workgroup, one pass over HBM per iteration:
+ * each qubit reads its checks' other messages (L2 serves the re-reads of the
+ * neighbouring qubits) and writes its own; the syndrome test runs inside the
+ * pass and a finished shot's lane takes the next shot at once (large codes;
+ * flooding BP, Momentum, AdaGrad and EWAInit, at most 4,079 checks, no
+ * verification outputs).  AUTO: LDS unless even one shot per workgroup would
+ * need more than 80 KB of LDS; then GATHER where it applies, else SOA. */
+enum { BP4_KERNEL_AUTO = 0, BP4_KERNEL_LDS = 1, BP4_KERNEL_SOA = 2, BP4_KERNEL_GATHER = 3 };
 
 /* Device workspace bytes of the SOA kernel for `shots` shots with soa_lanes
  * lanes in flight (0: the default): per lane, two records (the running one
@@ -229,9 +241,23 @@ enum { BP4_KERNEL_AUTO = 0, BP4_KERNEL_LDS = 1, BP4_KERNEL_SOA = 2 };
 int bp4_soa_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, int32_t soa_lanes,
                             size_t *bytes);
 
+/* Device workspace bytes of the single-pass HBM kernel (flooding decode of
+ * section II-B1 for large codes) for `shots` shots and gather_waves
+ * wavefronts per workgroup (0: 16): the shot queue head, the initial-message
+ * table (4 words per check) and, for each of the
+ * min(ceil(shots / 64), 256 x 32 / gather_waves) workgroups in flight, two
+ * records of 64 columns holding 4 message words per check and 3 posterior
+ * words (6 with the Momentum or AdaGrad accumulator) per qubit.
+ * Errors: EINVAL (NULL, negative shots, gather_waves not 0, 4, 8 or 16,
+ * parameters out of range). */
+int bp4_gather_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, int32_t gather_waves,
+                               size_t *bytes);
+
 /* As bp4_decode, with launch choices `tune` (NULL: automatic; with
  * tune->kernel = BP4_KERNEL_SOA the workspace must hold
- * bp4_soa_workspace_bytes) and, for
+ * bp4_soa_workspace_bytes, with BP4_KERNEL_GATHER
+ * bp4_gather_workspace_bytes; under AUTO a large code that asks for the
+ * verification outputs runs the SOA kernel and needs its workspace) and, for
  * verification, the state after the last iteration run: q_out dev
  * [shots][n][3] posterior LLRs Q; mvc_out and mcv_out dev [shots][nnz]
  * variable-to-check and check-to-variable messages in canonical edge order.

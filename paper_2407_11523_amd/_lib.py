@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("group_lanes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("soa_lanes", ctypes.c_int32), ("soa_iter_block", ctypes.c_int32), ("block_shots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("gather_waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CodeBatch(ctypes.Structure):
@@ -73,6 +73,8 @@ SIGNATURES = {
     "bp4_mixed_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_sz)]),
     "bp4_soa_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int32,
                                                ctypes.POINTER(_sz)]),
+    "bp4_gather_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int32,
+                                                  ctypes.POINTER(_sz)]),
     "bp4_lds_layout_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(_sz)]),
     "bp4_decode_mixed": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CodeBatch), _vp, _sz, _vp]),

@@ -120,6 +120,13 @@ class Graph:
                                                 ctypes.byref(b)))
         return int(b.value)
 
+    def gather_workspace_bytes(self, params: Params, shots: int, gather_waves: int = 0) -> int:
+        b = ctypes.c_size_t()
+        cp = params.c()
+        check(self._lib.bp4_gather_workspace_bytes(self._h, ctypes.byref(cp), int(shots), int(gather_waves),
+                                                   ctypes.byref(b)))
+        return int(b.value)
+
     @property
     def handle(self):
         return self._h
@@ -163,21 +170,24 @@ def sample(g: Graph, shots: int, thr, seed: int, stream_id: int = 0, shot0: int 
     return err, synd
 
 
-KERNELS = {"auto": 0, "lds": 1, "soa": 2}
+KERNELS = {"auto": 0, "lds": 1, "soa": 2, "gather": 3}
 
 
 def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *, trace: bool = False,
            group_lanes: int = 0, block_shots: int = 0, lds_bytes: int = 0, kernel: str = "auto",
-           soa_lanes: int = 0, soa_iter_block: int = 0, out: Optional[dict] = None,
+           soa_lanes: int = 0, soa_iter_block: int = 0, gather_waves: int = 0, out: Optional[dict] = None,
            ws: Optional[torch.Tensor] = None):
     """Decode syndromes [shots][m]; returns dict(est, conv, iters[, q, mvc, mcv]).
 
     group_lanes (4..64: lanes of one wavefront per shot) or block_shots (shots
     sharing a 512-lane workgroup) force the LDS kernel's lane mapping (0 and 0:
     automatic); lds_bytes reserves at least that much LDS per workgroup; kernel picks the
-    LDS ("lds") or structure-of-arrays ("soa") kernel ("auto": by code size);
-    soa_lanes sets the shots the SOA kernel keeps in flight and soa_iter_block
-    its iterations per launch (0: defaults)."""
+    LDS ("lds"), the two-phase structure-of-arrays ("soa") or the single-pass
+    HBM ("gather") kernel ("auto": by code size; large codes take "gather"
+    unless trace, serial or AEWA asks for "soa"); soa_lanes sets the shots the
+    SOA kernel keeps in flight and soa_iter_block its iterations per launch,
+    gather_waves the wavefronts per workgroup of the single-pass kernel (0:
+    defaults)."""
     dev = g.dev.device
     if synd.dtype != torch.uint8 or synd.dim() != 2 or synd.shape[1] != g.m or not synd.is_contiguous():
         raise BP4Error(-1, "synd must be a contiguous uint8 [shots][m] tensor")
@@ -198,11 +208,16 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
     if ws is None:
         if kernel == "soa" or soa_lanes or soa_iter_block:
             nbytes = g.soa_workspace_bytes(params, shots, soa_lanes)
+        elif kernel == "gather" or gather_waves:
+            nbytes = g.gather_workspace_bytes(params, shots, gather_waves)
         else:
             nbytes = g.workspace_bytes(params, shots)
+            if trace and kernel == "auto":   # a large code then runs the SOA kernel
+                nbytes = max(nbytes, g.soa_workspace_bytes(params, shots, 0))
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     res = {"est": est, "conv": conv, "iters": iters}
-    if trace or group_lanes or block_shots or lds_bytes or soa_lanes or soa_iter_block or kernel != "auto":
+    if (trace or group_lanes or block_shots or lds_bytes or soa_lanes or soa_iter_block or gather_waves
+            or kernel != "auto"):
         q = mvc = mcv = None
         if trace:
             q = torch.empty((shots, g.n, 3), dtype=torch.float32, device=dev)
@@ -210,7 +225,7 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
             mcv = torch.empty((shots, g.nnz), dtype=torch.float32, device=dev)
             res.update(q=q, mvc=mvc, mcv=mcv)
         tune = _CTuning(int(group_lanes), int(lds_bytes), KERNELS[kernel], int(soa_lanes), int(soa_iter_block),
-                        int(block_shots))
+                        int(block_shots), int(gather_waves))
         check(g._lib.bp4_decode_ex(g.handle, _ptr(g.dev), ctypes.byref(cp), ctypes.byref(tune), shots,
                                    _ptr(prior), _ptr(synd), _ptr(est), _ptr(conv), _ptr(iters), _ptr(q),
                                    _ptr(mvc), _ptr(mcv), _ptr(ws), ws.numel(), _stream(dev)))

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libbp4.so")
 ARCH = "gfx950"
 
 SOURCES = ["bp4_api.cpp", "bp4_decode.hip", "bp4_sample.hip", "bp4_plain.hip", "bp4_soa.hip",
-           "bp4_unrolled.hip", "bp4_noalloc.hip"]
+           "bp4_unrolled.hip", "bp4_noalloc.hip", "bp4_gather.hip"]
 
 # Packed FP32 VALU forms are kept out of generated code.
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "bp4.h"
+#include "bp4_gather.h"
 #include "bp4_internal.h"
 
 using namespace bp4;
@@ -54,9 +55,10 @@ struct bp4_graph {
     std::vector<uint32_t> sord, slev;            // serial order as levels (see graph_create)
     std::vector<uint32_t> vlab;                  // [n] slot labels of wide graphs
     std::vector<uint32_t> lptr, lent;            // logicals
+    std::vector<uint32_t> gord, gedge;           // walk of the single-pass HBM kernel (narrow graphs)
     // byte offsets of the sections in the device image
     size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_vchk = 0, off_sord = 0, off_slev = 0, off_vlab = 0,
-           off_lptr = 0, off_lent = 0, bytes = 0;
+           off_lptr = 0, off_lent = 0, off_gord = 0, off_gedge = 0, bytes = 0;
     bool wide() const { return cstride > kMaxCheckDeg; }
 
     void layout()
@@ -71,6 +73,8 @@ struct bp4_graph {
         off_vlab = o; o = align256(o + (vlab.empty() ? 1 : vlab.size()) * 4);
         off_lptr = o; o = align256(o + lptr.size() * 4);
         off_lent = o; o = align256(o + (lent.empty() ? 1 : lent.size()) * 4);
+        off_gord = o; o = align256(o + (gord.empty() ? 1 : gord.size()) * 4);
+        off_gedge = o; o = align256(o + (gedge.empty() ? 1 : gedge.size()) * 4);
         bytes = o;
     }
 
@@ -95,7 +99,160 @@ struct bp4_graph {
         v.nlog = nlog;
         return v;
     }
+
+    GatherTables gather_view(const void *dev) const
+    {
+        const char *b = static_cast<const char *>(dev);
+        GatherTables t;
+        t.gord = reinterpret_cast<const uint32_t *>(b + off_gord);
+        t.gedge = reinterpret_cast<const uint32_t *>(b + off_gedge);
+        return t;
+    }
 };
+
+// Walk order of the single-pass HBM kernel.  A qubit reads the other stored words of
+// each of its checks, which the check's other qubits read too; the re-reads are
+// served by L2 only while the check's qubits sit close together in the walk.
+// Breadth-first levels from a pseudo-peripheral qubit (the end of a repeated
+// farthest-first search; neighbours = qubits sharing a check, taken by increasing
+// degree) cut a lattice into thin slices; groups of B consecutive levels form bands,
+// and each band is walked breadth first along its length from a pseudo-peripheral
+// qubit of the band, so a check inside a band has its qubits a few positions apart
+// and only checks across two bands are re-read from far back.  B = 0 walks the levels
+// themselves (Cuthill-McKee).  The order with the fewest re-reads more than
+// kWalkReach positions after the previous read of the same check is kept.
+namespace {
+
+constexpr int kWalkReach = 24;
+
+struct WalkGraph {
+    int n = 0;
+    std::vector<std::vector<int32_t>> adj;     // neighbours by increasing degree
+    std::vector<std::vector<int32_t>> vchecks; // checks of each qubit
+};
+
+// Breadth-first search from s over the qubits with ok[v]; appends the visit order
+// to `out` and returns the depth.  lev: scratch, -1 outside the search.
+int32_t bfs_order(const WalkGraph &G, int32_t s, const std::vector<uint8_t> &ok, std::vector<int32_t> &lev,
+                  std::vector<int32_t> &out)
+{
+    const size_t b = out.size();
+    lev[s] = 0;
+    out.push_back(s);
+    for (size_t h = b; h < out.size(); ++h) {
+        const int32_t v = out[h];
+        for (int32_t u : G.adj[v])
+            if (ok[u] && lev[u] < 0) {
+                lev[u] = lev[v] + 1;
+                out.push_back(u);
+            }
+    }
+    return lev[out.back()];
+}
+
+// Pseudo-peripheral qubit of s's component among ok[]: repeated farthest-first
+// search (up to 8 rounds), ending at a least-degree qubit of the deepest level.
+int32_t peripheral(const WalkGraph &G, int32_t s, const std::vector<uint8_t> &ok)
+{
+    std::vector<int32_t> lev(G.n, -1), q;
+    int32_t depth = bfs_order(G, s, ok, lev, q);
+    for (int k = 0; k < 8; ++k) {
+        int32_t far = q.back();
+        for (int32_t v : q)
+            if (lev[v] == depth && G.adj[v].size() < G.adj[far].size()) far = v;
+        std::vector<int32_t> lev2(G.n, -1), q2;
+        const int32_t d2 = bfs_order(G, far, ok, lev2, q2);
+        if (d2 <= depth) break;
+        s = far;
+        depth = d2;
+        q.swap(q2);
+        lev.swap(lev2);
+    }
+    return s;
+}
+
+// Breadth-first walk of the qubits with ok[] (component by component, each from a
+// pseudo-peripheral start of least degree), appended to `order`; lev gets the depth.
+void walk_components(const WalkGraph &G, std::vector<uint8_t> ok, std::vector<int32_t> &order,
+                     std::vector<int32_t> *lev_out)
+{
+    std::vector<int32_t> lev(G.n, -1);
+    for (;;) {
+        int32_t s = -1;
+        for (int32_t v = 0; v < G.n; ++v)
+            if (ok[v] && (s < 0 || G.adj[v].size() < G.adj[s].size())) s = v;
+        if (s < 0) break;
+        s = peripheral(G, s, ok);
+        const size_t b = order.size();
+        bfs_order(G, s, ok, lev, order);
+        for (size_t h = b; h < order.size(); ++h) ok[order[h]] = 0;
+    }
+    if (lev_out) *lev_out = lev;
+}
+
+std::vector<int32_t> banded_walk(const WalkGraph &G, int B)
+{
+    std::vector<int32_t> cm, lev;
+    walk_components(G, std::vector<uint8_t>(G.n, 1), cm, &lev);
+    if (B <= 0) return cm;
+    int32_t maxlev = 0;
+    for (int32_t v = 0; v < G.n; ++v) maxlev = std::max(maxlev, lev[v]);
+    std::vector<int32_t> order;
+    order.reserve(G.n);
+    for (int32_t b = 0; b <= maxlev / B; ++b) {
+        std::vector<uint8_t> ok(G.n, 0);
+        for (int32_t v = 0; v < G.n; ++v) ok[v] = lev[v] / B == b;
+        walk_components(G, ok, order, nullptr);
+    }
+    return order;
+}
+
+// Re-reads of a check more than kWalkReach positions after its previous read.
+long far_rereads(const WalkGraph &G, const std::vector<int32_t> &order, int m)
+{
+    std::vector<int32_t> last(m, -1);
+    long far = 0;
+    for (int32_t i = 0; i < (int32_t)order.size(); ++i)
+        for (int32_t c : G.vchecks[order[i]]) {
+            if (last[c] >= 0 && i - last[c] > kWalkReach) ++far;
+            last[c] = i;
+        }
+    return far;
+}
+
+}  // namespace
+
+static std::vector<uint32_t> gather_walk(int n, int m, const std::vector<int32_t> &vptr,
+                                         const std::vector<uint32_t> &vchk, const std::vector<std::vector<int32_t>> &cq)
+{
+    WalkGraph G;
+    G.n = n;
+    G.adj.resize(n);
+    G.vchecks.resize(n);
+    for (int v = 0; v < n; ++v) {
+        for (int32_t s = vptr[v]; s < vptr[v + 1]; ++s) {
+            G.vchecks[v].push_back((int32_t)vchk[s]);
+            for (int32_t u : cq[vchk[s]])
+                if (u != v) G.adj[v].push_back(u);
+        }
+        std::sort(G.adj[v].begin(), G.adj[v].end());
+        G.adj[v].erase(std::unique(G.adj[v].begin(), G.adj[v].end()), G.adj[v].end());
+    }
+    for (int v = 0; v < n; ++v)
+        std::stable_sort(G.adj[v].begin(), G.adj[v].end(),
+                         [&](int32_t a, int32_t b) { return G.adj[a].size() < G.adj[b].size(); });
+    std::vector<int32_t> best;
+    long best_far = -1;
+    for (int B : {0, 3, 4, 5, 6, 8}) {
+        std::vector<int32_t> o = banded_walk(G, B);
+        const long f = far_rereads(G, o, m);
+        if (best_far < 0 || f < best_far) {
+            best_far = f;
+            best = o;
+        }
+    }
+    return std::vector<uint32_t>(best.begin(), best.end());
+}
 
 extern "C" {
 
@@ -317,12 +474,30 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
     }
     // packed check edges (ELL, padded)
     g->cedge.assign((size_t)m * g->cstride, edge_pad_word((int)nnz));
+    std::vector<int32_t> cpos_of_slot(nnz, 0);   // position of each message slot's edge in its check
     {
         std::vector<int> cfill(m, 0);
         for (long k = 0; k < nnz; ++k) {
             const int c = g->canon_chk[k];
             const uint32_t w = (uint32_t)slot_of[k] | ((uint32_t)g->canon_var[k] << 16) | (lab[k] << 30);
+            cpos_of_slot[slot_of[k]] = cfill[c];
             g->cedge[(size_t)c * g->cstride + cfill[c]++] = w;
+        }
+    }
+    // walk and gather words of the single-pass HBM kernel (narrow graphs)
+    if (!g->wide()) {
+        std::vector<std::vector<int32_t>> cq(m);
+        for (long k = 0; k < nnz; ++k) cq[g->canon_chk[k]].push_back(g->canon_var[k]);
+        g->gord = gather_walk(n, m, vptr, g->vchk, cq);
+        g->gedge.assign((size_t)4 * n, kGatherAbsent);
+        for (int i = 0; i < n; ++i) {
+            const int v = (int)g->gord[i];
+            for (int j = 0; j < vdeg[v]; ++j) {
+                const int32_t s = vptr[v] + j;
+                const uint32_t c = g->vchk[s];
+                const uint32_t pad = (0xFu << cdeg[c]) & 0xFu;
+                g->gedge[(size_t)4 * i + j] = (4u * c + (uint32_t)cpos_of_slot[s]) | (pad << 20);
+            }
         }
     }
     // packed qubit words
@@ -408,6 +583,8 @@ int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stre
     if (!g->vlab.empty()) std::memcpy(img.data() + g->off_vlab, g->vlab.data(), g->vlab.size() * 4);
     std::memcpy(img.data() + g->off_lptr, g->lptr.data(), g->lptr.size() * 4);
     if (!g->lent.empty()) std::memcpy(img.data() + g->off_lent, g->lent.data(), g->lent.size() * 4);
+    if (!g->gord.empty()) std::memcpy(img.data() + g->off_gord, g->gord.data(), g->gord.size() * 4);
+    if (!g->gedge.empty()) std::memcpy(img.data() + g->off_gedge, g->gedge.data(), g->gedge.size() * 4);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(dev_buf, img.data(), g->bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "graph_upload: hipMemcpyAsync");
@@ -511,6 +688,22 @@ int auto_kernel(const bp4_graph *g, int variant)
     if (!decode_lds_fits(g->m, g->n, kLdsBlock, 1)) return BP4_KERNEL_SOA;
     return decode_lds_layout(g->m, g->n, g->nnz, variant, kLdsBlock, 1).bytes > kLdsAutoLimit ? BP4_KERNEL_SOA
                                                                                       : BP4_KERNEL_LDS;
+}
+
+// LDS the single-pass HBM kernel may take per workgroup (the two per-check masks):
+// the 64 KB every workgroup is guaranteed.
+constexpr size_t kGatherMaxLds = 65536;
+
+bool gather_ok(const bp4_graph *g, int variant, int serial)
+{
+    return gather_supported(g->m, variant, serial, g->wide(), kGatherMaxLds);
+}
+
+// Large codes under AUTO: the single-pass HBM kernel where it applies (flooding, no
+// AEWA restarts, no verification outputs), else the two-phase SOA kernel.
+int large_kernel(const bp4_graph *g, int variant, int serial, bool verify)
+{
+    return !verify && gather_ok(g, variant, serial) ? BP4_KERNEL_GATHER : BP4_KERNEL_SOA;
 }
 
 // Serial schedule on the LDS kernel: wave groups of G in {1, 2, 4, ..., 64} lanes.
@@ -623,17 +816,21 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
     if (!ws) return fail(BP4_EINVAL, "decode: NULL workspace");
     if (ws_bytes < kSmallWorkspace) return fail(BP4_EWORKSPACE, "decode: workspace %zu < %zu bytes", ws_bytes, kSmallWorkspace);
     int32_t requested = 0, requested_S = 0, lds_floor = 0, kernel = BP4_KERNEL_AUTO, soa_lanes = 0, soa_block = 0;
+    int32_t gather_waves = 0;
     if (tune) {
-        for (int i = 0; i < 2; ++i)
-            if (tune->reserved[i]) return fail(BP4_EINVAL, "decode: reserved tuning fields must be 0");
+        if (tune->reserved) return fail(BP4_EINVAL, "decode: reserved tuning fields must be 0");
         lds_floor = tune->lds_bytes;
         if (lds_floor < 0) return fail(BP4_EINVAL, "decode: negative lds_bytes");
         kernel = tune->kernel;
-        if (kernel != BP4_KERNEL_AUTO && kernel != BP4_KERNEL_LDS && kernel != BP4_KERNEL_SOA)
+        if (kernel != BP4_KERNEL_AUTO && kernel != BP4_KERNEL_LDS && kernel != BP4_KERNEL_SOA &&
+            kernel != BP4_KERNEL_GATHER)
             return fail(BP4_EINVAL, "decode: kernel %d unknown", kernel);
         soa_lanes = tune->soa_lanes;
         soa_block = tune->soa_iter_block;
         if (soa_lanes < 0 || soa_block < 0) return fail(BP4_EINVAL, "decode: negative soa_lanes or soa_iter_block");
+        gather_waves = tune->gather_waves;
+        if (gather_waves != 0 && gather_waves != 4 && gather_waves != 8 && gather_waves != 16)
+            return fail(BP4_EINVAL, "decode: gather_waves %d not 0, 4, 8 or 16", gather_waves);
         requested = tune->group_lanes;
         requested_S = tune->block_shots;
         if (!p->serial) {
@@ -642,15 +839,39 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         }
     }
     const bool lds_knobs = requested || requested_S || lds_floor, soa_knobs = soa_lanes || soa_block;
-    if (lds_knobs && soa_knobs) return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields exclude each other");
-    if (kernel == BP4_KERNEL_AUTO)
+    const bool gather_knobs = gather_waves != 0, verify = q_out || mvc_out;
+    if ((int)lds_knobs + (int)soa_knobs + (int)gather_knobs > 1)
+        return fail(BP4_EINVAL, "decode: LDS, SOA and gather tuning fields exclude each other");
+    if (kernel == BP4_KERNEL_AUTO) {
         kernel = lds_knobs ? BP4_KERNEL_LDS
                  : soa_knobs ? BP4_KERNEL_SOA
+                 : gather_knobs ? BP4_KERNEL_GATHER
                  : p->serial ? serial_auto_kernel(g, p->variant) : auto_kernel(g, p->variant);
+        if (kernel == BP4_KERNEL_SOA && !soa_knobs) kernel = large_kernel(g, p->variant, p->serial, verify);
+    }
     if (kernel == BP4_KERNEL_LDS && soa_knobs)
         return fail(BP4_EINVAL, "decode: soa_lanes and soa_iter_block apply to the SOA kernel");
+    if (kernel != BP4_KERNEL_GATHER && gather_knobs)
+        return fail(BP4_EINVAL, "decode: gather_waves applies to the single-pass HBM kernel");
     if (g->wide() && (kernel != BP4_KERNEL_LDS || p->serial))
         return fail(BP4_EUNSUPPORTED, "decode: graphs with degrees above 4 run the flooding LDS kernel only");
+    if (kernel == BP4_KERNEL_GATHER) {
+        if (lds_knobs || soa_knobs)
+            return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields do not apply to the single-pass HBM kernel");
+        if (!gather_ok(g, p->variant, p->serial))
+            return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel runs flooding BP, Momentum, AdaGrad and "
+                                          "EWAInit on codes of at most %zu checks",
+                        (kGatherMaxLds - 64 * 4) / 16 - 1);
+        if (verify) return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel writes no q_out, mvc_out or mcv_out");
+        const size_t need = gather_workspace_bytes(g->m, g->n, p->variant, shots, gather_waves);
+        if (ws_bytes < need)
+            return fail(BP4_EWORKSPACE, "decode: single-pass HBM workspace %zu < %zu bytes", ws_bytes, need);
+        hipError_t e = launch_decode_gather(g->view(dev_graph), g->gather_view(dev_graph), *p, (int32_t)shots,
+                                           prior_llr, synd, est, conv, iters, ws, gather_waves, g->with_y,
+                                           static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "decode: single-pass HBM launch");
+        return BP4_OK;
+    }
     if (kernel == BP4_KERNEL_SOA) {
         if (lds_knobs) return fail(BP4_EINVAL, "decode: group_lanes, block_shots and lds_bytes apply to the LDS kernel");
         const size_t need = soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, soa_lanes);
@@ -707,8 +928,24 @@ int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, 
     int rc = check_params(p);
     if (rc) return rc;
     if (shots < 0) return fail(BP4_EINVAL, "workspace_bytes: negative shots");
-    const int k = p->serial ? serial_auto_kernel(g, p->variant) : auto_kernel(g, p->variant);
-    *bytes = k == BP4_KERNEL_SOA ? soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, 0) : kSmallWorkspace;
+    int k = p->serial ? serial_auto_kernel(g, p->variant) : auto_kernel(g, p->variant);
+    if (k == BP4_KERNEL_SOA) k = large_kernel(g, p->variant, p->serial, false);
+    *bytes = k == BP4_KERNEL_SOA      ? soa_workspace_bytes(g->m, g->n, g->nnz, p->variant, shots, 0)
+             : k == BP4_KERNEL_GATHER ? gather_workspace_bytes(g->m, g->n, p->variant, shots, 0)
+                                      : kSmallWorkspace;
+    return BP4_OK;
+}
+
+int bp4_gather_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, int32_t gather_waves,
+                               size_t *bytes)
+{
+    if (!g || !bytes) return fail(BP4_EINVAL, "gather_workspace_bytes: NULL argument");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (shots < 0) return fail(BP4_EINVAL, "gather_workspace_bytes: negative shots");
+    if (gather_waves != 0 && gather_waves != 4 && gather_waves != 8 && gather_waves != 16)
+        return fail(BP4_EINVAL, "gather_workspace_bytes: gather_waves %d not 0, 4, 8 or 16", gather_waves);
+    *bytes = gather_workspace_bytes(g->m, g->n, p->variant, shots, gather_waves);
     return BP4_OK;
 }
 

@@ -1,0 +1,49 @@
+// Internal declarations of the single-pass HBM decode kernel (large codes).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bp4.h"
+#include "bp4_internal.h"
+
+namespace bp4 {
+
+// Gather edge word of the qubit at one position of the walk, one per edge slot j of
+// the qubit (slots in increasing check order, as in the packed qubit word):
+// bits 0-19 the edge's check-major message item 4c + p (p: the edge's position in
+// check c), bits 20-23 the padding positions of check c (bit k: position k holds no
+// edge), bit 31 set for slots j >= the qubit's degree (the rest of the word is then
+// 0x00F00000: check 0, all positions padding).
+constexpr uint32_t kGatherAbsent = 0x80F00000u;
+__host__ __device__ inline uint32_t gather_item(uint32_t w) { return w & 0xFFFFFu; }
+__host__ __device__ inline uint32_t gather_pad(uint32_t w) { return (w >> 20) & 0xFu; }
+
+// Device tables of the walk: gord[i] the qubit at position i, gedge[4 i + j] its
+// gather words.
+struct GatherTables {
+    const uint32_t *gord;
+    const uint32_t *gedge;
+};
+
+// Wavefronts per workgroup: all of them walk the qubits of the same 64 shots.
+constexpr int kGatherDefaultWaves = 16;
+constexpr int kGatherMaxWaves = 16;
+// CUs the persistent grid is sized for.
+constexpr int kGatherCUs = 256;
+
+// Whether the kernel takes this code, variant and schedule: flooding, no AEWA
+// restarts, check and qubit degrees <= 4 and the two per-check bit masks within
+// the workgroup's LDS (max_lds bytes).
+bool gather_supported(int m, int variant, int serial, bool wide, size_t max_lds);
+// LDS bytes per workgroup.
+size_t gather_lds_bytes(int m);
+// Workgroups (64 shots each) in flight for `shots` shots and `waves` wavefronts
+// per workgroup (0: default).
+int32_t gather_groups(int64_t shots, int32_t waves);
+size_t gather_workspace_bytes(int m, int n, int variant, int64_t shots, int32_t waves);
+hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, const bp4_params &p, int32_t shots,
+                                const float *prior, const uint8_t *synd, uint8_t *est, uint8_t *conv,
+                                int32_t *iters, void *ws, int32_t waves, int with_y, hipStream_t s);
+
+}  // namespace bp4

@@ -1,0 +1,437 @@
+// Flooding GF(4) BP for large codes in one pass over HBM per iteration.
+//
+// One lane decodes one shot; the 64 lanes of a workgroup's wavefronts are its 64
+// columns, and every wavefront of the workgroup works on the same 64 shots.  Each
+// column keeps, in HBM, two records (iterations alternate between them) laid out
+// [item][64 lanes]: the check-major message items 4c + p, each holding the stored
+// word of m_{v->c} (phi(|m|) with the sign bit of m), then the posterior state
+// (and the momentum or AdaGrad accumulator) by walk position.
+//
+// An iteration walks the qubits in a Cuthill-McKee order, the workgroup's
+// wavefronts taking positions round robin, so the qubits in flight at any time sit
+// close together on the lattice.  A qubit reads the other stored words of each of
+// its checks from the previous record (eq. h_update in phi form: the sign is the
+// syndrome bit times the other signs, the magnitude phi of the sum of the other
+// phi values, summed in value order), forms its posterior (eqs. p_update, EWAInit,
+// mombp1-3, boost), and writes its new posterior and the stored words of its new
+// messages m_{v->c} = lambda(Q - m_{c->v}) (eq. v_update) to the other record.
+// Each stored word is written once and read by the check's other qubits within a
+// short stretch of the walk, so the re-reads are served by L2: HBM sees each
+// message read and written once, and the posterior read and written once, per
+// iteration (8E + 24N bytes per shot-iteration for EWAInit).
+//
+// The syndrome test of Algorithm 2 runs in the same pass: for each edge, a ballot
+// over the lanes of whether the qubit's decision anticommutes with the edge label
+// is XORed into the check's 64-bit parity word in LDS; after the walk every
+// check's parity word is compared with its syndrome word.  A column whose shot
+// meets the syndrome (or reaches iter_max) writes its decisions and takes the
+// next shot from the queue at once; its next iteration reads the initial messages
+// lambda(Pi) from a per-code table instead of its record.  Results do not depend
+// on the column a shot runs in, the walk order or the workgroup shape, and equal
+// those of the two-phase kernels bit for bit (same arithmetic in the same order).
+//
+// Paper: Chen, Yi, Liang, Wang, "Improved Belief Propagation Decoding
+// Algorithms for Surface Codes", section II-B1 (eqs. init, h_update, v_update,
+// p_update), section III (eqs. mombp1-3, boost, EWAInit, Algorithm 2).
+#include "bp4_math.h"
+#include "bp4_gather.h"
+
+namespace bp4 {
+namespace {
+
+constexpr uint32_t kSign = 0x80000000u;
+// Steps of the walk between two pacing barriers of the workgroup (even; 0: none).
+constexpr int kPaceSteps = 4;
+// Resident wavefronts per SIMD the kernel is built for (its register budget), and so
+// per CU 4 x this many, in workgroups of 64 x gather_waves lanes.  Each wavefront
+// has one qubit's reads in flight at a time; eight per SIMD hide the HBM latency
+// (measured: a two-deep software pipeline at four per SIMD was slower).
+constexpr int kWavesPerSimd = 8;
+
+template <typename T> using konst = const __attribute__((address_space(4))) T;
+template <typename T> __device__ __forceinline__ konst<T> *as_const(const T *p) { return (konst<T> *)p; }
+
+// Stored word of a message m: phi(|m|) carrying the sign bit of m.
+__device__ __forceinline__ float stored_word(float m)
+{
+    return __uint_as_float(__float_as_uint(phi(fabsf(m))) | (__float_as_uint(m) & kSign));
+}
+
+struct GatherArgs {
+    const uint32_t *vinfo;    // [n] packed qubit words
+    const uint32_t *gord;     // [n] qubit at each walk position
+    const uint32_t *gedge;    // [n][4] gather words
+    const float *prior;       // [n][3]
+    float *finit;             // [4m] stored words of the initial messages
+    const uint8_t *synd;      // [shots][m]
+    uint8_t *est;             // [shots][n]
+    uint8_t *conv;            // [shots]
+    int32_t *iters;           // [shots]
+    unsigned int *head;       // shot queue (zeroed before the launch)
+    char *recs;               // [group][2][items][64] words
+    int32_t m, n, shots, max_iter, stop, with_y;
+    int32_t st_off, acc_off;  // first posterior and accumulator items
+    uint32_t rec_bytes;       // bytes of one record: items x 256
+    float clamp;
+    VariantParams vp;
+};
+
+// Initial stored words lambda_{H_cv}(Pi_v) of every edge (eq. init), by walk position.
+__global__ void gather_init_kernel(GatherArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint32_t v = a.gord[i];
+    const uint32_t info = a.vinfo[v];
+    const float p3[3] = {a.prior[3 * v], a.prior[3 * v + 1], a.prior[3 * v + 2]};
+    float lam[4];
+    qubit_lambdas(p3, var_labels_present(info), lam);
+    const uint32_t deg = var_deg(info);
+    for (uint32_t j = 0; j < deg; ++j) {
+        const uint32_t w = a.gedge[4 * i + j];
+        a.finit[gather_item(w)] = stored_word(clampf(lam[var_lab(info, j)], a.clamp));
+    }
+}
+
+// What the update of one qubit reads: its walk entry (wavefront-uniform) and, per
+// lane, the other stored words of each of its checks and its state.
+struct QubitIn {
+    uint32_t v, info, ew[4];
+    float p3[3];
+    float x[4][3];
+    float s3[3], a3[3];
+};
+
+// One record item of this lane: `base` is the workgroup's record block (uniform),
+// `off` the lane's byte offset within it (record parity and lane).
+__device__ __forceinline__ float ld_item(const char *base, uint32_t item, uint32_t off)
+{
+    return *reinterpret_cast<const float *>(base + (size_t)item * 256 + off);
+}
+__device__ __forceinline__ void st_item(char *base, uint32_t item, uint32_t off, float x)
+{
+    __builtin_nontemporal_store(x, reinterpret_cast<float *>(base + (size_t)item * 256 + off));
+}
+
+template <int VAR>
+__global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_gather_kernel(GatherArgs a)
+{
+    extern __shared__ uint64_t lds[];
+    const int m = a.m, n = a.n;
+    uint64_t *S = lds;               // [m] syndrome bit of each column's shot, per check
+    uint64_t *P = lds + m;           // [m] parity of the decisions, per check
+    uint64_t *U = lds + 2 * m;       // [2] columns failing the test, alternate iterations
+    int32_t *col = reinterpret_cast<int32_t *>(lds + 2 * m + 2);   // [64] shot of each column
+    const int lane = threadIdx.x & 63;
+    // wavefront index, uniform across the wavefront (read from lane 0 so the compiler
+    // keeps the walk positions, and every table read and branch on them, scalar)
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int W = blockDim.x >> 6;
+    const float C = a.clamp;
+    constexpr bool kAcc = VAR == BP4_MOMENTUM || VAR == BP4_ADAGRAD;
+    const bool with_y = a.with_y != 0;
+    VariantParams vp = a.vp;
+    vp.variant = VAR;
+
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+        S[c] = 0;
+        P[c] = 0;
+    }
+    if (threadIdx.x < 64) col[threadIdx.x] = -1;
+    if (threadIdx.x == 0) U[0] = U[1] = 0;
+    __syncthreads();
+
+    char *rec = a.recs + (size_t)blockIdx.x * 2 * a.rec_bytes;
+    konst<uint32_t> *vinfo = as_const(a.vinfo);
+    konst<uint32_t> *gord = as_const(a.gord);
+    konst<uint32_t> *gedge = as_const(a.gedge);
+    konst<float> *prior = as_const(a.prior);
+    konst<float> *finit = as_const(a.finit);
+
+    int shot = -1, t = 0, cur = 0;
+    // Record parity from the workgroup's pass count, the same in every lane (a lane's
+    // own iteration count would split a wavefront's accesses over both records):
+    // every live column advances one iteration per pass, so the record a pass writes
+    // is the one the next pass reads; a new shot reads the initial table instead.
+    uint32_t pass = 0;
+    bool finish = false;
+    bool drained = false;            // wavefront 0: the queue is empty
+    for (;;) {
+        // ---- columns without a shot take the next ones from the queue ------------------
+        if (wv == 0) {
+            const bool want = shot < 0 || finish;
+            const uint64_t wm = __ballot(want);
+            int ns = want ? -1 : shot;
+            if (wm != 0 && !drained) {
+                const unsigned cnt = (unsigned)__popcll(wm);
+                unsigned base = 0;
+                if (lane == 0) base = atomicAdd(a.head, cnt);
+                base = (unsigned)__shfl((int)base, 0, 64);
+                const unsigned r = base + (unsigned)__popcll(wm & ((1ull << lane) - 1ull));
+                if (want && r < (unsigned)a.shots) ns = (int)r;
+                drained = base + cnt >= (unsigned)a.shots;
+            }
+            col[lane] = ns;
+        }
+        __syncthreads();
+        const int ns = col[lane];
+        const bool refill = ns >= 0 && (shot < 0 || finish);
+        shot = ns;
+        finish = false;
+        if (__ballot(shot >= 0) == 0) break;   // every column empty (the same in every wavefront)
+        if (refill) t = 0;
+        // syndrome words of the new shots
+        if (__ballot(refill) != 0) {
+            for (int c = wv; c < m; c += W) {
+                uint32_t bit = (uint32_t)(S[c] >> lane) & 1u;
+                if (refill) bit = a.synd[(size_t)shot * m + c] & 1u;
+                const uint64_t word = __ballot(bit);
+                if (lane == 0) S[c] = word;
+            }
+        }
+        __syncthreads();
+        ++t;
+
+        // ---- one flooding iteration over the walk ------------------------------------
+        const bool fresh = t == 1;
+        const uint32_t fresh_mask = fresh ? ~0u : 0u;
+        const uint32_t lane_off = (uint32_t)lane * 4u;
+        const uint32_t rd = lane_off + (pass & 1u) * a.rec_bytes;
+        const uint32_t wr = lane_off + ((pass + 1u) & 1u) * a.rec_bytes;
+        ++pass;
+        uint64_t nan_cols = 0;
+        // Reads of a qubit: its walk entry (scalar), the other stored words of each of
+        // its checks and its state from the record the pass reads.
+        auto load_qubit = [&](int i, QubitIn &q) {
+            q.v = gord[i];
+            q.info = vinfo[q.v];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q.ew[j] = gedge[4 * i + j];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) q.p3[k] = prior[3 * q.v + k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t item = gather_item(q.ew[j]);
+                const uint32_t c4 = item & ~3u, p = item & 3u;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    // the k-th position of the check other than p (k, or k + 1 past p)
+                    const uint32_t pk = (uint32_t)k + (((p - (uint32_t)k - 1u) >> 31) & 1u);
+                    // Every word is read, padding positions too (masked in the update),
+                    // so the loads form one straight run; a new shot takes the initial
+                    // word by a bit select (a per-lane branch would split the loads).
+                    const uint32_t rv = __float_as_uint(ld_item(rec, c4 + pk, rd));
+                    const uint32_t iv = __float_as_uint(finit[c4 + pk]);
+                    q.x[j][k] = __uint_as_float((iv & fresh_mask) | (rv & ~fresh_mask));
+                }
+            }
+            if (VAR != BP4_BP) {   // EWAInit: Q^{(t-1)}, unused at t = 1
+#pragma unroll
+                for (int k = 0; k < 3; ++k) q.s3[k] = ld_item(rec, a.st_off + 3 * i + k, rd);
+            }
+            if (kAcc) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) q.a3[k] = ld_item(rec, a.acc_off + 3 * i + k, rd);
+            }
+        };
+        // Update of a qubit from its reads: incoming messages, posterior, parity
+        // contributions, outgoing messages; writes to the record the pass writes.
+        auto update_qubit = [&](int i, QubitIn &q) {
+            const uint32_t deg = var_deg(q.info);
+            float s3[3], a3[3];
+            qubit_state_init(VAR, q.p3, s3, a3);
+            if (VAR != BP4_BP) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s3[k] = fresh ? s3[k] : q.s3[k];
+            }
+            if (kAcc) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) a3[k] = fresh ? a3[k] : q.a3[k];
+            }
+            // check-to-qubit messages (eq. h_update)
+            float mc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t item = gather_item(q.ew[j]), p = item & 3u, pad = gather_pad(q.ew[j]);
+                const uint32_t c = item >> 2;
+                const uint32_t sb = (uint32_t)(S[c] >> lane) & 1u;
+                float x[3];   // padding: +0
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const uint32_t pk = (uint32_t)k + (((p - (uint32_t)k - 1u) >> 31) & 1u);
+                    x[k] = ((pad >> pk) & 1u) ? 0.0f : q.x[j][k];
+                }
+                const uint32_t sgn =
+                    ((__float_as_uint(x[0]) ^ __float_as_uint(x[1]) ^ __float_as_uint(x[2])) & kSign) ^ (sb << 31);
+                const float mag = phi(sum3_canonical(fabsf(x[0]), fabsf(x[1]), fabsf(x[2])));
+                mc[j] = (uint32_t)j < deg ? clampf(__uint_as_float(__float_as_uint(mag) ^ sgn), C) : 0.0f;
+            }
+            float S4[4], A4[4], qn[3];
+            label_sums(q.info, mc, with_y, VAR == BP4_ADAGRAD, S4, A4);
+            qubit_posterior(vp, t, q.p3, S4, A4, s3, a3, qn);
+            // every variant keeps its posterior state (BP its posterior, for the decisions)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) st_item(rec, a.st_off + 3 * i + k, wr, VAR == BP4_BP ? qn[k] : s3[k]);
+            if (kAcc) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) st_item(rec, a.acc_off + 3 * i + k, wr, a3[k]);
+            }
+            // this qubit's share of every check's parity (Algorithm 2)
+            const uint32_t db = decision_byte_of(qn);
+            nan_cols |= __ballot(db & 1u);
+            float lam[4];
+            qubit_lambdas(qn, var_labels_present(q.info), lam);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if ((uint32_t)j >= deg) break;
+                const uint32_t lab = var_lab(q.info, j);
+                const uint64_t flip = __ballot((db >> lab) & 1u);
+                if (flip != 0 && lane == 0)
+                    atomicXor(reinterpret_cast<unsigned long long *>(&P[gather_item(q.ew[j]) >> 2]),
+                              (unsigned long long)flip);
+                // new message (eq. v_update) and its stored word
+                const float out = clampf(lam[lab] - mc[j], C);
+                st_item(rec, gather_item(q.ew[j]), wr, stored_word(out));
+            }
+        };
+        // The walk.  Step s takes positions s W .. s W + W - 1, one per wavefront; every
+        // kPaceSteps steps the wavefronts meet at a barrier, so they stay within a
+        // few steps of each other and the re-reads of a check by its other qubits
+        // still find it in L2.
+        const int steps = (n + W - 1) / W;
+        QubitIn qa;
+        for (int st = 0; st < steps; ++st) {
+            const int i0 = st * W + wv;
+            if (i0 < n) {
+                load_qubit(i0, qa);
+                update_qubit(i0, qa);
+            }
+            if (kPaceSteps > 0 && (st + 1) % kPaceSteps == 0) __builtin_amdgcn_s_barrier();
+        }
+        __syncthreads();
+
+        // ---- syndrome test -------------------------------------------------------------
+        uint64_t bad = nan_cols;
+        for (int c = wv; c < m; c += W) {
+            bad |= P[c] ^ S[c];
+            if (lane == 0) P[c] = 0;
+        }
+        if (lane == 0 && bad != 0) atomicOr(reinterpret_cast<unsigned long long *>(&U[cur]), (unsigned long long)bad);
+        __syncthreads();
+        const bool sat = ((U[cur] >> lane) & 1ull) == 0;
+        finish = shot >= 0 && ((a.stop && sat) || t >= a.max_iter);
+        if (__ballot(finish) != 0) {
+            // hard decisions of the finished shots from the posterior just written
+            for (int i = wv; i < n; i += W) {
+                if (!finish) continue;
+                const uint32_t v = gord[i];
+                float q[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const float sv = ld_item(rec, a.st_off + 3 * i + k, wr);
+                    q[k] = VAR == BP4_ADAGRAD ? prior[3 * v + k] + sv : sv;
+                }
+                a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(decision_byte_of(q));
+            }
+            if (wv == 0 && finish) {
+                a.conv[shot] = sat ? 1 : 0;
+                a.iters[shot] = t;
+            }
+        }
+        if (threadIdx.x == 0) U[cur ^ 1] = 0;
+        cur ^= 1;
+    }
+}
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int32_t record_items(int m, int n, int variant, int32_t *st_off, int32_t *acc_off)
+{
+    int32_t o = 4 * m;
+    *st_off = o;
+    o += 3 * n;
+    *acc_off = o;
+    if (variant == BP4_MOMENTUM || variant == BP4_ADAGRAD) o += 3 * n;
+    return o;
+}
+
+int32_t waves_of(int32_t waves) { return waves > 0 ? waves : kGatherDefaultWaves; }
+
+}  // namespace
+
+size_t gather_lds_bytes(int m) { return (size_t)(2 * m + 2) * 8 + 64 * 4; }
+
+bool gather_supported(int m, int variant, int serial, bool wide, size_t max_lds)
+{
+    return !serial && !wide && variant != BP4_AEWA && gather_lds_bytes(m) <= max_lds;
+}
+
+int32_t gather_groups(int64_t shots, int32_t waves)
+{
+    const int64_t per_cu = 4 * kWavesPerSimd / waves_of(waves);   // workgroups per CU
+    const int64_t cap = (int64_t)kGatherCUs * (per_cu > 0 ? per_cu : 1);
+    const int64_t need = (shots + 63) / 64;
+    const int64_t g = need < cap ? need : cap;
+    return (int32_t)(g > 0 ? g : 1);
+}
+
+// Workspace: the queue head, the initial-message table, the column records.
+size_t gather_workspace_bytes(int m, int n, int variant, int64_t shots, int32_t waves)
+{
+    int32_t st_off, acc_off;
+    const size_t items = (size_t)record_items(m, n, variant, &st_off, &acc_off);
+    return 256 + up256((size_t)4 * m * 4) + (size_t)gather_groups(shots, waves) * 2 * items * 256;
+}
+
+hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, const bp4_params &p, int32_t shots,
+                                const float *prior, const uint8_t *synd, uint8_t *est, uint8_t *conv,
+                                int32_t *iters, void *ws, int32_t waves, int with_y, hipStream_t s)
+{
+    GatherArgs a;
+    a.vinfo = g.vinfo;
+    a.gord = gt.gord;
+    a.gedge = gt.gedge;
+    a.prior = prior;
+    char *w = static_cast<char *>(ws);
+    a.head = reinterpret_cast<unsigned int *>(w);
+    w += 256;
+    a.finit = reinterpret_cast<float *>(w);
+    w += up256((size_t)4 * g.m * 4);
+    a.recs = w;
+    a.synd = synd;
+    a.est = est;
+    a.conv = conv;
+    a.iters = iters;
+    a.m = g.m;
+    a.n = g.n;
+    a.shots = shots;
+    a.max_iter = p.max_iter;
+    a.stop = p.stop_on_syndrome ? 1 : 0;
+    a.with_y = with_y;
+    const int32_t items = record_items(g.m, g.n, p.variant, &a.st_off, &a.acc_off);
+    a.rec_bytes = (uint32_t)items * 256u;
+    a.clamp = p.llr_clamp;
+    a.vp.variant = p.variant;
+    a.vp.g_from_t1 = p.adagrad_g_from_t1;
+    a.vp.alpha = p.alpha;
+    a.vp.gamma = p.gamma;
+    a.vp.eps = p.eps;
+
+    hipError_t e = launch_zero_u32(a.head, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gather_init_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int32_t W = waves_of(waves);
+    const dim3 grid((unsigned)gather_groups(shots, waves)), block((unsigned)(64 * W));
+    const size_t lds = gather_lds_bytes(g.m);
+    switch (p.variant) {
+    case BP4_BP: hipLaunchKernelGGL(decode_gather_kernel<BP4_BP>, grid, block, lds, s, a); break;
+    case BP4_MOMENTUM: hipLaunchKernelGGL(decode_gather_kernel<BP4_MOMENTUM>, grid, block, lds, s, a); break;
+    case BP4_ADAGRAD: hipLaunchKernelGGL(decode_gather_kernel<BP4_ADAGRAD>, grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL(decode_gather_kernel<BP4_EWAINIT>, grid, block, lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bp4

@@ -175,12 +175,17 @@ def test_mixed_and_plain_validation_without_gpu(lib):
                                 null, ctypes.byref(it)) == -4
 
 
-def test_large_codes_take_the_soa_kernel(lib):
-    """Codes whose LDS image exceeds the automatic limit get the SOA kernel: its workspace
-    holds every message and qubit state per resident lane and grows with the variant."""
+def test_large_codes_take_the_hbm_kernels(lib):
+    """Codes whose LDS image exceeds the automatic limit run from HBM.  The two-phase SOA
+    kernel's workspace holds every message and qubit state per resident lane and grows
+    with the variant; the automatic choice for flooding BP, Momentum, AdaGrad and EWAInit
+    is the single-pass kernel, whose workspace is two 64-column records per workgroup in
+    flight (32 wavefronts per CU; 4 message words per check, 3 posterior words per
+    qubit, 3 more for the Momentum and AdaGrad accumulators)."""
     from paper_2407_11523_amd import Graph, Params
     c = qecgen.planar(31)
     g = Graph(c.hx, c.hz, upload=False)
+    m, n = c.hx.shape
     shots = 1 << 18
     sizes = {}
     for v in ("bp", "ewainit", "momentum", "adagrad"):
@@ -188,7 +193,27 @@ def test_large_codes_take_the_soa_kernel(lib):
         b = ctypes.c_size_t()
         assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, 0, ctypes.byref(b)) == 0
         sizes[v] = b.value
-        assert g.workspace_bytes(prm, shots) == b.value
+        items = 4 * m + 3 * n + (3 * n if v in ("momentum", "adagrad") else 0)
+        head = 256 + (4 * m * 4 + 255) // 256 * 256
+        # 32 wavefronts per CU: 512 workgroups of 16 in flight, 1024 of 8, or one per 64 shots
+        want = head + 512 * 2 * items * 256
+        assert g.gather_workspace_bytes(prm, shots) == want
+        assert g.workspace_bytes(prm, shots) == want
+        assert g.gather_workspace_bytes(prm, 100) == head + 2 * 2 * items * 256
+        assert g.gather_workspace_bytes(prm, shots, 8) == head + 1024 * 2 * items * 256
+    # the serial schedule and AEWA keep the SOA kernel
+    ser = Params(variant="ewainit", alpha=0.5, serial=True)
+    b = ctypes.c_size_t()
+    assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(ser.c()), shots, 0, ctypes.byref(b)) == 0
+    assert g.workspace_bytes(ser, shots) == b.value
+    ae = Params(variant="aewa", alpha=0.5, alpha_last=0.9, alpha_steps=3)
+    assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(ae.c()), shots, 0, ctypes.byref(b)) == 0
+    assert g.workspace_bytes(ae, shots) == b.value
+    prm = Params(variant="bp")
+    for bad in (-1, 2, 32):
+        assert lib.bp4_gather_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, bad, ctypes.byref(b)) == -1
+    assert b"gather_waves" in lib.bp4_last_error() or b"negative" in lib.bp4_last_error()
+    assert lib.bp4_gather_workspace_bytes(g.handle, ctypes.byref(prm.c()), -1, 0, ctypes.byref(b)) == -1
     # BP: messages (nnz + 1 slots) + decisions + syndrome bits; EWAInit adds Q; the others add a second state
     lanes = shots
     # two records per lane (running and packed), plus decisions
@@ -198,7 +223,6 @@ def test_large_codes_take_the_soa_kernel(lib):
     assert sizes["adagrad"] == sizes["momentum"]
     # fewer lanes in flight: proportionally smaller
     b = ctypes.c_size_t()
-    prm = Params(variant="bp")
     assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, 1 << 14, ctypes.byref(b)) == 0
     assert b.value * 15 < sizes["bp"] < b.value * 17
     assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, -1, ctypes.byref(b)) == -1
@@ -206,6 +230,42 @@ def test_large_codes_take_the_soa_kernel(lib):
     s = qecgen.planar(13)
     gs = Graph(s.hx, s.hz, upload=False)
     assert gs.workspace_bytes(Params(variant="ewainit", alpha=0.5), shots) == 256
+
+
+def test_gather_kernel_validation_without_gpu(lib):
+    """The single-pass HBM kernel's argument checks run before any launch: no verification
+    outputs, no serial schedule or AEWA, gather_waves in {0, 4, 8, 16}, its own workspace
+    size, and its tuning field excludes the LDS and SOA ones."""
+    from paper_2407_11523_amd import Graph, Params, _lib
+    c = qecgen.toric(32)
+    g = Graph(c.hx, c.hz, upload=False)
+    fake = ctypes.c_void_p(1 << 20)
+    null = ctypes.c_void_p(0)
+    cp = Params(variant="ewainit", alpha=0.6).c()
+    need = g.gather_workspace_bytes(Params(variant="ewainit", alpha=0.6), 1000)
+
+    def dec(tune, q=null, ws_bytes=need, params=cp):
+        return lib.bp4_decode_ex(g.handle, fake, ctypes.byref(params), ctypes.byref(tune), 1000, fake, fake, fake,
+                                 fake, fake, q, q, q, fake, ws_bytes, null)
+
+    assert dec(_lib.Tuning(0, 0, 3), q=fake) == -6                      # verification outputs
+    assert b"q_out" in lib.bp4_last_error()
+    assert dec(_lib.Tuning(0, 0, 3), ws_bytes=need - 1) == -4           # workspace too small
+    assert dec(_lib.Tuning(0, 0, 3, 0, 0, 0, 5)) == -1                  # gather_waves 5
+    assert dec(_lib.Tuning(0, 0, 2, 0, 0, 0, 8)) == -1                  # gather_waves with SOA
+    assert dec(_lib.Tuning(0, 0, 1, 0, 0, 0, 8)) == -1                  # gather_waves with LDS
+    assert dec(_lib.Tuning(0, 0, 0, 1024, 0, 0, 8)) == -1               # SOA and gather fields together
+    assert dec(_lib.Tuning(64, 0, 3)) == -1                             # LDS field with the gather kernel
+    assert dec(_lib.Tuning(0, 0, 3, 0, 0, 0, 0, 1)) == -1               # reserved
+    ser = Params(variant="ewainit", alpha=0.6, serial=True).c()
+    assert dec(_lib.Tuning(0, 0, 3), params=ser) == -6                  # serial schedule
+    ae = Params(variant="aewa", alpha=0.5, alpha_last=0.9, alpha_steps=3).c()
+    assert dec(_lib.Tuning(0, 0, 3), params=ae) == -6                   # AEWA restarts
+    # wide graphs: LDS kernel only
+    bb = qecgen.bb(72)
+    gw = Graph(bb.hx, bb.hz, upload=False)
+    assert lib.bp4_decode_ex(gw.handle, fake, ctypes.byref(cp), ctypes.byref(_lib.Tuning(0, 0, 3)), 1000, fake,
+                             fake, fake, fake, fake, null, null, null, fake, 1 << 30, null) == -6
 
 
 def test_mixed_rejects_soa_only_codes(lib):

@@ -1,0 +1,146 @@
+"""GPU: the single-pass HBM kernel for large codes.
+
+It evaluates the same per-node arithmetic in the same order as the two-phase
+kernels (a qubit gathers its checks' other stored words phi(|m|) and sums them in
+value order, exactly as the check pass sums them), so its hard decisions,
+convergence flags and iteration counts must equal the SOA kernel's (and on codes
+both run, the LDS kernel's) bit for bit, for every variant, shot count, workgroup
+shape and stopping rule.  The oracle bar on the full large-code batch is in
+test_gpu_soa.py (test_large_codes_full_batch_sampled, run for both HBM kernels).
+"""
+import sys
+
+import pytest
+
+import qecgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2407_11523_amd as P  # noqa: E402
+
+VARIANTS = [("bp", 1.0, 0.0), ("ewainit", 0.6, 0.0), ("momentum", 0.6, 0.3), ("adagrad", 5.0, 0.0)]
+CODES = [("planar", 5), ("xzzx", 9), ("toric", 8), ("planar", 31), ("toric", 32)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(g, prm, pr, syn, kernel, **kw):
+    r = P.decode(g, prm, pr, syn, kernel=kernel, **kw)
+    torch.cuda.synchronize()
+    return r
+
+
+def same(a, b, what):
+    for k in ("est", "conv", "iters"):
+        assert torch.equal(a[k], b[k]), (what, k, int((a[k] != b[k]).sum()))
+
+
+@pytest.mark.parametrize("fam,size", CODES)
+@pytest.mark.parametrize("variant,alpha,gamma", VARIANTS)
+def test_gather_equals_two_phase(fam, size, variant, alpha, gamma):
+    code = qecgen.make(fam, size)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    p = 0.10
+    shots = 4100 if size > 20 else 5000
+    _, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=size * 31 + len(variant))
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    prm = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=60)
+    say("gather vs soa", code.name, variant, shots)
+    ref = run(g, prm, pr, syn, "soa")
+    r = run(g, prm, pr, syn, "gather")
+    same(ref, r, (code.name, variant, "soa"))
+    if size <= 20:
+        same(run(g, prm, pr, syn, "lds"), r, (code.name, variant, "lds"))
+    say("  conv", float(r["conv"].float().mean()), "iters", float(r["iters"].float().mean()))
+
+
+def test_gather_shot_counts_and_shapes():
+    """Fewer shots than one workgroup, ragged counts, more shots than columns in flight
+    (lanes take new shots in place), and 4, 8 or 16 wavefronts per workgroup."""
+    code = qecgen.planar(9)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    p = 0.12
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    prm = P.Params(variant="ewainit", alpha=0.6, max_iter=80)
+    for shots in (1, 63, 64, 65, 20000):
+        _, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=shots + 5)
+        ref = run(g, prm, pr, syn, "soa")
+        for waves in (4, 8, 16):
+            say("gather shots", shots, "waves", waves)
+            same(ref, run(g, prm, pr, syn, "gather", gather_waves=waves), (shots, waves))
+    # more shots than the 16,384 columns of a full chip: every lane is refilled many times
+    shots = (1 << 16) + 77
+    _, syn = P.sample(g, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=3)
+    say("gather shots", shots)
+    same(run(g, prm, pr, syn, "soa"), run(g, prm, pr, syn, "gather"), shots)
+    # zero shots: nothing launched
+    z = torch.empty(0, code.m, dtype=torch.uint8, device="cuda")
+    assert run(g, prm, pr, z, "gather")["est"].shape == (0, code.n)
+
+
+def test_gather_stopping_rules():
+    """No early stop (every shot runs max_iter, conv reports the last test), a single
+    iteration, and a zero syndrome (converges at t = 1 when every prior is positive)."""
+    code = qecgen.toric(10)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    p = 0.08
+    _, syn = P.sample(g, 3000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=11)
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    for prm in (P.Params(variant="ewainit", alpha=0.6, max_iter=7, stop_on_syndrome=False),
+                P.Params(variant="adagrad", alpha=5.0, max_iter=9, stop_on_syndrome=False),
+                P.Params(variant="momentum", alpha=0.6, gamma=0.7, max_iter=1),
+                P.Params(variant="bp", max_iter=1)):
+        say("gather stop rule", prm)
+        r = run(g, prm, pr, syn, "gather")
+        same(run(g, prm, pr, syn, "soa"), r, prm)
+        if not prm.stop_on_syndrome:
+            assert bool((r["iters"] == prm.max_iter).all())
+    zero = torch.zeros(100, code.m, dtype=torch.uint8, device="cuda")
+    r = run(g, P.Params(variant="ewainit", alpha=0.6, max_iter=20), pr, zero, "gather")
+    assert bool((r["iters"] == 1).all()) and bool((r["conv"] == 1).all()) and int(r["est"].sum()) == 0
+
+
+def test_gather_ignores_stale_workspace():
+    """The records start with whatever the workspace holds: a fresh shot reads the
+    initial messages from the table, never its record, so a workspace full of NaN
+    bytes, or one left by another decode, gives the same results."""
+    code = qecgen.planar(13)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    p = 0.1
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    prm = P.Params(variant="momentum", alpha=0.6, gamma=0.3, max_iter=50)
+    _, syn = P.sample(g, 9000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=21)
+    _, syn2 = P.sample(g, 9000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=22)
+    ws = torch.full((g.gather_workspace_bytes(prm, 9000),), 0xFF, dtype=torch.uint8, device="cuda")
+    a = run(g, prm, pr, syn, "gather", ws=ws)
+    run(g, prm, pr, syn2, "gather", ws=ws)
+    b = run(g, prm, pr, syn, "gather", ws=ws)
+    same(a, b, "stale")
+    same(run(g, prm, pr, syn, "soa"), a, "soa")
+
+
+def test_auto_runs_gather_on_large_codes():
+    """The automatic choice for a large flooding decode is the single-pass kernel (the
+    workspace it sizes is the single-pass one); trace, serial and AEWA keep the SOA
+    kernel; the single-pass kernel refuses the verification outputs."""
+    code = qecgen.planar(31)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    p = 0.1
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    prm = P.Params(variant="ewainit", alpha=0.6, max_iter=40)
+    assert g.workspace_bytes(prm, 5000) == g.gather_workspace_bytes(prm, 5000)
+    _, syn = P.sample(g, 5000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=8)
+    same(run(g, prm, pr, syn, "gather"), run(g, prm, pr, syn, "auto"), "auto")
+    tr = run(g, prm, pr, syn[:64], "auto", trace=True)
+    same(run(g, prm, pr, syn[:64], "soa"), tr, "trace")
+    with pytest.raises(P.BP4Error):
+        P.decode(g, prm, pr, syn[:64], kernel="gather", trace=True)
+    with pytest.raises(P.BP4Error):
+        P.decode(g, P.Params(variant="ewainit", alpha=0.6, serial=True), pr, syn[:64], kernel="gather")

@@ -1,10 +1,12 @@
-"""GPU: the structure-of-arrays kernel for large codes (messages in HBM).
+"""GPU: the structure-of-arrays kernels for large codes (messages in HBM).
 
 It runs the same per-node arithmetic as the LDS kernel, so on codes both can
 decode its outputs must be bit-identical to the LDS kernel's; it is also held
 to the oracle bar directly (messages at iterations 1..5, decisions and logical
 error rates) and, on the large planar d=31 and toric L=32 codes at the full
-2^18-shot batch, on a sample of shots that the oracle decodes one by one.
+2^18-shot batch (decoded by the single-pass HBM kernel the benchmark times, and
+bit-identical to the two-phase kernel), on a sample of shots that the oracle
+decodes one by one.
 """
 import sys
 
@@ -220,8 +222,9 @@ def test_soa_messages_large_codes(make, variant, alpha):
 @pytest.mark.parametrize("make", [lambda: qecgen.planar(31), lambda: qecgen.toric(32)])
 def test_large_codes_full_batch_sampled(make):
     """The full 2^18-shot batch at p = 0.10, EWAInit with the chosen discount, max 200
-    iterations, in the launch the benchmark times; 192 shots spread over the batch
-    decoded by the oracle.
+    iterations, in the launch the benchmark times (the single-pass HBM kernel, which
+    must also equal the two-phase SOA kernel bit for bit on the whole batch); 192 shots
+    spread over the batch decoded by the oracle.
 
     Near threshold most shots run for 100+ iterations and the map from priors to
     decisions is sensitive: the oracle itself, given priors perturbed by a relative
@@ -241,9 +244,15 @@ def test_large_codes_full_batch_sampled(make):
     err, syn = P.sample(g, shots, thr, seed=seed)
     prm = P.Params(variant="ewainit", alpha=alpha, max_iter=max_iter)
     say("large", code.name, shots, "alpha", alpha, "workspace", g.workspace_bytes(prm, shots))
-    rg = P.decode(g, prm, P.prior_llr(qecgen.depolarizing_probs(code.n, p)), syn, kernel="soa")
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    rg = P.decode(g, prm, pr, syn, kernel="gather")
     fail_g, cnt_g = P.bookkeep(g, err, rg["est"])
     torch.cuda.synchronize()
+    rs = P.decode(g, prm, pr, syn, kernel="soa")
+    torch.cuda.synchronize()
+    for k in ("est", "conv", "iters"):
+        assert torch.equal(rg[k], rs[k]), k
+    del rs
     sel = torch.as_tensor(idx, device=syn.device)
     e, s = matched(code, thr, seed, err, syn, idx=idx)
     est_g, conv_g, it_g = np_(rg["est"][sel]), np_(rg["conv"][sel]), np_(rg["iters"][sel])
