@@ -58,6 +58,7 @@ __device__ __forceinline__ float stored_word(float m)
 }
 
 struct GatherArgs {
+    const uint32_t *cedge;    // [m][4] packed check edges (padding marked)
     const uint32_t *vinfo;    // [n] packed qubit words
     const uint32_t *gord;     // [n] qubit at each walk position
     const uint32_t *gedge;    // [n][4] gather words
@@ -68,7 +69,7 @@ struct GatherArgs {
     uint8_t *conv;            // [shots]
     int32_t *iters;           // [shots]
     unsigned int *head;       // shot queue (zeroed before the launch)
-    char *recs;               // [group][2][items][64] words
+    char *recs;               // [group][2][items][64] words: the two iteration records
     int32_t m, n, shots, max_iter, stop, with_y;
     int32_t st_off, acc_off;  // first posterior and accumulator items
     uint32_t rec_bytes;       // bytes of one record: items x 256
@@ -76,10 +77,15 @@ struct GatherArgs {
     VariantParams vp;
 };
 
-// Initial stored words lambda_{H_cv}(Pi_v) of every edge (eq. init), by walk position.
+// Initial stored words lambda_{H_cv}(Pi_v) of every edge (eq. init), by walk position;
+// padding positions of the checks hold +0 (no stored word is +0: |m| <= clamp keeps
+// phi(|m|) above phi(clamp) > 0, so +0 marks padding).
 __global__ void gather_init_kernel(GatherArgs a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.m)
+        for (int p = 0; p < 4; ++p)
+            if (edge_is_pad(a.cedge[4 * i + p])) a.finit[4 * i + p] = 0.0f;
     if (i >= a.n) return;
     const uint32_t v = a.gord[i];
     const uint32_t info = a.vinfo[v];
@@ -102,16 +108,22 @@ struct QubitIn {
     float s3[3], a3[3];
 };
 
-// One record item of this lane: `base` is the workgroup's record block (uniform),
-// `off` the lane's byte offset within it (record parity and lane).
-__device__ __forceinline__ float ld_item(const char *base, uint32_t item, uint32_t off)
-{
-    return *reinterpret_cast<const float *>(base + (size_t)item * 256 + off);
-}
-__device__ __forceinline__ void st_item(char *base, uint32_t item, uint32_t off, float x)
-{
-    __builtin_nontemporal_store(x, reinterpret_cast<float *>(base + (size_t)item * 256 + off));
-}
+// The workgroup's records through one buffer resource: item i of record r for lane l
+// at byte r * rec_bytes + 256 i + 4 l; the per-lane part (record and lane) is the
+// vector offset, the item the scalar one, so no address arithmetic runs per lane,
+// and an access past the two records reads 0 and writes nothing.
+struct Records {
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ float ld(uint32_t item, uint32_t voff) const
+    {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)(item * 256u), 0));
+    }
+    // stores are streamed (nontemporal): the next read is a full pass later
+    __device__ __forceinline__ void st(uint32_t item, uint32_t voff, float x) const
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, (int)voff, (int)(item * 256u), 2);
+    }
+};
 
 template <int VAR>
 __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_gather_kernel(GatherArgs a)
@@ -132,7 +144,27 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
     const bool with_y = a.with_y != 0;
     VariantParams vp = a.vp;
     vp.variant = VAR;
+    konst<uint32_t> *vinfo = as_const(a.vinfo);
+    konst<uint32_t> *gord = as_const(a.gord);
+    konst<uint32_t> *gedge = as_const(a.gedge);
+    konst<float> *prior = as_const(a.prior);
+    konst<float> *finit = as_const(a.finit);
 
+    // Records 0 and 1 alternate between passes.  A new shot's first pass takes the
+    // stored words of lambda(Pi) (eq. init) from the per-code table and the variant's
+    // starting state instead of its record's contents.  Padding items are +0 in both
+    // records and are never written, so the gathers of a degree-3 check read +0 there
+    // (phi's identity) without a test.
+    Records R;
+    R.rs = __builtin_amdgcn_make_buffer_rsrc(a.recs + (size_t)blockIdx.x * 2 * a.rec_bytes, 0,
+                                             (int)(2 * a.rec_bytes), 0x00020000);
+    const uint32_t lane_off = (uint32_t)lane * 4u;
+    for (int i = wv; i < 4 * m; i += W) {
+        if (__float_as_uint(finit[i]) == 0u) {   // padding
+            R.st((uint32_t)i, lane_off, 0.0f);
+            R.st((uint32_t)i, lane_off + a.rec_bytes, 0.0f);
+        }
+    }
     for (int c = threadIdx.x; c < m; c += blockDim.x) {
         S[c] = 0;
         P[c] = 0;
@@ -141,18 +173,11 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
     if (threadIdx.x == 0) U[0] = U[1] = 0;
     __syncthreads();
 
-    char *rec = a.recs + (size_t)blockIdx.x * 2 * a.rec_bytes;
-    konst<uint32_t> *vinfo = as_const(a.vinfo);
-    konst<uint32_t> *gord = as_const(a.gord);
-    konst<uint32_t> *gedge = as_const(a.gedge);
-    konst<float> *prior = as_const(a.prior);
-    konst<float> *finit = as_const(a.finit);
-
     int shot = -1, t = 0, cur = 0;
     // Record parity from the workgroup's pass count, the same in every lane (a lane's
     // own iteration count would split a wavefront's accesses over both records):
     // every live column advances one iteration per pass, so the record a pass writes
-    // is the one the next pass reads; a new shot reads the initial table instead.
+    // is the one the next pass reads; a new shot reads the initial record instead.
     uint32_t pass = 0;
     bool finish = false;
     bool drained = false;            // wavefront 0: the queue is empty
@@ -194,14 +219,12 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
 
         // ---- one flooding iteration over the walk ------------------------------------
         const bool fresh = t == 1;
-        const uint32_t fresh_mask = fresh ? ~0u : 0u;
-        const uint32_t lane_off = (uint32_t)lane * 4u;
         const uint32_t rd = lane_off + (pass & 1u) * a.rec_bytes;
         const uint32_t wr = lane_off + ((pass + 1u) & 1u) * a.rec_bytes;
         ++pass;
         uint64_t nan_cols = 0;
         // Reads of a qubit: its walk entry (scalar), the other stored words of each of
-        // its checks and its state from the record the pass reads.
+        // its checks and its state.
         auto load_qubit = [&](int i, QubitIn &q) {
             q.v = gord[i];
             q.info = vinfo[q.v];
@@ -217,49 +240,33 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
                 for (int k = 0; k < 3; ++k) {
                     // the k-th position of the check other than p (k, or k + 1 past p)
                     const uint32_t pk = (uint32_t)k + (((p - (uint32_t)k - 1u) >> 31) & 1u);
-                    // Every word is read, padding positions too (masked in the update),
-                    // so the loads form one straight run; a new shot takes the initial
-                    // word by a bit select (a per-lane branch would split the loads).
-                    const uint32_t rv = __float_as_uint(ld_item(rec, c4 + pk, rd));
-                    const uint32_t iv = __float_as_uint(finit[c4 + pk]);
-                    q.x[j][k] = __uint_as_float((iv & fresh_mask) | (rv & ~fresh_mask));
+                    q.x[j][k] = R.ld(c4 + pk, rd);
                 }
             }
-            if (VAR != BP4_BP) {   // EWAInit: Q^{(t-1)}, unused at t = 1
 #pragma unroll
-                for (int k = 0; k < 3; ++k) q.s3[k] = ld_item(rec, a.st_off + 3 * i + k, rd);
-            }
-            if (kAcc) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) q.a3[k] = ld_item(rec, a.acc_off + 3 * i + k, rd);
+            for (int k = 0; k < 3; ++k) {
+                q.s3[k] = VAR != BP4_BP ? R.ld(a.st_off + 3 * i + k, rd) : 0.0f;
+                q.a3[k] = kAcc ? R.ld(a.acc_off + 3 * i + k, rd) : 0.0f;
             }
         };
         // Update of a qubit from its reads: incoming messages, posterior, parity
         // contributions, outgoing messages; writes to the record the pass writes.
         auto update_qubit = [&](int i, QubitIn &q) {
             const uint32_t deg = var_deg(q.info);
-            float s3[3], a3[3];
-            qubit_state_init(VAR, q.p3, s3, a3);
-            if (VAR != BP4_BP) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) s3[k] = fresh ? s3[k] : q.s3[k];
-            }
-            if (kAcc) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) a3[k] = fresh ? a3[k] : q.a3[k];
-            }
-            // check-to-qubit messages (eq. h_update)
+            // check-to-qubit messages (eq. h_update); slots past the degree give 0
             float mc[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const uint32_t item = gather_item(q.ew[j]), p = item & 3u, pad = gather_pad(q.ew[j]);
-                const uint32_t c = item >> 2;
+                const uint32_t item = gather_item(q.ew[j]);
+                const uint32_t c4 = item & ~3u, p = item & 3u, c = item >> 2;
                 const uint32_t sb = (uint32_t)(S[c] >> lane) & 1u;
-                float x[3];   // padding: +0
+                // a new shot's words come from the initial table (a per-lane select after
+                // the loads: a per-lane branch would split them)
+                float x[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const uint32_t pk = (uint32_t)k + (((p - (uint32_t)k - 1u) >> 31) & 1u);
-                    x[k] = ((pad >> pk) & 1u) ? 0.0f : q.x[j][k];
+                    x[k] = fresh ? finit[c4 + pk] : q.x[j][k];
                 }
                 const uint32_t sgn =
                     ((__float_as_uint(x[0]) ^ __float_as_uint(x[1]) ^ __float_as_uint(x[2])) & kSign) ^ (sb << 31);
@@ -267,14 +274,21 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
                 mc[j] = (uint32_t)j < deg ? clampf(__uint_as_float(__float_as_uint(mag) ^ sgn), C) : 0.0f;
             }
             float S4[4], A4[4], qn[3];
+            float s3[3], a3[3];
+            qubit_state_init(VAR, q.p3, s3, a3);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s3[k] = fresh ? s3[k] : q.s3[k];
+                a3[k] = fresh ? a3[k] : q.a3[k];
+            }
             label_sums(q.info, mc, with_y, VAR == BP4_ADAGRAD, S4, A4);
             qubit_posterior(vp, t, q.p3, S4, A4, s3, a3, qn);
             // every variant keeps its posterior state (BP its posterior, for the decisions)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) st_item(rec, a.st_off + 3 * i + k, wr, VAR == BP4_BP ? qn[k] : s3[k]);
+            for (int k = 0; k < 3; ++k) R.st(a.st_off + 3 * i + k, wr, VAR == BP4_BP ? qn[k] : s3[k]);
             if (kAcc) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) st_item(rec, a.acc_off + 3 * i + k, wr, a3[k]);
+                for (int k = 0; k < 3; ++k) R.st(a.acc_off + 3 * i + k, wr, a3[k]);
             }
             // this qubit's share of every check's parity (Algorithm 2)
             const uint32_t db = decision_byte_of(qn);
@@ -291,7 +305,7 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
                               (unsigned long long)flip);
                 // new message (eq. v_update) and its stored word
                 const float out = clampf(lam[lab] - mc[j], C);
-                st_item(rec, gather_item(q.ew[j]), wr, stored_word(out));
+                R.st(gather_item(q.ew[j]), wr, stored_word(out));
             }
         };
         // The walk.  Step s takes positions s W .. s W + W - 1, one per wavefront; every
@@ -328,7 +342,7 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
                 float q[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const float sv = ld_item(rec, a.st_off + 3 * i + k, wr);
+                    const float sv = R.ld(a.st_off + 3 * i + k, wr);
                     q[k] = VAR == BP4_ADAGRAD ? prior[3 * v + k] + sv : sv;
                 }
                 a.est[(size_t)shot * n + v] = (uint8_t)decision_pauli(decision_byte_of(q));
@@ -375,7 +389,8 @@ int32_t gather_groups(int64_t shots, int32_t waves)
     return (int32_t)(g > 0 ? g : 1);
 }
 
-// Workspace: the queue head, the initial-message table, the column records.
+// Workspace: the queue head, the initial-message table, the column records (two per
+// workgroup).
 size_t gather_workspace_bytes(int m, int n, int variant, int64_t shots, int32_t waves)
 {
     int32_t st_off, acc_off;
@@ -388,6 +403,7 @@ hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, cons
                                 int32_t *iters, void *ws, int32_t waves, int with_y, hipStream_t s)
 {
     GatherArgs a;
+    a.cedge = g.cedge;
     a.vinfo = g.vinfo;
     a.gord = gt.gord;
     a.gedge = gt.gedge;
@@ -419,7 +435,8 @@ hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, cons
 
     hipError_t e = launch_zero_u32(a.head, 1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gather_init_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, s, a);
+    const int init_threads = g.n > g.m ? g.n : g.m;
+    hipLaunchKernelGGL(gather_init_kernel, dim3((unsigned)((init_threads + 255) / 256)), dim3(256), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int32_t W = waves_of(waves);
