@@ -384,6 +384,39 @@ def test_adagrad_step_invariants():
     assert np.all(s2 <= np.abs(Q[:, 1] - Q[:, 0]) + 1e-12)
 
 
+def test_adagrad_steps_at_rounding_level_gradients_mpmath():
+    """Eq. boost has no threshold: wherever the first adaptive gradient g' = D^{(1)} - M^{(2)}
+    (D^{(1)} = M^{(1)}) is not exactly 0, the oracle moves Q by alpha |g'| / (|g'| + eps), also
+    where g' is FP64 rounding residue (1e-16 .. 1e-15, a step of about 5e-8 .. 4e-7), and
+    only where it is exactly 0 does Q stay put.  g' and the prescribed step are evaluated in
+    60-digit mpmath from the oracle's traced message sums."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 60
+    code = qecgen.planar(3)
+    probs = qecgen.depolarizing_probs(code.n, 0.08)
+    _, syn = O.sample(code.hx, code.hz, 2000, qecgen.thresholds(*probs[0]), seed=5)
+    pi = O.prior_llr(probs)
+    a, eps = 5.0, 1e-8
+    r = O.decode(code.hx, code.hz, O.Params(variant="adagrad", alpha=a, eps=eps, max_iter=3, stop_on_syndrome=False),
+                 pi, syn, want_trace=True)
+    Q, M = r["q_trace"], r["m_trace"]
+    step = (Q[:, 1] - Q[:, 0]).ravel()
+    m1, m2 = M[:, 0].ravel(), M[:, 1].ravel()
+    tiny = 0
+    for i in range(m1.size):
+        g = mp.mpf(float(m1[i])) - mp.mpf(float(m2[i]))
+        if g == 0:
+            assert step[i] == 0.0, i
+            continue
+        want = -a * g / (abs(g) + mp.mpf(eps))   # Q^{(2)} - Q^{(1)} = D^{(2)} - D^{(1)}
+        # Q is traced as Pi + D rounded, so the difference carries ~1e-15 absolute rounding
+        assert abs(mp.mpf(float(step[i])) - want) <= mp.mpf("1e-6") * abs(want) + mp.mpf("4e-15"), (i, g, step[i])
+        if abs(g) < mp.mpf("1e-12"):
+            tiny += 1
+            assert step[i] != 0.0 and abs(step[i]) > 1e-9, (i, g, step[i])
+    assert tiny >= 10, tiny
+
+
 def prob_bp4_optim(hx, hz, probs, s, T, variant, alpha, gamma=0.0, eps=1e-8, g_from_t1=False):
     """Probability-domain quaternary BP whose posterior follows a library optimiser.
 
