@@ -110,7 +110,9 @@ __device__ __forceinline__ Lane lane_of(const UnrArgs &a)
     Lane L;
     L.wave = blockIdx.x;
     L.lane = threadIdx.x & 63;
-    L.part = threadIdx.x >> 6;
+    // read from lane 0: uniform across the wavefront, so the node loops and every graph
+    // and prior read indexed by them stay scalar
+    L.part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     L.have = (int64_t)L.wave * 64 + L.lane < a.shots;
     L.SI = (size_t)a.g.nnz + 3 * (size_t)a.g.n;
     return L;
@@ -177,18 +179,20 @@ __device__ void forward_iteration(const UnrArgs &a, const Lane &L, int t, const 
     const int m = a.g.m, n = a.g.n, E = a.g.nnz;
     const float C = a.clamp;
     const uint8_t *s = a.synd + (size_t)shot * m;
-    for (int c = L.part; L.have && c < m; c += kUnrWaves) {
-        uint32_t w[4];
-        float mv[4], out[4];
+    if (L.have) {
+        for (int c = L.part; c < m; c += kUnrWaves) {
+            uint32_t w[4];
+            float mv[4], out[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            w[j] = cedge[kMaxCheckDeg * c + j];
-            mv[j] = edge_is_pad(w[j]) ? INFINITY : src[(size_t)edge_slot(w[j]) * 64];
+            for (int j = 0; j < 4; ++j) {
+                w[j] = cedge[kMaxCheckDeg * c + j];
+                mv[j] = edge_is_pad(w[j]) ? INFINITY : src[(size_t)edge_slot(w[j]) * 64];
+            }
+            check_update(mv, s[c] & 1u, C, out);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (!edge_is_pad(w[j])) dst[(size_t)edge_slot(w[j]) * 64] = out[j];
         }
-        check_update(mv, s[c] & 1u, C, out);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (!edge_is_pad(w[j])) dst[(size_t)edge_slot(w[j]) * 64] = out[j];
     }
     __syncthreads();
     VariantParams vp;
@@ -197,24 +201,26 @@ __device__ void forward_iteration(const UnrArgs &a, const Lane &L, int t, const 
     vp.alpha = a.alpha[t - 1];
     vp.gamma = 0.0f;
     vp.eps = 0.0f;
-    for (int v = L.part; L.have && v < n; v += kUnrWaves) {
-        const uint32_t info = vinfo[v];
-        const uint32_t base = var_base(info), deg = var_deg(info);
-        float mc[4];
+    if (L.have) {
+        for (int v = L.part; v < n; v += kUnrWaves) {
+            const uint32_t info = vinfo[v];
+            const uint32_t base = var_base(info), deg = var_deg(info);
+            float mc[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) mc[j] = (uint32_t)j < deg ? dst[(size_t)(base + j) * 64] : 0.0f;
-        float S[4], A[4];
-        label_sums(info, mc, true, false, S, A);
-        const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
-        float st[3], ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
-        for (int x = 0; x < 3; ++x) st[x] = src[(size_t)(E + 3 * v + x) * 64];
-        qubit_posterior(vp, t, p3, S, A, st, ac, qn);
-        for (int x = 0; x < 3; ++x) dst[(size_t)(E + 3 * v + x) * 64] = qn[x];
-        if (t < a.T) {
-            float lam[4];
-            qubit_lambdas(qn, var_labels_present(info), lam);
-            for (uint32_t j = 0; j < deg; ++j)
-                dst[(size_t)(base + j) * 64] = clampf(lam[var_lab(info, j)] - mc[j], C);
+            for (int j = 0; j < 4; ++j) mc[j] = (uint32_t)j < deg ? dst[(size_t)(base + j) * 64] : 0.0f;
+            float S[4], A[4];
+            label_sums(info, mc, true, false, S, A);
+            const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
+            float st[3], ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
+            for (int x = 0; x < 3; ++x) st[x] = src[(size_t)(E + 3 * v + x) * 64];
+            qubit_posterior(vp, t, p3, S, A, st, ac, qn);
+            for (int x = 0; x < 3; ++x) dst[(size_t)(E + 3 * v + x) * 64] = qn[x];
+            if (t < a.T) {
+                float lam[4];
+                qubit_lambdas(qn, var_labels_present(info), lam);
+                for (uint32_t j = 0; j < deg; ++j)
+                    dst[(size_t)(base + j) * 64] = clampf(lam[var_lab(info, j)] - mc[j], C);
+            }
         }
     }
     __syncthreads();
@@ -273,90 +279,94 @@ __device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, cons
     const float al = a.alpha[t - 1];
     float galpha = 0.0f;
     // ---- qubit side: vertical update (t < T), then posterior and EWA prior ------
-    for (int v = L.part; L.have && v < n; v += kUnrWaves) {
-        const uint32_t info = vinfo[v];
-        const uint32_t base = var_base(info), deg = var_deg(info);
-        float q[3], g[3];
-        for (int x = 0; x < 3; ++x) {
-            q[x] = cur[(size_t)(E + 3 * v + x) * 64];
-            g[x] = gQ[(size_t)(3 * v + x) * 64];
-        }
-        float gcv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (t < a.T) {
-            // m_{v->c} = clamp(lambda_H(Q) - m_{c->v}): lambda's partials, zero where clamped
+    if (L.have) {
+        for (int v = L.part; v < n; v += kUnrWaves) {
+            const uint32_t info = vinfo[v];
+            const uint32_t base = var_base(info), deg = var_deg(info);
+            float q[3], g[3];
+            for (int x = 0; x < 3; ++x) {
+                q[x] = cur[(size_t)(E + 3 * v + x) * 64];
+                g[x] = gQ[(size_t)(3 * v + x) * 64];
+            }
+            float gcv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (t < a.T) {
+                // m_{v->c} = clamp(lambda_H(Q) - m_{c->v}): lambda's partials, zero where clamped
+                for (uint32_t j = 0; j < deg; ++j) {
+                    const size_t sl = (size_t)(base + j) * 64;
+                    const float gj = gm[sl];
+                    if (!(fabsf(cur[sl]) < C)) continue;
+                    int h, ia, ib;
+                    label_indices(var_lab(info, j), h, ia, ib);
+                    g[h] -= gj * sigmoid(-q[h]);
+                    g[ia] += gj * sigmoid(q[ib] - q[ia]);
+                    g[ib] += gj * sigmoid(q[ia] - q[ib]);
+                    gcv[j] = -gj;
+                }
+            }
+            // Q = Pi^{(t)} + M: each m_{c->v} enters the two components that anticommute with H
             for (uint32_t j = 0; j < deg; ++j) {
-                const size_t sl = (size_t)(base + j) * 64;
-                const float gj = gm[sl];
-                if (!(fabsf(cur[sl]) < C)) continue;
                 int h, ia, ib;
                 label_indices(var_lab(info, j), h, ia, ib);
-                g[h] -= gj * sigmoid(-q[h]);
-                g[ia] += gj * sigmoid(q[ib] - q[ia]);
-                g[ib] += gj * sigmoid(q[ia] - q[ib]);
-                gcv[j] = -gj;
+                gm[(size_t)(base + j) * 64] = gcv[j] + g[ia] + g[ib];
             }
-        }
-        // Q = Pi^{(t)} + M: each m_{c->v} enters the two components that anticommute with H
-        for (uint32_t j = 0; j < deg; ++j) {
-            int h, ia, ib;
-            label_indices(var_lab(info, j), h, ia, ib);
-            gm[(size_t)(base + j) * 64] = gcv[j] + g[ia] + g[ib];
-        }
-        // Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}  (t > 1), Pi^{(1)} = Pi^{(0)}
-        for (int x = 0; x < 3; ++x) {
-            const size_t i = (size_t)(3 * v + x) * 64;
-            if (t == 1) {
-                gP[i] += g[x];
-                gQ[i] = 0.0f;
-            } else {
-                const float p0 = prior[3 * v + x];
-                galpha = fmaf(g[x], p0 - prev[(size_t)(E + 3 * v + x) * 64], galpha);
-                gP[i] = fmaf(al, g[x], gP[i]);
-                gQ[i] = (1.0f - al) * g[x];
+            // Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}  (t > 1), Pi^{(1)} = Pi^{(0)}
+            for (int x = 0; x < 3; ++x) {
+                const size_t i = (size_t)(3 * v + x) * 64;
+                if (t == 1) {
+                    gP[i] += g[x];
+                    gQ[i] = 0.0f;
+                } else {
+                    const float p0 = prior[3 * v + x];
+                    galpha = fmaf(g[x], p0 - prev[(size_t)(E + 3 * v + x) * 64], galpha);
+                    gP[i] = fmaf(al, g[x], gP[i]);
+                    gQ[i] = (1.0f - al) * g[x];
+                }
             }
         }
     }
     const double galpha_sum = block_sum((double)galpha, sh);   // also the barrier between the sides
     // ---- check side: m_{c->v} = clamp(sign * phi(sum_{v' != v} phi(|m_{v'->c}|))) ----
     const uint8_t *s = a.synd + (size_t)shot * m;
-    for (int c = L.part; L.have && c < m; c += kUnrWaves) {
-        uint32_t w[4];
-        float mv[4], f[4], gout[4];
-        uint32_t sgn[4];
-        uint32_t neg = s[c] & 1u;
+    if (L.have) {
+        for (int c = L.part; c < m; c += kUnrWaves) {
+            uint32_t w[4];
+            float mv[4], f[4], gout[4];
+            uint32_t sgn[4];
+            uint32_t neg = s[c] & 1u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            w[j] = cedge[kMaxCheckDeg * c + j];
-            const bool pad = edge_is_pad(w[j]);
-            const size_t sl = (size_t)edge_slot(w[j]) * 64;
-            mv[j] = pad ? INFINITY : prev[sl];
-            gout[j] = pad ? 0.0f : gm[sl];
-            sgn[j] = mv[j] < 0.0f ? 1u : 0u;
-            neg ^= sgn[j];
-            f[j] = phi(fabsf(mv[j]));
-        }
-        float loo[4];
-        loo4(f, loo);   // the forward check rule's sums, bit for bit
-        float wsum[4];
+            for (int j = 0; j < 4; ++j) {
+                w[j] = cedge[kMaxCheckDeg * c + j];
+                const bool pad = edge_is_pad(w[j]);
+                const size_t sl = (size_t)edge_slot(w[j]) * 64;
+                mv[j] = pad ? INFINITY : prev[sl];
+                gout[j] = pad ? 0.0f : gm[sl];
+                sgn[j] = mv[j] < 0.0f ? 1u : 0u;
+                neg ^= sgn[j];
+                f[j] = phi(fabsf(mv[j]));
+            }
+            float loo[4];
+            loo4(f, loo);   // the forward check rule's sums, bit for bit
+            float wsum[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float mag = phi(loo[j]);
-            const float sj = (neg ^ sgn[j]) ? -1.0f : 1.0f;
-            // the clamp passes the derivative only where it did not act
-            wsum[j] = (mag < C && gout[j] != 0.0f) ? gout[j] * sj * dphi(loo[j]) : 0.0f;
-        }
-        // leave-one-out sums formed directly: one term can exceed the others by many
-        // orders of magnitude (an output whose other inputs are all saturated), and
-        // subtracting it from the total would cancel the rest
-        const float others4[4] = {wsum[1] + wsum[2] + wsum[3], wsum[0] + wsum[2] + wsum[3],
-                                  wsum[0] + wsum[1] + wsum[3], wsum[0] + wsum[1] + wsum[2]};
+            for (int j = 0; j < 4; ++j) {
+                const float mag = phi(loo[j]);
+                const float sj = (neg ^ sgn[j]) ? -1.0f : 1.0f;
+                // the clamp passes the derivative only where it did not act
+                wsum[j] = (mag < C && gout[j] != 0.0f) ? gout[j] * sj * dphi(loo[j]) : 0.0f;
+            }
+            // leave-one-out sums formed directly: one term can exceed the others by many
+            // orders of magnitude (an output whose other inputs are all saturated), and
+            // subtracting it from the total would cancel the rest
+            const float others4[4] = {wsum[1] + wsum[2] + wsum[3], wsum[0] + wsum[2] + wsum[3],
+                                      wsum[0] + wsum[1] + wsum[3], wsum[0] + wsum[1] + wsum[2]};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (edge_is_pad(w[k])) continue;
-            const float others = others4[k];
-            // a zero message has phi = inf: its outputs do not depend on it
-            const float gk = isinf(f[k]) ? 0.0f : (sgn[k] ? -1.0f : 1.0f) * dphi(fabsf(mv[k])) * others;
-            gm[(size_t)edge_slot(w[k]) * 64] = gk;
+            for (int k = 0; k < 4; ++k) {
+                if (edge_is_pad(w[k])) continue;
+                const float others = others4[k];
+                // a zero message has phi = inf: its outputs do not depend on it
+                const float gk = isinf(f[k]) ? 0.0f : (sgn[k] ? -1.0f : 1.0f) * dphi(fabsf(mv[k])) * others;
+                gm[(size_t)edge_slot(w[k]) * 64] = gk;
+            }
         }
     }
     __syncthreads();
