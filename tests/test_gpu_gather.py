@@ -144,3 +144,35 @@ def test_auto_runs_gather_on_large_codes():
         P.decode(g, prm, pr, syn[:64], kernel="gather", trace=True)
     with pytest.raises(P.BP4Error):
         P.decode(g, P.Params(variant="ewainit", alpha=0.6, serial=True), pr, syn[:64], kernel="gather")
+
+
+def _clifford_relabel(code, seed):
+    """Random local Clifford on every qubit: permutes each qubit's X, Y, Z labels, so
+    the checks carry Y labels (the code stays a valid stabilizer code)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    lab = code.labels()
+    new = np.zeros_like(lab)
+    for v in range(code.n):
+        p = rng.permutation([1, 2, 3])
+        new[:, v] = np.array([0, p[0], p[1], p[2]], np.uint8)[lab[:, v]]
+    return (new & 1).astype(np.uint8), (new >> 1).astype(np.uint8)
+
+
+@pytest.mark.parametrize("variant,alpha,gamma", VARIANTS)
+def test_gather_y_labels_and_per_qubit_priors(variant, alpha, gamma):
+    """Y labels (a Clifford-relabelled toric code: three labels per qubit, the with-Y
+    label sums and lambdas) and per-qubit priors (biased noise jittered per qubit, so the
+    initial-message table differs from qubit to qubit): bit-identical to the two-phase
+    kernel."""
+    import numpy as np
+    code = qecgen.toric(16)
+    hx, hz = _clifford_relabel(code, 3)
+    g = P.Graph(hx, hz)
+    p = 0.09
+    probs = qecgen.biased_probs(code.n, p) * np.random.default_rng(4).uniform(0.7, 1.3, (code.n, 1))
+    pr = P.prior_llr(probs)
+    _, syn = P.sample(g, 6000, qecgen.thresholds(p / 6, p / 6, 2 * p / 3), seed=9)
+    prm = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=60)
+    say("gather y labels", variant)
+    same(run(g, prm, pr, syn, "soa"), run(g, prm, pr, syn, "gather"), variant)
