@@ -564,32 +564,55 @@ def run_serial(torch, qecgen, P, dev):
 
 
 def run_biased(torch, qecgen, P, dev):
-    """XZZX L=5, 7, 9 under biased noise (p_Z = 2p/3, p_X = p_Y = p/6), EWAInit alpha 0.5,
-    iter_max 100, 2^16 shots per point: the LER curves and where L=5 and L=9 cross (the
-    paper reads about 10% for EWAInit under parallel scheduling)."""
+    """XZZX L=5, 7, 9 under biased noise (p_Z = 2p/3, p_X = p_Y = p/6), iter_max 100, 2^16
+    shots per point: the LER curves of EWAInit at alpha 0.5 and where the L=5 and L=9 curves
+    cross (the paper reads about 10% for EWAInit under parallel scheduling), then the same
+    crossings (L5/L9 and L7/L9) for every discount of the paper's grid 0, 0.1, ..., 1 on the
+    same syndromes (alpha 1 is traditional BP)."""
     shots = 1 << 16
-    ps = (0.06, 0.08, 0.10, 0.12, 0.14, 0.16, 0.18, 0.20)
-    prm = P.Params(variant="ewainit", alpha=ALPHA_EXTRA, max_iter=100)
-    ler = {}
-    for i, L in enumerate((5, 7, 9)):
+    ps = (0.04, 0.06, 0.08, 0.10, 0.12, 0.14, 0.16, 0.18, 0.20, 0.22)
+    sizes = (5, 7, 9)
+    cases = {}
+    for i, L in enumerate(sizes):
         code = qecgen.xzzx(L)
         g = P.Graph(code.hx, code.hz, code.lx, code.lz, device=dev)
-        ler[L] = []
+        cases[L] = []
         for j, p in enumerate(ps):
             probs = qecgen.biased_probs(code.n, p)
             err, syn = P.sample(g, shots, qecgen.thresholds(*probs[0]), seed=qecgen.config_seed(7, i, j))
-            r = P.decode(g, prm, P.prior_llr(probs, device=dev), syn)
-            _, cnt = P.bookkeep(g, err, r["est"])
-            ler[L].append(float(cnt[1] + cnt[2]) / shots)
-    cross = None
-    for j in range(len(ps) - 1):
-        d0, d1 = ler[9][j] - ler[5][j], ler[9][j + 1] - ler[5][j + 1]
-        if d0 < 0 <= d1 or d0 <= 0 < d1:
-            cross = ps[j] + (ps[j + 1] - ps[j]) * (-d0) / (d1 - d0)
-    log(f"biased XZZX: L=5/9 LER curves cross near p = {cross}")
-    return {"workload": "XZZX L=5, 7, 9, p_Z = 2p/3, p_X = p_Y = p/6, EWAInit alpha 0.5, iter_max 100, 2^16 shots",
-            "p": list(ps), "ler": {f"L{L}": v for L, v in ler.items()}, "crossing_L5_L9": cross,
-            "paper_crossing": 0.10}
+            cases[L].append((g, err, syn, P.prior_llr(probs, device=dev)))
+
+    def curves(alpha):
+        prm = P.Params(variant="ewainit", alpha=alpha, max_iter=100)
+        ler = {}
+        for L in sizes:
+            ler[L] = []
+            for g, err, syn, pr in cases[L]:
+                r = P.decode(g, prm, pr, syn)
+                _, cnt = P.bookkeep(g, err, r["est"])
+                ler[L].append(float(cnt[1] + cnt[2]) / shots)
+        return ler
+
+    def cross(a, b):   # first sign change of b - a, linearly interpolated
+        for j in range(len(ps) - 1):
+            d0, d1 = b[j] - a[j], b[j + 1] - a[j + 1]
+            if d0 < 0 <= d1 or d0 <= 0 < d1:
+                return ps[j] + (ps[j + 1] - ps[j]) * (-d0) / (d1 - d0)
+        return None
+
+    ler = curves(ALPHA_EXTRA)
+    x59 = cross(ler[5], ler[9])
+    log(f"biased XZZX: L=5/9 LER curves cross near p = {x59}")
+    sweep = []
+    for k in range(11):
+        lk = ler if k == round(ALPHA_EXTRA * 10) else curves(k / 10)
+        sweep.append({"alpha": k / 10, "crossing_L5_L9": cross(lk[5], lk[9]), "crossing_L7_L9": cross(lk[7], lk[9]),
+                      "ler_L9": lk[9]})
+    log("biased XZZX crossings L5/L9 by alpha: " +
+        ", ".join(f"{r['alpha']:.1f}: {r['crossing_L5_L9']}" for r in sweep))
+    return {"workload": "XZZX L=5, 7, 9, p_Z = 2p/3, p_X = p_Y = p/6, EWAInit, iter_max 100, 2^16 shots per point",
+            "p": list(ps), "alpha": ALPHA_EXTRA, "ler": {f"L{L}": v for L, v in ler.items()}, "crossing_L5_L9": x59,
+            "paper_crossing": 0.10, "alpha_sweep": sweep}
 
 
 def run_qldpc(torch, qecgen, P, dev):
