@@ -7,9 +7,10 @@
 // word of m_{v->c} (phi(|m|) with the sign bit of m), then the posterior state
 // (and the momentum or AdaGrad accumulator) by walk position.
 //
-// An iteration walks the qubits in a Cuthill-McKee order, the workgroup's
-// wavefronts taking positions round robin, so the qubits in flight at any time sit
-// close together on the lattice.  A qubit reads the other stored words of each of
+// An iteration walks the qubits in an order fixed on the host (bands of a few
+// breadth-first levels, each band walked breadth first along its length), the
+// workgroup's wavefronts taking positions round robin, so the qubits in flight at
+// any time sit close together on the lattice.  A qubit reads the other stored words of each of
 // its checks from the previous record (eq. h_update in phi form: the sign is the
 // syndrome bit times the other signs, the magnitude phi of the sum of the other
 // phi values, summed in value order), forms its posterior (eqs. p_update, EWAInit,
