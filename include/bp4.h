@@ -144,7 +144,7 @@ int bp4_graph_edges(const bp4_graph *g, int32_t *check, int32_t *qubit);
 /* Device workspace bytes bp4_decode needs for `shots` shots with the automatic
  * kernel choice (a queue counter for the LDS kernel; the column records of the
  * single-pass HBM kernel, or the lane-resident message and state arrays of the
- * SOA kernel where that one applies: serial schedule, AEWA). */
+ * SOA kernel where that one applies: the serial schedule). */
 int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes);
 
 /* Sample i.i.d. Pauli errors and their syndromes (section IV: each qubit is
@@ -227,8 +227,9 @@ typedef struct {
  * each qubit reads its checks' other messages (L2 serves the re-reads of the
  * neighbouring qubits) and writes its own; the syndrome test runs inside the
  * pass and a finished shot's lane takes the next shot at once (large codes;
- * flooding BP, Momentum, AdaGrad and EWAInit, at most 4,079 checks, no
- * verification outputs).  AUTO: LDS unless even one shot per workgroup would
+ * flooding BP, Momentum, AdaGrad, EWAInit and AEWA, whose unsolved shot keeps
+ * its lane for the next attempt; at most 4,079 checks, no verification
+ * outputs).  AUTO: LDS unless even one shot per workgroup would
  * need more than 80 KB of LDS; then GATHER where it applies, else SOA. */
 enum { BP4_KERNEL_AUTO = 0, BP4_KERNEL_LDS = 1, BP4_KERNEL_SOA = 2, BP4_KERNEL_GATHER = 3 };
 

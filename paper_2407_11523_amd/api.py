@@ -184,7 +184,7 @@ def decode(g: Graph, params: Params, prior: torch.Tensor, synd: torch.Tensor, *,
     automatic); lds_bytes reserves at least that much LDS per workgroup; kernel picks the
     LDS ("lds"), the two-phase structure-of-arrays ("soa") or the single-pass
     HBM ("gather") kernel ("auto": by code size; large codes take "gather"
-    unless trace, serial or AEWA asks for "soa"); soa_lanes sets the shots the
+    unless trace or serial asks for "soa"); soa_lanes sets the shots the
     SOA kernel keeps in flight and soa_iter_block its iterations per launch,
     gather_waves the wavefronts per workgroup of the single-pass kernel (0:
     defaults)."""

@@ -700,7 +700,7 @@ bool gather_ok(const bp4_graph *g, int variant, int serial)
 }
 
 // Large codes under AUTO: the single-pass HBM kernel where it applies (flooding, no
-// AEWA restarts, no verification outputs), else the two-phase SOA kernel.
+// verification outputs), else the two-phase SOA kernel.
 int large_kernel(const bp4_graph *g, int variant, int serial, bool verify)
 {
     return !verify && gather_ok(g, variant, serial) ? BP4_KERNEL_GATHER : BP4_KERNEL_SOA;
@@ -859,8 +859,8 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         if (lds_knobs || soa_knobs)
             return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields do not apply to the single-pass HBM kernel");
         if (!gather_ok(g, p->variant, p->serial))
-            return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel runs flooding BP, Momentum, AdaGrad and "
-                                          "EWAInit on codes of at most %zu checks",
+            return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel runs the flooding schedule on codes of at "
+                                          "most %zu checks",
                         (kGatherMaxLds - 64 * 4) / 16 - 1);
         if (verify) return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel writes no q_out, mvc_out or mcv_out");
         const size_t need = gather_workspace_bytes(g->m, g->n, p->variant, shots, gather_waves);

@@ -32,9 +32,9 @@ constexpr int kGatherMaxWaves = 16;
 // CUs the persistent grid is sized for.
 constexpr int kGatherCUs = 256;
 
-// Whether the kernel takes this code, variant and schedule: flooding, no AEWA
-// restarts, check and qubit degrees <= 4 and the two per-check bit masks within
-// the workgroup's LDS (max_lds bytes).
+// Whether the kernel takes this code, variant and schedule: flooding (every variant,
+// AEWA restarts included), check and qubit degrees <= 4 and the two per-check bit
+// masks within the workgroup's LDS (max_lds bytes).
 bool gather_supported(int m, int variant, int serial, bool wide, size_t max_lds);
 // LDS bytes per workgroup.
 size_t gather_lds_bytes(int m);

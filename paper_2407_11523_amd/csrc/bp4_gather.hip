@@ -76,6 +76,8 @@ struct GatherArgs {
     uint32_t rec_bytes;       // bytes of one record: items x 256
     float clamp;
     VariantParams vp;
+    float alpha_last;         // AEWA: discount of the last attempt (vp.alpha: the first)
+    int32_t alpha_steps;      // AEWA: attempts
 };
 
 // Initial stored words lambda_{H_cv}(Pi_v) of every edge (eq. init), by walk position;
@@ -175,6 +177,9 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
     __syncthreads();
 
     int shot = -1, t = 0, cur = 0;
+    // AEWA: the column's attempt, the iterations of its earlier attempts and its discount
+    int att = 0, t_before = 0;
+    float alpha = a.vp.alpha;
     // Record parity from the workgroup's pass count, the same in every lane (a lane's
     // own iteration count would split a wavefront's accesses over both records):
     // every live column advances one iteration per pass, so the record a pass writes
@@ -205,7 +210,13 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
         shot = ns;
         finish = false;
         if (__ballot(shot >= 0) == 0) break;   // every column empty (the same in every wavefront)
-        if (refill) t = 0;
+        if (refill) {
+            t = 0;
+            att = 0;
+            t_before = 0;
+            alpha = a.vp.alpha;
+        }
+        if constexpr (VAR == BP4_AEWA) vp.alpha = alpha;   // per column
         // syndrome words of the new shots
         if (__ballot(refill) != 0) {
             for (int c = wv; c < m; c += W) {
@@ -334,7 +345,11 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
         if (lane == 0 && bad != 0) atomicOr(reinterpret_cast<unsigned long long *>(&U[cur]), (unsigned long long)bad);
         __syncthreads();
         const bool sat = ((U[cur] >> lane) & 1ull) == 0;
-        finish = shot >= 0 && ((a.stop && sat) || t >= a.max_iter);
+        // AEWA: a column whose attempt ends unsolved starts the next attempt of its shot
+        // (eq. EWAInit with the next discount, from the initial messages again)
+        bool restart = false;
+        if constexpr (VAR == BP4_AEWA) restart = shot >= 0 && !sat && t >= a.max_iter && att + 1 < a.alpha_steps;
+        finish = shot >= 0 && !restart && ((a.stop && sat) || t >= a.max_iter);
         if (__ballot(finish) != 0) {
             // hard decisions of the finished shots from the posterior just written
             for (int i = wv; i < n; i += W) {
@@ -350,8 +365,14 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
             }
             if (wv == 0 && finish) {
                 a.conv[shot] = sat ? 1 : 0;
-                a.iters[shot] = t;
+                a.iters[shot] = t_before + t;
             }
+        }
+        if (restart) {
+            t_before += t;
+            ++att;
+            alpha = aewa_alpha(a.vp.alpha, a.alpha_last, a.alpha_steps, att);
+            t = 0;   // the next pass is the attempt's first: fresh reads, as for a new shot
         }
         if (threadIdx.x == 0) U[cur ^ 1] = 0;
         cur ^= 1;
@@ -378,7 +399,7 @@ size_t gather_lds_bytes(int m) { return (size_t)(2 * m + 2) * 8 + 64 * 4; }
 
 bool gather_supported(int m, int variant, int serial, bool wide, size_t max_lds)
 {
-    return !serial && !wide && variant != BP4_AEWA && gather_lds_bytes(m) <= max_lds;
+    return !serial && !wide && gather_lds_bytes(m) <= max_lds;
 }
 
 int32_t gather_groups(int64_t shots, int32_t waves)
@@ -433,6 +454,8 @@ hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, cons
     a.vp.alpha = p.alpha;
     a.vp.gamma = p.gamma;
     a.vp.eps = p.eps;
+    a.alpha_last = p.alpha_last;
+    a.alpha_steps = p.alpha_steps;
 
     hipError_t e = launch_zero_u32(a.head, 1, s);
     if (e != hipSuccess) return e;
@@ -447,6 +470,7 @@ hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, cons
     case BP4_BP: hipLaunchKernelGGL(decode_gather_kernel<BP4_BP>, grid, block, lds, s, a); break;
     case BP4_MOMENTUM: hipLaunchKernelGGL(decode_gather_kernel<BP4_MOMENTUM>, grid, block, lds, s, a); break;
     case BP4_ADAGRAD: hipLaunchKernelGGL(decode_gather_kernel<BP4_ADAGRAD>, grid, block, lds, s, a); break;
+    case BP4_AEWA: hipLaunchKernelGGL(decode_gather_kernel<BP4_AEWA>, grid, block, lds, s, a); break;
     default: hipLaunchKernelGGL(decode_gather_kernel<BP4_EWAINIT>, grid, block, lds, s, a); break;
     }
     return hipGetLastError();

@@ -178,8 +178,8 @@ def test_mixed_and_plain_validation_without_gpu(lib):
 def test_large_codes_take_the_hbm_kernels(lib):
     """Codes whose LDS image exceeds the automatic limit run from HBM.  The two-phase SOA
     kernel's workspace holds every message and qubit state per resident lane and grows
-    with the variant; the automatic choice for flooding BP, Momentum, AdaGrad and EWAInit
-    is the single-pass kernel, whose workspace is two 64-column records per workgroup in
+    with the variant; the automatic choice for every flooding variant is the single-pass
+    kernel, whose workspace is two 64-column records per workgroup in
     flight (32 wavefronts per CU; 4 message words per check, 3 posterior words per
     qubit, 3 more for the Momentum and AdaGrad accumulators)."""
     from paper_2407_11523_amd import Graph, Params
@@ -201,14 +201,13 @@ def test_large_codes_take_the_hbm_kernels(lib):
         assert g.workspace_bytes(prm, shots) == want
         assert g.gather_workspace_bytes(prm, 100) == head + 2 * 2 * items * 256
         assert g.gather_workspace_bytes(prm, shots, 8) == head + 1024 * 2 * items * 256
-    # the serial schedule and AEWA keep the SOA kernel
+    # the serial schedule keeps the SOA kernel; AEWA (EWAInit's records) takes the single-pass one
     ser = Params(variant="ewainit", alpha=0.5, serial=True)
     b = ctypes.c_size_t()
     assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(ser.c()), shots, 0, ctypes.byref(b)) == 0
     assert g.workspace_bytes(ser, shots) == b.value
     ae = Params(variant="aewa", alpha=0.5, alpha_last=0.9, alpha_steps=3)
-    assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(ae.c()), shots, 0, ctypes.byref(b)) == 0
-    assert g.workspace_bytes(ae, shots) == b.value
+    assert g.workspace_bytes(ae, shots) == g.gather_workspace_bytes(ae, shots) == head + 512 * 2 * (4 * m + 3 * n) * 256
     prm = Params(variant="bp")
     for bad in (-1, 2, 32):
         assert lib.bp4_gather_workspace_bytes(g.handle, ctypes.byref(prm.c()), shots, bad, ctypes.byref(b)) == -1
@@ -234,7 +233,7 @@ def test_large_codes_take_the_hbm_kernels(lib):
 
 def test_gather_kernel_validation_without_gpu(lib):
     """The single-pass HBM kernel's argument checks run before any launch: no verification
-    outputs, no serial schedule or AEWA, gather_waves in {0, 4, 8, 16}, its own workspace
+    outputs, no serial schedule, gather_waves in {0, 4, 8, 16}, its own workspace
     size, and its tuning field excludes the LDS and SOA ones."""
     from paper_2407_11523_amd import Graph, Params, _lib
     c = qecgen.toric(32)
@@ -259,8 +258,9 @@ def test_gather_kernel_validation_without_gpu(lib):
     assert dec(_lib.Tuning(0, 0, 3, 0, 0, 0, 0, 1)) == -1               # reserved
     ser = Params(variant="ewainit", alpha=0.6, serial=True).c()
     assert dec(_lib.Tuning(0, 0, 3), params=ser) == -6                  # serial schedule
-    ae = Params(variant="aewa", alpha=0.5, alpha_last=0.9, alpha_steps=3).c()
-    assert dec(_lib.Tuning(0, 0, 3), params=ae) == -6                   # AEWA restarts
+    ae = Params(variant="aewa", alpha=0.5, alpha_last=0.9, alpha_steps=3)
+    need_ae = g.gather_workspace_bytes(ae, 1000)
+    assert dec(_lib.Tuning(0, 0, 3), params=ae.c(), ws_bytes=need_ae - 1) == -4   # AEWA runs: its workspace
     # wide graphs: LDS kernel only
     bb = qecgen.bb(72)
     gw = Graph(bb.hx, bb.hz, upload=False)

@@ -22,7 +22,9 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 
 import paper_2407_11523_amd as P  # noqa: E402
 
-VARIANTS = [("bp", 1.0, 0.0), ("ewainit", 0.6, 0.0), ("momentum", 0.6, 0.3), ("adagrad", 5.0, 0.0)]
+# AEWA: the default attempt list, discounts 1, 0.9, ..., 0 (attempt k restarts from the priors)
+VARIANTS = [("bp", 1.0, 0.0), ("ewainit", 0.6, 0.0), ("momentum", 0.6, 0.3), ("adagrad", 5.0, 0.0),
+            ("aewa", 1.0, 0.0)]
 CODES = [("planar", 5), ("xzzx", 9), ("toric", 8), ("planar", 31), ("toric", 32)]
 
 
@@ -128,8 +130,8 @@ def test_gather_ignores_stale_workspace():
 
 def test_auto_runs_gather_on_large_codes():
     """The automatic choice for a large flooding decode is the single-pass kernel (the
-    workspace it sizes is the single-pass one); trace, serial and AEWA keep the SOA
-    kernel; the single-pass kernel refuses the verification outputs."""
+    workspace it sizes is the single-pass one), AEWA included; trace and serial keep the
+    SOA kernel; the single-pass kernel refuses the verification outputs."""
     code = qecgen.planar(31)
     g = P.Graph(code.hx, code.hz, code.lx, code.lz)
     p = 0.1
@@ -144,6 +146,9 @@ def test_auto_runs_gather_on_large_codes():
         P.decode(g, prm, pr, syn[:64], kernel="gather", trace=True)
     with pytest.raises(P.BP4Error):
         P.decode(g, P.Params(variant="ewainit", alpha=0.6, serial=True), pr, syn[:64], kernel="gather")
+    ae = P.Params(variant="aewa", alpha=1.0, alpha_last=0.0, alpha_steps=11, max_iter=30)
+    assert g.workspace_bytes(ae, 5000) == g.gather_workspace_bytes(ae, 5000)
+    same(run(g, ae, pr, syn, "gather"), run(g, ae, pr, syn, "auto"), "auto aewa")
 
 
 def _clifford_relabel(code, seed):
@@ -176,3 +181,24 @@ def test_gather_y_labels_and_per_qubit_priors(variant, alpha, gamma):
     prm = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=60)
     say("gather y labels", variant)
     same(run(g, prm, pr, syn, "soa"), run(g, prm, pr, syn, "gather"), variant)
+
+
+def test_gather_aewa_attempts():
+    """AEWA on the single-pass kernel: an unsolved shot keeps its column and restarts from
+    the priors with the next discount (eq. EWAInit), its iterations summed over the
+    attempts.  Short and long attempt lists, rising and falling discounts, several
+    workgroup shapes, a batch where columns restart while others take new shots: equal
+    to the LDS kernel's in-place restarts and the SOA kernel's attempt launches."""
+    code = qecgen.planar(9)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    p = 0.12
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    _, syn = P.sample(g, 20000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=41)
+    for alpha, last, steps, mi in ((1.0, 0.0, 11, 25), (0.5, 0.9, 3, 10), (0.7, 0.7, 1, 40), (0.0, 1.0, 5, 3)):
+        prm = P.Params(variant="aewa", alpha=alpha, alpha_last=last, alpha_steps=steps, max_iter=mi)
+        ref = run(g, prm, pr, syn, "lds")
+        assert int(ref["iters"].max()) > mi or steps == 1   # some shot restarted
+        for waves in (4, 16):
+            say("gather aewa", alpha, last, steps, mi, "waves", waves)
+            same(ref, run(g, prm, pr, syn, "gather", gather_waves=waves), (alpha, last, steps, waves))
+        same(ref, run(g, prm, pr, syn, "soa"), (alpha, last, steps, "soa"))
