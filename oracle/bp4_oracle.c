@@ -195,11 +195,14 @@ typedef struct {
     double gamma;               /* Momentum decay */
     double eps;                 /* AdaGrad epsilon */
     double clamp;               /* message magnitude bound C (INFINITY: none) */
-    const double *alpha_t;      /* EWAInit: per-iteration discount, alpha_t[t - 1] at iteration t
-                                   (entry 0 unused), or NULL for the constant alpha */
+    const double *alpha_t;      /* per-iteration alpha, alpha_t[t - 1] at iteration t, or NULL for
+                                   the constant alpha: the EWAInit discount (entry 0 unused) or the
+                                   Momentum step */
     double alpha_last;          /* AEWA: discount of the last attempt */
     int32_t alpha_steps;        /* AEWA: attempts; alpha_k = alpha + (alpha_last - alpha) k / (steps - 1) */
     int32_t serial;             /* 0: flooding schedule (Alg. 2); 1: serial schedule (Alg. 1) */
+    const double *gamma_t;      /* Momentum: per-iteration decay, gamma_t[t - 1] at iteration t, or
+                                   NULL for the constant gamma */
 } or_params;
 
 typedef struct {
@@ -267,9 +270,11 @@ static void posterior(const or_params *p, int t, int i, const double *pi0, const
         q[i] = pit[i] + msum[i];
         break;
     case OR_MOMENTUM: { /* eqs. mombp1, mombp2, with the gradient of eq. mombp3 */
+        const double a = p->alpha_t ? p->alpha_t[t - 1] : p->alpha;
+        const double gm = p->gamma_t ? p->gamma_t[t - 1] : p->gamma;
         double grad = qprev[i] - pi0[i] - msum[i];
-        acc[i] = p->gamma * acc[i] + (1.0 - p->gamma) * grad;
-        q[i] = qprev[i] - p->alpha * acc[i];
+        acc[i] = gm * acc[i] + (1.0 - gm) * grad;
+        q[i] = qprev[i] - a * acc[i];
         break;
     }
     case OR_ADAGRAD: { /* eq. boost; active from the second iteration (READING) */

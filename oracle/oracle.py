@@ -45,7 +45,8 @@ class _Params(ctypes.Structure):
                 ("stop_on_syndrome", ctypes.c_int32), ("adagrad_g_from_t1", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("eps", ctypes.c_double), ("clamp", ctypes.c_double), ("alpha_t", ctypes.c_void_p),
-                ("alpha_last", ctypes.c_double), ("alpha_steps", ctypes.c_int32), ("serial", ctypes.c_int32)]
+                ("alpha_last", ctypes.c_double), ("alpha_steps", ctypes.c_int32), ("serial", ctypes.c_int32),
+                ("gamma_t", ctypes.c_void_p)]
 
 
 class _Outputs(ctypes.Structure):
@@ -105,7 +106,8 @@ class Params:
     gamma: float = 0.0
     eps: float = 1e-8
     clamp: float = 30.0
-    alpha_t: Optional[np.ndarray] = None   # EWAInit per-iteration discount, entry t-1 at iteration t
+    alpha_t: Optional[np.ndarray] = None   # per-iteration EWAInit discount or Momentum step, entry t-1 at t
+    gamma_t: Optional[np.ndarray] = None   # per-iteration Momentum decay, entry t-1 at iteration t
     alpha_last: float = 0.0                # AEWA: discount of the last attempt (alpha is the first)
     alpha_steps: int = 11                  # AEWA: number of attempts
     serial: bool = False                   # serial schedule (Alg. 1) instead of flooding (Alg. 2)
@@ -115,12 +117,16 @@ class Params:
                      int(bool(self.adagrad_g_from_t1)), float(self.alpha), float(self.gamma),
                      float(self.eps), float(self.clamp), None, float(self.alpha_last), int(self.alpha_steps),
                      int(bool(self.serial)))
-        if self.alpha_t is not None:
-            a = np.ascontiguousarray(self.alpha_t, dtype=np.float64)
-            if a.shape != (self.max_iter,):
-                raise ValueError("alpha_t needs one entry per iteration")
-            cp._keep = a                      # keeps the buffer alive as long as the struct
-            cp.alpha_t = a.ctypes.data
+        keep = []
+        for name in ("alpha_t", "gamma_t"):
+            v = getattr(self, name)
+            if v is not None:
+                a = np.ascontiguousarray(v, dtype=np.float64)
+                if a.shape != (self.max_iter,):
+                    raise ValueError(f"{name} needs one entry per iteration")
+                keep.append(a)
+                setattr(cp, name, a.ctypes.data)
+        cp._keep = keep                       # keeps the buffers alive as long as the struct
         return cp
 
 

@@ -1,17 +1,21 @@
-"""FP64 reference of the unrolled EWAInit-BP soft loss and its gradient.
+"""FP64 reference of the unrolled EWAInit-BP and Momentum-BP soft loss and its gradient.
 
 TEST INFRASTRUCTURE: only the tests and the benchmark's reference leg use it;
 it shares nothing with the GPU library.
 
-The forward is EWAInit-BP over GF(4) in the flooding schedule (section III,
-eq. EWAInit and Algorithm 2; check and qubit rules of section II-B1) run for a
-fixed number T of iterations with no early stop, with a discount alpha_t per
-iteration (alpha_1 unused: Pi^{(1)} = Pi^{(0)}) and learnable priors Pi^{(0)}.
+The forward is EWAInit-BP (section III-B, eq. EWAInit and Algorithm 2) or
+Momentum-BP (section III-A1, eqs. mombp1-3) over GF(4) in the flooding schedule
+(check and qubit rules of section II-B1) run for a fixed number T of iterations
+with no early stop, with learnable per-iteration parameters and priors Pi^{(0)}:
+EWAInit a discount alpha_t per iteration (alpha_1 unused: Pi^{(1)} = Pi^{(0)});
+Momentum a step alpha_t and a decay gamma_t per iteration (params [T, 2]):
+g^{(t)} = gamma_t g^{(t-1)} + (1 - gamma_t)(Q^{(t-1)} - Pi^{(0)} - M^{(t)}),
+Q^{(t)} = Q^{(t-1)} - alpha_t g^{(t)}, g^{(0)} = 0, Q^{(0)} = Pi^{(0)}.
 The loss is the mean over shots and qubits of the negative log GF(4) marginal
 of the sampled error at iteration T, with P_v(I) prop. to 1 and P_v(W) prop.
 to exp(-Q_W):  ln(1 + sum_W exp(-Q_W)) + Q_{e_v}  (Q_I = 0).
-The gradient with respect to alpha_t and Pi^{(0)} is torch autograd in
-float64 on the CPU.  Every step is written as the formula it implements, with
+The gradient with respect to the per-iteration parameters and Pi^{(0)} is torch
+autograd in float64 on the CPU.  Every step is written as the formula it implements, with
 whole-batch tensor operations and no reordering beyond plain sums.
 """
 from __future__ import annotations
@@ -78,9 +82,12 @@ def lam(tg: Tanner, Q):
             - torch.logaddexp(-Q[:, tg.a_idx], -Q[:, tg.b_idx]))
 
 
-def forward(tg: Tanner, alpha, prior, synd, err, T: int, clamp: float = 30.0):
-    """Unrolled EWAInit forward.  alpha: [T] (entry t-1 at iteration t), prior: [n, 3],
-    synd: [shots, m] {0,1}, err: [shots, n] Pauli codes.  Returns (loss, Q^{(T)} [shots, n, 3])."""
+def forward(tg: Tanner, alpha, prior, synd, err, T: int, clamp: float = 30.0, variant: str = "ewainit"):
+    """Unrolled forward.  alpha: EWAInit [T] (entry t-1 at iteration t), Momentum [T, 2]
+    (step, decay of iteration t in row t-1); prior: [n, 3], synd: [shots, m] {0,1}, err:
+    [shots, n] Pauli codes.  Returns (loss, Q^{(T)} [shots, n, 3])."""
+    if variant not in ("ewainit", "momentum"):
+        raise ValueError(f"unrolled reference: variant {variant}")
     synd = torch.as_tensor(np.asarray(synd), dtype=F64)
     err = np.asarray(err, np.uint8)
     shots = synd.shape[0]
@@ -92,7 +99,8 @@ def forward(tg: Tanner, alpha, prior, synd, err, T: int, clamp: float = 30.0):
     # initialisation (eq. init): m^{(0)}_{v->c} = lambda_{H_cv}(Pi^{(0)}_v)
     m_vc = clampC(lam(tg, pi0.expand(shots, -1)))
     check_sign = 1.0 - 2.0 * synd[:, tg.check]          # (-1)^{s_c} per edge
-    Q_prev = None
+    Q_prev = pi0.expand(shots, -1)                       # Q^{(0)} = Pi^{(0)}
+    g = torch.zeros(shots, 3 * tg.n, dtype=F64)          # Momentum: g^{(0)} = 0
     Q = None
     for t in range(1, T + 1):
         # horizontal update (eq. h_update): sign and phi-sum over the other edges of the check
@@ -101,10 +109,16 @@ def forward(tg: Tanner, alpha, prior, synd, err, T: int, clamp: float = 30.0):
         S = f[:, tg.others[:, 0]] + f[:, tg.others[:, 1]] + f[:, tg.others[:, 2]]
         sgn = check_sign * sg[:, tg.others[:, 0]] * sg[:, tg.others[:, 1]] * sg[:, tg.others[:, 2]]
         m_cv = clampC(sgn * phi(S))
-        # EWA prior (eq. EWAInit): Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}
-        pit = pi0 if t == 1 else alpha[t - 1] * pi0 + (1.0 - alpha[t - 1]) * Q_prev
-        # posterior (eq. p_update): Q^{(t)} = Pi^{(t)} + M^{(t)}
-        Q = pit + m_cv @ tg.A
+        M = m_cv @ tg.A
+        if variant == "ewainit":
+            # EWA prior (eq. EWAInit): Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}
+            pit = pi0 if t == 1 else alpha[t - 1] * pi0 + (1.0 - alpha[t - 1]) * Q_prev
+            # posterior (eq. p_update): Q^{(t)} = Pi^{(t)} + M^{(t)}
+            Q = pit + M
+        else:
+            # momentum (eqs. mombp1, mombp2; the gradient of eq. mombp3 is Q^{(t-1)} - Pi - M^{(t)})
+            g = alpha[t - 1, 1] * g + (1.0 - alpha[t - 1, 1]) * (Q_prev - pi0 - M)
+            Q = Q_prev - alpha[t - 1, 0] * g
         if t < T:
             # vertical update (eq. v_update): m_{v->c} = lambda_{H_cv}(Q_v) - m_{c->v}
             m_vc = clampC(lam(tg, Q) - m_cv)
@@ -119,12 +133,14 @@ def forward(tg: Tanner, alpha, prior, synd, err, T: int, clamp: float = 30.0):
     return (lse + q_e).mean(), Q3
 
 
-def loss_and_grad(hx, hz, alpha, prior, synd, err, T: int, clamp: float = 30.0, tg: Tanner = None):
-    """Loss and its gradient with respect to alpha [T] and prior [n, 3] (float64 numpy)."""
+def loss_and_grad(hx, hz, alpha, prior, synd, err, T: int, clamp: float = 30.0, tg: Tanner = None,
+                  variant: str = "ewainit"):
+    """Loss and its gradient with respect to the per-iteration parameters (alpha [T] for
+    EWAInit, [T, 2] for Momentum) and prior [n, 3] (float64 numpy)."""
     tg = tg or Tanner(hx, hz)
     a = torch.tensor(np.asarray(alpha, np.float64), requires_grad=True)
     p = torch.tensor(np.asarray(prior, np.float64).reshape(tg.n, 3), requires_grad=True)
-    loss, Q = forward(tg, a, p, synd, err, T, clamp)
+    loss, Q = forward(tg, a, p, synd, err, T, clamp, variant)
     loss.backward()
     # alpha is not used at all when T = 1 (alpha_1 is unused): its gradient is then 0
     ga = a.grad.numpy().copy() if a.grad is not None else np.zeros(a.shape)
