@@ -32,6 +32,7 @@ from qecgen import configs  # noqa: E402
 P_ERR = configs.CONFIG3["p"]
 ALPHA = configs.alpha(3, "ewainit")     # EWAInit discount of the mixed batch (chosen on the oracle)
 ALPHA_EXTRA = 0.5    # the paper's trapping-set value, for the sections it gives no discount for
+MOMENTUM_ALPHA = configs.alpha(2, "momentum")   # Momentum step of the toric sweep (chosen on the oracle)
 MAX_ITER = configs.CONFIG3["max_iter"]
 BASE_SHOTS = configs.CONFIG3["base_shots"]
 # (family, size, shot multiplier): smallest size(s) 1, middle 2, largest 4
@@ -698,12 +699,36 @@ def run_unrolled(torch, qecgen, P, dev):
     fwd, bwd = min(times, key=lambda x: x[0] + x[1])
     eu = shots * T * g.nnz
     log(f"unrolled: forward {fwd:.2f} ms, backward {bwd:.2f} ms")
-    return {"workload": "planar d=9, p=0.06, 65,536 shots, T=32 unrolled EWAInit iterations, checkpoints every 8, "
-                        "loss and gradients w.r.t. alpha_t and the priors",
-            "forward_ms": fwd, "backward_ms": bwd, "loss": float(loss.detach()),
-            "shots_per_s_forward_backward": shots / ((fwd + bwd) / 1e3),
-            "edge_updates_per_s_forward": eu / (fwd / 1e3),
-            "grad_alpha_norm": float(alpha.grad.norm()), "grad_prior_norm": float(prior.grad.norm())}
+    res = {"workload": "planar d=9, p=0.06, 65,536 shots, T=32 unrolled EWAInit iterations, checkpoints every 8, "
+                       "loss and gradients w.r.t. alpha_t and the priors",
+           "forward_ms": fwd, "backward_ms": bwd, "loss": float(loss.detach()),
+           "shots_per_s_forward_backward": shots / ((fwd + bwd) / 1e3),
+           "edge_updates_per_s_forward": eu / (fwd / 1e3),
+           "grad_alpha_norm": float(alpha.grad.norm()), "grad_prior_norm": float(prior.grad.norm())}
+    # the same batch unrolled as Momentum-BP: a step and a decay per iteration (starting
+    # from the toric sweep's step and gamma 0)
+    params = torch.tensor([[MOMENTUM_ALPHA, 0.0]] * T, dtype=torch.float32, device=dev, requires_grad=True)
+    times = []
+    for rep in range(3):
+        params.grad = None
+        prior.grad = None
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        c = torch.cuda.Event(enable_timing=True)
+        a.record()
+        loss_m = P.unrolled_loss(g, params, prior, syn, err, T, K, variant="momentum")
+        b.record()
+        loss_m.backward()
+        c.record()
+        torch.cuda.synchronize()
+        times.append((a.elapsed_time(b), b.elapsed_time(c)))
+    fwd_m, bwd_m = min(times, key=lambda x: x[0] + x[1])
+    log(f"unrolled momentum: forward {fwd_m:.2f} ms, backward {bwd_m:.2f} ms")
+    res["momentum"] = {"workload": "the same batch, T=32 unrolled Momentum-BP iterations, loss and gradients w.r.t. "
+                                   "the steps alpha_t, the decays gamma_t and the priors",
+                       "forward_ms": fwd_m, "backward_ms": bwd_m, "loss": float(loss_m.detach()),
+                       "grad_params_norm": float(params.grad.norm()), "grad_prior_norm": float(prior.grad.norm())}
+    return res
 
 
 def run_large(torch, qecgen, P, dev):

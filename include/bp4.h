@@ -352,10 +352,15 @@ int bp4_bookkeep(const bp4_graph *g, const void *dev_graph, int64_t shots,
  * A variant of section III run for exactly T iterations (Algorithm 2 without
  * the early stop) with learnable per-iteration parameters param_t dev float
  * [T][k] and learnable priors Pi^{(0)} dev float [n][3]; messages clamped to
- * [-llr_clamp, llr_clamp] as in bp4_decode.  Built for variant BP4_EWAINIT,
- * k = 1: param_t[t-1] is the discount alpha_t of iteration t (Pi^{(1)} =
- * Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}, eq.
- * EWAInit; entry 0 is unused).  Every other variant answers EUNSUPPORTED.
+ * [-llr_clamp, llr_clamp] as in bp4_decode.  Built for two variants:
+ *   BP4_EWAINIT, k = 1: param_t[t-1] is the discount alpha_t of iteration t
+ *   (Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)},
+ *   eq. EWAInit; entry 0 is unused);
+ *   BP4_MOMENTUM, k = 2: param_t[t-1] = (alpha_t, gamma_t), the step and decay
+ *   of iteration t (g^{(t)} = gamma_t g^{(t-1)} + (1 - gamma_t)(Q^{(t-1)} -
+ *   Pi^{(0)} - M^{(t)}), Q^{(t)} = Q^{(t-1)} - alpha_t g^{(t)}, g^{(0)} = 0, eqs.
+ *   mombp1-3; the state also keeps g and M, 9 words per qubit instead of 3).
+ * Every other variant answers EUNSUPPORTED.
  * Loss: the mean over shots and qubits of
  * ln(1 + sum_W e^{-Q_W^{(T)}}) + Q_{e_v}^{(T)} (Q_I = 0), the negative log of
  * the GF(4) marginal of the sampled error e_v.  The adjoint returns its
@@ -367,7 +372,7 @@ int bp4_bookkeep(const bp4_graph *g, const void *dev_graph, int64_t shots,
  * err uint8 [shots][n] (Pauli codes), saved and ws of the sizes below.
  * Errors: EINVAL (T < 1, ckpt_every < 1, shots < 1, llr_clamp not > 0, NULL
  * pointers, variant outside bp4_variant), EUNSUPPORTED (a variant other than
- * EWAInit, a wide graph), EWORKSPACE (saved or ws too small), EHIP. */
+ * EWAInit or Momentum, a wide graph), EWORKSPACE (saved or ws too small), EHIP. */
 
 /* Bytes of the checkpoint buffer and of the workspace for these sizes. */
 int bp4_unrolled_sizes(const bp4_graph *g, int32_t variant, int32_t T, int32_t ckpt_every, int64_t shots,

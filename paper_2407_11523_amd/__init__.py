@@ -5,8 +5,9 @@ Traditional LLR-BP4, Momentum-BP, AdaGrad-BP and EWAInit-BP (Chen, Yi, Liang, Wa
 batches of syndromes, as hand-written HIP kernels behind the C ABI of include/bp4.h.
 """
 from ._lib import BP4Error, load
-from .api import (Captured, Graph, MixedBatch, Params, UnrolledEWAInit, bookkeep, decode, decode_mixed, decode_plain,
-                  prior_llr, sample, unrolled_forward, unrolled_loss, unrolled_sizes)
+from .api import (Captured, Graph, MixedBatch, Params, UnrolledBP, UnrolledEWAInit, bookkeep, decode, decode_mixed,
+                  decode_plain, prior_llr, sample, unrolled_forward, unrolled_loss, unrolled_sizes)
 
-__all__ = ["BP4Error", "Captured", "Graph", "MixedBatch", "Params", "UnrolledEWAInit", "bookkeep", "decode", "decode_mixed",
-           "decode_plain", "load", "prior_llr", "sample", "unrolled_forward", "unrolled_loss", "unrolled_sizes"]
+__all__ = ["BP4Error", "Captured", "Graph", "MixedBatch", "Params", "UnrolledBP", "UnrolledEWAInit", "bookkeep", "decode",
+           "decode_mixed", "decode_plain", "load", "prior_llr", "sample", "unrolled_forward", "unrolled_loss",
+           "unrolled_sizes"]

@@ -353,8 +353,13 @@ class Captured:
 
 
 # ---------------------------------------------------------------------------
-# Differentiable unrolled EWAInit-BP
+# Differentiable unrolled EWAInit-BP and Momentum-BP
 # ---------------------------------------------------------------------------
+
+# per-iteration parameters of each unrolled variant: EWAInit alpha_t [T]; Momentum
+# (alpha_t, gamma_t) [T, 2]
+UNROLLED_PARAMS = {"ewainit": 1, "momentum": 2}
+
 
 def unrolled_sizes(g: Graph, T: int, ckpt_every: int, shots: int, variant: str = "ewainit"):
     """(checkpoint bytes, workspace bytes) of the unrolled forward/backward."""
@@ -364,11 +369,14 @@ def unrolled_sizes(g: Graph, T: int, ckpt_every: int, shots: int, variant: str =
     return int(a.value), int(b.value)
 
 
-def _unrolled_inputs(g: Graph, alpha, prior, synd, err, T: int):
-    """Validated, contiguous device inputs of the unrolled kernels: alpha float32 [T],
-    prior float32 [n, 3], synd uint8 [shots, m], err uint8 [shots, n] on the graph's device."""
+def _unrolled_inputs(g: Graph, params, prior, synd, err, T: int, variant: str):
+    """Validated, contiguous device inputs of the unrolled kernels: params float32 [T]
+    (EWAInit) or [T, 2] (Momentum), prior float32 [n, 3], synd uint8 [shots, m], err uint8
+    [shots, n] on the graph's device."""
     dev = g.dev.device
-    for name, t in (("alpha", alpha), ("prior", prior), ("synd", synd), ("err", err)):
+    if variant not in UNROLLED_PARAMS:
+        raise BP4Error(-6, f"the unrolled path is built for {sorted(UNROLLED_PARAMS)}, not {variant}")
+    for name, t in (("params", params), ("prior", prior), ("synd", synd), ("err", err)):
         if not isinstance(t, torch.Tensor) or t.device != dev:
             raise BP4Error(-1, f"{name} must be a tensor on {dev}")
     if synd.dtype != torch.uint8 or err.dtype != torch.uint8:
@@ -377,74 +385,93 @@ def _unrolled_inputs(g: Graph, alpha, prior, synd, err, T: int):
         raise BP4Error(-1, "synd must be [shots, m] with shots >= 1")
     if tuple(err.shape) != (synd.shape[0], g.n):
         raise BP4Error(-1, "err must be [shots, n]")
-    if tuple(alpha.shape) != (int(T),) or tuple(prior.shape) != (g.n, 3):
-        raise BP4Error(-1, "alpha must be [T] and prior [n, 3]")
-    if not (alpha.is_floating_point() and prior.is_floating_point()):
-        raise BP4Error(-1, "alpha and prior must be floating point")
-    return (alpha.detach().to(torch.float32).contiguous(), prior.detach().to(torch.float32).contiguous(),
+    k = UNROLLED_PARAMS[variant]
+    want = (int(T),) if k == 1 else (int(T), k)
+    if tuple(params.shape) != want or tuple(prior.shape) != (g.n, 3):
+        raise BP4Error(-1, f"{variant} parameters must be {list(want)} and prior [n, 3]")
+    if not (params.is_floating_point() and prior.is_floating_point()):
+        raise BP4Error(-1, "parameters and prior must be floating point")
+    return (params.detach().to(torch.float32).contiguous(), prior.detach().to(torch.float32).contiguous(),
             synd.contiguous(), err.contiguous())
 
 
-class UnrolledEWAInit(torch.autograd.Function):
-    """Soft loss of T unrolled EWAInit-BP iterations (HIP forward and hand-written adjoint).
+class UnrolledBP(torch.autograd.Function):
+    """Soft loss of T unrolled EWAInit-BP or Momentum-BP iterations (HIP forward and
+    hand-written adjoint).
 
-    forward(alpha [T] float32, prior [n, 3] float32, graph, synd, err, T, ckpt_every, clamp)
-    returns the mean over shots and qubits of ln(1 + sum_W e^{-Q_W}) + Q_{e_v} at t = T
-    as a float64 scalar; backward gives the gradients of alpha and prior."""
+    forward(params, prior [n, 3], graph, synd, err, T, ckpt_every, clamp, variant):
+    params is EWAInit's discounts alpha_t [T] or Momentum's steps and decays
+    (alpha_t, gamma_t) [T, 2]; returns the mean over shots and qubits of
+    ln(1 + sum_W e^{-Q_W}) + Q_{e_v} at t = T as a float64 scalar; backward gives the
+    gradients of params and prior."""
 
     @staticmethod
-    def forward(ctx, alpha, prior, g, synd, err, T, ckpt_every, clamp):
+    def forward(ctx, params, prior, g, synd, err, T, ckpt_every, clamp, variant):
         dev = synd.device
-        a32, p32, syn, er = _unrolled_inputs(g, alpha, prior, synd, err, T)
+        p32, pr32, syn, er = _unrolled_inputs(g, params, prior, synd, err, T, variant)
         shots = syn.shape[0]
-        sb, wb = unrolled_sizes(g, T, ckpt_every, shots)
+        sb, wb = unrolled_sizes(g, T, ckpt_every, shots, variant)
         saved = torch.empty(sb, dtype=torch.uint8, device=dev)
         ws = torch.empty(wb, dtype=torch.uint8, device=dev)
         loss = torch.empty(1, dtype=torch.float64, device=dev)
-        check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), VARIANTS["ewainit"], int(T), int(ckpt_every),
-                                          float(clamp), shots, _ptr(a32), _ptr(p32), _ptr(syn), _ptr(er),
+        check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), VARIANTS[variant], int(T), int(ckpt_every),
+                                          float(clamp), shots, _ptr(p32), _ptr(pr32), _ptr(syn), _ptr(er),
                                           _ptr(loss), ctypes.c_void_p(0), _ptr(saved), sb, _ptr(ws), wb,
                                           _stream(dev)))
-        ctx.g, ctx.T, ctx.K, ctx.clamp = g, int(T), int(ckpt_every), float(clamp)
-        ctx.bufs = (a32, p32, syn, er, saved, ws)
-        ctx.dtypes = (alpha.dtype, prior.dtype)
+        ctx.g, ctx.T, ctx.K, ctx.clamp, ctx.variant = g, int(T), int(ckpt_every), float(clamp), variant
+        ctx.bufs = (p32, pr32, syn, er, saved, ws)
+        ctx.dtypes = (params.dtype, prior.dtype)
         return loss[0]
 
     @staticmethod
     def backward(ctx, dloss):
-        alpha, prior, synd, err, saved, ws = ctx.bufs
+        params, prior, synd, err, saved, ws = ctx.bufs
         g = ctx.g
         dev = synd.device
         dl = dloss.detach().to(device=dev, dtype=torch.float32).reshape(1).contiguous()
-        dalpha = torch.empty(ctx.T, dtype=torch.float64, device=dev)
+        dparams = torch.empty(params.shape, dtype=torch.float64, device=dev)
         dprior = torch.empty(g.n, 3, dtype=torch.float64, device=dev)
-        check(g._lib.bp4_unrolled_backward(g.handle, _ptr(g.dev), VARIANTS["ewainit"], ctx.T, ctx.K, ctx.clamp,
-                                           synd.shape[0], _ptr(alpha), _ptr(prior), _ptr(synd), _ptr(err), _ptr(dl),
-                                           _ptr(saved), saved.numel(), _ptr(dalpha), _ptr(dprior), _ptr(ws),
+        check(g._lib.bp4_unrolled_backward(g.handle, _ptr(g.dev), VARIANTS[ctx.variant], ctx.T, ctx.K, ctx.clamp,
+                                           synd.shape[0], _ptr(params), _ptr(prior), _ptr(synd), _ptr(err), _ptr(dl),
+                                           _ptr(saved), saved.numel(), _ptr(dparams), _ptr(dprior), _ptr(ws),
                                            ws.numel(), _stream(dev)))
         ctx.bufs = None
-        return dalpha.to(ctx.dtypes[0]), dprior.to(ctx.dtypes[1]), None, None, None, None, None, None
+        return dparams.to(ctx.dtypes[0]), dprior.to(ctx.dtypes[1]), None, None, None, None, None, None, None
 
 
-def unrolled_loss(g: Graph, alpha: torch.Tensor, prior: torch.Tensor, synd: torch.Tensor, err: torch.Tensor,
-                  T: int, ckpt_every: int = 8, clamp: float = 30.0) -> torch.Tensor:
-    """Differentiable soft loss of T unrolled EWAInit-BP iterations (see UnrolledEWAInit)."""
-    return UnrolledEWAInit.apply(alpha, prior, g, synd, err, T, ckpt_every, clamp)
+class UnrolledEWAInit(torch.autograd.Function):
+    """UnrolledBP for EWAInit: forward(alpha [T], prior [n, 3], graph, synd, err, T,
+    ckpt_every, clamp)."""
+
+    @staticmethod
+    def forward(ctx, alpha, prior, g, synd, err, T, ckpt_every, clamp):
+        return UnrolledBP.forward(ctx, alpha, prior, g, synd, err, T, ckpt_every, clamp, "ewainit")
+
+    @staticmethod
+    def backward(ctx, dloss):
+        return UnrolledBP.backward(ctx, dloss)[:8]
 
 
-def unrolled_forward(g: Graph, alpha: torch.Tensor, prior: torch.Tensor, synd: torch.Tensor, err: torch.Tensor,
-                     T: int, ckpt_every: int = 8, clamp: float = 30.0, want_q: bool = False):
+def unrolled_loss(g: Graph, params: torch.Tensor, prior: torch.Tensor, synd: torch.Tensor, err: torch.Tensor,
+                  T: int, ckpt_every: int = 8, clamp: float = 30.0, variant: str = "ewainit") -> torch.Tensor:
+    """Differentiable soft loss of T unrolled iterations of `variant` (see UnrolledBP)."""
+    return UnrolledBP.apply(params, prior, g, synd, err, T, ckpt_every, clamp, variant)
+
+
+def unrolled_forward(g: Graph, params: torch.Tensor, prior: torch.Tensor, synd: torch.Tensor, err: torch.Tensor,
+                     T: int, ckpt_every: int = 8, clamp: float = 30.0, want_q: bool = False,
+                     variant: str = "ewainit"):
     """Forward only: (loss float64 [1], Q^{(T)} [shots, n, 3] or None)."""
     dev = synd.device
-    a32, p32, syn, er = _unrolled_inputs(g, alpha, prior, synd, err, T)
+    p32, pr32, syn, er = _unrolled_inputs(g, params, prior, synd, err, T, variant)
     shots = syn.shape[0]
-    sb, wb = unrolled_sizes(g, T, ckpt_every, shots)
+    sb, wb = unrolled_sizes(g, T, ckpt_every, shots, variant)
     saved = torch.empty(sb, dtype=torch.uint8, device=dev)
     ws = torch.empty(wb, dtype=torch.uint8, device=dev)
     loss = torch.empty(1, dtype=torch.float64, device=dev)
     q = torch.empty(shots, g.n, 3, dtype=torch.float32, device=dev) if want_q else None
-    check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), VARIANTS["ewainit"], int(T), int(ckpt_every),
-                                      float(clamp), shots, _ptr(a32), _ptr(p32), _ptr(syn), _ptr(er), _ptr(loss),
+    check(g._lib.bp4_unrolled_forward(g.handle, _ptr(g.dev), VARIANTS[variant], int(T), int(ckpt_every),
+                                      float(clamp), shots, _ptr(p32), _ptr(pr32), _ptr(syn), _ptr(er), _ptr(loss),
                                       _ptr(q), _ptr(saved), sb, _ptr(ws), wb, _stream(dev)))
     # the contiguous copies are named, so none is freed (and reused) before the launch
     return loss, q

@@ -256,13 +256,14 @@ static std::vector<uint32_t> gather_walk(int n, int m, const std::vector<int32_t
 
 extern "C" {
 
-// Variants with a built unrolled forward and adjoint, and their per-iteration
-// parameter count k of param_t [T][k].
+// Variants with a built unrolled forward and adjoint (EWAInit: param_t [T][1], the
+// discounts; Momentum: [T][2], the steps and decays).
 static int unrolled_variant(int32_t variant, const char *who)
 {
     if (variant < BP4_BP || variant > BP4_AEWA) return fail(BP4_EINVAL, "%s: variant %d is not a bp4_variant", who, variant);
-    if (variant != BP4_EWAINIT)
-        return fail(BP4_EUNSUPPORTED, "%s: the unrolled path is built for EWAInit-BP only (variant %d)", who, variant);
+    if (variant != BP4_EWAINIT && variant != BP4_MOMENTUM)
+        return fail(BP4_EUNSUPPORTED, "%s: the unrolled path is built for EWAInit-BP and Momentum-BP (variant %d)", who,
+                    variant);
     return BP4_OK;
 }
 
@@ -289,7 +290,7 @@ int bp4_unrolled_sizes(const bp4_graph *g, int32_t variant, int32_t T, int32_t c
     if (rc) return rc;
     if (T < 1 || ckpt_every < 1) return fail(BP4_EINVAL, "unrolled_sizes: T and ckpt_every must be >= 1");
     if (shots < 1 || shots > 0x7FFFFFFF) return fail(BP4_EINVAL, "unrolled_sizes: shots out of range");
-    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
+    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, variant, T, ckpt_every, shots);
     *saved_bytes = z.saved;
     *ws_bytes = z.ws;
     return BP4_OK;
@@ -303,11 +304,11 @@ int bp4_unrolled_forward(const bp4_graph *g, const void *dev_graph, int32_t vari
     int rc = unrolled_check(g, dev_graph, variant, T, ckpt_every, llr_clamp, shots, param_t, prior, synd, err);
     if (rc) return rc;
     if (!loss || !saved || !ws) return fail(BP4_EINVAL, "unrolled_forward: NULL output or buffer");
-    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
+    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, variant, T, ckpt_every, shots);
     if (saved_bytes < z.saved || ws_bytes < z.ws)
         return fail(BP4_EWORKSPACE, "unrolled_forward: saved %zu < %zu or ws %zu < %zu bytes", saved_bytes, z.saved,
                     ws_bytes, z.ws);
-    hipError_t e = launch_unrolled_forward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, param_t,
+    hipError_t e = launch_unrolled_forward(g->view(dev_graph), variant, T, ckpt_every, llr_clamp, (int32_t)shots, param_t,
                                            prior, synd, err, loss, q_out, saved, ws, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "unrolled_forward: launch");
     return BP4_OK;
@@ -322,11 +323,11 @@ int bp4_unrolled_backward(const bp4_graph *g, const void *dev_graph, int32_t var
     int rc = unrolled_check(g, dev_graph, variant, T, ckpt_every, llr_clamp, shots, param_t, prior, synd, err);
     if (rc) return rc;
     if (!dparam_t || !dprior || !saved || !ws) return fail(BP4_EINVAL, "unrolled_backward: NULL output or buffer");
-    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, T, ckpt_every, shots);
+    const UnrolledSizes z = unrolled_sizes(g->m, g->n, g->nnz, variant, T, ckpt_every, shots);
     if (saved_bytes < z.saved || ws_bytes < z.ws)
         return fail(BP4_EWORKSPACE, "unrolled_backward: saved %zu < %zu or ws %zu < %zu bytes", saved_bytes,
                     z.saved, ws_bytes, z.ws);
-    hipError_t e = launch_unrolled_backward(g->view(dev_graph), T, ckpt_every, llr_clamp, (int32_t)shots, param_t,
+    hipError_t e = launch_unrolled_backward(g->view(dev_graph), variant, T, ckpt_every, llr_clamp, (int32_t)shots, param_t,
                                             prior, synd, err, dloss, saved, dparam_t, dprior, ws,
                                             static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "unrolled_backward: launch");

@@ -141,18 +141,19 @@ hipError_t launch_decode_soa(const GraphView &g, const bp4_params &p, int32_t sh
                              const uint8_t *synd, uint8_t *est, uint8_t *conv, int32_t *iters, float *q_out,
                              float *mvc_out, float *mcv_out, void *ws, int32_t lanes, int32_t iter_block,
                              int with_y, hipStream_t s);
-// Unrolled EWAInit forward and adjoint (fixed T, checkpoints every K iterations).
+// Unrolled EWAInit / Momentum forward and adjoint (fixed T, checkpoints every K
+// iterations); variant BP4_EWAINIT (param [T]) or BP4_MOMENTUM (param [T][2]).
 struct UnrolledSizes {
     size_t saved;   // checkpoints written by the forward, read by the adjoint
     size_t ws;      // segment states, adjoint record, per-wavefront partial sums
 };
-UnrolledSizes unrolled_sizes(int m, int n, int nnz, int32_t T, int32_t K, int64_t shots);
-hipError_t launch_unrolled_forward(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots,
-                                   const float *alpha, const float *prior, const uint8_t *synd, const uint8_t *err,
+UnrolledSizes unrolled_sizes(int m, int n, int nnz, int variant, int32_t T, int32_t K, int64_t shots);
+hipError_t launch_unrolled_forward(const GraphView &g, int variant, int32_t T, int32_t K, float clamp, int32_t shots,
+                                   const float *param, const float *prior, const uint8_t *synd, const uint8_t *err,
                                    double *loss, float *q_out, void *saved, void *ws, hipStream_t s);
-hipError_t launch_unrolled_backward(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots,
-                                    const float *alpha, const float *prior, const uint8_t *synd, const uint8_t *err,
-                                    const float *dloss, const void *saved, double *dalpha, double *dprior, void *ws,
+hipError_t launch_unrolled_backward(const GraphView &g, int variant, int32_t T, int32_t K, float clamp, int32_t shots,
+                                    const float *param, const float *prior, const uint8_t *synd, const uint8_t *err,
+                                    const float *dloss, const void *saved, double *dparam, double *dprior, void *ws,
                                     hipStream_t s);
 
 // The large-code kernel is the automatic choice when even 256-lane groups need more

@@ -1,20 +1,26 @@
-// Unrolled EWAInit-BP over GF(4) with a fixed number T of flooding iterations
-// and no early stop, its soft loss, and the hand-written adjoint (reverse-mode
-// derivative) with respect to the per-iteration discounts alpha_t and the
-// priors Pi^{(0)}.
+// Unrolled EWAInit-BP and Momentum-BP over GF(4) with a fixed number T of
+// flooding iterations and no early stop, their soft loss, and the hand-written
+// adjoint (reverse-mode derivative) with respect to the per-iteration parameters
+// and the priors Pi^{(0)}.
 //
-// Forward (section III, eq. EWAInit and Algorithm 2; check and qubit rules of
-// section II-B1): Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t)
-// Q^{(t-1)}, with the same per-node arithmetic as the decode kernels.  Loss: the
-// mean over shots and qubits of ln(1 + sum_W e^{-Q_W}) + Q_{e_v} at t = T
-// (Q_I = 0), the negative log GF(4) marginal of the sampled error.
+// Forward (check and qubit rules of section II-B1, the same per-node arithmetic
+// as the decode kernels):
+//   EWAInit (section III-B, eq. EWAInit and Algorithm 2), a discount alpha_t per
+//   iteration: Pi^{(1)} = Pi^{(0)}, Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t)
+//   Q^{(t-1)}, Q^{(t)} = Pi^{(t)} + M^{(t)}.
+//   Momentum (section III-A1, eqs. mombp1-3), a step alpha_t and a decay gamma_t
+//   per iteration: g^{(t)} = gamma_t g^{(t-1)} + (1 - gamma_t)(Q^{(t-1)} - Pi^{(0)}
+//   - M^{(t)}), Q^{(t)} = Q^{(t-1)} - alpha_t g^{(t)}, g^{(0)} = 0.
+// Loss: the mean over shots and qubits of ln(1 + sum_W e^{-Q_W}) + Q_{e_v} at
+// t = T (Q_I = 0), the negative log GF(4) marginal of the sampled error.
 //
 // A workgroup of kUnrWaves wavefronts runs a chunk of 64 shots, one shot per
 // lane column: wavefront g takes the checks and the qubits whose index is g
 // modulo kUnrWaves, with a workgroup barrier between the check and the qubit
 // pass.  The state of a shot after iteration t is its messages m_{v->c}^{(t)}
-// (E words) and its posterior Q^{(t)} (3N words), kept as a column of a
-// per-chunk record [chunk][item][64 columns] in HBM.
+// (E words) and its posterior Q^{(t)} (3N words), for Momentum also g^{(t)} and
+// the incoming sums M^{(t)} (3N words each), kept as a column of a per-chunk
+// record [chunk][item][64 columns] in HBM.
 // The forward keeps the state every `ckpt` iterations; the adjoint walks the
 // segments from last to first, recomputes a segment's states from its
 // checkpoint, then runs the reverse sweep through it.  Gradient sums over
@@ -28,18 +34,34 @@ constexpr int kUnrWaves = 8;                // wavefronts sharing one chunk of 6
 constexpr int kUnrBlock = 64 * kUnrWaves;
 constexpr int kUnrRound = 256;               // records are allocated for shots rounded up to this
 
+// Per-variant layout: words per qubit of a state after the messages (Q; Momentum: Q,
+// g, M), of the adjoint record after the message adjoints (Q, Pi^{(0)}; Momentum also
+// g), and parameters per iteration (alpha_t; Momentum alpha_t, gamma_t).
+template <int VAR> struct UnrLayout {
+    static_assert(VAR == BP4_EWAINIT || VAR == BP4_MOMENTUM, "unrolled variants: EWAInit, Momentum");
+    static constexpr bool kMom = VAR == BP4_MOMENTUM;
+    static constexpr int kState = kMom ? 9 : 3;
+    static constexpr int kAdj = kMom ? 9 : 6;
+    static constexpr int kParams = kMom ? 2 : 1;
+};
+constexpr int unr_state_words(int variant) { return variant == BP4_MOMENTUM ? 9 : 3; }
+constexpr int unr_adj_words(int variant) { return variant == BP4_MOMENTUM ? 9 : 6; }
+constexpr int unr_params(int variant) { return variant == BP4_MOMENTUM ? 2 : 1; }
+
 template <typename T> using konst = const __attribute__((address_space(4))) T;
 template <typename T> __device__ __forceinline__ konst<T> *as_const(const T *p) { return (konst<T> *)p; }
 
 struct UnrArgs {
     GraphView g;
-    const float *alpha;       // [T], entry t-1 at iteration t (entry 0 unused)
+    const float *param;       // [T][k]: row t-1 at iteration t (EWAInit alpha_t, entry 0 unused;
+                              // Momentum alpha_t, gamma_t)
     const float *prior;       // [n][3] Pi^{(0)}
     const uint8_t *synd;      // [shots][m]
     const uint8_t *err;       // [shots][n] Pauli codes of the sampled errors
-    float *ckpt;              // [nseg][waves][E + 3N][64] states at t = 0, K, 2K, ...
-    float *seg;               // [K + 1][waves][E + 3N][64] states of one segment
-    float *adj;               // [waves][E + 6N][64] adjoints: m (E), Q (3N), Pi^{(0)} (3N)
+    float *ckpt;              // [nseg][waves][SI][64] states at t = 0, K, 2K, ... (SI = E + 3N or E + 9N)
+    float *seg;               // [K + 1][waves][SI][64] states of one segment
+    float *adj;               // [waves][E + 6N or E + 9N][64] adjoints: m (E), Q (3N), Pi^{(0)} (3N),
+                              // Momentum g (3N)
     double *partial;          // [waves][nout] per-chunk sums
     float *q_out;             // optional [shots][n][3] Q^{(T)}
     int32_t shots, T, K, nseg, waves, nout;
@@ -105,6 +127,7 @@ struct Lane {
     }
 };
 
+template <int VAR>
 __device__ __forceinline__ Lane lane_of(const UnrArgs &a)
 {
     Lane L;
@@ -114,7 +137,7 @@ __device__ __forceinline__ Lane lane_of(const UnrArgs &a)
     // and prior read indexed by them stay scalar
     L.part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     L.have = (int64_t)L.wave * 64 + L.lane < a.shots;
-    L.SI = (size_t)a.g.nnz + 3 * (size_t)a.g.n;
+    L.SI = (size_t)a.g.nnz + UnrLayout<VAR>::kState * (size_t)a.g.n;
     return L;
 }
 
@@ -139,8 +162,9 @@ __device__ double block_sum(double x, double *sh)
     return t;
 }
 
-// m^{(0)}_{v->c} = lambda(Pi^{(0)}) clamped, Q^{(0)} = Pi^{(0)}  (eq. init), written
-// to st and ck.
+// m^{(0)}_{v->c} = lambda(Pi^{(0)}) clamped, Q^{(0)} = Pi^{(0)}  (eq. init), Momentum
+// g^{(0)} = 0 (and M, unused at t = 0, = 0), written to st and ck.
+template <int VAR>
 __device__ void init_state(const UnrArgs &a, const Lane &L, float *st, float *ck)
 {
     if (!L.have) return;
@@ -161,6 +185,13 @@ __device__ void init_state(const UnrArgs &a, const Lane &L, float *st, float *ck
         for (int x = 0; x < 3; ++x) {
             st[(size_t)(E + 3 * v + x) * 64] = p3[x];
             ck[(size_t)(E + 3 * v + x) * 64] = p3[x];
+            if constexpr (UnrLayout<VAR>::kMom) {
+                const int n = a.g.n;
+                for (int w = 1; w <= 2; ++w) {
+                    st[(size_t)(E + 3 * w * n + 3 * v + x) * 64] = 0.0f;
+                    ck[(size_t)(E + 3 * w * n + 3 * v + x) * 64] = 0.0f;
+                }
+            }
         }
     }
 }
@@ -171,6 +202,7 @@ __device__ void init_state(const UnrArgs &a, const Lane &L, float *st, float *ck
 // message and posterior item belongs to one check and one qubit, so the passes
 // need only the workgroup barrier between them and the one at the end.  Called by
 // every thread of the workgroup.
+template <int VAR>
 __device__ void forward_iteration(const UnrArgs &a, const Lane &L, int t, const float *src, float *dst, int shot)
 {
     konst<uint32_t> *cedge = as_const(a.g.cedge);
@@ -195,11 +227,12 @@ __device__ void forward_iteration(const UnrArgs &a, const Lane &L, int t, const 
         }
     }
     __syncthreads();
+    constexpr bool kMom = UnrLayout<VAR>::kMom;
     VariantParams vp;
-    vp.variant = BP4_EWAINIT;
+    vp.variant = VAR;
     vp.g_from_t1 = 0;
-    vp.alpha = a.alpha[t - 1];
-    vp.gamma = 0.0f;
+    vp.alpha = a.param[UnrLayout<VAR>::kParams * (t - 1)];
+    vp.gamma = kMom ? a.param[2 * (t - 1) + 1] : 0.0f;
     vp.eps = 0.0f;
     if (L.have) {
         for (int v = L.part; v < n; v += kUnrWaves) {
@@ -213,8 +246,24 @@ __device__ void forward_iteration(const UnrArgs &a, const Lane &L, int t, const 
             const float p3[3] = {prior[3 * v], prior[3 * v + 1], prior[3 * v + 2]};
             float st[3], ac[3] = {0.0f, 0.0f, 0.0f}, qn[3];
             for (int x = 0; x < 3; ++x) st[x] = src[(size_t)(E + 3 * v + x) * 64];
+            if constexpr (kMom)
+                for (int x = 0; x < 3; ++x) ac[x] = src[(size_t)(E + 3 * n + 3 * v + x) * 64];
             qubit_posterior(vp, t, p3, S, A, st, ac, qn);
             for (int x = 0; x < 3; ++x) dst[(size_t)(E + 3 * v + x) * 64] = qn[x];
+            if constexpr (kMom) {
+                // g^{(t)} and the sums M^{(t)} the posterior rule used (for the adjoint)
+                float M[3];
+                {
+#pragma clang fp contract(off)
+                    M[0] = S[3] + S[2];
+                    M[1] = S[1] + S[2];
+                    M[2] = S[1] + S[3];
+                }
+                for (int x = 0; x < 3; ++x) {
+                    dst[(size_t)(E + 3 * n + 3 * v + x) * 64] = ac[x];
+                    dst[(size_t)(E + 6 * n + 3 * v + x) * 64] = M[x];
+                }
+            }
             if (t < a.T) {
                 float lam[4];
                 qubit_lambdas(qn, var_labels_present(info), lam);
@@ -226,18 +275,19 @@ __device__ void forward_iteration(const UnrArgs &a, const Lane &L, int t, const 
     __syncthreads();
 }
 
+template <int VAR>
 __global__ void __launch_bounds__(kUnrBlock) unrolled_forward_kernel(UnrArgs a)
 {
     __shared__ double sh[kUnrWaves];
-    const Lane L = lane_of(a);
+    const Lane L = lane_of<VAR>(a);
     if ((int)L.wave >= a.waves) return;   // the whole workgroup: no such chunk
     const int col = (int)L.wave * 64 + L.lane;
     const int n = a.g.n, E = a.g.nnz;
     float *work = L.state(a.seg, 0, a.waves);
-    init_state(a, L, work, L.state(a.ckpt, 0, a.waves));
+    init_state<VAR>(a, L, work, L.state(a.ckpt, 0, a.waves));
     __syncthreads();
     for (int t = 1; t <= a.T; ++t) {
-        forward_iteration(a, L, t, work, work, col);
+        forward_iteration<VAR>(a, L, t, work, work, col);
         if (t % a.K == 0 && t < a.T) {
             copy_column(L, L.state(a.ckpt, t / a.K, a.waves), work, L.SI);
             __syncthreads();              // the next check pass rewrites work in place
@@ -260,14 +310,17 @@ __global__ void __launch_bounds__(kUnrBlock) unrolled_forward_kernel(UnrArgs a)
 
 // Reverse sweep of iteration t.  cur: state t, prev: state t-1.  On entry the
 // adjoint holds dL/dm_{v->c}^{(t)} (gm) and dL/dQ^{(t)} (gQ, only the loss term
-// at t = T); on exit dL/dm_{v->c}^{(t-1)} and dL/dQ^{(t-1)}.  Every message and
-// posterior adjoint belongs to one qubit and one check, so the qubit side and the
-// check side need only the workgroup barrier between them and the one at the end.
-// Called by every thread of the workgroup; returns the workgroup's dL/dalpha_t in
-// thread 0.
-__device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, const float *cur, const float *prev,
-                                    float *adj, int shot, double *sh)
+// at t = T), for Momentum also dL/dg^{(t)} through iteration t+1 (gG); on exit
+// those of iteration t-1.  Every message and posterior adjoint belongs to one
+// qubit and one check, so the qubit side and the check side need only the
+// workgroup barrier between them and the one at the end.  Called by every thread
+// of the workgroup; tot gets the workgroup's dL/dalpha_t (and Momentum's
+// dL/dgamma_t) in thread 0.
+template <int VAR>
+__device__ void reverse_iteration(const UnrArgs &a, const Lane &L, int t, const float *cur, const float *prev,
+                                  float *adj, int shot, double *sh, double tot[2])
 {
+    constexpr bool kMom = UnrLayout<VAR>::kMom;
     konst<uint32_t> *cedge = as_const(a.g.cedge);
     konst<uint32_t> *vinfo = as_const(a.g.vinfo);
     konst<float> *prior = as_const(a.prior);
@@ -276,8 +329,10 @@ __device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, cons
     float *gm = adj;
     float *gQ = adj + (size_t)E * 64;
     float *gP = adj + (size_t)(E + 3 * n) * 64;
-    const float al = a.alpha[t - 1];
-    float galpha = 0.0f;
+    float *gG = adj + (size_t)(E + 6 * n) * 64;   // Momentum
+    const float al = a.param[UnrLayout<VAR>::kParams * (t - 1)];
+    const float ga = kMom ? a.param[2 * (t - 1) + 1] : 0.0f;
+    float galpha = 0.0f, ggamma = 0.0f;
     // ---- qubit side: vertical update (t < T), then posterior and EWA prior ------
     if (L.have) {
         for (int v = L.part; v < n; v += kUnrWaves) {
@@ -303,28 +358,62 @@ __device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, cons
                     gcv[j] = -gj;
                 }
             }
-            // Q = Pi^{(t)} + M: each m_{c->v} enters the two components that anticommute with H
-            for (uint32_t j = 0; j < deg; ++j) {
-                int h, ia, ib;
-                label_indices(var_lab(info, j), h, ia, ib);
-                gm[(size_t)(base + j) * 64] = gcv[j] + g[ia] + g[ib];
-            }
-            // Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}  (t > 1), Pi^{(1)} = Pi^{(0)}
-            for (int x = 0; x < 3; ++x) {
-                const size_t i = (size_t)(3 * v + x) * 64;
-                if (t == 1) {
-                    gP[i] += g[x];
-                    gQ[i] = 0.0f;
-                } else {
-                    const float p0 = prior[3 * v + x];
-                    galpha = fmaf(g[x], p0 - prev[(size_t)(E + 3 * v + x) * 64], galpha);
-                    gP[i] = fmaf(al, g[x], gP[i]);
-                    gQ[i] = (1.0f - al) * g[x];
+            if constexpr (!kMom) {
+                // Q = Pi^{(t)} + M: each m_{c->v} enters the two components that anticommute with H
+                for (uint32_t j = 0; j < deg; ++j) {
+                    int h, ia, ib;
+                    label_indices(var_lab(info, j), h, ia, ib);
+                    gm[(size_t)(base + j) * 64] = gcv[j] + g[ia] + g[ib];
+                }
+                // Pi^{(t)} = alpha_t Pi^{(0)} + (1 - alpha_t) Q^{(t-1)}  (t > 1), Pi^{(1)} = Pi^{(0)}
+                for (int x = 0; x < 3; ++x) {
+                    const size_t i = (size_t)(3 * v + x) * 64;
+                    if (t == 1) {
+                        gP[i] += g[x];
+                        gQ[i] = 0.0f;
+                    } else {
+                        const float p0 = prior[3 * v + x];
+                        galpha = fmaf(g[x], p0 - prev[(size_t)(E + 3 * v + x) * 64], galpha);
+                        gP[i] = fmaf(al, g[x], gP[i]);
+                        gQ[i] = (1.0f - al) * g[x];
+                    }
+                }
+            } else {
+                // Q^{(t)} = Q^{(t-1)} - alpha_t g^{(t)},
+                // g^{(t)} = gamma_t g^{(t-1)} + (1 - gamma_t) d, d = Q^{(t-1)} - Pi^{(0)} - M^{(t)}
+                float gM[3];
+                for (int x = 0; x < 3; ++x) {
+                    const size_t i = (size_t)(3 * v + x) * 64;
+                    const float gt = cur[(size_t)(E + 3 * n + 3 * v + x) * 64];
+                    const float gprev = prev[(size_t)(E + 3 * n + 3 * v + x) * 64];
+                    const float d = (prev[(size_t)(E + 3 * v + x) * 64] - prior[3 * v + x]) -
+                                    cur[(size_t)(E + 6 * n + 3 * v + x) * 64];
+                    const float ggt = fmaf(-al, g[x], gG[i]);   // dL/dg^{(t)}, all paths
+                    galpha = fmaf(-gt, g[x], galpha);
+                    ggamma = fmaf(gprev - d, ggt, ggamma);
+                    const float gd = (1.0f - ga) * ggt;
+                    gM[x] = -gd;
+                    gG[i] = ga * ggt;                          // dL/dg^{(t-1)}
+                    const float gq = g[x] + gd;                // dL/dQ^{(t-1)}
+                    gP[i] -= gd;
+                    if (t == 1) {                              // Q^{(0)} = Pi^{(0)}
+                        gP[i] += gq;
+                        gQ[i] = 0.0f;
+                    } else {
+                        gQ[i] = gq;
+                    }
+                }
+                // each m_{c->v} enters the two components of M that anticommute with H
+                for (uint32_t j = 0; j < deg; ++j) {
+                    int h, ia, ib;
+                    label_indices(var_lab(info, j), h, ia, ib);
+                    gm[(size_t)(base + j) * 64] = gcv[j] + gM[ia] + gM[ib];
                 }
             }
         }
     }
-    const double galpha_sum = block_sum((double)galpha, sh);   // also the barrier between the sides
+    tot[0] = block_sum((double)galpha, sh);   // also the barrier between the sides
+    if constexpr (kMom) tot[1] = block_sum((double)ggamma, sh);
     // ---- check side: m_{c->v} = clamp(sign * phi(sum_{v' != v} phi(|m_{v'->c}|))) ----
     const uint8_t *s = a.synd + (size_t)shot * m;
     if (L.have) {
@@ -370,28 +459,30 @@ __device__ double reverse_iteration(const UnrArgs &a, const Lane &L, int t, cons
         }
     }
     __syncthreads();
-    return galpha_sum;
 }
 
 // Adjoint, part 1 for segment sg: recompute the segment's states from its
 // checkpoint; for the last segment first clear the adjoint record and seed it
 // with dL/dQ^{(T)} of the soft loss (unscaled: the mean's 1/(shots n) comes last).
+template <int VAR>
 __global__ void __launch_bounds__(kUnrBlock) unrolled_recompute_kernel(UnrArgs a, int sg)
 {
-    const Lane L = lane_of(a);
+    constexpr int kAdj = UnrLayout<VAR>::kAdj;
+    const Lane L = lane_of<VAR>(a);
     if ((int)L.wave >= a.waves) return;   // the whole workgroup: no such chunk
     const int col = (int)L.wave * 64 + L.lane;
     const int n = a.g.n, E = a.g.nnz;
     const int t0 = sg * a.K;
     const int t1 = t0 + a.K < a.T ? t0 + a.K : a.T;
-    float *adj = a.adj + L.wave * ((size_t)E + 6 * (size_t)n) * 64 + L.lane;
+    float *adj = a.adj + L.wave * ((size_t)E + kAdj * (size_t)n) * 64 + L.lane;
     copy_column(L, L.state(a.seg, 0, a.waves), L.state(a.ckpt, sg, a.waves), L.SI);
     __syncthreads();
     for (int t = t0 + 1; t <= t1; ++t)
-        forward_iteration(a, L, t, L.state(a.seg, t - 1 - t0, a.waves), L.state(a.seg, t - t0, a.waves), col);
+        forward_iteration<VAR>(a, L, t, L.state(a.seg, t - 1 - t0, a.waves), L.state(a.seg, t - t0, a.waves),
+                               col);
     if (t1 != a.T) return;
     if (L.have)
-        for (size_t i = L.part; i < (size_t)E + 6 * (size_t)n; i += kUnrWaves) adj[i * 64] = 0.0f;
+        for (size_t i = L.part; i < (size_t)E + kAdj * (size_t)n; i += kUnrWaves) adj[i * 64] = 0.0f;
     __syncthreads();                      // other wavefronts cleared some of the items written below
     if (!L.have) return;
     const float *sT = L.state(a.seg, t1 - t0, a.waves);
@@ -409,22 +500,32 @@ __global__ void __launch_bounds__(kUnrBlock) unrolled_recompute_kernel(UnrArgs a
 // 64 VGPRs (8 wavefronts per SIMD): the few values that spill cost less than the
 // latency hidden by the extra wavefronts (96 VGPRs without spills: 5 per SIMD,
 // 17% slower).
+template <int VAR>
 __global__ void __launch_bounds__(kUnrBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 unrolled_reverse_kernel(UnrArgs a, int sg)
 {
+    constexpr int kAdj = UnrLayout<VAR>::kAdj, kP = UnrLayout<VAR>::kParams;
     __shared__ double sh[kUnrWaves];
-    const Lane L = lane_of(a);
+    const Lane L = lane_of<VAR>(a);
     if ((int)L.wave >= a.waves) return;   // the whole workgroup: no such chunk
     const int col = (int)L.wave * 64 + L.lane;
     const int n = a.g.n, E = a.g.nnz;
     const int t0 = sg * a.K;
     const int t1 = t0 + a.K < a.T ? t0 + a.K : a.T;
-    float *adj = a.adj + L.wave * ((size_t)E + 6 * (size_t)n) * 64 + L.lane;
+    float *adj = a.adj + L.wave * ((size_t)E + kAdj * (size_t)n) * 64 + L.lane;
     double *part = a.partial + L.wave * a.nout;
     for (int t = t1; t > t0; --t) {
-        const double tot = reverse_iteration(a, L, t, L.state(a.seg, t - t0, a.waves),
-                                             L.state(a.seg, t - 1 - t0, a.waves), adj, col, sh);
-        if (threadIdx.x == 0) part[t - 1] = t == 1 ? 0.0 : tot;
+        double tot[2] = {0.0, 0.0};
+        reverse_iteration<VAR>(a, L, t, L.state(a.seg, t - t0, a.waves), L.state(a.seg, t - 1 - t0, a.waves), adj,
+                               col, sh, tot);
+        if (threadIdx.x == 0) {
+            if constexpr (kP == 2) {
+                part[2 * (t - 1)] = tot[0];
+                part[2 * (t - 1) + 1] = tot[1];
+            } else {
+                part[t - 1] = t == 1 ? 0.0 : tot[0];   // alpha_1 is unused
+            }
+        }
     }
     if (sg != 0) return;
     // ---- initialisation: m^{(0)}_{v->c} = clamp(lambda_H(Pi^{(0)})) ----------------
@@ -455,7 +556,7 @@ unrolled_reverse_kernel(UnrArgs a, int sg)
         }
         for (int x = 0; x < 3; ++x) {
             const double tot = wave_sum((double)g[x]);
-            if (L.lane == 0) part[a.T + 3 * v + x] = tot;
+            if (L.lane == 0) part[kP * a.T + 3 * v + x] = tot;
         }
     }
 }
@@ -477,27 +578,28 @@ __global__ void __launch_bounds__(256) unrolled_reduce_kernel(const double *part
 
 static size_t up256u(size_t x) { return (x + 255) & ~size_t(255); }
 
-UnrolledSizes unrolled_sizes(int m, int n, int nnz, int32_t T, int32_t K, int64_t shots)
+UnrolledSizes unrolled_sizes(int m, int n, int nnz, int variant, int32_t T, int32_t K, int64_t shots)
 {
     (void)m;
     UnrolledSizes z;
     const size_t lanes = (size_t)((shots + kUnrRound - 1) / kUnrRound) * kUnrRound;
     const size_t waves = lanes / 64;
-    const size_t SI = (size_t)nnz + 3 * (size_t)n;
+    const size_t SI = (size_t)nnz + unr_state_words(variant) * (size_t)n;
     const size_t nseg = (size_t)((T + K - 1) / K);
     z.saved = up256u(nseg * waves * SI * 64 * 4);
-    z.ws = up256u((size_t)(K + 1) * waves * SI * 64 * 4) + up256u(waves * ((size_t)nnz + 6 * (size_t)n) * 64 * 4) +
-           up256u(waves * (size_t)(T + 3 * n) * 8);
+    z.ws = up256u((size_t)(K + 1) * waves * SI * 64 * 4) +
+           up256u(waves * ((size_t)nnz + unr_adj_words(variant) * (size_t)n) * 64 * 4) +
+           up256u(waves * (size_t)(unr_params(variant) * T + 3 * n) * 8);
     return z;
 }
 
-static UnrArgs unrolled_args(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots, const float *alpha,
-                             const float *prior, const uint8_t *synd, const uint8_t *err, void *saved, void *ws,
-                             int nout)
+static UnrArgs unrolled_args(const GraphView &g, int variant, int32_t T, int32_t K, float clamp, int32_t shots,
+                             const float *param, const float *prior, const uint8_t *synd, const uint8_t *err,
+                             void *saved, void *ws, int nout)
 {
     UnrArgs a;
     a.g = g;
-    a.alpha = alpha;
+    a.param = param;
     a.prior = prior;
     a.synd = synd;
     a.err = err;
@@ -510,26 +612,29 @@ static UnrArgs unrolled_args(const GraphView &g, int32_t T, int32_t K, float cla
     a.q_out = nullptr;
     const size_t lanes = (size_t)((shots + kUnrRound - 1) / kUnrRound) * kUnrRound;
     const size_t waves_alloc = lanes / 64;
-    const size_t SI = (size_t)g.nnz + 3 * (size_t)g.n;
+    const size_t SI = (size_t)g.nnz + unr_state_words(variant) * (size_t)g.n;
     a.ckpt = static_cast<float *>(saved);
     char *w = static_cast<char *>(ws);
     a.seg = reinterpret_cast<float *>(w);
     w += up256u((size_t)(K + 1) * waves_alloc * SI * 64 * 4);
     a.adj = reinterpret_cast<float *>(w);
-    w += up256u(waves_alloc * ((size_t)g.nnz + 6 * (size_t)g.n) * 64 * 4);
+    w += up256u(waves_alloc * ((size_t)g.nnz + unr_adj_words(variant) * (size_t)g.n) * 64 * 4);
     a.partial = reinterpret_cast<double *>(w);
     // every allocated chunk runs (those past the last shot contribute zeros)
     a.waves = (int)waves_alloc;
     return a;
 }
 
-hipError_t launch_unrolled_forward(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots,
-                                   const float *alpha, const float *prior, const uint8_t *synd, const uint8_t *err,
+hipError_t launch_unrolled_forward(const GraphView &g, int variant, int32_t T, int32_t K, float clamp, int32_t shots,
+                                   const float *param, const float *prior, const uint8_t *synd, const uint8_t *err,
                                    double *loss, float *q_out, void *saved, void *ws, hipStream_t s)
 {
-    UnrArgs a = unrolled_args(g, T, K, clamp, shots, alpha, prior, synd, err, saved, ws, 1);
+    UnrArgs a = unrolled_args(g, variant, T, K, clamp, shots, param, prior, synd, err, saved, ws, 1);
     a.q_out = q_out;
-    hipLaunchKernelGGL(unrolled_forward_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a);
+    if (variant == BP4_MOMENTUM)
+        hipLaunchKernelGGL(unrolled_forward_kernel<BP4_MOMENTUM>, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(unrolled_forward_kernel<BP4_EWAINIT>, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = 1.0 / ((double)shots * (double)g.n);
@@ -538,22 +643,30 @@ hipError_t launch_unrolled_forward(const GraphView &g, int32_t T, int32_t K, flo
     return hipGetLastError();
 }
 
-hipError_t launch_unrolled_backward(const GraphView &g, int32_t T, int32_t K, float clamp, int32_t shots,
-                                    const float *alpha, const float *prior, const uint8_t *synd, const uint8_t *err,
-                                    const float *dloss, const void *saved, double *dalpha, double *dprior, void *ws,
+hipError_t launch_unrolled_backward(const GraphView &g, int variant, int32_t T, int32_t K, float clamp, int32_t shots,
+                                    const float *param, const float *prior, const uint8_t *synd, const uint8_t *err,
+                                    const float *dloss, const void *saved, double *dparam, double *dprior, void *ws,
                                     hipStream_t s)
 {
-    const int nout = T + 3 * g.n;
-    UnrArgs a = unrolled_args(g, T, K, clamp, shots, alpha, prior, synd, err, const_cast<void *>(saved), ws, nout);
+    const int np = unr_params(variant) * T;
+    const int nout = np + 3 * g.n;
+    UnrArgs a = unrolled_args(g, variant, T, K, clamp, shots, param, prior, synd, err, const_cast<void *>(saved), ws,
+                              nout);
+    const dim3 grid((unsigned)a.waves), block(kUnrBlock);
     for (int sg = a.nseg - 1; sg >= 0; --sg) {
-        hipLaunchKernelGGL(unrolled_recompute_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a, sg);
-        hipLaunchKernelGGL(unrolled_reverse_kernel, dim3((unsigned)a.waves), dim3(kUnrBlock), 0, s, a, sg);
+        if (variant == BP4_MOMENTUM) {
+            hipLaunchKernelGGL(unrolled_recompute_kernel<BP4_MOMENTUM>, grid, block, 0, s, a, sg);
+            hipLaunchKernelGGL(unrolled_reverse_kernel<BP4_MOMENTUM>, grid, block, 0, s, a, sg);
+        } else {
+            hipLaunchKernelGGL(unrolled_recompute_kernel<BP4_EWAINIT>, grid, block, 0, s, a, sg);
+            hipLaunchKernelGGL(unrolled_reverse_kernel<BP4_EWAINIT>, grid, block, 0, s, a, sg);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = 1.0 / ((double)shots * (double)g.n);
     hipLaunchKernelGGL(unrolled_reduce_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, a.partial, a.waves, nout,
-                       scale, dloss, dalpha, T, dprior);
+                       scale, dloss, dparam, np, dprior);
     return hipGetLastError();
 }
 

@@ -312,8 +312,18 @@ def test_unrolled_sizes_and_validation(lib):
     rc = lib.bp4_unrolled_backward(g.handle, fake, EW, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, null, fake,
                                    1 << 40, fake, fake, fake, 64, null)
     assert rc == -4
-    # the unrolled path is built for EWAInit only: other variants are refused before any launch
-    for variant in (0, 1, 2, 4):
+    # Momentum: a state holds Q, g and M (9 words per qubit after the messages); undersized
+    # buffers fail before any launch
+    assert lib.bp4_unrolled_sizes(g.handle, 1, 32, 8, 1 << 16, ctypes.byref(a), ctypes.byref(b)) == 0
+    assert a.value == 4 * (544 + 9 * 145) * 4 * (1 << 16)
+    rc = lib.bp4_unrolled_forward(g.handle, fake, 1, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, fake, null,
+                                  fake, 1024, fake, 1 << 40, null)
+    assert rc == -4
+    rc = lib.bp4_unrolled_backward(g.handle, fake, 1, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, null, fake,
+                                   1 << 40, fake, fake, fake, 64, null)
+    assert rc == -4
+    # the unrolled path is built for EWAInit and Momentum: the others are refused before any launch
+    for variant in (0, 2, 4):
         assert lib.bp4_unrolled_sizes(g.handle, variant, 32, 8, 1 << 16, ctypes.byref(a), ctypes.byref(b)) == -6
         rc = lib.bp4_unrolled_forward(g.handle, fake, variant, 32, 8, 30.0, 1 << 16, fake, fake, fake, fake, fake,
                                       null, fake, 1 << 40, fake, 1 << 40, null)
@@ -343,6 +353,12 @@ def test_unrolled_binding_validates_inputs(lib):
         kw = dict(ok, **b)
         with pytest.raises(BP4Error):
             unrolled_forward(g, kw["alpha"], kw["prior"], kw["synd"], kw["err"], T)
+    # Momentum takes (alpha_t, gamma_t) per iteration, [T, 2]; variants without an unrolled
+    # build are refused
+    for params, variant in ((torch.zeros(T), "momentum"), (torch.zeros(T, 3), "momentum"),
+                            (torch.zeros(T, 2), "ewainit"), (torch.zeros(T), "adagrad"), (torch.zeros(T), "bp")):
+        with pytest.raises(BP4Error):
+            unrolled_forward(g, params, ok["prior"], ok["synd"], ok["err"], T, variant=variant)
 
 
 def test_prior_llr_validation_without_gpu(lib):

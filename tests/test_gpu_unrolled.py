@@ -195,3 +195,93 @@ def test_config4_planar_d9_full_batch():
     assert excluded <= 0.1
     for rel_norm, rel_elem in (rak, rpk):
         assert rel_norm <= 1e-4 and rel_elem <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Momentum-BP unrolled: a step alpha_t and a decay gamma_t per iteration (section III-A1,
+# eqs. mombp1-3), params [T, 2]; the same bars as EWAInit
+# ---------------------------------------------------------------------------
+
+def momentum_params(seed, T):
+    rng = np.random.default_rng(seed + 1000)
+    return np.stack([rng.uniform(0.3, 1.0, T), rng.uniform(0.0, 0.8, T)], axis=1)
+
+
+def gpu_loss_grad_momentum(g, params, prior, syn, err, T, K, clamp=30.0, scale=1.0):
+    a = torch.tensor(params, dtype=torch.float32, device="cuda", requires_grad=True)
+    pr = torch.tensor(prior, dtype=torch.float32, device="cuda", requires_grad=True)
+    loss = P.unrolled_loss(g, a, pr, syn, err, T, K, clamp, variant="momentum")
+    (loss * scale).backward()
+    torch.cuda.synchronize()
+    return float(loss.detach()), np_(a.grad).astype(np.float64), np_(pr.grad).astype(np.float64)
+
+
+@pytest.mark.parametrize("name", ["planar5", "xzzx5-clifford"])
+def test_momentum_forward_posteriors_equal_decoder_bitwise(name):
+    if name == "planar5":
+        c = qecgen.planar(5)
+        hx, hz = c.hx, c.hz
+    else:
+        c = qecgen.xzzx(5)
+        hx, hz = clifford_relabel(c, 4)
+    T = 6
+    g, err, syn, _, prior = setup(hx, hz, c.lx, c.lz, 0.08, 3000, 23, T)
+    pr = torch.tensor(prior, dtype=torch.float32, device="cuda")
+    for alpha, gamma in ((0.6, 0.0), (0.8, 0.5)):
+        params = torch.tensor([[alpha, gamma]] * T, dtype=torch.float32, device="cuda")
+        _, q = P.unrolled_forward(g, params, pr, syn, err, T, 4, want_q=True, variant="momentum")
+        r = P.decode(g, P.Params(variant="momentum", alpha=alpha, gamma=gamma, max_iter=T, stop_on_syndrome=False),
+                     pr, syn, trace=True)
+        torch.cuda.synchronize()
+        assert torch.equal(q, r["q"]), (alpha, gamma)
+
+
+@pytest.mark.parametrize("code,T,K,shots", [("planar3", 8, 3, 512), ("planar5", 12, 5, 300),
+                                            ("xzzx3-clifford", 7, 2, 129)])
+def test_momentum_loss_and_gradient_vs_fp64_reference(code, T, K, shots):
+    if code == "planar3":
+        c = qecgen.planar(3)
+        hx, hz = c.hx, c.hz
+    elif code == "planar5":
+        c = qecgen.planar(5)
+        hx, hz = c.hx, c.hz
+    else:
+        c = qecgen.xzzx(3)
+        hx, hz = clifford_relabel(c, 6)
+    g, err, syn, _, prior = setup(hx, hz, c.lx, c.lz, 0.07, shots, 35, T)
+    params = momentum_params(35, T)
+    L32, ga32, gp32 = gpu_loss_grad_momentum(g, params, prior, syn, err, T, K)
+    L64, ga64, gp64, _ = U.loss_and_grad(hx, hz, params, prior, np_(syn), np_(err), T, 30.0, variant="momentum")
+    ra = compare(ga32, ga64)
+    rp = compare(gp32, gp64)
+    say("unrolled momentum", code, dict(loss32=L32, loss64=L64, params=ra, prior=rp))
+    assert ga32.shape == (T, 2)
+    assert abs(L32 - L64) <= 1e-5 * abs(L64)
+    for rel_norm, rel_elem in (ra, rp):
+        assert rel_norm <= 1e-4 and rel_elem <= 1e-4
+
+
+def test_momentum_checkpoint_interval_and_edge_sizes():
+    c = qecgen.planar(5)
+    T = 10
+    g, err, syn, _, prior = setup(c.hx, c.hz, c.lx, c.lz, 0.08, 777, 46, T)
+    params = momentum_params(46, T)
+    ref = None
+    for K in (1, 3, 8, 10, 64):
+        r = gpu_loss_grad_momentum(g, params, prior, syn, err, T, K)
+        if ref is None:
+            ref = r
+        else:
+            assert r[0] == ref[0] and np.array_equal(r[1], ref[1]) and np.array_equal(r[2], ref[2]), K
+    r = gpu_loss_grad_momentum(g, params, prior, syn, err, T, 4, scale=-2.5)
+    assert np.allclose(r[1], -2.5 * ref[1], rtol=1e-6, atol=0) and np.allclose(r[2], -2.5 * ref[2], rtol=1e-6, atol=0)
+    c = qecgen.planar(3)
+    for shots, T, K in ((1, 1, 1), (65, 3, 2), (64, 1, 5)):
+        g, err, syn, _, prior = setup(c.hx, c.hz, c.lx, c.lz, 0.1, shots, 9 + shots, T)
+        params = momentum_params(shots, T)
+        L32, ga32, gp32 = gpu_loss_grad_momentum(g, params, prior, syn, err, T, K)
+        L64, ga64, gp64, _ = U.loss_and_grad(c.hx, c.hz, params, prior, np_(syn), np_(err), T, 30.0,
+                                            variant="momentum")
+        say("momentum edge", shots, T, K, L32, L64)
+        assert abs(L32 - L64) <= 1e-5 * abs(L64)
+        assert compare(gp32, gp64)[0] <= 1e-4 and compare(ga32, ga64)[0] <= 1e-4
