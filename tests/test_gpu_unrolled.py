@@ -131,6 +131,14 @@ def test_checkpoint_interval_and_dloss():
     # the incoming gradient scales the result (before the cast to the parameters' FP32)
     r = gpu_loss_grad(g, alpha, prior, syn, err, T, 4, scale=-2.5)
     assert np.allclose(r[1], -2.5 * ref[1], rtol=1e-6, atol=0) and np.allclose(r[2], -2.5 * ref[2], rtol=1e-6, atol=0)
+    # the EWAInit-only autograd function is the same computation
+    a = torch.tensor(alpha, dtype=torch.float32, device="cuda", requires_grad=True)
+    pr = torch.tensor(prior, dtype=torch.float32, device="cuda", requires_grad=True)
+    loss = P.UnrolledEWAInit.apply(a, pr, g, syn, err, T, 4, 30.0)
+    loss.backward()
+    torch.cuda.synchronize()
+    assert float(loss.detach()) == ref[0] and np.array_equal(np_(a.grad).astype(np.float64), ref[1])
+    assert np.array_equal(np_(pr.grad).astype(np.float64), ref[2])
 
 
 def test_edge_sizes():
