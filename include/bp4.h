@@ -78,8 +78,12 @@ typedef enum {
  *          highest level of an earlier qubit sharing a check with it, so the
  *          qubits of a level are updated together with the sequential result;
  *          wave groups of group_lanes 1, 2, 4, ..., 64 lanes per shot
- *          (block_shots must be 0).  Large codes take the SOA kernel, one lane
- *          per shot.  Both give the same bits.  bp4_decode_mixed and
+ *          (block_shots must be 0).  Large codes take the single-pass HBM
+ *          kernel: one lane per shot, the same level sweep with each shot's
+ *          messages updated in place in HBM and a workgroup barrier per level
+ *          (also available for small codes with BP4_KERNEL_GATHER); the SOA
+ *          kernel runs it one lane per shot, qubit by qubit.  All give the same
+ *          bits.  bp4_decode_mixed and
  *          bp4_decode_plain answer EUNSUPPORTED. */
 typedef struct {
     int32_t variant;
@@ -143,8 +147,8 @@ int bp4_graph_edges(const bp4_graph *g, int32_t *check, int32_t *qubit);
 
 /* Device workspace bytes bp4_decode needs for `shots` shots with the automatic
  * kernel choice (a queue counter for the LDS kernel; the column records of the
- * single-pass HBM kernel, or the lane-resident message and state arrays of the
- * SOA kernel where that one applies: the serial schedule). */
+ * single-pass HBM kernel; the SOA kernel's lane-resident message and state
+ * arrays only with its tuning fields). */
 int bp4_workspace_bytes(const bp4_graph *g, const bp4_params *p, int64_t shots, size_t *bytes);
 
 /* Sample i.i.d. Pauli errors and their syndromes (section IV: each qubit is
@@ -227,10 +231,11 @@ typedef struct {
  * each qubit reads its checks' other messages (L2 serves the re-reads of the
  * neighbouring qubits) and writes its own; the syndrome test runs inside the
  * pass and a finished shot's lane takes the next shot at once (large codes;
- * flooding BP, Momentum, AdaGrad, EWAInit and AEWA, whose unsolved shot keeps
- * its lane for the next attempt; at most 4,079 checks, no verification
- * outputs).  AUTO: LDS unless even one shot per workgroup would
- * need more than 80 KB of LDS; then GATHER where it applies, else SOA. */
+ * every variant, AEWA's unsolved shot keeping its lane for the next attempt,
+ * and both schedules, the serial one as a level sweep with the messages
+ * updated in place; at most 4,079 checks, no verification outputs).
+ * AUTO: LDS unless even one shot per workgroup would need more than 80 KB of
+ * LDS; then GATHER where it applies, else SOA. */
 enum { BP4_KERNEL_AUTO = 0, BP4_KERNEL_LDS = 1, BP4_KERNEL_SOA = 2, BP4_KERNEL_GATHER = 3 };
 
 /* Device workspace bytes of the SOA kernel for `shots` shots with soa_lanes

@@ -56,9 +56,10 @@ struct bp4_graph {
     std::vector<uint32_t> vlab;                  // [n] slot labels of wide graphs
     std::vector<uint32_t> lptr, lent;            // logicals
     std::vector<uint32_t> gord, gedge;           // walk of the single-pass HBM kernel (narrow graphs)
+    std::vector<uint32_t> sgedge;                // its gather words along the serial order sord
     // byte offsets of the sections in the device image
     size_t off_cedge = 0, off_vinfo = 0, off_vcanon = 0, off_vchk = 0, off_sord = 0, off_slev = 0, off_vlab = 0,
-           off_lptr = 0, off_lent = 0, off_gord = 0, off_gedge = 0, bytes = 0;
+           off_lptr = 0, off_lent = 0, off_gord = 0, off_gedge = 0, off_sgedge = 0, bytes = 0;
     bool wide() const { return cstride > kMaxCheckDeg; }
 
     void layout()
@@ -75,6 +76,7 @@ struct bp4_graph {
         off_lent = o; o = align256(o + (lent.empty() ? 1 : lent.size()) * 4);
         off_gord = o; o = align256(o + (gord.empty() ? 1 : gord.size()) * 4);
         off_gedge = o; o = align256(o + (gedge.empty() ? 1 : gedge.size()) * 4);
+        off_sgedge = o; o = align256(o + (sgedge.empty() ? 1 : sgedge.size()) * 4);
         bytes = o;
     }
 
@@ -106,6 +108,10 @@ struct bp4_graph {
         GatherTables t;
         t.gord = reinterpret_cast<const uint32_t *>(b + off_gord);
         t.gedge = reinterpret_cast<const uint32_t *>(b + off_gedge);
+        t.sord = reinterpret_cast<const uint32_t *>(b + off_sord);
+        t.sgedge = reinterpret_cast<const uint32_t *>(b + off_sgedge);
+        t.slev = reinterpret_cast<const uint32_t *>(b + off_slev);
+        t.nlev = (int32_t)slev.size() - 1;
         return t;
     }
 };
@@ -427,8 +433,9 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
     // lower level, every later one on a higher level, so sweeping the levels in
     // order, each level's qubits in parallel, reads and writes exactly what the
     // qubit-by-qubit sweep does.  sord: qubits by (level, index); slev: offsets.
+    std::vector<int32_t> lev(n, 0);
     {
-        std::vector<int32_t> lev(n, 0), chk_top(m, -1);
+        std::vector<int32_t> chk_top(m, -1);
         int32_t nlev = 0;
         for (int v = 0; v < n; ++v) {
             int32_t l = 0;
@@ -498,6 +505,25 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
                 const uint32_t c = g->vchk[s];
                 const uint32_t pad = (0xFu << cdeg[c]) & 0xFu;
                 g->gedge[(size_t)4 * i + j] = (4u * c + (uint32_t)cpos_of_slot[s]) | (pad << 20);
+            }
+        }
+        // the same words along the serial order, with bit 24 + k set where the k-th other
+        // position of the check belongs to a qubit on a lower level (updated earlier in the
+        // same sweep)
+        g->sgedge.assign((size_t)4 * n, kGatherAbsent);
+        for (int i = 0; i < n; ++i) {
+            const int v = (int)g->sord[i];
+            for (int j = 0; j < vdeg[v]; ++j) {
+                const int32_t s = vptr[v] + j;
+                const uint32_t c = g->vchk[s], p = (uint32_t)cpos_of_slot[s];
+                const uint32_t pad = (0xFu << cdeg[c]) & 0xFu;
+                uint32_t w = (4u * c + p) | (pad << 20);
+                for (uint32_t k = 0; k < 3; ++k) {
+                    const uint32_t pk = k + (k >= p ? 1u : 0u);
+                    const uint32_t e = g->cedge[(size_t)c * g->cstride + pk];
+                    if (!edge_is_pad(e) && lev[edge_var(e)] < lev[v]) w |= 1u << (kGatherEarlierShift + k);
+                }
+                g->sgedge[(size_t)4 * i + j] = w;
             }
         }
     }
@@ -586,6 +612,7 @@ int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stre
     if (!g->lent.empty()) std::memcpy(img.data() + g->off_lent, g->lent.data(), g->lent.size() * 4);
     if (!g->gord.empty()) std::memcpy(img.data() + g->off_gord, g->gord.data(), g->gord.size() * 4);
     if (!g->gedge.empty()) std::memcpy(img.data() + g->off_gedge, g->gedge.data(), g->gedge.size() * 4);
+    if (!g->sgedge.empty()) std::memcpy(img.data() + g->off_sgedge, g->sgedge.data(), g->sgedge.size() * 4);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(dev_buf, img.data(), g->bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "graph_upload: hipMemcpyAsync");
@@ -700,8 +727,8 @@ bool gather_ok(const bp4_graph *g, int variant, int serial)
     return gather_supported(g->m, variant, serial, g->wide(), kGatherMaxLds);
 }
 
-// Large codes under AUTO: the single-pass HBM kernel where it applies (flooding, no
-// verification outputs), else the two-phase SOA kernel.
+// Large codes under AUTO: the single-pass HBM kernel where it applies (no verification
+// outputs), else the two-phase SOA kernel.
 int large_kernel(const bp4_graph *g, int variant, int serial, bool verify)
 {
     return !verify && gather_ok(g, variant, serial) ? BP4_KERNEL_GATHER : BP4_KERNEL_SOA;
@@ -860,8 +887,7 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         if (lds_knobs || soa_knobs)
             return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields do not apply to the single-pass HBM kernel");
         if (!gather_ok(g, p->variant, p->serial))
-            return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel runs the flooding schedule on codes of at "
-                                          "most %zu checks",
+            return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel runs narrow codes of at most %zu checks",
                         (kGatherMaxLds - 64 * 4) / 16 - 1);
         if (verify) return fail(BP4_EUNSUPPORTED, "decode: the single-pass HBM kernel writes no q_out, mvc_out or mcv_out");
         const size_t need = gather_workspace_bytes(g->m, g->n, p->variant, shots, gather_waves);

@@ -14,16 +14,24 @@ namespace bp4 {
 // bits 0-19 the edge's check-major message item 4c + p (p: the edge's position in
 // check c), bits 20-23 the padding positions of check c (bit k: position k holds no
 // edge), bit 31 set for slots j >= the qubit's degree (the rest of the word is then
-// 0x00F00000: check 0, all positions padding).
+// 0x00F00000: check 0, all positions padding).  Serial walk only: bits 24-26, bit
+// 24 + k set when the k-th other position of the check (k, or k + 1 past p) belongs
+// to a qubit of a lower level, i.e. one the sweep has already updated.
 constexpr uint32_t kGatherAbsent = 0x80F00000u;
+constexpr int kGatherEarlierShift = 24;
 __host__ __device__ inline uint32_t gather_item(uint32_t w) { return w & 0xFFFFFu; }
 __host__ __device__ inline uint32_t gather_pad(uint32_t w) { return (w >> 20) & 0xFu; }
 
-// Device tables of the walk: gord[i] the qubit at position i, gedge[4 i + j] its
-// gather words.
+// Device tables of the walks: gord[i] the qubit at position i of the flooding walk,
+// gedge[4 i + j] its gather words; the serial schedule's walk sord (qubits by level),
+// its gather words sgedge and its level offsets slev[0 .. nlev].
 struct GatherTables {
     const uint32_t *gord;
     const uint32_t *gedge;
+    const uint32_t *sord;
+    const uint32_t *sgedge;
+    const uint32_t *slev;
+    int32_t nlev;
 };
 
 // Wavefronts per workgroup: all of them walk the qubits of the same 64 shots.

@@ -57,12 +57,22 @@ __device__ __forceinline__ float stored_word(float m)
 {
     return __uint_as_float(__float_as_uint(phi(fabsf(m))) | (__float_as_uint(m) & kSign));
 }
+// The serial schedule's stored word, as the other serial kernels keep it: phi(|m|),
+// negated when m < 0 (a -0 message counts as positive).
+__device__ __forceinline__ float serial_word(float m)
+{
+    const float f = phi(fabsf(m));
+    return m < 0.0f ? -f : f;
+}
 
 struct GatherArgs {
     const uint32_t *cedge;    // [m][4] packed check edges (padding marked)
     const uint32_t *vinfo;    // [n] packed qubit words
-    const uint32_t *gord;     // [n] qubit at each walk position
+    const uint32_t *gord;     // [n] qubit at each walk position (serial schedule: its level order)
     const uint32_t *gedge;    // [n][4] gather words
+    const uint32_t *slev;     // serial schedule: [nlev + 1] level offsets into the walk
+    int32_t nlev;
+    int32_t serial;           // the records hold serial_word values
     const float *prior;       // [n][3]
     float *finit;             // [4m] stored words of the initial messages
     const uint8_t *synd;      // [shots][m]
@@ -98,7 +108,8 @@ __global__ void gather_init_kernel(GatherArgs a)
     const uint32_t deg = var_deg(info);
     for (uint32_t j = 0; j < deg; ++j) {
         const uint32_t w = a.gedge[4 * i + j];
-        a.finit[gather_item(w)] = stored_word(clampf(lam[var_lab(info, j)], a.clamp));
+        const float m0 = clampf(lam[var_lab(info, j)], a.clamp);
+        a.finit[gather_item(w)] = a.serial ? serial_word(m0) : stored_word(m0);
     }
 }
 
@@ -128,7 +139,13 @@ struct Records {
     }
 };
 
-template <int VAR>
+// SER: the serial schedule (Algorithm 1) instead of flooding.  The walk is then the
+// level order of the qubit-by-qubit sweep (a level's qubits share no check); a column
+// keeps one record, updated in place, and each level ends with a workgroup barrier, so a
+// qubit reads the stored words its check's earlier qubits wrote in this sweep and the
+// previous sweep's words of the later ones, exactly as the sweep in index order.  In a
+// shot's first sweep the words not yet rewritten come from the initial table.
+template <int VAR, bool SER>
 __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_gather_kernel(GatherArgs a)
 {
     extern __shared__ uint64_t lds[];
@@ -231,8 +248,8 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
 
         // ---- one flooding iteration over the walk ------------------------------------
         const bool fresh = t == 1;
-        const uint32_t rd = lane_off + (pass & 1u) * a.rec_bytes;
-        const uint32_t wr = lane_off + ((pass + 1u) & 1u) * a.rec_bytes;
+        const uint32_t rd = lane_off + (SER ? 0u : (pass & 1u) * a.rec_bytes);
+        const uint32_t wr = lane_off + (SER ? 0u : ((pass + 1u) & 1u) * a.rec_bytes);
         ++pass;
         uint64_t nan_cols = 0;
         // Reads of a qubit: its walk entry (scalar), the other stored words of each of
@@ -278,11 +295,25 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const uint32_t pk = (uint32_t)k + (((p - (uint32_t)k - 1u) >> 31) & 1u);
-                    x[k] = fresh ? finit[c4 + pk] : q.x[j][k];
+                    // serial: a word an earlier qubit of this sweep rewrote is read from the record
+                    const bool init = fresh && (!SER || ((q.ew[j] >> (kGatherEarlierShift + k)) & 1u) == 0u);
+                    x[k] = init ? finit[c4 + pk] : q.x[j][k];
                 }
                 const uint32_t sgn =
                     ((__float_as_uint(x[0]) ^ __float_as_uint(x[1]) ^ __float_as_uint(x[2])) & kSign) ^ (sb << 31);
-                const float mag = phi(sum3_canonical(fabsf(x[0]), fabsf(x[1]), fabsf(x[2])));
+                float mag;
+                if constexpr (SER) {
+                    // the serial kernels' sum over the check's four positions in order, this
+                    // qubit's own position (p) contributing 0: the k-th other word sits at
+                    // position k below p and k + 1 above it
+                    const float f0 = p == 0u ? 0.0f : fabsf(x[0]);
+                    const float f1 = p == 1u ? 0.0f : fabsf(x[p < 1u ? 0 : 1]);
+                    const float f2 = p == 2u ? 0.0f : fabsf(x[p < 2u ? 1 : 2]);
+                    const float f3 = p == 3u ? 0.0f : fabsf(x[2]);
+                    mag = phi((f0 + f1) + (f2 + f3));
+                } else {
+                    mag = phi(sum3_canonical(fabsf(x[0]), fabsf(x[1]), fabsf(x[2])));
+                }
                 mc[j] = (uint32_t)j < deg ? clampf(__uint_as_float(__float_as_uint(mag) ^ sgn), C) : 0.0f;
             }
             float S4[4], A4[4], qn[3];
@@ -317,22 +348,35 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
                               (unsigned long long)flip);
                 // new message (eq. v_update) and its stored word
                 const float out = clampf(lam[lab] - mc[j], C);
-                R.st(gather_item(q.ew[j]), wr, stored_word(out));
+                R.st(gather_item(q.ew[j]), wr, SER ? serial_word(out) : stored_word(out));
             }
         };
         // The walk.  Step s takes positions s W .. s W + W - 1, one per wavefront; every
         // kPaceSteps steps the wavefronts meet at a barrier, so they stay within a
         // few steps of each other and the re-reads of a check by its other qubits
         // still find it in L2.
-        const int steps = (n + W - 1) / W;
         QubitIn qa;
-        for (int st = 0; st < steps; ++st) {
-            const int i0 = st * W + wv;
-            if (i0 < n) {
-                load_qubit(i0, qa);
-                update_qubit(i0, qa);
+        if constexpr (SER) {
+            // level by level, a workgroup barrier (with its memory fences) after each
+            konst<uint32_t> *slev = as_const(a.slev);
+            for (int l = 0; l < a.nlev; ++l) {
+                const int p1 = (int)slev[l + 1];
+                for (int i = (int)slev[l] + wv; i < p1; i += W) {
+                    load_qubit(i, qa);
+                    update_qubit(i, qa);
+                }
+                __syncthreads();
             }
-            if (kPaceSteps > 0 && (st + 1) % kPaceSteps == 0) __builtin_amdgcn_s_barrier();
+        } else {
+            const int steps = (n + W - 1) / W;
+            for (int st = 0; st < steps; ++st) {
+                const int i0 = st * W + wv;
+                if (i0 < n) {
+                    load_qubit(i0, qa);
+                    update_qubit(i0, qa);
+                }
+                if (kPaceSteps > 0 && (st + 1) % kPaceSteps == 0) __builtin_amdgcn_s_barrier();
+            }
         }
         __syncthreads();
 
@@ -399,7 +443,9 @@ size_t gather_lds_bytes(int m) { return (size_t)(2 * m + 2) * 8 + 64 * 4; }
 
 bool gather_supported(int m, int variant, int serial, bool wide, size_t max_lds)
 {
-    return !serial && !wide && gather_lds_bytes(m) <= max_lds;
+    (void)variant;
+    (void)serial;
+    return !wide && gather_lds_bytes(m) <= max_lds;
 }
 
 int32_t gather_groups(int64_t shots, int32_t waves)
@@ -425,10 +471,14 @@ hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, cons
                                 int32_t *iters, void *ws, int32_t waves, int with_y, hipStream_t s)
 {
     GatherArgs a;
+    const bool ser = p.serial != 0;
     a.cedge = g.cedge;
     a.vinfo = g.vinfo;
-    a.gord = gt.gord;
-    a.gedge = gt.gedge;
+    a.gord = ser ? gt.sord : gt.gord;
+    a.gedge = ser ? gt.sgedge : gt.gedge;
+    a.slev = gt.slev;
+    a.nlev = gt.nlev;
+    a.serial = ser ? 1 : 0;
     a.prior = prior;
     char *w = static_cast<char *>(ws);
     a.head = reinterpret_cast<unsigned int *>(w);
@@ -466,13 +516,19 @@ hipError_t launch_decode_gather(const GraphView &g, const GatherTables &gt, cons
     const int32_t W = waves_of(waves);
     const dim3 grid((unsigned)gather_groups(shots, waves)), block((unsigned)(64 * W));
     const size_t lds = gather_lds_bytes(g.m);
+#define BP4_GATHER_LAUNCH(V)                                                                    \
+    do {                                                                                        \
+        if (ser) hipLaunchKernelGGL(HIP_KERNEL_NAME(decode_gather_kernel<V, true>), grid, block, lds, s, a);  \
+        else hipLaunchKernelGGL(HIP_KERNEL_NAME(decode_gather_kernel<V, false>), grid, block, lds, s, a);     \
+    } while (0)
     switch (p.variant) {
-    case BP4_BP: hipLaunchKernelGGL(decode_gather_kernel<BP4_BP>, grid, block, lds, s, a); break;
-    case BP4_MOMENTUM: hipLaunchKernelGGL(decode_gather_kernel<BP4_MOMENTUM>, grid, block, lds, s, a); break;
-    case BP4_ADAGRAD: hipLaunchKernelGGL(decode_gather_kernel<BP4_ADAGRAD>, grid, block, lds, s, a); break;
-    case BP4_AEWA: hipLaunchKernelGGL(decode_gather_kernel<BP4_AEWA>, grid, block, lds, s, a); break;
-    default: hipLaunchKernelGGL(decode_gather_kernel<BP4_EWAINIT>, grid, block, lds, s, a); break;
+    case BP4_BP: BP4_GATHER_LAUNCH(BP4_BP); break;
+    case BP4_MOMENTUM: BP4_GATHER_LAUNCH(BP4_MOMENTUM); break;
+    case BP4_ADAGRAD: BP4_GATHER_LAUNCH(BP4_ADAGRAD); break;
+    case BP4_AEWA: BP4_GATHER_LAUNCH(BP4_AEWA); break;
+    default: BP4_GATHER_LAUNCH(BP4_EWAINIT); break;
     }
+#undef BP4_GATHER_LAUNCH
     return hipGetLastError();
 }
 

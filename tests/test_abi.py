@@ -201,11 +201,10 @@ def test_large_codes_take_the_hbm_kernels(lib):
         assert g.workspace_bytes(prm, shots) == want
         assert g.gather_workspace_bytes(prm, 100) == head + 2 * 2 * items * 256
         assert g.gather_workspace_bytes(prm, shots, 8) == head + 1024 * 2 * items * 256
-    # the serial schedule keeps the SOA kernel; AEWA (EWAInit's records) takes the single-pass one
+    # the serial schedule and AEWA (EWAInit's records) take the single-pass kernel too
     ser = Params(variant="ewainit", alpha=0.5, serial=True)
     b = ctypes.c_size_t()
-    assert lib.bp4_soa_workspace_bytes(g.handle, ctypes.byref(ser.c()), shots, 0, ctypes.byref(b)) == 0
-    assert g.workspace_bytes(ser, shots) == b.value
+    assert g.workspace_bytes(ser, shots) == g.gather_workspace_bytes(ser, shots) == head + 512 * 2 * (4 * m + 3 * n) * 256
     ae = Params(variant="aewa", alpha=0.5, alpha_last=0.9, alpha_steps=3)
     assert g.workspace_bytes(ae, shots) == g.gather_workspace_bytes(ae, shots) == head + 512 * 2 * (4 * m + 3 * n) * 256
     prm = Params(variant="bp")
@@ -233,7 +232,7 @@ def test_large_codes_take_the_hbm_kernels(lib):
 
 def test_gather_kernel_validation_without_gpu(lib):
     """The single-pass HBM kernel's argument checks run before any launch: no verification
-    outputs, no serial schedule, gather_waves in {0, 4, 8, 16}, its own workspace
+    outputs, gather_waves in {0, 4, 8, 16}, its own workspace
     size, and its tuning field excludes the LDS and SOA ones."""
     from paper_2407_11523_amd import Graph, Params, _lib
     c = qecgen.toric(32)
@@ -256,8 +255,9 @@ def test_gather_kernel_validation_without_gpu(lib):
     assert dec(_lib.Tuning(0, 0, 0, 1024, 0, 0, 8)) == -1               # SOA and gather fields together
     assert dec(_lib.Tuning(64, 0, 3)) == -1                             # LDS field with the gather kernel
     assert dec(_lib.Tuning(0, 0, 3, 0, 0, 0, 0, 1)) == -1               # reserved
-    ser = Params(variant="ewainit", alpha=0.6, serial=True).c()
-    assert dec(_lib.Tuning(0, 0, 3), params=ser) == -6                  # serial schedule
+    ser = Params(variant="ewainit", alpha=0.6, serial=True)
+    need_ser = g.gather_workspace_bytes(ser, 1000)
+    assert dec(_lib.Tuning(0, 0, 3), params=ser.c(), ws_bytes=need_ser - 1) == -4   # serial runs: its workspace
     ae = Params(variant="aewa", alpha=0.5, alpha_last=0.9, alpha_steps=3)
     need_ae = g.gather_workspace_bytes(ae, 1000)
     assert dec(_lib.Tuning(0, 0, 3), params=ae.c(), ws_bytes=need_ae - 1) == -4   # AEWA runs: its workspace

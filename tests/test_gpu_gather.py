@@ -39,9 +39,11 @@ def run(g, prm, pr, syn, kernel, **kw):
     return r
 
 
-def same(a, b, what):
+def same(a, b, what, n=None):
+    """Outputs equal bit for bit (on the first n shots of a, if given)."""
     for k in ("est", "conv", "iters"):
-        assert torch.equal(a[k], b[k]), (what, k, int((a[k] != b[k]).sum()))
+        x = a[k] if n is None else a[k][:n]
+        assert torch.equal(x, b[k]), (what, k, int((x != b[k]).sum()))
 
 
 @pytest.mark.parametrize("fam,size", CODES)
@@ -129,9 +131,9 @@ def test_gather_ignores_stale_workspace():
 
 
 def test_auto_runs_gather_on_large_codes():
-    """The automatic choice for a large flooding decode is the single-pass kernel (the
-    workspace it sizes is the single-pass one), AEWA included; trace and serial keep the
-    SOA kernel; the single-pass kernel refuses the verification outputs."""
+    """The automatic choice for a large decode is the single-pass kernel (the workspace it
+    sizes is the single-pass one), AEWA and the serial schedule included; the verification
+    outputs keep the SOA kernel, and the single-pass kernel refuses them."""
     code = qecgen.planar(31)
     g = P.Graph(code.hx, code.hz, code.lx, code.lz)
     p = 0.1
@@ -144,8 +146,9 @@ def test_auto_runs_gather_on_large_codes():
     same(run(g, prm, pr, syn[:64], "soa"), tr, "trace")
     with pytest.raises(P.BP4Error):
         P.decode(g, prm, pr, syn[:64], kernel="gather", trace=True)
-    with pytest.raises(P.BP4Error):
-        P.decode(g, P.Params(variant="ewainit", alpha=0.6, serial=True), pr, syn[:64], kernel="gather")
+    ser = P.Params(variant="ewainit", alpha=0.6, max_iter=20, serial=True)
+    assert g.workspace_bytes(ser, 5000) == g.gather_workspace_bytes(ser, 5000)
+    same(run(g, ser, pr, syn[:600], "gather"), run(g, ser, pr, syn[:600], "auto"), "auto serial")
     ae = P.Params(variant="aewa", alpha=1.0, alpha_last=0.0, alpha_steps=11, max_iter=30)
     assert g.workspace_bytes(ae, 5000) == g.gather_workspace_bytes(ae, 5000)
     same(run(g, ae, pr, syn, "gather"), run(g, ae, pr, syn, "auto"), "auto aewa")
@@ -202,3 +205,34 @@ def test_gather_aewa_attempts():
             say("gather aewa", alpha, last, steps, mi, "waves", waves)
             same(ref, run(g, prm, pr, syn, "gather", gather_waves=waves), (alpha, last, steps, waves))
         same(ref, run(g, prm, pr, syn, "soa"), (alpha, last, steps, "soa"))
+
+
+@pytest.mark.parametrize("variant,alpha,gamma", VARIANTS)
+def test_gather_serial_schedule(variant, alpha, gamma):
+    """The serial schedule (Algorithm 1) on the single-pass kernel: the level sweep with each
+    column's record updated in place, a workgroup barrier after each level and, in a shot's
+    first sweep, the words not yet rewritten taken from the initial table gives the
+    qubit-by-qubit sweep bit for bit: equal to the LDS kernel's level sweep and the SOA
+    kernel's one-lane sweep, for every variant, with Y labels, on a large code, for every
+    workgroup shape and with lanes that take new shots while others run."""
+    cases = [(qecgen.make("planar", 5), None), (qecgen.make("toric", 8), None), (qecgen.make("xzzx", 9), None),
+             (qecgen.toric(6), 5)]
+    for code, relabel in cases:
+        hx, hz = (code.hx, code.hz) if relabel is None else _clifford_relabel(code, relabel)
+        g = P.Graph(hx, hz)
+        p = 0.09
+        pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+        _, syn = P.sample(g, 3000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=code.n + 3)
+        prm = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=40, serial=True)
+        say("gather serial", code.name, relabel, variant)
+        ref = run(g, prm, pr, syn, "lds")
+        same(ref, run(g, prm, pr, syn, "gather"), (code.name, variant))
+        same(ref, run(g, prm, pr, syn, "gather", gather_waves=4), (code.name, variant, 4))
+        same(ref, run(g, prm, pr, syn[:700], "soa"), (code.name, variant, "soa"), n=700)
+    code = qecgen.planar(31)
+    g = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, 0.06))
+    _, syn = P.sample(g, 1500, qecgen.thresholds(0.02, 0.02, 0.02), seed=61)
+    prm = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=25, serial=True)
+    say("gather serial planar 31", variant)
+    same(run(g, prm, pr, syn, "soa"), run(g, prm, pr, syn, "gather"), ("planar31", variant))
