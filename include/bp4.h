@@ -126,6 +126,17 @@ int bp4_graph_create(const uint8_t *hx, const uint8_t *hz, int32_t m, int32_t n,
  * success (section IV).  Errors: EINVAL. */
 int bp4_graph_set_logicals(bp4_graph *g, const uint8_t *lx, const uint8_t *lz, int32_t nlog);
 
+/* Optional locality hint of a narrow graph: xy, host int32 [n][2], a position
+ * of each qubit on a 2-D layout of the code (any integer units, e.g. lattice
+ * coordinates).  Only the order in which the single-pass HBM kernel walks the
+ * qubits depends on it: strips of the layout walked row by row join the
+ * candidate orders, and the one with the fewest misses in a model of the
+ * kernel's L2 reuse is kept, which decides how many of its message re-reads L2
+ * serves.  Decoding results never depend on it.  The input is copied; call
+ * bp4_graph_upload afterwards (an uploaded image keeps the previous order).
+ * Errors: EINVAL (NULL), EUNSUPPORTED (wide graph: no single-pass kernel). */
+int bp4_graph_set_coords(bp4_graph *g, const int32_t *xy);
+
 /* Sizes of the graph: qubits, checks, edges, maximum check and qubit degree. */
 int bp4_graph_info(const bp4_graph *g, int32_t *n, int32_t *m, int32_t *nnz,
                    int32_t *max_cdeg, int32_t *max_vdeg);
@@ -135,7 +146,8 @@ int bp4_graph_device_bytes(const bp4_graph *g, size_t *bytes);
 
 /* Copy the graph image (edge lists, labels, logicals) into dev_buf
  * (caller-owned, >= bp4_graph_device_bytes, 256-byte aligned).  Blocks until
- * the copy is done.  Call again after bp4_graph_set_logicals.
+ * the copy is done.  Call again after bp4_graph_set_logicals and
+ * bp4_graph_set_coords.
  * Errors: EINVAL, EWORKSPACE (buffer too small), EHIP. */
 int bp4_graph_upload(const bp4_graph *g, void *dev_buf, size_t bytes, void *stream);
 

@@ -55,6 +55,7 @@ SIGNATURES = {
     "bp4_graph_create": (ctypes.c_int, [_u8p, _u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                         ctypes.POINTER(_vp)]),
     "bp4_graph_set_logicals": (ctypes.c_int, [_vp, _u8p, _u8p, ctypes.c_int32]),
+    "bp4_graph_set_coords": (ctypes.c_int, [_vp, _i32p]),
     "bp4_graph_info": (ctypes.c_int, [_vp, _i32p, _i32p, _i32p, _i32p, _i32p]),
     "bp4_graph_device_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(_sz)]),
     "bp4_graph_upload": (ctypes.c_int, [_vp, _vp, _sz, _vp]),

@@ -57,7 +57,7 @@ class Graph:
     """A code's Tanner graph: host object plus its uploaded device image."""
 
     def __init__(self, hx, hz, lx=None, lz=None, *, allow_anticommuting: bool = False,
-                 device: Optional[torch.device] = None, upload: bool = True):
+                 device: Optional[torch.device] = None, upload: bool = True, coords=None):
         lib = load()
         hx, hz = _u8(hx), _u8(hz)
         if hx.ndim != 2 or hx.shape != hz.shape:
@@ -76,6 +76,8 @@ class Graph:
         if lx is not None:
             self.set_logicals(lx, lz)
         self.dev = None
+        if coords is not None:
+            self.set_coords(coords)
         if upload:
             self.upload(device)
 
@@ -85,6 +87,16 @@ class Graph:
                                                lz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                                int(lx.shape[0])))
         self.nlog = int(lx.shape[0])
+        if getattr(self, "dev", None) is not None:
+            self.upload(self.dev.device)
+
+    def set_coords(self, coords) -> None:
+        """Qubit positions [n][2] on a 2-D layout: a locality hint for the single-pass
+        HBM kernel's walk order (results do not depend on it)."""
+        xy = np.ascontiguousarray(np.asarray(coords), dtype=np.int32)
+        if xy.shape != (self.n, 2):
+            raise BP4Error(-1, f"coords must have shape ({self.n}, 2), got {xy.shape}")
+        check(self._lib.bp4_graph_set_coords(self._h, xy.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         if getattr(self, "dev", None) is not None:
             self.upload(self.dev.device)
 

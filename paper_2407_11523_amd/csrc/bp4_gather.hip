@@ -8,9 +8,10 @@
 // (and the momentum or AdaGrad accumulator) by walk position.
 //
 // An iteration walks the qubits in an order fixed on the host (bands of a few
-// breadth-first levels, each band walked breadth first along its length), the
-// workgroup's wavefronts taking positions round robin, so the qubits in flight at
-// any time sit close together on the lattice.  A qubit reads the other stored words of each of
+// breadth-first levels, each band walked breadth first along its length, or strips
+// of the layout when qubit positions are given), the workgroup's wavefronts taking
+// positions round robin, so the qubits in flight at any time sit close together on
+// the lattice.  A qubit reads the other stored words of each of
 // its checks from the previous record (eq. h_update in phi form: the sign is the
 // syndrome bit times the other signs, the magnitude phi of the sum of the other
 // phi values, summed in value order), forms its posterior (eqs. p_update, EWAInit,
@@ -27,9 +28,13 @@
 // check's parity word is compared with its syndrome word.  A column whose shot
 // meets the syndrome (or reaches iter_max) writes its decisions and takes the
 // next shot from the queue at once; its next iteration reads the initial messages
-// lambda(Pi) from a per-code table instead of its record.  Results do not depend
-// on the column a shot runs in, the walk order or the workgroup shape, and equal
-// those of the two-phase kernels bit for bit (same arithmetic in the same order).
+// lambda(Pi) from a per-code table instead of its record.  Once the queue is empty
+// and the live shots fit in columns 0-31, those of columns 32-63 move there (their
+// next pass reads the old column and writes the new one) and columns 32-63 stop
+// accessing memory, so the workgroup's last passes touch one L2 line of each record
+// row instead of two.  Results do not depend on the column a shot
+// runs in, the walk order or the workgroup shape, and equal those of the two-phase
+// kernels bit for bit (same arithmetic in the same order).
 //
 // Paper: Chen, Yi, Liang, Wang, "Improved Belief Propagation Decoding
 // Algorithms for Surface Codes", section II-B1 (eqs. init, h_update, v_update,
@@ -154,6 +159,7 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
     uint64_t *P = lds + m;           // [m] parity of the decisions, per check
     uint64_t *U = lds + 2 * m;       // [2] columns failing the test, alternate iterations
     int32_t *col = reinterpret_cast<int32_t *>(lds + 2 * m + 2);   // [64] shot of each column
+    int32_t *mig = col + 64;   // [64] column whose shot moves into this one this pass (-1: none)
     const int lane = threadIdx.x & 63;
     // wavefront index, uniform across the wavefront (read from lane 0 so the compiler
     // keeps the walk positions, and every table read and branch on them, scalar)
@@ -179,6 +185,9 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
     R.rs = __builtin_amdgcn_make_buffer_rsrc(a.recs + (size_t)blockIdx.x * 2 * a.rec_bytes, 0,
                                              (int)(2 * a.rec_bytes), 0x00020000);
     const uint32_t lane_off = (uint32_t)lane * 4u;
+    // vector offset of an access that must not happen: past both records, it reads 0
+    // and writes nothing (the range check of the buffer resource)
+    constexpr uint32_t no_off = 0x80000000u;
     for (int i = wv; i < 4 * m; i += W) {
         if (__float_as_uint(finit[i]) == 0u) {   // padding
             R.st((uint32_t)i, lane_off, 0.0f);
@@ -210,6 +219,7 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
             const bool want = shot < 0 || finish;
             const uint64_t wm = __ballot(want);
             int ns = want ? -1 : shot;
+            const bool was_drained = drained;
             if (wm != 0 && !drained) {
                 const unsigned cnt = (unsigned)__popcll(wm);
                 unsigned base = 0;
@@ -219,11 +229,45 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
                 if (want && r < (unsigned)a.shots) ns = (int)r;
                 drained = base + cnt >= (unsigned)a.shots;
             }
+            // Once the queue is empty, the live shots of columns 32-63 move to empty
+            // columns 0-31 as soon as they all fit there (the r-th live upper column to
+            // the r-th empty lower one): the upper half of every record row, one L2 line,
+            // then goes untouched for the rest of the launch.  (Flooding only: the serial
+            // sweep's single record is read and rewritten within the pass.)
+            int from = -1;
+            const uint64_t live = __ballot(ns >= 0);
+            if (!SER && was_drained && (live >> 32) != 0 && __popcll(live) <= 32) {
+                if (lane < 32 && ns < 0) {
+                    const uint64_t holes = ~live & 0xFFFFFFFFull;
+                    const int r = __popcll(holes & ((1ull << lane) - 1ull));
+                    uint64_t up = live >> 32;
+                    if (r < __popcll(up)) {
+                        for (int k = 0; k < r; ++k) up &= up - 1ull;
+                        from = 32 + __builtin_ctzll(up);
+                    }
+                }
+                const int moved = __shfl(ns, from >= 0 ? from : lane, 64);
+                if (from >= 0) ns = moved;
+                if (lane >= 32) ns = -1;   // the live upper shots number at most the lower holes
+            }
             col[lane] = ns;
+            mig[lane] = from;
         }
         __syncthreads();
         const int ns = col[lane];
-        const bool refill = ns >= 0 && (shot < 0 || finish);
+        const int from = mig[lane];
+        const bool refill = ns >= 0 && from < 0 && (shot < 0 || finish);
+        {   // a column taking over a moved shot takes its iteration state too
+            const int sl = from >= 0 ? from : lane;
+            const int t2 = __shfl(t, sl, 64), att2 = __shfl(att, sl, 64), tb2 = __shfl(t_before, sl, 64);
+            const float alpha2 = __shfl(alpha, sl, 64);
+            if (from >= 0) {
+                t = t2;
+                att = att2;
+                t_before = tb2;
+                alpha = alpha2;
+            }
+        }
         shot = ns;
         finish = false;
         if (__ballot(shot >= 0) == 0) break;   // every column empty (the same in every wavefront)
@@ -234,10 +278,11 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
             alpha = a.vp.alpha;
         }
         if constexpr (VAR == BP4_AEWA) vp.alpha = alpha;   // per column
-        // syndrome words of the new shots
-        if (__ballot(refill) != 0) {
+        const bool moving = __ballot(from >= 0) != 0;
+        // syndrome words of the new and the moved shots
+        if (__ballot(refill) != 0 || moving) {
             for (int c = wv; c < m; c += W) {
-                uint32_t bit = (uint32_t)(S[c] >> lane) & 1u;
+                uint32_t bit = (uint32_t)(S[c] >> (from >= 0 ? from : lane)) & 1u;
                 if (refill) bit = a.synd[(size_t)shot * m + c] & 1u;
                 const uint64_t word = __ballot(bit);
                 if (lane == 0) S[c] = word;
@@ -248,8 +293,14 @@ __global__ void __launch_bounds__(64 * kGatherMaxWaves, kWavesPerSimd) decode_ga
 
         // ---- one flooding iteration over the walk ------------------------------------
         const bool fresh = t == 1;
-        const uint32_t rd = lane_off + (SER ? 0u : (pass & 1u) * a.rec_bytes);
-        const uint32_t wr = lane_off + (SER ? 0u : ((pass + 1u) & 1u) * a.rec_bytes);
+        // A moved shot's pass reads its old column and writes its new one.  Columns
+        // 32-63 read and write nothing once all of them are empty; a column without a
+        // shot otherwise reads and writes its own column like the others (masking single
+        // lanes would leave partly written L2 lines, which measured slower).
+        const uint32_t rcol = from >= 0 ? (uint32_t)from * 4u : lane_off;
+        const bool skip = lane >= 32 && (__ballot(shot >= 0) >> 32) == 0;
+        const uint32_t rd = skip ? no_off : rcol + (SER ? 0u : (pass & 1u) * a.rec_bytes);
+        const uint32_t wr = skip ? no_off : lane_off + (SER ? 0u : ((pass + 1u) & 1u) * a.rec_bytes);
         ++pass;
         uint64_t nan_cols = 0;
         // Reads of a qubit: its walk entry (scalar), the other stored words of each of
@@ -439,7 +490,7 @@ int32_t waves_of(int32_t waves) { return waves > 0 ? waves : kGatherDefaultWaves
 
 }  // namespace
 
-size_t gather_lds_bytes(int m) { return (size_t)(2 * m + 2) * 8 + 64 * 4; }
+size_t gather_lds_bytes(int m) { return (size_t)(2 * m + 2) * 8 + 128 * 4; }
 
 bool gather_supported(int m, int variant, int serial, bool wide, size_t max_lds)
 {

@@ -122,6 +122,7 @@ class StabilizerCode:
     hz: np.ndarray            # (m, n) uint8
     lx: np.ndarray = field(default=None)  # (2k, n) uint8 logical basis, x part
     lz: np.ndarray = field(default=None)  # (2k, n) uint8 logical basis, z part
+    coords: np.ndarray = field(default=None)  # (n, 2) int32 qubit positions on the layout, if the family has one
 
     @property
     def n(self) -> int:
@@ -148,12 +149,25 @@ class StabilizerCode:
         return (self.hx | (self.hz << 1)).astype(np.uint8)
 
 
-def _finish(name: str, hx: np.ndarray, hz: np.ndarray) -> StabilizerCode:
+def _finish(name: str, hx: np.ndarray, hz: np.ndarray, coords=None) -> StabilizerCode:
     hx = (np.asarray(hx) & 1).astype(np.uint8)
     hz = (np.asarray(hz) & 1).astype(np.uint8)
     code = StabilizerCode(name, hx, hz)
     code.lx, code.lz = logical_basis(hx, hz)
+    if coords is not None:
+        code.coords = np.asarray(coords, dtype=np.int32)
     return code
+
+
+def _repetition_product_coords(n1: int, m1: int, n2: int, m2: int) -> np.ndarray:
+    """Lattice positions of the qubits of a hypergraph product of two repetition codes
+    (check r between bits r and r + 1): bit x bit qubit (i, j) at (2i, 2j), check x check
+    qubit (a, b) at (2a + 1, 2b + 1), in the qubit order of hypergraph_product."""
+    i, j = np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")
+    a, b = np.meshgrid(np.arange(m1), np.arange(m2), indexing="ij")
+    first = np.stack([2 * i.ravel(), 2 * j.ravel()], axis=1)
+    second = np.stack([2 * a.ravel() + 1, 2 * b.ravel() + 1], axis=1)
+    return np.vstack([first, second]).astype(np.int32)
 
 
 # ---------------------------------------------------------------------------
@@ -202,7 +216,7 @@ def planar(L: int) -> StabilizerCode:
         raise ValueError("planar code needs L >= 2")
     h = repetition_open(L)
     hx, hz = hypergraph_product(h, h)
-    return _finish(f"planar_d{L}", hx, hz)
+    return _finish(f"planar_d{L}", hx, hz, _repetition_product_coords(L, L - 1, L, L - 1))
 
 
 def toric(L: int) -> StabilizerCode:
@@ -211,7 +225,7 @@ def toric(L: int) -> StabilizerCode:
         raise ValueError("toric code needs L >= 2")
     h = repetition_cyclic(L)
     hx, hz = hypergraph_product(h, h)
-    return _finish(f"toric_L{L}", hx, hz)
+    return _finish(f"toric_L{L}", hx, hz, _repetition_product_coords(L, L, L, L))
 
 
 def xzzx(L: int) -> StabilizerCode:
@@ -236,7 +250,8 @@ def xzzx(L: int) -> StabilizerCode:
             hz[r, q(a + 1, b)] = 1
             hz[r, q(a, b + 1)] = 1
             hx[r, q(a + 1, b + 1)] = 1
-    return _finish(f"xzzx_L{L}", hx, hz)
+    a, b = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    return _finish(f"xzzx_L{L}", hx, hz, np.stack([a.ravel(), b.ravel()], axis=1))
 
 
 def trapping_ring() -> StabilizerCode:

@@ -473,3 +473,39 @@ def test_wide_graphs_route_to_the_flooding_lds_kernel(lib):
     arr[1] = _lib.CodeBatch(gn.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
                             fake.value, 0, 0)
     assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -6
+
+
+def test_graph_set_coords(lib):
+    """Qubit coordinates re-order the single-pass kernel's walk only: any integer layout
+    is accepted for a narrow graph, the image size does not change, wide graphs (no
+    single-pass kernel) and NULL arguments are refused."""
+    from paper_2407_11523_amd import BP4Error, Graph
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    code = qecgen.planar(7)
+    g = Graph(code.hx, code.hz, code.lx, code.lz, upload=False)
+    before = g.device_bytes()
+    xy = np.ascontiguousarray(code.coords, dtype=np.int32)
+    assert lib.bp4_graph_set_coords(None, xy.ctypes.data_as(i32p)) == -1
+    assert lib.bp4_graph_set_coords(g.handle, None) == -1
+    assert lib.bp4_graph_set_coords(g.handle, xy.ctypes.data_as(i32p)) == 0
+    assert g.device_bytes() == before
+    # every qubit at one point, or a random layout: still a valid walk
+    same = np.zeros((code.n, 2), np.int32)
+    assert lib.bp4_graph_set_coords(g.handle, same.ctypes.data_as(i32p)) == 0
+    g.set_coords(np.random.default_rng(1).integers(-50, 50, (code.n, 2)))
+    with pytest.raises(BP4Error):
+        g.set_coords(xy[:-1])
+    wide = Graph(qecgen.bb(72).hx, qecgen.bb(72).hz, upload=False)
+    xyw = np.zeros((wide.n, 2), np.int32)
+    assert lib.bp4_graph_set_coords(wide.handle, xyw.ctypes.data_as(i32p)) == -6
+    # the lattice families carry their layouts; each check's qubits sit within two units
+    for fam, size, per in (("planar", 5, None), ("toric", 6, 12), ("xzzx", 5, 5)):
+        c = qecgen.make(fam, size)
+        assert c.coords.shape == (c.n, 2) and len({tuple(p) for p in c.coords}) == c.n
+        H = (c.hx | c.hz).astype(bool)
+        for r in range(c.m):
+            pts = c.coords[np.nonzero(H[r])[0]]
+            d = np.abs(pts[:, None, :] - pts[None, :, :])
+            if per:
+                d = np.minimum(d, per - d)
+            assert int(d.max()) <= 2, (fam, r)

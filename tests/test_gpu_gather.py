@@ -65,6 +65,31 @@ def test_gather_equals_two_phase(fam, size, variant, alpha, gamma):
     say("  conv", float(r["conv"].float().mean()), "iters", float(r["iters"].float().mean()))
 
 
+@pytest.mark.parametrize("fam,size", [("planar", 31), ("toric", 32), ("xzzx", 9)])
+def test_gather_walk_order_changes_nothing(fam, size):
+    """The walk order is a locality choice only: the lattice-strip walk that qubit
+    coordinates select, and the one a random layout selects, give the same outputs
+    as the default walk and the two-phase kernel, across a queue tail long enough for
+    the live shots to move to the lower columns."""
+    code = qecgen.make(fam, size)
+    p = 0.10
+    plain = P.Graph(code.hx, code.hz, code.lx, code.lz)
+    lattice = P.Graph(code.hx, code.hz, code.lx, code.lz, coords=code.coords)
+    rng = torch.Generator().manual_seed(size)
+    rand_xy = torch.randint(-1000, 1000, (code.n, 2), generator=rng, dtype=torch.int32).numpy()
+    scrambled = P.Graph(code.hx, code.hz, code.lx, code.lz, coords=rand_xy)
+    shots = 9000
+    _, syn = P.sample(plain, shots, qecgen.thresholds(p / 3, p / 3, p / 3), seed=size + 100)
+    pr = P.prior_llr(qecgen.depolarizing_probs(code.n, p))
+    for variant, alpha, gamma in (("ewainit", 0.6, 0.0), ("momentum", 0.6, 0.3), ("aewa", 1.0, 0.0)):
+        prm = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=70)
+        say("walk orders", code.name, variant)
+        ref = run(plain, prm, pr, syn, "soa")
+        same(ref, run(plain, prm, pr, syn, "gather"), (code.name, variant, "default walk"))
+        same(ref, run(lattice, prm, pr, syn, "gather"), (code.name, variant, "lattice strips"))
+        same(ref, run(scrambled, prm, pr, syn, "gather"), (code.name, variant, "random layout"))
+
+
 def test_gather_shot_counts_and_shapes():
     """Fewer shots than one workgroup, ragged counts, more shots than columns in flight
     (lanes take new shots in place), and 4, 8 or 16 wavefronts per workgroup."""
