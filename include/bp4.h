@@ -112,8 +112,9 @@ typedef struct bp4_graph bp4_graph;
  * every kernel; otherwise it is wide (checks of degree <= 8, qubits <= 7, as
  * the bivariate bicycle and 3D Chamon codes of section IV-C need) and runs on
  * the flooding LDS kernel, the sampler and bookkeeping only (the serial
- * schedule, the SOA, plain and unrolled paths answer EUNSUPPORTED, and
- * bp4_decode_mixed does not mix wide and narrow codes in one launch).
+ * schedule, the SOA, plain and unrolled paths answer EUNSUPPORTED; a
+ * bp4_decode_mixed launch holding a wide code runs the kernel's wide build,
+ * four wavefronts per SIMD instead of six, for all of its codes).
  * Errors: EINVAL (m, n <= 0, entries not 0/1, empty row or column, NULL),
  * ENONCOMM (rows anticommute, unless BP4_ALLOW_ANTICOMMUTING), EDEGREE
  * (check degree above 8 or qubit degree above 7), EUNSUPPORTED (n > 16383 or

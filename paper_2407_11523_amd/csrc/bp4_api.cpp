@@ -1178,8 +1178,6 @@ int bp4::decode_mixed_with(int32_t ncodes, const bp4_code_batch *codes, unsigned
         if (c.group_lanes == 0 && c.block_shots == 0 && auto_kernel(c.graph, c.params.variant) == BP4_KERNEL_SOA)
             return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d needs the large-code (SOA) kernel", i);
         if (c.params.serial) return fail(BP4_EUNSUPPORTED, "decode_mixed: code %d asks for the serial schedule", i);
-        if (c.graph->wide() != codes[0].graph->wide())
-            return fail(BP4_EUNSUPPORTED, "decode_mixed: codes with degrees above 4 and codes without share no launch");
     }
     size_t max_lds = 0;
     int rc = device_max_lds(&max_lds);

@@ -882,8 +882,8 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *e
 
 // VSET: the variant every code of the launch uses, kMixedVariants for a flooding
 // launch that mixes variants (a switch per code), kSerial for the serial schedule
-// (one code, a switch on its variant), kWide for a flooding launch of wide graphs
-// (a switch on the variant).  Register budget: 80 VGPRs (six wavefronts per
+// (one code, a switch on its variant), kWide for a flooding launch with a wide graph
+// (a switch on the variant and the width: its narrow codes run the narrow steps).  Register budget: 80 VGPRs (six wavefronts per
 // SIMD: three 512-lane workgroups per CU) for every build but kWide, 128 (four)
 // for kWide, whose 8-edge checks hold twice the messages in registers.  The
 // AdaGrad and switching builds spill 12-13 registers at 80 and still ran an
@@ -927,11 +927,11 @@ decode_lds_kernel(MixedArgs args)
             // layout holds kSlots n message words in LDS.
             // Two-plus-two layout: position = 2 [Z label] + rank among the qubit's slots
             // of the same label.
-            constexpr bool W = VSET == kWide;
+            const bool wc = VSET == kWide && a.wide;   // the wide build also runs narrow codes
             const bool c22 = VSET >= 0 && a.css22;
             for (int i = threadIdx.x; i < cs * m; i += kBlock) {
                 const uint32_t w = a.g.cedge[i];
-                uint32_t slot = lds_pad_slot<W>((uint32_t)n);
+                uint32_t slot = wc ? lds_pad_slot<true>((uint32_t)n) : lds_pad_slot<false>((uint32_t)n);
                 if (!edge_is_pad(w)) {
                     const uint32_t v = edge_var(w);
                     const uint32_t info = a.g.vinfo[v];
@@ -977,7 +977,7 @@ decode_lds_kernel(MixedArgs args)
                 default: run_serial<BP4_EWAINIT, false>(a, lds); break;
                 }
             }
-        } else if (VSET == kWide) {   // the host launches only wide codes here
+        } else if (VSET == kWide) {   // a launch with a wide code; its narrow codes run here too
             if (a.wide) {
                 switch (a.variant) {
                 case BP4_BP: run_code<BP4_BP, true>(a, lds, events); break;
@@ -985,6 +985,14 @@ decode_lds_kernel(MixedArgs args)
                 case BP4_ADAGRAD: run_code<BP4_ADAGRAD, true>(a, lds, events); break;
                 case BP4_AEWA: run_code<BP4_AEWA, true>(a, lds, events); break;
                 default: run_code<BP4_EWAINIT, true>(a, lds, events); break;
+                }
+            } else {
+                switch (a.variant) {
+                case BP4_BP: run_code<BP4_BP, false>(a, lds, events); break;
+                case BP4_MOMENTUM: run_code<BP4_MOMENTUM, false>(a, lds, events); break;
+                case BP4_ADAGRAD: run_code<BP4_ADAGRAD, false>(a, lds, events); break;
+                case BP4_AEWA: run_code<BP4_AEWA, false>(a, lds, events); break;
+                default: run_code<BP4_EWAINIT, false>(a, lds, events); break;
                 }
             }
         } else if (VSET == kMixedVariants) {
@@ -1160,7 +1168,7 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
     for (int i = 0; i < args.ncodes; ++i) serial = serial || args.codes[i].serial;
     if (serial) return launch_lds_kernel<kSerial>(args, lds_bytes, s, grid_out);   // a single code
     for (int i = 0; i < args.ncodes; ++i)
-        if (args.codes[i].wide) return launch_lds_kernel<kWide>(args, lds_bytes, s, grid_out);   // all wide
+        if (args.codes[i].wide) return launch_lds_kernel<kWide>(args, lds_bytes, s, grid_out);   // any wide
     switch (v) {
     case BP4_BP: return launch_lds_kernel<BP4_BP>(args, lds_bytes, s, grid_out);
     case BP4_MOMENTUM: return launch_lds_kernel<BP4_MOMENTUM>(args, lds_bytes, s, grid_out);

@@ -463,16 +463,16 @@ def test_wide_graphs_route_to_the_flooding_lds_kernel(lib):
                                     1 << 30, null, ctypes.byref(it)) == -6
         s1, s2 = ctypes.c_size_t(), ctypes.c_size_t()
         assert lib.bp4_unrolled_sizes(g.handle, EW, 4, 2, 64, ctypes.byref(s1), ctypes.byref(s2)) == 0
-    # a mixed launch does not combine wide and narrow codes
+    # a mixed launch may combine wide and narrow codes; its buffers are still checked first
     gw = Graph(qecgen.bb(72).hx, qecgen.bb(72).hz, upload=False)
     gn = Graph(qecgen.toric(4).hx, qecgen.toric(4).hz, upload=False)
     cp = Params(variant="ewainit", alpha=0.5).c()
     arr = (_lib.CodeBatch * 2)()
     arr[0] = _lib.CodeBatch(gw.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
                             fake.value, 0, 0)
-    arr[1] = _lib.CodeBatch(gn.handle.value, fake.value, cp, 10, fake.value, fake.value, fake.value, fake.value,
+    arr[1] = _lib.CodeBatch(gn.handle.value, fake.value, cp, 10, fake.value, fake.value, None, fake.value,
                             fake.value, 0, 0)
-    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -6
+    assert lib.bp4_decode_mixed(2, arr, fake, 256, null) == -1                         # EINVAL: NULL est
 
 
 def test_graph_set_coords(lib):

@@ -153,3 +153,27 @@ def test_wide_lane_mappings_bitwise_and_mixed():
     for o, r in zip(outs, refs):
         for k in ("est", "conv", "iters"):
             assert torch.equal(o[k], r[k]), k
+
+
+def test_mixed_launch_with_wide_and_narrow_codes():
+    """One launch holding wide and narrow codes runs the wide build for all of them; every
+    code's outputs equal its own single-code decode (the narrow codes' from the narrow
+    build), for block slots and wave groups, and for two variants in one launch."""
+    entries, refs = [], []
+    specs = [("bb72", CODES["bb72"](), 0.06, "ewainit", 0.5), ("toric6", qecgen.toric(6), 0.08, "ewainit", 0.6),
+             ("planar5", qecgen.planar(5), 0.08, "momentum", 0.6), ("chamon3", CODES["chamon3"](), 0.06, "bp", 1.0),
+             ("xzzx5", qecgen.xzzx(5), 0.08, "ewainit", 0.6)]
+    lanes = [0, (0, 4), 64, 32, (0, 8)]
+    for i, ((name, c, p, variant, alpha), ln) in enumerate(zip(specs, lanes)):
+        g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+        _, syn = P.sample(g, 3000 + 11 * i, qecgen.thresholds(p / 3, p / 3, p / 3), seed=70 + i)
+        pr = P.prior_llr(qecgen.depolarizing_probs(c.n, p))
+        prm = P.Params(variant=variant, alpha=alpha, gamma=0.0, max_iter=60)
+        say("mixed wide and narrow", name, variant, ln)
+        entries.append((g, prm, pr, syn, ln))
+        refs.append(P.decode(g, prm, pr, syn))
+    outs = P.decode_mixed(entries)
+    torch.cuda.synchronize()
+    for (name, *_), o, r in zip(specs, outs, refs):
+        for k in ("est", "conv", "iters"):
+            assert torch.equal(o[k], r[k]), (name, k, int((o[k] != r[k]).sum()))
