@@ -16,7 +16,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbp4.so")
 ARCH = "gfx950"
 
-SOURCES = ["bp4_api.cpp", "bp4_decode.hip", "bp4_sample.hip", "bp4_plain.hip", "bp4_soa.hip",
+SOURCES = ["bp4_api.cpp", "bp4_walk.cpp", "bp4_decode.hip", "bp4_sample.hip", "bp4_plain.hip", "bp4_soa.hip",
            "bp4_unrolled.hip", "bp4_noalloc.hip", "bp4_gather.hip"]
 
 # Packed FP32 VALU forms are kept out of generated code.
@@ -64,19 +64,21 @@ def build(verbose: bool = False) -> str:
 
 SAN_LIB = os.path.join(PKG, "libbp4_san.so")
 # host code of the ABI layer only: the device code objects are the regular ones
+HOST_SOURCES = ("bp4_api.cpp", "bp4_walk.cpp")
 SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined", "-g"]
 
 
 def build_sanitized() -> str:
-    """libbp4_san.so: bp4_api.cpp (argument checks, graph construction, launch set-up)
-    with AddressSanitizer and UndefinedBehaviorSanitizer, linked with the regular
-    kernel objects; loaded with BP4_SANITIZE=1 and clang's ASan runtime preloaded."""
+    """libbp4_san.so: the host sources bp4_api.cpp (argument checks, graph construction,
+    launch set-up) and bp4_walk.cpp (walk order of the single-pass kernel) with
+    AddressSanitizer and UndefinedBehaviorSanitizer, linked with the regular kernel
+    objects; loaded with BP4_SANITIZE=1 and clang's ASan runtime preloaded."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src in SOURCES:
-        if src == "bp4_api.cpp":
-            obj = os.path.join(BUILD, "bp4_api_san.o")
+        if src in HOST_SOURCES:
+            obj = os.path.join(BUILD, src.replace(".cpp", "_san.o"))
             cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + HIP_FLAGS + SAN_FLAGS
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "bp4.h"
 #include "bp4_internal.h"
 
@@ -33,6 +35,21 @@ struct GatherTables {
     const uint32_t *slev;
     int32_t nlev;
 };
+
+// Host: what the walk builder reads of a narrow graph (packed check edges [m][cstride],
+// first message slot of each qubit [n + 1], check of each slot [nnz], position of each
+// slot's edge in its check [nnz]).
+struct GatherWalkInput {
+    int n, m, cstride;
+    const uint32_t *cedge;
+    const int32_t *vptr;
+    const uint32_t *vchk;
+    const int32_t *cpos;
+};
+// Host: the walk order (gord [n]) and its gather words (gedge [4n]); xy: qubit positions
+// [n][2] or NULL.
+void build_gather_walk(const GatherWalkInput &in, const int32_t *xy, std::vector<uint32_t> &gord,
+                       std::vector<uint32_t> &gedge);
 
 // Wavefronts per workgroup: all of them walk the qubits of the same 64 shots.
 constexpr int kGatherDefaultWaves = 16;
