@@ -705,6 +705,10 @@ def run_unrolled(torch, qecgen, P, dev):
            "forward_ms": fwd, "backward_ms": bwd, "loss": float(loss.detach()),
            "shots_per_s_forward_backward": shots / ((fwd + bwd) / 1e3),
            "edge_updates_per_s_forward": eu / (fwd / 1e3),
+           # the forward's state (messages and Q) read and written once per shot-iteration
+           "forward_algorithmic_bytes_per_shot_iteration": algorithmic_bytes(g.nnz, g.n),
+           "forward_algorithmic_gb_s": shots * T * algorithmic_bytes(g.nnz, g.n) / (fwd / 1e3) / 1e9,
+           "forward_hbm_frac": shots * T * algorithmic_bytes(g.nnz, g.n) / (fwd / 1e3) / 8e12,
            "grad_alpha_norm": float(alpha.grad.norm()), "grad_prior_norm": float(prior.grad.norm())}
     # the same batch unrolled as Momentum-BP: a step and a decay per iteration (starting
     # from the toric sweep's step and gamma 0)
@@ -725,9 +729,12 @@ def run_unrolled(torch, qecgen, P, dev):
         times.append((a.elapsed_time(b), b.elapsed_time(c)))
     fwd_m, bwd_m = min(times, key=lambda x: x[0] + x[1])
     log(f"unrolled momentum: forward {fwd_m:.2f} ms, backward {bwd_m:.2f} ms")
+    mom_bytes = 8 * g.nnz + 72 * g.n   # messages, Q, g and M read and written once per shot-iteration
     res["momentum"] = {"workload": "the same batch, T=32 unrolled Momentum-BP iterations, loss and gradients w.r.t. "
                                    "the steps alpha_t, the decays gamma_t and the priors",
                        "forward_ms": fwd_m, "backward_ms": bwd_m, "loss": float(loss_m.detach()),
+                       "forward_algorithmic_bytes_per_shot_iteration": mom_bytes,
+                       "forward_hbm_frac": shots * T * mom_bytes / (fwd_m / 1e3) / 8e12,
                        "grad_params_norm": float(params.grad.norm()), "grad_prior_norm": float(prior.grad.norm())}
     return res
 

@@ -562,13 +562,25 @@ unrolled_reverse_kernel(UnrArgs a, int sg)
 }
 
 // out[i] = scale * (*dloss) * sum over wavefronts of partial[w][i], in wavefront order.
+// The loads of 16 partials are issued before their additions (a few hundred threads
+// walk thousands of partials each; one load in flight per thread left the kernel
+// waiting on memory); the additions keep the wavefront order.
 __global__ void __launch_bounds__(256) unrolled_reduce_kernel(const double *partial, int waves, int nout, double scale,
                                                             const float *dloss, double *out0, int n0, double *out1)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nout) return;
+    constexpr int kBatch = 16;
     double s = 0.0;
-    for (int w = 0; w < waves; ++w) s += partial[(size_t)w * nout + i];
+    int w = 0;
+    for (; w + kBatch <= waves; w += kBatch) {
+        double v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) v[k] = partial[(size_t)(w + k) * nout + i];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) s += v[k];
+    }
+    for (; w < waves; ++w) s += partial[(size_t)w * nout + i];
     s *= scale * (dloss ? (double)*dloss : 1.0);
     if (i < n0) out0[i] = s;
     else out1[i - n0] = s;
