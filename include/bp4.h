@@ -111,8 +111,8 @@ typedef struct bp4_graph bp4_graph;
  * A graph whose checks and qubits all have degree <= 4 is narrow and runs on
  * every kernel; otherwise it is wide (checks of degree <= 8, qubits <= 7, as
  * the bivariate bicycle and 3D Chamon codes of section IV-C need) and runs on
- * the flooding LDS kernel, the sampler and bookkeeping only (the serial
- * schedule, the SOA, plain and unrolled paths answer EUNSUPPORTED; a
+ * the flooding LDS kernel, the plain decoder, the sampler and bookkeeping (the
+ * serial schedule, the SOA and unrolled paths answer EUNSUPPORTED; a
  * bp4_decode_mixed launch holding a wide code runs the kernel's wide build,
  * four wavefronts per SIMD instead of six, for all of its codes).
  * Errors: EINVAL (m, n <= 0, entries not 0/1, empty row or column, NULL),

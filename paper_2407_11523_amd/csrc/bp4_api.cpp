@@ -1007,7 +1007,6 @@ int bp4_decode_plain(const bp4_graph *g, const void *dev_graph, const bp4_params
     if (!prior_llr) return fail(BP4_EINVAL, "decode_plain: NULL prior");
     if (iterations_run) *iterations_run = 0;
     if (p->serial) return fail(BP4_EUNSUPPORTED, "decode_plain: flooding schedule only");
-    if (g->wide()) return fail(BP4_EUNSUPPORTED, "decode_plain: graphs with degrees above 4 are not supported");
     if (p->variant == BP4_AEWA) return fail(BP4_EUNSUPPORTED, "decode_plain: AEWA restarts need the persistent kernels");
     if (shots == 0) return BP4_OK;
     if (!synd || !est || !conv || !iters || !ws) return fail(BP4_EINVAL, "decode_plain: NULL buffer");

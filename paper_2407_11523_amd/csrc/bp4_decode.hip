@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "bp4_math.h"
+#include "bp4_wide.h"
 
 namespace bp4 {
 
@@ -64,33 +65,6 @@ __device__ __forceinline__ void load_check(const uint32_t *s_ce, int c, uint32_t
         w[4 * q + 1] = w4.y;
         w[4 * q + 2] = w4.z;
         w[4 * q + 3] = w4.w;
-    }
-}
-
-// Check rule of a wide check (up to 8 edges, padding +inf): as check_update, with
-// the leave-one-out sums of phi formed from prefix and suffix sums in edge order.
-__device__ __forceinline__ void check_update_wide(const float mv[8], uint32_t s, float C, float out[8])
-{
-    float f[8];
-    uint32_t b[8];
-    uint32_t neg = s << 31;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        b[j] = __float_as_uint(mv[j]);
-        neg ^= b[j];
-        f[j] = phi(fabsf(mv[j]));
-    }
-    float pre[8], suf[8];
-    pre[0] = 0.0f;
-#pragma unroll
-    for (int j = 1; j < 8; ++j) pre[j] = pre[j - 1] + f[j - 1];
-    suf[7] = 0.0f;
-#pragma unroll
-    for (int j = 6; j >= 0; --j) suf[j] = suf[j + 1] + f[j + 1];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float mag = phi(pre[j] + suf[j]);
-        out[j] = clampf(__uint_as_float(__float_as_uint(mag) ^ ((neg ^ b[j]) & 0x80000000u)), C);
     }
 }
 
@@ -133,9 +107,8 @@ __device__ __forceinline__ uint32_t test_node(const uint32_t *s_ce, const uint8_
     return par | (any & 1u);   // bit 0: a NaN posterior never converges
 }
 
-// Label of slot j from a qubit's label word (narrow: the qubit word shifted right
-// by 20; wide: the separate label word).
-__device__ __forceinline__ uint32_t slot_label(uint32_t labw, int j) { return (labw >> (2 * j)) & 3u; }
+// Label word of qubit v: the qubit word shifted right by 20 (narrow), the separate
+// label word (wide).
 template <bool W>
 __device__ __forceinline__ uint32_t label_word(const uint32_t *s_vl, uint32_t info, int v)
 {
@@ -172,39 +145,6 @@ __device__ __forceinline__ uint32_t c22_info(uint32_t info)
 __device__ __forceinline__ uint32_t c22_keep(uint32_t info, int p)
 {
     return (uint32_t)__builtin_amdgcn_sbfe((int)info, 20 + p, 1);
-}
-
-// Per-label sums S[lab] of a qubit's incoming messages and of their magnitudes A[lab]
-// over its DV slots (label 0 for unused slots), as label_sums.
-template <int DV>
-__device__ __forceinline__ void label_sums_w(uint32_t labw, const float mc[DV], bool with_y, bool with_abs, float S[4],
-                                             float A[4])
-{
-    S[0] = A[0] = 0.0f;
-    float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-#pragma unroll
-    for (int j = 0; j < DV; ++j) {
-        const uint32_t l = slot_label(labw, j);
-        s1 += l == 1u ? mc[j] : 0.0f;
-        s2 += l == 2u ? mc[j] : 0.0f;
-        if (with_y) s3 += l == 3u ? mc[j] : 0.0f;
-    }
-    S[1] = s1;
-    S[2] = s2;
-    S[3] = s3;
-    float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    if (with_abs) {
-#pragma unroll
-        for (int j = 0; j < DV; ++j) {
-            const uint32_t l = slot_label(labw, j);
-            a1 += l == 1u ? fabsf(mc[j]) : 0.0f;
-            a2 += l == 2u ? fabsf(mc[j]) : 0.0f;
-            a3 += l == 3u ? fabsf(mc[j]) : 0.0f;
-        }
-    }
-    A[1] = a1;
-    A[2] = a2;
-    A[3] = a3;
 }
 
 // Initialisation of qubit v (eq. init, Algorithm 2): m^{(0)}_{v->c} =

@@ -6,8 +6,10 @@
 // consecutive shots.  Finished shots are masked, not compacted; the host reads
 // the number of unfinished shots after every iteration and stops at zero or at
 // iter_max.  The arithmetic per node is the shared device code, so results are
-// bitwise equal to the LDS kernel's.
+// bitwise equal to the LDS kernel's.  Wide graphs (checks of up to 8 edges, qubits of
+// up to 7, their slot labels in a separate word) take the same kernels built at width 8.
 #include "bp4_math.h"
+#include "bp4_wide.h"
 
 namespace bp4 {
 namespace {
@@ -53,41 +55,54 @@ __global__ void __launch_bounds__(kTile) plain_init_kernel(PlainArgs a)
     float lam[4];
     qubit_lambdas(p3, var_labels_present(info), lam);
     const uint32_t base = var_base(info), deg = var_deg(info);
-    for (uint32_t j = 0; j < deg; ++j) a.msg[(base + j) * S + shot] = clampf(lam[var_lab(info, j)], a.clamp);
+    const bool wide = a.g.cstride > kMaxCheckDeg;
+    for (uint32_t j = 0; j < deg; ++j) {
+        const uint32_t lab = wide ? slot_label(a.g.vlab[v], (int)j) : var_lab(info, j);
+        a.msg[(base + j) * S + shot] = clampf(lam[lab], a.clamp);
+    }
 }
 
+// W: wide graph (8 edge words per check).
+template <bool W>
 __global__ void __launch_bounds__(kTile) plain_check_kernel(PlainArgs a)
 {
+    constexpr int D = W ? kMaxCheckDegWide : kMaxCheckDeg;
     const int shot = blockIdx.x * kTile + threadIdx.x;
     const int c = blockIdx.y;
     if (shot >= a.shots || !a.active[shot]) return;
     const size_t S = (size_t)a.shots;
-    uint32_t w[4];
-    float mv[4], out[4];
+    uint32_t w[D];
+    float mv[D], out[D];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        w[j] = a.g.cedge[c * kMaxCheckDeg + j];
+    for (int j = 0; j < D; ++j) {
+        w[j] = a.g.cedge[c * D + j];
         mv[j] = edge_is_pad(w[j]) ? INFINITY : a.msg[edge_slot(w[j]) * S + shot];
     }
-    check_update(mv, a.synd[(size_t)shot * a.g.m + c], a.clamp, out);
+    const uint32_t sb = a.synd[(size_t)shot * a.g.m + c];
+    if constexpr (W) check_update_wide(mv, sb, a.clamp, out);
+    else check_update(mv, sb, a.clamp, out);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < D; ++j)
         if (!edge_is_pad(w[j])) a.msg[edge_slot(w[j]) * S + shot] = out[j];
 }
 
+template <bool W>
 __global__ void __launch_bounds__(kTile) plain_var_kernel(PlainArgs a)
 {
+    constexpr int DV = W ? 8 : 4;
     const int shot = blockIdx.x * kTile + threadIdx.x;
     const int v = blockIdx.y;
     if (shot >= a.shots || !a.active[shot]) return;
     const size_t S = (size_t)a.shots;
     const uint32_t info = a.g.vinfo[v];
     const uint32_t base = var_base(info), deg = var_deg(info);
-    float mc[4];
+    float mc[DV];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) mc[j] = (uint32_t)j < deg ? a.msg[(base + j) * S + shot] : 0.0f;
+    for (int j = 0; j < DV; ++j) mc[j] = (uint32_t)j < deg ? a.msg[(base + j) * S + shot] : 0.0f;
     float Sl[4], Al[4];
-    label_sums(info, mc, true, a.vp.variant == BP4_ADAGRAD, Sl, Al);
+    const uint32_t labw = W ? a.g.vlab[v] : 0u;
+    if constexpr (W) label_sums_w<DV>(labw, mc, true, a.vp.variant == BP4_ADAGRAD, Sl, Al);
+    else label_sums(info, mc, true, a.vp.variant == BP4_ADAGRAD, Sl, Al);
     const float p3[3] = {a.prior[3 * v], a.prior[3 * v + 1], a.prior[3 * v + 2]};
     const bool keep_q = a.vp.variant != BP4_BP;
     const bool keep_acc = a.vp.variant == BP4_MOMENTUM || a.vp.variant == BP4_ADAGRAD;
@@ -105,20 +120,25 @@ __global__ void __launch_bounds__(kTile) plain_var_kernel(PlainArgs a)
     float lam[4];
     qubit_lambdas(qn, var_labels_present(info), lam);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if ((uint32_t)j < deg) a.msg[(base + j) * S + shot] = clampf(lam[var_lab(info, j)] - mc[j], a.clamp);
+    for (int j = 0; j < DV; ++j)
+        if ((uint32_t)j < deg) {
+            const uint32_t lab = W ? slot_label(labw, j) : var_lab(info, j);
+            a.msg[(base + j) * S + shot] = clampf(lam[lab] - mc[j], a.clamp);
+        }
 }
 
+template <bool W>
 __global__ void __launch_bounds__(kTile) plain_test_kernel(PlainArgs a)
 {
+    constexpr int D = W ? kMaxCheckDegWide : kMaxCheckDeg;
     const int shot = blockIdx.x * kTile + threadIdx.x;
     const int c = blockIdx.y;
     if (shot >= a.shots || !a.active[shot]) return;
     const size_t S = (size_t)a.shots;
     uint32_t par = a.synd[(size_t)shot * a.g.m + c] & 1u, bad = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t w = a.g.cedge[c * kMaxCheckDeg + j];
+    for (int j = 0; j < D; ++j) {
+        const uint32_t w = a.g.cedge[c * D + j];
         if (edge_is_pad(w)) continue;
         const uint32_t e = a.ehat[(size_t)edge_var(w) * S + shot];
         if (e == 0xFFu) bad = 1u;
@@ -212,9 +232,15 @@ hipError_t run_plain(const GraphView &g, const bp4_params &p, int32_t shots, con
         a.t = t;
         e = launch_zero_u32(a.remaining, 1, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(plain_check_kernel, dim3(xb, g.m), dim3(kTile), 0, s, a);
-        hipLaunchKernelGGL(plain_var_kernel, dim3(xb, g.n), dim3(kTile), 0, s, a);
-        hipLaunchKernelGGL(plain_test_kernel, dim3(xb, g.m), dim3(kTile), 0, s, a);
+        if (g.cstride > kMaxCheckDeg) {
+            hipLaunchKernelGGL(plain_check_kernel<true>, dim3(xb, g.m), dim3(kTile), 0, s, a);
+            hipLaunchKernelGGL(plain_var_kernel<true>, dim3(xb, g.n), dim3(kTile), 0, s, a);
+            hipLaunchKernelGGL(plain_test_kernel<true>, dim3(xb, g.m), dim3(kTile), 0, s, a);
+        } else {
+            hipLaunchKernelGGL(plain_check_kernel<false>, dim3(xb, g.m), dim3(kTile), 0, s, a);
+            hipLaunchKernelGGL(plain_var_kernel<false>, dim3(xb, g.n), dim3(kTile), 0, s, a);
+            hipLaunchKernelGGL(plain_test_kernel<false>, dim3(xb, g.m), dim3(kTile), 0, s, a);
+        }
         hipLaunchKernelGGL(plain_finish_kernel, dim3(xb), dim3(kTile), 0, s, a);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -177,3 +177,23 @@ def test_mixed_launch_with_wide_and_narrow_codes():
     for (name, *_), o, r in zip(specs, outs, refs):
         for k in ("est", "conv", "iters"):
             assert torch.equal(o[k], r[k]), (name, k, int((o[k] != r[k]).sum()))
+
+
+@pytest.mark.parametrize("name", ["bb72", "chamon3"])
+def test_plain_decoder_on_wide_graphs(name):
+    """The per-phase plain decoder built at width 8 equals the LDS kernel's wide build bit
+    for bit, for every variant it runs."""
+    c = CODES[name]()
+    g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+    p = 0.06
+    _, syn = P.sample(g, 3000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=91)
+    pr = P.prior_llr(qecgen.depolarizing_probs(c.n, p))
+    for variant, alpha, gamma in (("ewainit", 0.5, 0.0), ("bp", 1.0, 0.0), ("momentum", 0.6, 0.3),
+                                  ("adagrad", 5.0, 0.0)):
+        prm = P.Params(variant=variant, alpha=alpha, gamma=gamma, max_iter=50)
+        say("plain on wide", name, variant)
+        ref = P.decode(g, prm, pr, syn)
+        r = P.decode_plain(g, prm, pr, syn)
+        torch.cuda.synchronize()
+        for k in ("est", "conv", "iters"):
+            assert torch.equal(r[k], ref[k]), (name, variant, k, int((r[k] != ref[k]).sum()))
