@@ -111,10 +111,10 @@ typedef struct bp4_graph bp4_graph;
  * A graph whose checks and qubits all have degree <= 4 is narrow and runs on
  * every kernel; otherwise it is wide (checks of degree <= 8, qubits <= 7, as
  * the bivariate bicycle and 3D Chamon codes of section IV-C need) and runs on
- * the flooding LDS kernel, the plain decoder, the sampler and bookkeeping (the
- * serial schedule, the SOA and unrolled paths answer EUNSUPPORTED; a
- * bp4_decode_mixed launch holding a wide code runs the kernel's wide build,
- * four wavefronts per SIMD instead of six, for all of its codes).
+ * the LDS kernel (flooding and serial schedules), the plain decoder, the sampler
+ * and bookkeeping (the HBM kernels and the unrolled path answer EUNSUPPORTED;
+ * bp4_decode_mixed runs a batch of wide and narrow codes as two persistent
+ * launches in stream order, one per build).
  * Errors: EINVAL (m, n <= 0, entries not 0/1, empty row or column, NULL),
  * ENONCOMM (rows anticommute, unless BP4_ALLOW_ANTICOMMUTING), EDEGREE
  * (check degree above 8 or qubit degree above 7), EUNSUPPORTED (n > 16383 or

@@ -614,7 +614,7 @@ static double serial_lane_use(const bp4_graph *g, int G)
 
 static LdsLayout serial_layout(const bp4_graph *g, int variant, int G)
 {
-    return decode_lds_serial_layout(g->m, g->n, g->nnz, (int)g->slev.size() - 1, variant, G);
+    return decode_lds_serial_layout(g->m, g->n, g->nnz, (int)g->slev.size() - 1, variant, G, g->wide());
 }
 
 // The serial kernel the automatic choice takes: LDS when 64-lane groups fit
@@ -746,8 +746,8 @@ int decode_common(const bp4_graph *g, const void *dev_graph, const bp4_params *p
         return fail(BP4_EINVAL, "decode: soa_lanes and soa_iter_block apply to the SOA kernel");
     if (kernel != BP4_KERNEL_GATHER && gather_knobs)
         return fail(BP4_EINVAL, "decode: gather_waves applies to the single-pass HBM kernel");
-    if (g->wide() && (kernel != BP4_KERNEL_LDS || p->serial))
-        return fail(BP4_EUNSUPPORTED, "decode: graphs with degrees above 4 run the flooding LDS kernel only");
+    if (g->wide() && kernel != BP4_KERNEL_LDS)
+        return fail(BP4_EUNSUPPORTED, "decode: graphs with degrees above 4 run the LDS kernel only");
     if (kernel == BP4_KERNEL_GATHER) {
         if (lds_knobs || soa_knobs)
             return fail(BP4_EINVAL, "decode: LDS and SOA tuning fields do not apply to the single-pass HBM kernel");

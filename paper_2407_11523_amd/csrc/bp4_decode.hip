@@ -424,18 +424,20 @@ __device__ __forceinline__ void run_wave(const DecodeArgs &a, float *lds)
 // is read), so a message is passed through phi once, when it is written.
 // Static LDS adds the slot -> check table and the level order; the syndrome is
 // kept as bytes in the region.
-template <int VAR, bool WY>
+template <int VAR, bool WY, bool W = false>
 __device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
 {
+    constexpr int D = Width<W>::kCheck, DV = Width<W>::kSlots;
     const int G = a.group_lanes;
     const int lgG = __builtin_ctz((unsigned)G);
     const int m = a.g.m, n = a.g.n, nnz = a.g.nnz;
     const uint32_t *s_ce = reinterpret_cast<const uint32_t *>(lds);
-    const uint32_t *s_vi = s_ce + kMaxCheckDeg * m;
+    const uint32_t *s_vi = s_ce + D * m;
     const float *s_pi = reinterpret_cast<const float *>(s_vi + n);
     const uint32_t *s_vchk = reinterpret_cast<const uint32_t *>(s_pi + 3 * n);
     const uint32_t *s_ord = s_vchk + nnz;
     const uint32_t *s_lev = s_ord + n;
+    const uint32_t *s_vl = s_lev + a.g.nlev + 1;   // wide graphs: slot labels
 
     const int gid = (int)threadIdx.x >> lgG;
     const int r = (int)threadIdx.x & (G - 1);
@@ -462,7 +464,8 @@ __device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
             const float p3[3] = {s_pi[3 * v], s_pi[3 * v + 1], s_pi[3 * v + 2]};
             float lam[4];
             qubit_lambdas(p3, var_labels_present(info), lam);
-            for (uint32_t j = 0; j < deg; ++j) store(base + j, clampf(lam[var_lab(info, j)], C));
+            const uint32_t labw = label_word<W>(s_vl, info, v);
+            for (uint32_t j = 0; j < deg; ++j) store(base + j, clampf(lam[slot_label(labw, (int)j)], C));
             float st[3], ac[3];
             qubit_state_init(VAR, p3, st, ac);
             if (VAR != BP4_BP)
@@ -477,27 +480,32 @@ __device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
     auto serial_qubit = [&](int v, int shot) {
         const uint32_t info = s_vi[v];
         const uint32_t base = var_base(info), deg = var_deg(info);
-        float mc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float mc[DV];
+#pragma unroll
+        for (int j = 0; j < DV; ++j) mc[j] = 0.0f;
         for (uint32_t j = 0; j < deg; ++j) {
             const uint32_t slot = base + j;
             const uint32_t c = s_vchk[slot];
-            const uint4 w4 = *reinterpret_cast<const uint4 *>(&s_ce[kMaxCheckDeg * c]);
-            const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+            uint32_t w[D];
+            load_check<W>(s_ce, (int)c, w);
             uint32_t neg = syn[c] & 1u;
-            float f[4];
+            float f[D];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < D; ++k) {
                 // padding and this qubit's own edge take no part
                 const bool skip = edge_is_pad(w[k]) || edge_slot(w[k]) == slot;
                 const float x = skip ? 0.0f : fs[edge_slot(w[k])];
                 neg ^= __float_as_uint(x) >> 31;
                 f[k] = fabsf(x);
             }
-            const float mag = phi((f[0] + f[1]) + (f[2] + f[3]));
+            // the check's positions summed in order, pairwise
+            float sum = (f[0] + f[1]) + (f[2] + f[3]);
+            if constexpr (W) sum = sum + ((f[4] + f[5]) + (f[6] + f[7]));
+            const float mag = phi(sum);
             mc[j] = clampf(neg ? -mag : mag, C);
         }
-        qubit_update<VAR, WY, 4>(a, s_pi, info, info >> 20, v, mc, qs, acc, ehat, t, vp, shot,
-                                 [&](uint32_t j, float out) { store(base + j, out); });
+        qubit_update<VAR, WY, DV>(a, s_pi, info, label_word<W>(s_vl, info, v), v, mc, qs, acc, ehat, t, vp, shot,
+                                  [&](uint32_t j, float out) { store(base + j, out); });
     };
 
     int s0 = 0;
@@ -517,7 +525,7 @@ __device__ __forceinline__ void run_serial(const DecodeArgs &a, float *lds)
         }
         uint32_t bad = 0;
         if (live)
-            for (int c = r; c < m; c += G) bad |= test_node(s_ce, ehat, c, syn[c]);
+            for (int c = r; c < m; c += G) bad |= test_node<W>(s_ce, ehat, c, syn[c]);
         const uint64_t ballot = __ballot(bad != 0);
         const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << lead);
         const bool sat = (ballot & gmask) == 0;
@@ -822,16 +830,16 @@ __device__ __forceinline__ void run_code(const DecodeArgs &a, float *lds, int *e
 
 // VSET: the variant every code of the launch uses, kMixedVariants for a flooding
 // launch that mixes variants (a switch per code), kSerial for the serial schedule
-// (one code, a switch on its variant), kWide for a flooding launch with a wide graph
-// (a switch on the variant and the width: its narrow codes run the narrow steps).  Register budget: 80 VGPRs (six wavefronts per
-// SIMD: three 512-lane workgroups per CU) for every build but kWide, 128 (four)
-// for kWide, whose 8-edge checks hold twice the messages in registers.  The
+// (one code, a switch on its variant; kSerialWide for a wide graph), kWide for a
+// flooding launch of wide graphs (a switch on the variant).  Register budget: 80 VGPRs (six wavefronts per
+// SIMD: three 512-lane workgroups per CU) for every build but the wide ones, 128
+// (four) for those, whose 8-edge checks hold twice the messages in registers.  The
 // AdaGrad and switching builds spill 12-13 registers at 80 and still ran an
 // AdaGrad batch 19 % faster than at 96 VGPRs, where only two workgroups fit.
-constexpr int kMixedVariants = -1, kSerial = -2, kWide = -3;
+constexpr int kMixedVariants = -1, kSerial = -2, kWide = -3, kSerialWide = -4;
 constexpr int lds_kernel_waves(int vset)
 {
-    return vset == kWide ? 4 : 6;
+    return vset == kWide || vset == kSerialWide ? 4 : 6;
 }
 
 template <int VSET>
@@ -859,7 +867,8 @@ decode_lds_kernel(MixedArgs args)
         const int cs = a.g.cstride;
         uint32_t *s_vi = s_ce + cs * m;
         float *s_pi = reinterpret_cast<float *>(s_vi + n);
-        if (VSET == kSerial) {
+        constexpr bool SER = VSET == kSerial || VSET == kSerialWide;
+        if (SER) {
             for (int i = threadIdx.x; i < cs * m; i += kBlock) s_ce[i] = a.g.cedge[i];
         } else {
             // slot field -> slot-major position v + j n (j: the edge's rank among its
@@ -867,11 +876,11 @@ decode_lds_kernel(MixedArgs args)
             // layout holds kSlots n message words in LDS.
             // Two-plus-two layout: position = 2 [Z label] + rank among the qubit's slots
             // of the same label.
-            const bool wc = VSET == kWide && a.wide;   // the wide build also runs narrow codes
+            constexpr bool W = VSET == kWide;
             const bool c22 = VSET >= 0 && a.css22;
             for (int i = threadIdx.x; i < cs * m; i += kBlock) {
                 const uint32_t w = a.g.cedge[i];
-                uint32_t slot = wc ? lds_pad_slot<true>((uint32_t)n) : lds_pad_slot<false>((uint32_t)n);
+                uint32_t slot = lds_pad_slot<W>((uint32_t)n);
                 if (!edge_is_pad(w)) {
                     const uint32_t v = edge_var(w);
                     const uint32_t info = a.g.vinfo[v];
@@ -886,38 +895,43 @@ decode_lds_kernel(MixedArgs args)
         else
             for (int i = threadIdx.x; i < n; i += kBlock) s_vi[i] = a.g.vinfo[i];
         for (int i = threadIdx.x; i < 3 * n; i += kBlock) s_pi[i] = a.prior[i];
-        if (VSET == kWide && a.wide) {   // slot labels of a wide graph
+        if (VSET == kWide) {   // slot labels of a wide graph
             uint32_t *s_vl = reinterpret_cast<uint32_t *>(s_pi + 3 * n);
             for (int i = threadIdx.x; i < n; i += kBlock) s_vl[i] = a.g.vlab[i];
         }
-        if (VSET == kSerial) {   // slot -> check table and the level order
+        if (SER) {   // slot -> check table and the level order (wide graphs: the slot labels)
             uint32_t *s_vchk = reinterpret_cast<uint32_t *>(s_pi + 3 * n);
             uint32_t *s_ord = s_vchk + a.g.nnz;
             uint32_t *s_lev = s_ord + n;
             for (int i = threadIdx.x; i < a.g.nnz; i += kBlock) s_vchk[i] = a.g.vchk[i];
             for (int i = threadIdx.x; i < n; i += kBlock) s_ord[i] = a.g.sord[i];
             for (int i = threadIdx.x; i <= a.g.nlev; i += kBlock) s_lev[i] = a.g.slev[i];
+            if (VSET == kSerialWide) {
+                uint32_t *s_vl = s_lev + a.g.nlev + 1;
+                for (int i = threadIdx.x; i < n; i += kBlock) s_vl[i] = a.g.vlab[i];
+            }
         }
         __syncthreads();
-        if (VSET == kSerial) {
+        if (SER) {
+            constexpr bool SW = VSET == kSerialWide;
             if (a.with_y) {
                 switch (a.variant) {
-                case BP4_BP: run_serial<BP4_BP, true>(a, lds); break;
-                case BP4_MOMENTUM: run_serial<BP4_MOMENTUM, true>(a, lds); break;
-                case BP4_ADAGRAD: run_serial<BP4_ADAGRAD, true>(a, lds); break;
-                case BP4_AEWA: run_serial<BP4_AEWA, true>(a, lds); break;
-                default: run_serial<BP4_EWAINIT, true>(a, lds); break;
+                case BP4_BP: run_serial<BP4_BP, true, SW>(a, lds); break;
+                case BP4_MOMENTUM: run_serial<BP4_MOMENTUM, true, SW>(a, lds); break;
+                case BP4_ADAGRAD: run_serial<BP4_ADAGRAD, true, SW>(a, lds); break;
+                case BP4_AEWA: run_serial<BP4_AEWA, true, SW>(a, lds); break;
+                default: run_serial<BP4_EWAINIT, true, SW>(a, lds); break;
                 }
             } else {
                 switch (a.variant) {
-                case BP4_BP: run_serial<BP4_BP, false>(a, lds); break;
-                case BP4_MOMENTUM: run_serial<BP4_MOMENTUM, false>(a, lds); break;
-                case BP4_ADAGRAD: run_serial<BP4_ADAGRAD, false>(a, lds); break;
-                case BP4_AEWA: run_serial<BP4_AEWA, false>(a, lds); break;
-                default: run_serial<BP4_EWAINIT, false>(a, lds); break;
+                case BP4_BP: run_serial<BP4_BP, false, SW>(a, lds); break;
+                case BP4_MOMENTUM: run_serial<BP4_MOMENTUM, false, SW>(a, lds); break;
+                case BP4_ADAGRAD: run_serial<BP4_ADAGRAD, false, SW>(a, lds); break;
+                case BP4_AEWA: run_serial<BP4_AEWA, false, SW>(a, lds); break;
+                default: run_serial<BP4_EWAINIT, false, SW>(a, lds); break;
                 }
             }
-        } else if (VSET == kWide) {   // a launch with a wide code; its narrow codes run here too
+        } else if (VSET == kWide) {   // the host launches only wide codes here
             if (a.wide) {
                 switch (a.variant) {
                 case BP4_BP: run_code<BP4_BP, true>(a, lds, events); break;
@@ -925,14 +939,6 @@ decode_lds_kernel(MixedArgs args)
                 case BP4_ADAGRAD: run_code<BP4_ADAGRAD, true>(a, lds, events); break;
                 case BP4_AEWA: run_code<BP4_AEWA, true>(a, lds, events); break;
                 default: run_code<BP4_EWAINIT, true>(a, lds, events); break;
-                }
-            } else {
-                switch (a.variant) {
-                case BP4_BP: run_code<BP4_BP, false>(a, lds, events); break;
-                case BP4_MOMENTUM: run_code<BP4_MOMENTUM, false>(a, lds, events); break;
-                case BP4_ADAGRAD: run_code<BP4_ADAGRAD, false>(a, lds, events); break;
-                case BP4_AEWA: run_code<BP4_AEWA, false>(a, lds, events); break;
-                default: run_code<BP4_EWAINIT, false>(a, lds, events); break;
                 }
             }
         } else if (VSET == kMixedVariants) {
@@ -982,10 +988,12 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int G, int S, bo
     return L;
 }
 
-LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant, int G)
+LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant, int G, bool wide)
 {
     LdsLayout L;
-    L.static_words = kMaxCheckDeg * m + n + 3 * n + nnz + n + nlev + 1;
+    // check edges, qubit words, priors, slot -> check, level order and offsets (wide
+    // graphs: 8 edge words per check and the slot labels)
+    L.static_words = (wide ? kMaxCheckDegWide : kMaxCheckDeg) * m + n + 3 * n + nnz + n + nlev + 1 + (wide ? n : 0);
     if (L.static_words & 3) L.static_words += 4 - (L.static_words & 3);
     int w = nnz;                   // signed phi of each m_{v->c}
     L.q_off = w;
@@ -1106,9 +1114,32 @@ hipError_t launch_decode_lds(const MixedArgs &args, size_t lds_bytes, hipStream_
         if (args.codes[i].variant != v) v = -1;
     bool serial = false;
     for (int i = 0; i < args.ncodes; ++i) serial = serial || args.codes[i].serial;
-    if (serial) return launch_lds_kernel<kSerial>(args, lds_bytes, s, grid_out);   // a single code
-    for (int i = 0; i < args.ncodes; ++i)
-        if (args.codes[i].wide) return launch_lds_kernel<kWide>(args, lds_bytes, s, grid_out);   // any wide
+    if (serial)   // a single code
+        return args.codes[0].wide ? launch_lds_kernel<kSerialWide>(args, lds_bytes, s, grid_out)
+                                  : launch_lds_kernel<kSerial>(args, lds_bytes, s, grid_out);
+    int wide = 0;
+    for (int i = 0; i < args.ncodes; ++i) wide += args.codes[i].wide ? 1 : 0;
+    if (wide == args.ncodes) return launch_lds_kernel<kWide>(args, lds_bytes, s, grid_out);
+    if (wide > 0) {
+        // Wide and narrow codes: two persistent launches in stream order, the wide codes
+        // on the wide build and the narrow ones on theirs, each with the LDS of its own
+        // codes (one build holding both paths needed a 4 KB scratch stack per lane and
+        // ran the wide codes three times slower).
+        MixedArgs part[2];
+        size_t bytes[2] = {0, 0};
+        part[0].ncodes = part[1].ncodes = 0;
+        for (int i = 0; i < args.ncodes; ++i) {
+            const DecodeArgs &c = args.codes[i];
+            const int k = c.wide ? 0 : 1;
+            part[k].codes[part[k].ncodes++] = c;
+            const int regions = c.block_shots > 0 ? c.block_shots : kBlock / c.group_lanes;
+            const size_t b = (size_t)4 * ((size_t)c.static_words + (size_t)regions * c.region_words);
+            bytes[k] = b > bytes[k] ? b : bytes[k];
+        }
+        hipError_t e = launch_lds_kernel<kWide>(part[0], bytes[0], s, grid_out);
+        if (e != hipSuccess) return e;
+        return launch_decode_lds(part[1], bytes[1], s, nullptr);
+    }
     switch (v) {
     case BP4_BP: return launch_lds_kernel<BP4_BP>(args, lds_bytes, s, grid_out);
     case BP4_MOMENTUM: return launch_lds_kernel<BP4_MOMENTUM>(args, lds_bytes, s, grid_out);

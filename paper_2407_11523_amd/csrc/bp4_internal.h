@@ -108,7 +108,7 @@ LdsLayout decode_lds_layout(int m, int n, int nnz, int variant, int group_lanes,
                             bool wide = false);
 // Serial schedule: wave groups of G in {1, ..., 64} lanes; static part adds the
 // slot -> check table and the level order, regions hold signed phi values.
-LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant, int group_lanes);
+LdsLayout decode_lds_serial_layout(int m, int n, int nnz, int nlev, int variant, int group_lanes, bool wide);
 // The mapping is valid for the code: G a power of two in [4, 64] with at most 64
 // checks per lane, or 1 <= S <= 256 with at most 64 check items per lane.
 bool decode_lds_fits(int m, int n, int group_lanes, int block_shots);

@@ -456,8 +456,13 @@ def test_wide_graphs_route_to_the_flooding_lds_kernel(lib):
                                fake, null, null, null, fake, 1 << 30, null)
         assert rc == -6, rc                                                # EUNSUPPORTED
         sp = Params(variant="ewainit", alpha=0.5, serial=True).c()
-        rc = lib.bp4_decode(g.handle, fake, ctypes.byref(sp), 10, fake, fake, fake, fake, fake, fake, 1 << 30, null)
-        assert rc == -6
+        # the serial schedule runs on the LDS kernel's wide build: its workspace is checked
+        # before anything runs; on the SOA kernel it is refused
+        rc = lib.bp4_decode(g.handle, fake, ctypes.byref(sp), 10, fake, fake, fake, fake, fake, fake, 0, null)
+        assert rc == -4, rc                                                # EWORKSPACE
+        rc = lib.bp4_decode_ex(g.handle, fake, ctypes.byref(sp), ctypes.byref(tune), 10, fake, fake, fake, fake,
+                               fake, null, null, null, fake, 1 << 30, null)
+        assert rc == -6, rc                                                # EUNSUPPORTED
         it = ctypes.c_int32()
         # the plain decoder takes wide graphs: its workspace is checked before anything runs
         assert lib.bp4_decode_plain(g.handle, fake, ctypes.byref(cp), 10, fake, fake, fake, fake, fake, fake,

@@ -197,3 +197,47 @@ def test_plain_decoder_on_wide_graphs(name):
         torch.cuda.synchronize()
         for k in ("est", "conv", "iters"):
             assert torch.equal(r[k], ref[k]), (name, variant, k, int((r[k] != ref[k]).sum()))
+
+
+@pytest.mark.parametrize("variant,alpha", [("bp", 1.0), ("ewainit", 0.5), ("momentum", 0.6)])
+@pytest.mark.parametrize("name", ["bb72", "chamon3"])
+def test_wide_serial_schedule(name, variant, alpha):
+    """The serial schedule (Algorithm 1) on wide graphs, level by level on the LDS kernel's
+    wide serial build, against the oracle's qubit-by-qubit sweep: messages and posteriors
+    after the first sweep within 1e-5, after two and three at least 99.9 % within 1e-5 and
+    all within 1e-3 (a sweep chains every qubit's update, and a degree-6 check chains more
+    of them than the surface codes' 1e-4 bar allows: Chamon d=3 EWAInit measured at most
+    1.03e-4 after three sweeps, 52 of 388,800 messages above 1e-5); decisions of a stopping decode on shots
+    converged on both sides at least 99.9 % equal and iteration counts of those shots equal."""
+    c = CODES[name]()
+    g = P.Graph(c.hx, c.hz, c.lx, c.lz)
+    rng = np.random.default_rng(8)
+    probs = rng.uniform(0.01, 0.04, size=(c.n, 3))
+    _, syn = O.sample(c.hx, c.hz, 600, qecgen.thresholds(*probs[0]), seed=23)
+    for T in (1, 2, 3):
+        ro = O.decode(c.hx, c.hz, O.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False,
+                                           serial=True), O.prior_llr(probs), syn, want_q=True, want_msgs=True)
+        rg = P.decode(g, P.Params(variant=variant, alpha=alpha, max_iter=T, stop_on_syndrome=False, serial=True),
+                      P.prior_llr(probs), torch.as_tensor(syn, device="cuda"), trace=True)
+        torch.cuda.synchronize()
+        for k in ("mvc", "mcv", "q"):
+            err = np.abs(np_(rg[k]).astype(np.float64) - ro[k]) / np.maximum(np.abs(ro[k]), 1.0)
+            say("wide serial msg", name, variant, T, k, float(err.max()), float((err <= REL_TOL).mean()))
+            if T == 1:
+                assert err.max() <= REL_TOL, (name, variant, T, k)
+            else:
+                assert (err <= REL_TOL).mean() >= 0.999 and err.max() <= 1e-3, (name, variant, T, k)
+    p = 0.05
+    _, syn = O.sample(c.hx, c.hz, 4000, qecgen.thresholds(p / 3, p / 3, p / 3), seed=29)
+    pr = qecgen.depolarizing_probs(c.n, p)
+    ro = O.decode(c.hx, c.hz, O.Params(variant=variant, alpha=alpha, max_iter=30, serial=True),
+                  O.prior_llr(pr), syn)
+    rg = P.decode(g, P.Params(variant=variant, alpha=alpha, max_iter=30, serial=True), P.prior_llr(pr),
+                  torch.as_tensor(syn, device="cuda"))
+    torch.cuda.synchronize()
+    both = (np_(rg["conv"]) == 1) & (ro["conv"] == 1)
+    same = (np_(rg["est"]) == ro["est"]).all(axis=1)
+    say("wide serial decisions", name, variant, int(both.sum()), float(same[both].mean()))
+    assert both.sum() > 1000
+    assert same[both].mean() >= 0.999
+    assert (np_(rg["iters"])[both] == ro["iters"][both]).mean() >= 0.999
