@@ -99,8 +99,8 @@ HBM_PEAK = 8.0e12   # bytes/s
 KERNEL_SOURCES = {"decode_lds_kernel": ("bp4_decode.hip", "bp4_wide.h", "bp4_math.h", "bp4_internal.h"),
                   "decode_gather_kernel": ("bp4_gather.hip", "bp4_gather.h", "bp4_math.h", "bp4_internal.h",
                                            "bp4_walk.cpp")}
-MEASURED_TRAFFIC = {"decode_lds_kernel": ("6ee40c8b8f79404e", 3.910e+09),    # mixed batch, one launch
-                    "decode_gather_kernel": ("b6ca92371a77853c", 4.152e+12)}   # large codes, mean of 2 launches
+MEASURED_TRAFFIC = {"decode_lds_kernel": ("4fb5ef9c8464eddb", 3.910e+09),    # mixed batch, one launch
+                    "decode_gather_kernel": ("4a8ae5b0af21aa50", 4.153e+12)}   # large codes, mean of 2 launches
 
 
 def measured_traffic(kernel):

@@ -91,13 +91,13 @@ __device__ __forceinline__ float lambda_lab(uint32_t lab, const float q[3])
 // inputs are a permutation of another check's gives bitwise equal outputs, and
 // exact symmetries of a syndrome survive FP32 rounding.  Non-negative floats order
 // like their bit patterns as unsigned integers, so the order comes from integer
-// min / max (the median is the XOR of the three values, their minimum and their
-// maximum) instead of floating-point compares.
+// min / max / median (the median written in the form the compiler turns into one
+// v_med3_u32) instead of floating-point compares.
 __device__ __forceinline__ float sum3_canonical(float a, float b, float c)
 {
     const uint32_t ua = __float_as_uint(a), ub = __float_as_uint(b), uc = __float_as_uint(c);
-    const uint32_t lo = min(min(ua, ub), uc), hi = max(max(ua, ub), uc);
-    const uint32_t mid = ua ^ ub ^ uc ^ lo ^ hi;
+    const uint32_t lo = min(ua, min(ub, uc)), hi = max(ua, max(ub, uc));
+    const uint32_t mid = min(max(ua, ub), max(min(ua, ub), uc));   // one v_med3_u32
     return (__uint_as_float(lo) + __uint_as_float(mid)) + __uint_as_float(hi);
 }
 
